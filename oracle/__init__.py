@@ -1,0 +1,103 @@
+"""Slow CPU reference ("the oracle") for the quantile-mechanics hot path.
+
+TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the benchmark's
+CPU-baseline leg may import this package.  The product library never imports,
+links or runs it, and it shares no code with the product; both sides only
+share the seeded input generator in ``qm_inputs``.
+
+Functions (all FP64 results, plain definitions solved in x87 extended
+precision, see oracle.c):
+
+  norm_quantile(u)        w(u) = Phi^{-1}(u)                  (Section 1, eq. 1)
+  exp_to_normal(x)        sign(x) Phi^{-1}(1 - e^{-|x|}/2)     (Section 6)
+  student_t_map(z, nu)    F_nu^{-1}(Phi(z))                    (Sections 1, 3.1)
+  betainc(a, b, x)        regularized incomplete beta I_x(a,b) (used by the t map)
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force=True):
+    """Compile liboracle.so with gcc (no fast-math: the oracle needs IEEE semantics)."""
+    if not force and os.path.exists(_LIB):
+        return _LIB
+    cmd = ["gcc", "-O2", "-Wall", "-shared", "-fPIC", "-o", _LIB + ".tmp", _SRC, "-lm", "-lpthread"]
+    subprocess.run(cmd, check=True)
+    os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB):
+        build()
+    lib = ctypes.CDLL(_LIB)
+    dp = ctypes.POINTER(ctypes.c_double)
+    for name in ("oracle_norm_quantile", "oracle_exp_to_normal"):
+        f = getattr(lib, name)
+        f.argtypes = [dp, dp, ctypes.c_size_t, ctypes.c_int]
+        f.restype = ctypes.c_int
+    lib.oracle_student_t_map.argtypes = [dp, dp, ctypes.c_size_t, ctypes.c_double, ctypes.c_int]
+    lib.oracle_student_t_map.restype = ctypes.c_int
+    lib.oracle_betainc.argtypes = [ctypes.c_double] * 3
+    lib.oracle_betainc.restype = ctypes.c_double
+    for name in ("oracle_norm_quantile1", "oracle_exp_to_normal1"):
+        f = getattr(lib, name)
+        f.argtypes = [ctypes.c_double]
+        f.restype = ctypes.c_double
+    lib.oracle_student_t_map1.argtypes = [ctypes.c_double, ctypes.c_double]
+    lib.oracle_student_t_map1.restype = ctypes.c_double
+    _lib = lib
+    return lib
+
+
+def _as_f64(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def norm_quantile(u, threads=0):
+    """Phi^{-1}(u) element-wise (FP64 in/out).  threads<=0: all cores."""
+    u = _as_f64(u)
+    out = np.empty_like(u)
+    _load().oracle_norm_quantile(_ptr(u), _ptr(out), u.size, threads)
+    return out
+
+
+def exp_to_normal(x, threads=0):
+    """sign(x) Phi^{-1}(1 - exp(-|x|)/2) element-wise."""
+    x = _as_f64(x)
+    out = np.empty_like(x)
+    _load().oracle_exp_to_normal(_ptr(x), _ptr(out), x.size, threads)
+    return out
+
+
+def student_t_map(z, nu, threads=0):
+    """F_nu^{-1}(Phi(z)) element-wise for real nu > 0 (nu = inf: identity)."""
+    z = _as_f64(z)
+    out = np.empty_like(z)
+    _load().oracle_student_t_map(_ptr(z), _ptr(out), z.size, float(nu), threads)
+    return out
+
+
+def betainc(a, b, x):
+    """Regularized incomplete beta I_x(a, b) (scalar)."""
+    return _load().oracle_betainc(float(a), float(b), float(x))
+
+
+def threads_used(threads=0):
+    """Number of threads the array drivers use for a given request."""
+    return threads if threads > 0 else (os.cpu_count() or 1)

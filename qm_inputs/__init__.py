@@ -1,0 +1,127 @@
+"""Seeded synthetic inputs shared by the tests, the oracle checks and the benchmark.
+
+Holds none of the quantile method's arithmetic: only a counter-based
+generator (Philox4x32-10, SC'11) and the transforms that define the workload
+arrays.  Each element depends only on (seed, stream, index), so the oracle can
+regenerate any sampled element without the full array.
+
+Workloads (sizes and seeds as used by the tests and the benchmark):
+
+  uniform53      u = (k + 1/2) 2^-53, k the top 53 bits of a Philox word pair
+  mixture        90% open uniform, 10% tail t log-uniform in [lo, 1e-2],
+                 mirrored to 1 - t with probability 1/2
+  normals        Box-Muller pairs from two open uniforms
+  exponentials   -log(u) of an open uniform
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "qm_inputs.c")
+_LIB = os.path.join(_HERE, "libqm_inputs.so")
+_lib = None
+
+
+def build(force=True):
+    if not force and os.path.exists(_LIB):
+        return _LIB
+    cmd = ["gcc", "-O2", "-Wall", "-shared", "-fPIC", "-o", _LIB + ".tmp", _SRC, "-lm", "-lpthread"]
+    subprocess.run(cmd, check=True)
+    os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB):
+        build()
+    lib = ctypes.CDLL(_LIB)
+    u64, sz, ci, cd = ctypes.c_uint64, ctypes.c_size_t, ctypes.c_int, ctypes.c_double
+    vp = ctypes.c_void_p
+    lib.qmi_philox4x32_10.argtypes = [vp, vp, vp]
+    lib.qmi_philox4x32_10.restype = None
+    for name in ("qmi_uniform53", "qmi_uniform24", "qmi_normals", "qmi_exponentials"):
+        f = getattr(lib, name)
+        f.argtypes = [u64, u64, vp, sz, ci]
+        f.restype = ci
+    for name in ("qmi_mixture_f64", "qmi_mixture_f32"):
+        f = getattr(lib, name)
+        f.argtypes = [u64, u64, cd, cd, vp, sz, ci]
+        f.restype = ci
+    _lib = lib
+    return lib
+
+
+def philox4x32_10(counter, key):
+    """One Philox4x32-10 block: counter (4 x u32), key (2 x u32) -> 4 x u32."""
+    c = np.ascontiguousarray(counter, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.empty(4, dtype=np.uint32)
+    _load().qmi_philox4x32_10(c.ctypes.data, k.ctypes.data, out.ctypes.data)
+    return out
+
+
+def uniform53(seed, stream, n, threads=0, out=None):
+    out = np.empty(n, np.float64) if out is None else out
+    _load().qmi_uniform53(seed, stream, out.ctypes.data, n, threads)
+    return out
+
+
+def uniform24(seed, stream, n, threads=0, out=None):
+    out = np.empty(n, np.float32) if out is None else out
+    _load().qmi_uniform24(seed, stream, out.ctypes.data, n, threads)
+    return out
+
+
+def mixture(seed, stream, n, dtype=np.float64, p_tail=0.1, tail_lo=None, threads=0, out=None):
+    """Bulk/tail mixture; tail_lo defaults to 1e-300 (f64) or 1e-37 (f32)."""
+    dtype = np.dtype(dtype)
+    if tail_lo is None:
+        tail_lo = 1e-300 if dtype == np.float64 else 1e-37
+    out = np.empty(n, dtype) if out is None else out
+    f = _load().qmi_mixture_f64 if dtype == np.float64 else _load().qmi_mixture_f32
+    f(seed, stream, p_tail, tail_lo, out.ctypes.data, n, threads)
+    return out
+
+
+def normals(seed, stream, n, threads=0, out=None):
+    out = np.empty(n, np.float64) if out is None else out
+    _load().qmi_normals(seed, stream, out.ctypes.data, n, threads)
+    return out
+
+
+def exponentials(seed, stream, n, threads=0, out=None):
+    out = np.empty(n, np.float64) if out is None else out
+    _load().qmi_exponentials(seed, stream, out.ctypes.data, n, threads)
+    return out
+
+
+# Workload definitions (seeds and streams fixed here so every user agrees).
+def uniforms_2e20():
+    """Plain FP64 quantile workload: 2^20 open uniforms, seed 0."""
+    return uniform53(0, 0, 1 << 20)
+
+
+def mixture_f64(n=1 << 28, threads=0):
+    """FP64 mixture workload: 10% tail log-uniform in [1e-300, 1e-2], seed 1."""
+    return mixture(1, 0, n, np.float64, 0.1, 1e-300, threads)
+
+
+def mixture_f32(n=1 << 28, threads=0):
+    """FP32 mixture workload: 10% tail log-uniform in [1e-37, 1e-2], seed 1."""
+    return mixture(1, 0, n, np.float32, 0.1, 1e-37, threads)
+
+
+def recycle_normals(n=1 << 26, threads=0):
+    """Box-Muller normals for the Student t map, seed 2 stream 0."""
+    return normals(2, 0, n, threads)
+
+
+def recycle_exponentials(n=1 << 26, threads=0):
+    """Exp(1) samples for the exponential -> normal map, seed 2 stream 1."""
+    return exponentials(2, 1, n, threads)

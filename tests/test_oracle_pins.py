@@ -1,0 +1,401 @@
+"""Pins of the CPU oracle against values the paper and the mathematics fix.
+
+None of these re-types the oracle's own formula or re-calls its library
+routine (x87 erfl/erfcl and its own incomplete beta): the references are the
+paper's printed constants and approximations, closed forms, and mpmath at
+50-60 significant digits.
+"""
+import math
+from fractions import Fraction
+
+import mpmath as mp
+import numpy as np
+import pytest
+
+import oracle
+from tests import _golden
+
+pytestmark = pytest.mark.filterwarnings("ignore::RuntimeWarning")
+
+ULP_REL = 2.0 ** -52
+
+
+def mpf_list(strs):
+    return [mp.mpf(s) for s in strs]
+
+
+def horner(coeffs, x):
+    acc = mp.mpf(0)
+    for c in coeffs:
+        acc = acc * x + c
+    return acc
+
+
+# ---------------------------------------------------------------------------
+# Normal quantile w(u) = Phi^{-1}(u)  (Section 1, eq. 1)
+# ---------------------------------------------------------------------------
+
+def test_quantile_anchor_0975():
+    """w(0.975) = 1.959963984540054 (textbook 97.5% point).  The double nearest
+    0.975 sits below it, so the pin is moved by (fl(0.975) - 0.975)/phi(w)."""
+    du = float(Fraction(0.975) - Fraction(975, 1000))
+    w_true = 1.959963984540054
+    phi = math.exp(-0.5 * w_true * w_true) / math.sqrt(2 * math.pi)
+    expect = w_true + du / phi
+    got = oracle.norm_quantile([0.975])[0]
+    assert abs(got - expect) <= 3e-16 * 2, (got, expect)
+
+
+def test_quantile_paper_caps():
+    """Right-tail caps Phi^{-1}(1 - 2^-k) printed in Section 7, pinned through
+    -Phi^{-1}(2^-k) (the 2^-24 entry corrected to 5.2947)."""
+    vals = _golden.keyed("paper_values.txt")
+    for key in ("cap_k23", "cap_k24", "cap_k53", "cap_k54"):
+        k, val, prec = vals[key][0]
+        w = -oracle.norm_quantile([2.0 ** -int(k)])[0]
+        assert abs(w / float(val) - 1) <= float(prec), (key, w, val)
+    # where 1 - 2^-k is representable the upper side agrees exactly
+    for k in (23, 24, 53):
+        assert oracle.norm_quantile([1 - 2.0 ** -k])[0] == -oracle.norm_quantile([2.0 ** -k])[0]
+
+
+def test_quantile_vs_paper_13_13_rational():
+    """The paper's FP64 (13,13) rational (Appendix B) is an independent
+    high-precision approximation with relative error < 5.4e-17 on v <= 42.
+    Evaluated exactly (mpmath, 40 digits) at the oracle's own inputs it must
+    agree with the oracle to that bound plus the oracle's rounding."""
+    p, q, bound, vmax = _golden.rational("paper_rational_13_13.txt")
+    rng = np.random.default_rng(11)
+    v = np.concatenate([np.linspace(1e-6, vmax, 700), rng.uniform(0, vmax, 300),
+                        10.0 ** rng.uniform(-12, 0, 60)])
+    u = 0.5 * np.exp(-v)                     # lower-tail uniforms (double)
+    w = oracle.norm_quantile(u)
+    worst = 0.0
+    with mp.workdps(40):
+        P, Qc = mpf_list(p), mpf_list(q)
+        for ui, wi in zip(u, w):
+            vv = -mp.log(2 * mp.mpf(ui))     # exact v of the double input
+            if vv > vmax:
+                continue
+            ref = -(vv * horner(P, vv) / horner(Qc, vv))
+            worst = max(worst, float(abs(mp.mpf(wi) / ref - 1)))
+    assert worst <= bound + 1.2e-16, worst
+
+
+def test_quantile_vs_paper_5_6_rational():
+    """The FP32 (5,6) rational (Section 6.1) bounds the relative distance by
+    2.98e-8 on v <= 25; a dropped term anywhere in the oracle would show."""
+    p, q, bound, vmax = _golden.rational("paper_rational_5_6.txt")
+    v = np.linspace(0.001, vmax, 400)
+    u = 0.5 * np.exp(-v)
+    w = oracle.norm_quantile(u)
+    with mp.workdps(30):
+        P, Qc = mpf_list(p), mpf_list(q)
+        worst = max(float(abs(mp.mpf(wi) / (-(mp.mpf(-math.log(2 * ui)) * horner(P, -math.log(2 * ui))
+                                                / horner(Qc, -math.log(2 * ui)))) - 1))
+                    for ui, wi in zip(u, w))
+    assert worst <= bound + 1e-15, worst
+
+
+def _quantile_sample(seed, n_bulk=150, n_tail=150):
+    rng = np.random.default_rng(seed)
+    u = np.concatenate([rng.random(n_bulk), 10.0 ** -rng.uniform(2, 323, n_tail),
+                        1 - 10.0 ** -rng.uniform(1, 15.9, 40),
+                        0.5 + (rng.random(20) - 0.5) * 1e-9, [5e-324, 2.2e-308, 0.25, 0.75]])
+    return u[(u > 0) & (u < 1)]
+
+
+def test_quantile_brackets_mpmath():
+    """The returned double brackets the exact root: Phi(w^-) <= u <= Phi(w^+)
+    with Phi evaluated by mpmath at 50 digits (independent of libm)."""
+    u = _quantile_sample(5)
+    w = oracle.norm_quantile(u)
+    with mp.workdps(50):
+        for ui, wi in zip(u, w):
+            if ui == 0.5:
+                continue
+            lo, hi = np.nextafter(wi, -np.inf), np.nextafter(wi, np.inf)
+            assert mp.ncdf(lo) <= ui <= mp.ncdf(hi), (ui, wi)
+
+
+def test_quantile_within_one_ulp_of_mpmath_root():
+    u = _quantile_sample(6, 60, 60)
+    w = oracle.norm_quantile(u)
+    with mp.workdps(50):
+        for ui, wi in zip(u, w):
+            if ui == 0.5:
+                continue
+            x = mp.mpf(ui)
+            p = min(x, 1 - x)
+            f = lambda z: mp.log(mp.ncdf(-z)) - mp.log(p)
+            z = mp.findroot(f, mp.mpf(abs(wi)))
+            ref = -z if ui < 0.5 else z
+            assert abs(mp.mpf(wi) / ref - 1) <= 1.2e-16, (ui, wi)
+
+
+def test_quantile_exact_symmetry():
+    rng = np.random.default_rng(7)
+    hi = 0.5 + rng.random(500) * 0.5
+    hi = hi[hi < 1.0]
+    lo = 1.0 - hi                      # exact (Sterbenz)
+    assert np.array_equal(oracle.norm_quantile(hi), -oracle.norm_quantile(lo))
+
+
+def test_quantile_specials():
+    w = oracle.norm_quantile([0.0, 1.0, 0.5, np.nan, -0.1, 1.1, -0.0, np.inf])
+    assert w[0] == -np.inf and w[1] == np.inf and w[2] == 0.0
+    assert np.isnan(w[3]) and np.isnan(w[4]) and np.isnan(w[5])
+    assert w[6] == -np.inf and np.isnan(w[7])
+
+
+def test_quantile_t2_filter_value():
+    """Section 7.3: Psi(15.5) = Phi^{-1}((1 + v/sqrt(1+v^2))/2) = 3.07933 at
+    u = 0.998963."""
+    vals = _golden.keyed("paper_values.txt")
+    v = 15.5
+    u = 0.5 * (1 + v / math.sqrt(1 + v * v))
+    w = oracle.norm_quantile([u])[0]
+    assert abs(w / float(vals["psi_15_5"][0][1]) - 1) < 1e-5
+    assert abs(u / float(vals["psi_15_5_u"][0][1]) - 1) < 1e-6
+
+
+# ---------------------------------------------------------------------------
+# Exponential -> normal  (Section 6)
+# ---------------------------------------------------------------------------
+
+def _taylor_coeffs():
+    out = {}
+    for f in _golden.keyed("paper_exp_normal_taylor.txt")["k"]:
+        k, sign, D = int(f[0]), f[1], int(f[2])
+        pairs = [(int(f[i]), int(f[i + 1])) for i in range(3, len(f), 2)]
+        c = sum(a * mp.pi ** (mp.mpf(j) / 2) for a, j in pairs) / (D * mp.sqrt(2))
+        out[k] = -c if sign == "-" else c
+    return out
+
+
+def test_exp_to_normal_taylor_series():
+    """Section 6 series to v^10, exact coefficients; truncation error at
+    x <= 0.02 is below 1e-17 relative."""
+    with mp.workdps(40):
+        c = _taylor_coeffs()
+        xs = np.concatenate([10.0 ** np.linspace(-12, math.log10(0.02), 80)])
+        z = oracle.exp_to_normal(xs)
+        for x, zi in zip(xs, z):
+            ref = sum(c[k] * mp.mpf(x) ** k for k in c)
+            assert abs(mp.mpf(zi) / ref - 1) <= 1.5e-16, (x, zi)
+
+
+def test_exp_to_normal_initial_slope():
+    """Q(0) = 0 and Q'(0) = sqrt(pi/2) (Section 6 initial conditions)."""
+    x = 1e-12
+    z = oracle.exp_to_normal([x, 0.0, -0.0])
+    assert abs(z[0] / x / math.sqrt(math.pi / 2) - 1) < 1e-11
+    assert z[1] == 0.0 and math.copysign(1, z[2]) == -1
+
+
+def test_exp_to_normal_vs_paper_13_13_rational():
+    """The (13,13) rational of Appendix B is a rational approximation of this
+    very map (v = x): agreement to 5.4e-17 plus rounding on [0, 42]."""
+    p, q, bound, vmax = _golden.rational("paper_rational_13_13.txt")
+    x = np.concatenate([np.linspace(1e-4, vmax, 500), 10.0 ** np.linspace(-10, -4, 30)])
+    z = oracle.exp_to_normal(x)
+    zneg = oracle.exp_to_normal(-x)
+    assert np.array_equal(zneg, -z)
+    with mp.workdps(40):
+        P, Qc = mpf_list(p), mpf_list(q)
+        worst = max(float(abs(mp.mpf(zi) / (mp.mpf(xi) * horner(P, xi) / horner(Qc, xi)) - 1))
+                    for xi, zi in zip(x, z))
+    assert worst <= bound + 1.2e-16, worst
+
+
+def test_exp_to_normal_far_tail_brackets():
+    """For x far beyond the paper's range the result brackets the root of
+    log q(z) = -x - log 2 (mpmath erfc at 60 digits)."""
+    xs = [43.0, 100.0, 745.0, 1000.0, 5000.0, 1e4]
+    z = oracle.exp_to_normal(xs)
+    with mp.workdps(60):
+        for x, zi in zip(xs, z):
+            g = lambda t: mp.log(mp.erfc(mp.mpf(t) / mp.sqrt(2)) / 2) + x + mp.log(2)
+            assert g(np.nextafter(zi, -np.inf)) >= 0 >= g(np.nextafter(zi, np.inf)), (x, zi)
+
+
+def test_exp_to_normal_specials():
+    z = oracle.exp_to_normal([np.inf, -np.inf, np.nan])
+    assert z[0] == np.inf and z[1] == -np.inf and np.isnan(z[2])
+
+
+# ---------------------------------------------------------------------------
+# Normal -> Student t  (Sections 1, 3)
+# ---------------------------------------------------------------------------
+
+def _c_and_q(z):
+    s = abs(mp.mpf(z))
+    return mp.erf(s / mp.sqrt(2)) / 2, mp.erfc(s / mp.sqrt(2)) / 2
+
+
+def closed_form(nu, z):
+    """Closed-form Student quantiles of Phi(z) for nu = 1, 2, 4.
+    nu=1: t = tan(pi c) with c = Phi(z) - 1/2.
+    nu=2: t = 2c / sqrt(2 q (1-q)) (the T2 quantile of Section 4.4).
+    nu=4: t = 2 sqrt(cos(arccos(sqrt(a))/3)/sqrt(a) - 1), a = 4 q (1-q)."""
+    c, q = _c_and_q(z)
+    if nu == 1:
+        t = mp.tan(mp.pi * c) if c < 0.25 else 1 / mp.tan(mp.pi * q)
+    elif nu == 2:
+        t = 2 * c / mp.sqrt(2 * q * (1 - q))
+    elif nu == 4:
+        a = 4 * q * (1 - q)
+        t = 2 * mp.sqrt(mp.cos(mp.acos(mp.sqrt(a)) / 3) / mp.sqrt(a) - 1)
+    else:
+        raise ValueError(nu)
+    return t if z > 0 else -t
+
+
+def _t_sample(seed, n=50):
+    rng = np.random.default_rng(seed)
+    return np.concatenate([rng.normal(size=n), rng.uniform(-8.7, 8.7, n),
+                           [1e-6, -1e-3, 0.5, 0.67, 0.6700000001, 3.93473, 8.652, -8.652, 12.0, 30.0]])
+
+
+@pytest.mark.parametrize("nu", [1, 2, 4])
+def test_student_closed_forms(nu):
+    z = _t_sample(100 + nu)
+    t = oracle.student_t_map(z, nu)
+    with mp.workdps(80):
+        for zi, ti in zip(z, t):
+            ref = closed_form(nu, zi)
+            assert abs(mp.mpf(ti) / ref - 1) <= 1.2e-16, (nu, zi, ti)
+
+
+@pytest.mark.parametrize("nu", [0.7, 2.5, 3, 5, 10, 30, 50])
+def test_student_vs_mpmath_betainc_root(nu):
+    """Root of I_{nu/(nu+t^2)}(nu/2, 1/2)/2 = q (or the central form) found by
+    mpmath at 60 digits, bracketing the oracle's value."""
+    z = _t_sample(200 + int(10 * nu), 12)
+    t = oracle.student_t_map(z, nu)
+    a = mp.mpf(nu) / 2
+    with mp.workdps(60):
+        for zi, ti in zip(z, t):
+            if not np.isfinite(ti):
+                continue
+            c, q = _c_and_q(zi)
+            if c < 0.25:
+                f = lambda tt: mp.log(mp.betainc(mp.mpf(1) / 2, a, 0, tt ** 2 / (nu + tt ** 2), regularized=True) / 2) - mp.log(c)
+            else:
+                f = lambda tt: mp.log(mp.betainc(a, mp.mpf(1) / 2, 0, nu / (nu + tt ** 2), regularized=True) / 2) - mp.log(q)
+            T = abs(mp.mpf(ti))
+            r = mp.findroot(f, (T * (1 - mp.mpf("1e-12")), T * (1 + mp.mpf("1e-12"))), solver="illinois")
+            assert abs(T / r - 1) <= 1.2e-16, (nu, zi, ti)
+
+
+def _paper_t4_series():
+    """Printed coefficients; convert inside a workdps block for full digits."""
+    return [mp.mpf(c[0]) for c in _golden.keyed("paper_t4_series.txt")["c"]]
+
+
+def test_student_paper_t4_series_near_centre():
+    """Section 3.5 series (c_0..c_10) for n = 4: at |z| <= 0.5 the truncation
+    is below 1e-17, so it must match the oracle to rounding."""
+    c = _paper_t4_series()
+    z = np.linspace(-0.5, 0.5, 101)
+    z = z[z != 0]
+    t = oracle.student_t_map(z, 4)
+    with mp.workdps(30):
+        c = _paper_t4_series()
+        for zi, ti in zip(z, t):
+            y = mp.mpf(zi) ** 2
+            ref = mp.mpf(zi) * horner(c[::-1], y)
+            assert abs(mp.mpf(ti) / ref - 1) <= 2.5e-16, (zi, ti)
+
+
+def test_student_paper_t4_accuracy_claims():
+    """Section 3.5: series error < 2e-5 on |z| < 4; series + two-term tail with
+    crossover 3.93473 below 1.4e-5 everywhere (the oracle as the exact map)."""
+    meta = _golden.keyed("paper_t4_series.txt")
+    c = [float(x) for x in _paper_t4_series()]
+    zc = float(meta["crossover"][0][0])
+    z = np.linspace(0.01, 8.5, 1200)
+    t = oracle.student_t_map(z, 4)
+    y = z * z
+    series = z * np.polyval(c[::-1], y)
+    qv = np.array([float(mp.ncdf(-mp.mpf(x))) for x in z])
+    w = qv * 16.0 / 3.0
+    tail = 2.0 * w ** -0.25 * (1 - 5.0 / 12.0 * w ** 0.5)
+    in_series = z < float(meta["series_zmax"][0][0])
+    assert np.max(np.abs(series[in_series] / t[in_series] - 1)) < float(meta["series_bound"][0][0])
+    comb = np.where(z < zc, series, tail)
+    assert np.max(np.abs(comb / t - 1)) < float(meta["combined_bound"][0][0])
+
+
+@pytest.mark.parametrize("nu", [1, 3, 7.5, 50])
+def test_student_centre_conditions(nu):
+    """Section 3.1/3.2: Q(0) = 0, Q'(0) = gamma = sqrt(n/2) G(n/2)/G((n+1)/2),
+    and Q(z)/z = gamma + c1 z^2 + c2 z^4 + O(z^6) with the printed c1, c2."""
+    with mp.workdps(40):
+        n = mp.mpf(nu)
+        g = mp.sqrt(n / 2) * mp.gamma(n / 2) / mp.gamma((n + 1) / 2)
+        c1 = ((n + 1) * g ** 3 - n * g) / (6 * n)
+        c2 = ((7 * n ** 2 + 8 * n + 1) * g ** 5 - (10 * n ** 2 + 10 * n) * g ** 3 + 3 * n ** 2 * g) / (120 * n ** 2)
+        z0 = 1e-200
+        assert abs(oracle.student_t_map([z0], nu)[0] / z0 / g - 1) < 3e-16
+        for z in (1e-4, 3e-4):
+            t = oracle.student_t_map([z], nu)[0]
+            est_c1 = (mp.mpf(t) / z - g) / z ** 2
+            # remaining error: c2 z^2 and the half-ulp rounding of t
+            half_ulp = 0.5 * np.spacing(t) / z ** 3
+            assert abs(est_c1 - c1) <= abs(c2) * z ** 2 * 1.5 + half_ulp, (nu, z)
+        z = 0.02
+        t = oracle.student_t_map([z], nu)[0]
+        est_c2 = (mp.mpf(t) / z - g - c1 * z ** 2) / z ** 4
+        assert abs(est_c2 / c2 - 1) < 0.05, (nu, est_c2, c2)
+
+
+@pytest.mark.parametrize("nu,z0", [(1, 6.0), (2, 8.0), (3, 8.6)])
+def test_student_tail_formula(nu, z0):
+    """Section 3.3/3.5: with w = q n sqrt(pi) G(n/2)/G((n+1)/2) the tail is
+    t = sqrt(n) w^{-1/n} (1 - (n+1)/(2(n+2)) w^{2/n}) up to O(w^{4/n}), which is
+    below 1e-20 relative in these ranges."""
+    zs = np.linspace(z0, z0 + 3, 15)
+    t = oracle.student_t_map(zs, nu)
+    with mp.workdps(50):
+        n = mp.mpf(nu)
+        K = n * mp.sqrt(mp.pi) * mp.gamma(n / 2) / mp.gamma((n + 1) / 2)
+        for zi, ti in zip(zs, t):
+            w = mp.ncdf(-mp.mpf(zi)) * K
+            ref = mp.sqrt(n) * w ** (-1 / n) * (1 - (n + 1) / (2 * (n + 2)) * w ** (2 / n))
+            assert abs(mp.mpf(ti) / ref - 1) <= 1.2e-16, (nu, zi)
+
+
+def test_student_large_nu_cornish_fisher():
+    """Section 3.4 (A&S 26.7.5): t = z + (z^3+z)/(4n) + ... to 1/n^4; at
+    n = 2000 the truncation is O(n^-5)."""
+    n = 2000.0
+    for z in (0.3, 1.0, 2.0):
+        t = oracle.student_t_map([z], n)[0]
+        cf = (z + (z ** 3 + z) / (4 * n) + (5 * z ** 5 + 16 * z ** 3 + 3 * z) / (96 * n ** 2)
+              + (3 * z ** 7 + 19 * z ** 5 + 17 * z ** 3 - 15 * z) / (384 * n ** 3)
+              + (79 * z ** 9 + 776 * z ** 7 + 1482 * z ** 5 - 1920 * z ** 3 - 945 * z) / (92160 * n ** 4))
+        assert abs(t / cf - 1) < 2e-15, (z, t, cf)
+
+
+def test_student_odd_and_specials():
+    z = _t_sample(300, 10)
+    for nu in (1.5, 9):
+        assert np.array_equal(oracle.student_t_map(-z, nu), -oracle.student_t_map(z, nu))
+    t = oracle.student_t_map([0.0, np.inf, -np.inf, np.nan], 3)
+    assert t[0] == 0 and t[1] == np.inf and t[2] == -np.inf and np.isnan(t[3])
+    assert np.array_equal(oracle.student_t_map(z, np.inf), z)
+    assert np.all(np.isnan(oracle.student_t_map(z[:3], -1.0)))
+    # small nu overflows to infinity in the far tail rather than failing
+    assert oracle.student_t_map([30.0], 0.5)[0] == np.inf
+
+
+def test_betainc_vs_mpmath():
+    rng = np.random.default_rng(9)
+    with mp.workdps(40):
+        for _ in range(60):
+            a, b = rng.uniform(0.1, 40, 2)
+            x = rng.random()
+            ref = mp.betainc(a, b, 0, x, regularized=True)
+            got = oracle.betainc(a, b, x)
+            assert abs(got - ref) <= 4e-16 * abs(ref) + 1e-300, (a, b, x)
