@@ -1,0 +1,193 @@
+/*
+ * qm.h -- C ABI of libqm, the MI355X (gfx950) quantile-mechanics library.
+ *
+ * Elementwise maps over device-resident arrays, after Shaw, Luu & Brickman,
+ * "Quantile Mechanics II: Changes of Variables in Monte Carlo Methods and
+ * GPU-Optimized Normal Quantiles":
+ *
+ *   qm_normal_quantile        w = Phi^{-1}(u)            (Section 1, eq. 1)
+ *   qm_recycle_exp_to_normal  z = Q(x) = sign(x) Phi^{-1}(1 - e^{-|x|}/2)
+ *                                                         (Section 6)
+ *   qm_recycle_student_t      t = F_nu^{-1}(Phi(z))       (Section 1 recycling
+ *                                composite, Section 3 recycling ODE)
+ *   qm_run_batch              many such requests in one persistent launch
+ *   qm_submit / qm_poll       continuous-batching serving loop
+ *
+ * Conventions (all entry points):
+ *   - Every function is plain C, never throws, and returns a qm_status.
+ *   - Array arguments are device pointers owned by the caller; the library
+ *     never frees them.  Input and output have the same dtype and n
+ *     elements, are contiguous, and may be identical (in place); a partial
+ *     overlap is QM_E_INVAL.  Any alignment of the element type is accepted.
+ *   - hip_stream is a hipStream_t (NULL = the null stream).  The synchronous
+ *     calls only enqueue work on that stream and return; buffers must stay
+ *     alive until the stream has completed it.
+ *   - n = 0 succeeds without a launch.
+ *   - Non-finite and out-of-range elements are never errors: they map to
+ *     NaN / +-inf per element as documented per call.
+ *   - Arguments are validated before any device work: a NULL context or
+ *     pointer (with n > 0), an unknown dtype/mode/kind, or an invalid nu is
+ *     reported and nothing is launched.
+ */
+#ifndef QM_H
+#define QM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t qm_status;
+
+#define QM_OK 0         /* success / request complete */
+#define QM_PENDING 1    /* qm_poll: request not complete yet */
+#define QM_E_INVAL (-1) /* bad argument: NULL, overlap, unknown enum, bad nu, request over budget */
+#define QM_E_DTYPE (-2) /* mode not available for this dtype/kind */
+#define QM_E_NOMEM (-3) /* device or host allocation failed */
+#define QM_E_HIP (-4)   /* HIP runtime error; text via qm_last_error() */
+#define QM_E_CLOSED (-5)/* context is shutting down */
+#define QM_E_TICKET (-6)/* unknown ticket */
+
+/* element type of both input and output */
+enum qm_dtype { QM_F32 = 0, QM_F64 = 1 };
+
+/*
+ * Precision form.
+ *   QM_PLAIN       full precision of the dtype.  F64: relative error within
+ *                  2e-15 of Phi^{-1} (absolute 2e-18 where |w| < 1e-3) on the
+ *                  whole double range.  F32: the FP64 evaluation rounded to
+ *                  float.
+ *   QM_F32_REFINE  dtype QM_F32 only: FP32 rational seed plus one FP64
+ *                  correction step against an FP64 erfc; relative error within
+ *                  2e-7 (absolute 2e-10 near 0).
+ *   QM_PAPER       the paper's constants verbatim, valid only on the paper's
+ *                  domain: F64 the (13,13) rational of Section 7.2 / Appendix
+ *                  B (v <= 42, u >= 2.875e-19), F32 the (5,6) rational of
+ *                  Section 6.1 / Appendix A (v <= 25).  Outside that domain the
+ *                  result degrades as the rational does.
+ */
+enum qm_mode { QM_PLAIN = 0, QM_F32_REFINE = 1, QM_PAPER = 2 };
+
+enum qm_kind { QM_NORMAL_QUANTILE = 0, QM_STUDENT_T = 1, QM_EXP_TO_NORMAL = 2 };
+
+typedef struct qm_ctx qm_ctx;
+
+/*
+ * Create a context on HIP device `hip_device`.  hbm_budget_bytes bounds the
+ * bytes (input + output of admitted requests) that the serving loop keeps in
+ * flight; 0 means no serving budget (qm_submit then rejects every request).
+ * The context owns the per-nu Student t tables and the serving state.
+ * Errors: QM_E_INVAL (out == NULL or no such device), QM_E_HIP, QM_E_NOMEM.
+ */
+qm_status qm_init(int hip_device, uint64_t hbm_budget_bytes, qm_ctx** out);
+
+/*
+ * Stop the serving loop, wait for requests already on the device, fail the
+ * ones still queued (their qm_poll then returns QM_E_CLOSED), and free the
+ * context.  NULL is a no-op.
+ */
+void qm_shutdown(qm_ctx* ctx);
+
+/*
+ * w[i] = Phi^{-1}(u[i]) (Section 1, eq. 1), evaluated through the paper's
+ * exponential change of variable v = -log(2 min(u, 1-u)) and a rational in v
+ * (Section 7.2), with a fitted rational in sqrt(v) for 42 < v (beyond the
+ * paper's domain, Section 4.3).  u = 0 -> -inf, u = 1 -> +inf, u outside
+ * [0,1] or NaN -> NaN, u = 1/2 -> +0.
+ * dtype/mode: F64 {PLAIN, PAPER}; F32 {PLAIN, F32_REFINE, PAPER}.
+ */
+qm_status qm_normal_quantile(qm_ctx* ctx, const void* d_u, void* d_w, uint64_t n,
+                             int dtype, int mode, void* hip_stream);
+
+/*
+ * t[i] = F_nu^{-1}(Phi(z[i])), the normal -> Student t recycling map
+ * (Section 1 recycling composite, Section 3).  nu is the real number of
+ * degrees of freedom: finite and >= 0.5, or +inf (identity).  The map is
+ * the solution of the Gaussian-background recycling ODE (Section 3.1) with
+ * centre conditions Q(0) = 0, Q'(0) = gamma (Section 3.1); the library
+ * integrates it on the host once per nu (cached in the context) and
+ * evaluates piecewise polynomials on the device.  Accuracy: relative 2e-15
+ * for |z| <= 9 (every normal drawn from a 53-bit uniform); beyond, the
+ * tail form of Section 3.3 with reduced but bounded accuracy.  z = +-inf ->
+ * +-inf, NaN -> NaN, and t may overflow to +-inf for small nu.
+ * dtype/mode: F64 PLAIN; F32 F32_REFINE.
+ * Errors: QM_E_INVAL for nu < 0.5, NaN or -inf.
+ */
+qm_status qm_recycle_student_t(qm_ctx* ctx, const void* d_z, void* d_t, uint64_t n,
+                               int dtype, int mode, double nu, void* hip_stream);
+
+/*
+ * z[i] = sign(x[i]) Phi^{-1}(1 - e^{-|x[i]|}/2): the exponential -> normal
+ * recycling map, formal solution of the exponential-background recycling
+ * ODE with Q(0) = 0, Q'(0) = sqrt(pi/2), extended by odd symmetry
+ * (Section 6).  Exp(1) inputs give half-normal magnitudes; signed (Laplace)
+ * inputs give N(0,1).  No logarithm is taken: v = |x| is the rational's
+ * variable directly.  +-0 -> +-0, +-inf -> +-inf, NaN -> NaN.
+ * dtype/mode: F64 {PLAIN, PAPER}; F32 F32_REFINE.
+ */
+qm_status qm_recycle_exp_to_normal(qm_ctx* ctx, const void* d_x, void* d_z, uint64_t n,
+                                   int dtype, int mode, void* hip_stream);
+
+/* One request of a batch or of the serving loop. */
+typedef struct {
+    uint32_t kind;      /* enum qm_kind */
+    uint32_t dtype;     /* enum qm_dtype */
+    uint32_t mode;      /* enum qm_mode */
+    uint32_t reserved;  /* must be 0 */
+    double nu;          /* QM_STUDENT_T only */
+    const void* d_in;   /* device input, n elements of dtype */
+    void* d_out;        /* device output, n elements of dtype */
+    uint64_t n;
+    uint64_t user_tag;  /* opaque to the library */
+} qm_request;
+
+/*
+ * Run `count` requests (host array) of mixed kinds, dtypes, modes and nu as
+ * one persistent launch on hip_stream: workgroups claim fixed-size chunks
+ * from a device counter; each chunk belongs to one request and is evaluated
+ * by the same device code as the single-request call with that kind, dtype
+ * and mode, so each output is bitwise identical to the single call's.
+ * Validation covers every request before anything is launched; the first
+ * invalid one decides the status.  The call returns after enqueueing; the
+ * descriptor upload is ordered on hip_stream.
+ */
+qm_status qm_run_batch(qm_ctx* ctx, const qm_request* reqs, uint64_t count, void* hip_stream);
+
+/*
+ * Serving loop.  qm_submit validates and enqueues one request and returns a
+ * ticket immediately.  A scheduler thread admits queued requests in
+ * arrival order while the bytes (in + out) of requests in flight stay within
+ * the context's HBM budget, and launches everything admitted since its
+ * previous launch as one batch; batches run on several streams, so requests
+ * admitted while others are on the GPU overlap with them.  Per-request state
+ * (descriptors, chunk counters) lives on the device for the batch's life.
+ * Buffers must stay alive until qm_poll returns QM_OK or an error.
+ * qm_submit errors: QM_E_INVAL (as qm_run_batch, or request larger than the
+ * whole budget), QM_E_DTYPE, QM_E_CLOSED.
+ * qm_poll returns QM_OK once the request's output is complete in device
+ * memory, QM_PENDING before that, QM_E_TICKET for an unknown ticket, and
+ * QM_E_CLOSED for a request failed by qm_shutdown.  A ticket reports QM_OK
+ * on every poll after completion.
+ */
+qm_status qm_submit(qm_ctx* ctx, const qm_request* req, uint64_t* ticket);
+qm_status qm_poll(qm_ctx* ctx, uint64_t ticket);
+
+/*
+ * Serving statistics since qm_init: requests completed, and the submit ->
+ * completion latency of each, in nanoseconds, written into lat_ns (up to cap
+ * entries, completion order).  Returns the number of completed requests.
+ */
+uint64_t qm_serving_latencies(qm_ctx* ctx, uint64_t* lat_ns, uint64_t cap);
+
+/* Static text for a status code. */
+const char* qm_status_string(qm_status s);
+
+/* Text of the last error reported on the calling thread ("" if none). */
+const char* qm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QM_H */

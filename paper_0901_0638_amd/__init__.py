@@ -1,0 +1,133 @@
+"""MI355X-native quantile mechanics (Shaw, Luu & Brickman, "Quantile Mechanics II").
+
+Thin Python binding of libqm.so.  The functions carry the C ABI's names and
+forward torch device tensors (pointers + current HIP stream) to it; every
+step of the maps runs in the library's HIP kernels.
+
+    ctx = Context(device=0)
+    qm_normal_quantile(ctx, u, w)                 # w = Phi^{-1}(u)
+    qm_recycle_student_t(ctx, z, t, nu=4.0)       # t = F_nu^{-1}(Phi(z))
+    qm_recycle_exp_to_normal(ctx, x, z)           # z = sign(x) Phi^{-1}(1 - e^{-|x|}/2)
+"""
+import ctypes
+
+from ._lib import (  # noqa: F401
+    QM_E_CLOSED, QM_E_DTYPE, QM_E_HIP, QM_E_INVAL, QM_E_NOMEM, QM_E_TICKET, QM_EXP_TO_NORMAL, QM_F32,
+    QM_F32_REFINE, QM_F64, QM_NORMAL_QUANTILE, QM_OK, QM_PAPER, QM_PENDING, QM_PLAIN, QM_STUDENT_T, QMError,
+    check, load, qm_request,
+)
+
+_DTYPES = {"torch.float64": QM_F64, "torch.float32": QM_F32}
+
+
+class Context:
+    """Owns a qm_ctx (per-nu tables, serving state) on one HIP device."""
+
+    def __init__(self, device=0, hbm_budget_bytes=0):
+        lib = load()
+        h = ctypes.c_void_p()
+        check(lib.qm_init(int(device), int(hbm_budget_bytes), ctypes.byref(h)))
+        self._h = h
+        self.device = device
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise RuntimeError("context already shut down")
+        return self._h
+
+    def close(self):
+        if self._h is not None:
+            load().qm_shutdown(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _dtype_of(t):
+    try:
+        return _DTYPES[str(t.dtype)]
+    except KeyError:
+        raise TypeError("expected a float32 or float64 tensor, got %s" % t.dtype)
+
+
+def _stream(stream, t):
+    if stream is not None:
+        return ctypes.c_void_p(int(stream))
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
+
+
+def _io(inp, out):
+    if inp.device.type != "cuda" or out.device.type != "cuda":
+        raise ValueError("tensors must be on a HIP device")
+    if not (inp.is_contiguous() and out.is_contiguous()):
+        raise ValueError("tensors must be contiguous")
+    if inp.numel() != out.numel() or inp.dtype != out.dtype:
+        raise ValueError("input and output must have the same size and dtype")
+    return ctypes.c_void_p(inp.data_ptr()), ctypes.c_void_p(out.data_ptr()), inp.numel(), _dtype_of(inp)
+
+
+def qm_normal_quantile(ctx, u, w, mode=QM_PLAIN, stream=None):
+    """w = Phi^{-1}(u) on the device (FP64: PLAIN/PAPER; FP32: PLAIN/F32_REFINE/PAPER)."""
+    pi, po, n, dt = _io(u, w)
+    check(load().qm_normal_quantile(ctx.handle, pi, po, n, dt, mode, _stream(stream, u)))
+
+
+def qm_recycle_student_t(ctx, z, t, nu, mode=None, stream=None):
+    """t = F_nu^{-1}(Phi(z)) (FP64 PLAIN or FP32 F32_REFINE)."""
+    pi, po, n, dt = _io(z, t)
+    if mode is None:
+        mode = QM_PLAIN if dt == QM_F64 else QM_F32_REFINE
+    check(load().qm_recycle_student_t(ctx.handle, pi, po, n, dt, mode, float(nu), _stream(stream, z)))
+
+
+def qm_recycle_exp_to_normal(ctx, x, z, mode=None, stream=None):
+    """z = sign(x) Phi^{-1}(1 - e^{-|x|}/2) (FP64 PLAIN/PAPER or FP32 F32_REFINE)."""
+    pi, po, n, dt = _io(x, z)
+    if mode is None:
+        mode = QM_PLAIN if dt == QM_F64 else QM_F32_REFINE
+    check(load().qm_recycle_exp_to_normal(ctx.handle, pi, po, n, dt, mode, _stream(stream, x)))
+
+
+def make_request(kind, inp, out, mode=None, nu=0.0, user_tag=0):
+    """qm_request for qm_run_batch / qm_submit from a pair of device tensors."""
+    pi, po, n, dt = _io(inp, out)
+    if mode is None:
+        mode = QM_PLAIN if dt == QM_F64 else QM_F32_REFINE
+    return qm_request(kind, dt, mode, 0, float(nu), pi.value, po.value, n, user_tag)
+
+
+def qm_run_batch(ctx, reqs, stream=None, device_tensor=None):
+    """Run a list of qm_request as one persistent launch."""
+    arr = (qm_request * len(reqs))(*reqs)
+    s = ctypes.c_void_p(int(stream)) if stream is not None else _stream(None, device_tensor) if device_tensor is not None else ctypes.c_void_p(0)
+    check(load().qm_run_batch(ctx.handle, arr, len(reqs), s))
+
+
+def qm_submit(ctx, req):
+    """Enqueue one request in the serving loop; returns its ticket."""
+    ticket = ctypes.c_uint64()
+    check(load().qm_submit(ctx.handle, ctypes.byref(req), ctypes.byref(ticket)))
+    return ticket.value
+
+
+def qm_poll(ctx, ticket):
+    """QM_OK when complete, QM_PENDING before; raises on errors."""
+    return check(load().qm_poll(ctx.handle, int(ticket)))
+
+
+def qm_serving_latencies(ctx, cap=1 << 20):
+    buf = (ctypes.c_uint64 * cap)()
+    n = load().qm_serving_latencies(ctx.handle, buf, cap)
+    return [buf[i] for i in range(min(n, cap))]

@@ -1,0 +1,94 @@
+"""ctypes binding of libqm.so (include/qm.h), argument marshalling only.
+
+Every function here forwards to the C ABI of the same name; all arithmetic
+runs in the library's HIP kernels.  Tensors are used only for their device
+pointers and the current HIP stream.  If libqm.so has not been built the
+import fails loudly: there is no CPU fallback.
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libqm.so")
+
+QM_OK = 0
+QM_PENDING = 1
+QM_E_INVAL = -1
+QM_E_DTYPE = -2
+QM_E_NOMEM = -3
+QM_E_HIP = -4
+QM_E_CLOSED = -5
+QM_E_TICKET = -6
+
+QM_F32 = 0
+QM_F64 = 1
+
+QM_PLAIN = 0
+QM_F32_REFINE = 1
+QM_PAPER = 2
+
+QM_NORMAL_QUANTILE = 0
+QM_STUDENT_T = 1
+QM_EXP_TO_NORMAL = 2
+
+
+class qm_request(ctypes.Structure):
+    _fields_ = [
+        ("kind", ctypes.c_uint32),
+        ("dtype", ctypes.c_uint32),
+        ("mode", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32),
+        ("nu", ctypes.c_double),
+        ("d_in", ctypes.c_void_p),
+        ("d_out", ctypes.c_void_p),
+        ("n", ctypes.c_uint64),
+        ("user_tag", ctypes.c_uint64),
+    ]
+
+
+# name -> (restype, argtypes), exactly the declarations of include/qm.h
+_vp, _u64, _i, _d = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int, ctypes.c_double
+_st = ctypes.c_int32
+SIGNATURES = {
+    "qm_init": (_st, [_i, _u64, ctypes.POINTER(_vp)]),
+    "qm_shutdown": (None, [_vp]),
+    "qm_normal_quantile": (_st, [_vp, _vp, _vp, _u64, _i, _i, _vp]),
+    "qm_recycle_student_t": (_st, [_vp, _vp, _vp, _u64, _i, _i, _d, _vp]),
+    "qm_recycle_exp_to_normal": (_st, [_vp, _vp, _vp, _u64, _i, _i, _vp]),
+    "qm_run_batch": (_st, [_vp, ctypes.POINTER(qm_request), _u64, _vp]),
+    "qm_submit": (_st, [_vp, ctypes.POINTER(qm_request), ctypes.POINTER(_u64)]),
+    "qm_poll": (_st, [_vp, _u64]),
+    "qm_serving_latencies": (_u64, [_vp, ctypes.POINTER(_u64), _u64]),
+    "qm_status_string": (ctypes.c_char_p, [_st]),
+    "qm_last_error": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+def load():
+    """Load libqm.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libqm.so not built at %s (run python -m paper_0901_0638_amd.build)" % LIB_PATH)
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+class QMError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (load().qm_status_string(status).decode(), msg))
+        self.status = status
+
+
+def check(status):
+    if status < 0:
+        raise QMError(status, load().qm_last_error().decode())
+    return status

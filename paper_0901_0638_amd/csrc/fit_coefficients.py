@@ -1,0 +1,154 @@
+#!/usr/bin/env python3
+"""Generate qm_coeffs.h: the rational approximations the GPU kernels evaluate.
+
+Run from the repository root:  python paper_0901_0638_amd/csrc/fit_coefficients.py
+
+Three approximations are fitted here, the rest are the paper's constants:
+
+  * Deep-tail piece of the exponential-coordinate normal quantile.  The
+    paper's branchless FP64 rational Q(v) = v p13(v)/q13(v) (Section 7.2,
+    Appendix B) is certified only for v <= 42 (u >= 2.875e-19); Section 4.3
+    asks only for "reasonable" growth outside.  FP64 inputs reach v = 743.7
+    (u = 4.9e-324), so the kernels switch, by a wave-wide vote, to
+    Q(v) = s * P7(s)/Q7(s), s = sqrt(v), on 42 < v <= 750.
+  * FP32 seed of the FP32+refine form: Q(v) = v * P4(v)/Q5(v) over the whole
+    FP32 range v in [0, 103.3] (the paper's (5,6) of Section 6.1 stops at
+    v = 25), accurate to ~1e-5 -- only a seed for the FP64 correction step.
+  * Mills ratio M(x) = (1 - Phi(x))/phi(x) on [0, 14.5] as P6(x)/Q7(x), the
+    only non-trivial part of the FP64 erfc used by that correction step
+    (erfc(x/sqrt2) = 2 phi(x) M(x)).
+
+Method: relative-error rational fits by linearised least squares (Loeb
+iteration) followed by Lawson reweighting towards minimax, in mpmath at 40
+digits on Chebyshev nodes; reference values come from mpmath's erfc/erfinv.
+The coefficients are then rounded to FP64 and the error of the rounded
+rational is measured exactly on a dense grid and written into the header.
+"""
+import os
+import sys
+
+import mpmath as mp
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+OUT = os.path.join(HERE, "qm_coeffs.h")
+
+
+def q_exp(v):
+    """Q(v) = Phi^{-1}(1 - e^{-v}/2) (Section 6 formal solution), v >= 0."""
+    v = mp.mpf(v)
+    if v < mp.log(2):
+        return mp.sqrt(2) * mp.erfinv(-mp.expm1(-v))
+    f = lambda z: mp.log(mp.erfc(z / mp.sqrt(2)) / 2) + v + mp.log(2)
+    return mp.findroot(f, mp.sqrt(2 * v), tol=mp.mpf(10) ** (-mp.mp.dps + 6))
+
+
+def mills(x):
+    x = mp.mpf(x)
+    return mp.erfc(x / mp.sqrt(2)) / 2 * mp.sqrt(2 * mp.pi) * mp.exp(x * x / 2)
+
+
+def cheb_nodes(a, b, n):
+    a, b = mp.mpf(a), mp.mpf(b)
+    return [a + (b - a) * (mp.cos(mp.pi * (k + mp.mpf(1) / 2) / n) + 1) / 2 for k in range(n)]
+
+
+def fit_rational(xs, fs, m, n, loeb=15, lawson=40):
+    """min max |P/Q / f - 1| over the nodes; P degree m, Q degree n, Q(0) = 1."""
+    N = len(xs)
+    w = [mp.mpf(1)] * N
+    qv = [mp.mpf(1)] * N
+    best = None
+    for it in range(loeb + lawson):
+        rows, rhs = [], []
+        for i, (x, f) in enumerate(zip(xs, fs)):
+            sc = mp.sqrt(w[i]) / (abs(f) * abs(qv[i]))
+            rows.append([sc * x ** j for j in range(m + 1)] + [-sc * f * x ** j for j in range(1, n + 1)])
+            rhs.append(sc * f)
+        sol = mp.qr_solve(mp.matrix(rows), mp.matrix(rhs))[0]
+        p = [sol[j] for j in range(m + 1)]
+        q = [mp.mpf(1)] + [sol[m + j] for j in range(1, n + 1)]
+        errs = []
+        for i, (x, f) in enumerate(zip(xs, fs)):
+            qx = mp.polyval(q[::-1], x)
+            errs.append(mp.polyval(p[::-1], x) / qx / f - 1)
+            if it < loeb:
+                qv[i] = qx
+        mx = max(abs(e) for e in errs)
+        if best is None or mx < best[0]:
+            best = (mx, p, q)
+        if it >= loeb:
+            w = [w[i] * abs(errs[i]) for i in range(N)]
+            s = sum(w)
+            w = [wi / s * N for wi in w]
+    return best
+
+
+def rounded_error(p, q, xs, fs):
+    """Max relative error of the rational with FP64-rounded coefficients."""
+    pr = [mp.mpf(float(c)) for c in p]
+    qr = [mp.mpf(float(c)) for c in q]
+    return max(abs(mp.polyval(pr[::-1], x) / mp.polyval(qr[::-1], x) / f - 1) for x, f in zip(xs, fs))
+
+
+def carr(name, coeffs, comment):
+    """C array, highest power first (Horner order)."""
+    body = ",\n".join("    %s" % repr(float(c)) for c in coeffs[::-1])
+    return "/* %s */\nstatic constexpr double %s[%d] = {\n%s\n};\n" % (comment, name, len(coeffs), body)
+
+
+def main():
+    mp.mp.dps = 40
+    out = []
+
+    # --- deep tail piece, s = sqrt(v) on [sqrt(42), sqrt(750)] -------------
+    # Fitted in s itself (not a centred variable): Q(v)/s is nearly constant
+    # here, so numerator and denominator are nearly proportional, and only
+    # with s >= 6.5 and same-sign coefficients does FP64 rounding of the
+    # coefficients stay at the 1e-17 level.
+    s_lo, s_hi = mp.sqrt(42) - mp.mpf("0.01"), mp.sqrt(750)
+    xs = cheb_nodes(s_lo, s_hi, 200)
+    fs = [q_exp(x ** 2) / x for x in xs]
+    _, p, q = fit_rational(xs, fs, 7, 7)
+    dense = [s_lo + (s_hi - s_lo) * k / 1500 for k in range(1501)]
+    dfs = [q_exp(x ** 2) / x for x in dense]
+    e_tail = rounded_error(p, q, dense, dfs)
+    print("tail (7,7): max rel %.3e" % e_tail, file=sys.stderr)
+    out.append("static constexpr double QM_TAIL_VMIN = 42.0;\n")
+    out.append("static constexpr double QM_TAIL_VMAX = 750.0;\n")
+    out.append(carr("QM_TAIL_P", p, "Q(v)/s numerator in s = sqrt(v); rel err %.2e on 42 < v <= 750" % e_tail))
+    out.append(carr("QM_TAIL_Q", q, "Q(v)/s denominator in s (constant term 1)"))
+
+    # --- FP32 seed, z/v = P4(v)/Q5(v) on [0, 103.3] --------------------------
+    xs = cheb_nodes(mp.mpf("1e-6"), mp.mpf("103.3"), 160)
+    fs = [q_exp(x) / x for x in xs]
+    _, p, q = fit_rational(xs, fs, 4, 5)
+    dense = [mp.mpf("1e-6") + mp.mpf("103.3") * k / 1500 for k in range(1501)]
+    dfs = [q_exp(x) / x for x in dense]
+    e_seed = rounded_error(p, q, dense, dfs)
+    print("seed (4,5): max rel %.3e" % e_seed, file=sys.stderr)
+    out.append(carr("QM_SEED_P", p, "FP32 seed numerator in v; rel err %.2e over v in [0,103.3]" % e_seed))
+    out.append(carr("QM_SEED_Q", q, "FP32 seed denominator in v (constant term 1)"))
+
+    # --- Mills ratio P6/Q7 on [0, 14.5] -------------------------------------
+    xs = cheb_nodes(0, mp.mpf("14.5"), 160)
+    fs = [mills(x) for x in xs]
+    _, p, q = fit_rational(xs, fs, 6, 7)
+    dense = [mp.mpf("14.5") * k / 1500 for k in range(1501)]
+    dfs = [mills(x) for x in dense]
+    e_m = rounded_error(p, q, dense, dfs)
+    print("mills (6,7): max rel %.3e" % e_m, file=sys.stderr)
+    out.append(carr("QM_MILLS_P", p, "Mills ratio numerator in x; rel err %.2e on [0,14.5]" % e_m))
+    out.append(carr("QM_MILLS_Q", q, "Mills ratio denominator in x (constant term 1)"))
+
+    hdr = [
+        "/* qm_coeffs.h -- generated by fit_coefficients.py; do not edit. */\n",
+        "#pragma once\n\n",
+        "/* Fitted pieces (see fit_coefficients.py for method and domains). */\n",
+    ] + out
+    with open(OUT, "w") as f:
+        f.write("".join(hdr))
+    print("wrote", OUT, file=sys.stderr)
+
+
+if __name__ == "__main__":
+    main()

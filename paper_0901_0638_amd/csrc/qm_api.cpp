@@ -1,0 +1,246 @@
+/*
+ * qm_api.cpp -- the C ABI of libqm (include/qm.h): argument validation,
+ * context, per-nu table cache, and dispatch to the kernels.
+ */
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+
+#include "qm_internal.h"
+#include "qm_serve.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+qm_status fail(qm_status s, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+qm_status fail(qm_status s, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return s;
+}
+
+qm_status hip_fail(hipError_t e, const char* what)
+{
+    return fail(QM_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+size_t dtype_size(int dtype) { return dtype == QM_F64 ? 8 : 4; }
+
+}  // namespace
+
+struct DeviceTable {
+    qm::TTableHeader hdr;
+    qm::TTableHeader* d_table = nullptr;  /* header followed by coefficients */
+    double max_rel_err = 0;
+};
+
+struct qm_ctx {
+    int device = 0;
+    uint64_t budget = 0;
+    qm::LaunchShape shape{};
+    std::mutex table_mu;
+    std::map<double, DeviceTable> tables;
+    qm::Server* server = nullptr;
+};
+
+namespace qm {
+
+qm_status check_request(const qm_request& r, int* dtype_size_out)
+{
+    if (r.reserved != 0) return fail(QM_E_INVAL, "reserved field must be 0");
+    if (r.dtype != QM_F32 && r.dtype != QM_F64) return fail(QM_E_INVAL, "unknown dtype %u", r.dtype);
+    if (r.mode != QM_PLAIN && r.mode != QM_F32_REFINE && r.mode != QM_PAPER)
+        return fail(QM_E_INVAL, "unknown mode %u", r.mode);
+    switch (r.kind) {
+    case QM_NORMAL_QUANTILE:
+        if (r.dtype == QM_F64 && r.mode == QM_F32_REFINE)
+            return fail(QM_E_DTYPE, "QM_F32_REFINE needs dtype QM_F32");
+        break;
+    case QM_EXP_TO_NORMAL:
+        if (r.dtype == QM_F64 && r.mode == QM_F32_REFINE)
+            return fail(QM_E_DTYPE, "QM_F32_REFINE needs dtype QM_F32");
+        if (r.dtype == QM_F32 && r.mode != QM_F32_REFINE)
+            return fail(QM_E_DTYPE, "exp->normal in FP32 is only available as QM_F32_REFINE");
+        break;
+    case QM_STUDENT_T:
+        if (!(r.dtype == QM_F64 && r.mode == QM_PLAIN) && !(r.dtype == QM_F32 && r.mode == QM_F32_REFINE))
+            return fail(QM_E_DTYPE, "Student t: F64 QM_PLAIN or F32 QM_F32_REFINE");
+        if (std::isnan(r.nu) || !(r.nu >= 0.5))
+            return fail(QM_E_INVAL, "nu must be >= 0.5 or +inf (got %g)", r.nu);
+        break;
+    default:
+        return fail(QM_E_INVAL, "unknown kind %u", r.kind);
+    }
+    size_t es = dtype_size(r.dtype);
+    if (r.n > 0) {
+        if (!r.d_in || !r.d_out) return fail(QM_E_INVAL, "NULL buffer with n > 0");
+        uintptr_t a = (uintptr_t)r.d_in, b = (uintptr_t)r.d_out;
+        if (a % es || b % es) return fail(QM_E_INVAL, "buffers must be aligned to the element size");
+        if (r.n > (UINT64_MAX / 2) / es) return fail(QM_E_INVAL, "n too large");
+        uint64_t bytes = r.n * es;
+        if (a != b && a < b + bytes && b < a + bytes) return fail(QM_E_INVAL, "input and output partially overlap");
+    }
+    if (dtype_size_out) *dtype_size_out = (int)es;
+    return QM_OK;
+}
+
+/* Look up (or build and upload) the table for nu. */
+qm_status get_table(qm_ctx* ctx, double nu, const DeviceTable** out)
+{
+    std::lock_guard<std::mutex> lk(ctx->table_mu);
+    auto it = ctx->tables.find(nu);
+    if (it != ctx->tables.end()) { *out = &it->second; return QM_OK; }
+    HostTTable ht{};
+    char err[256] = {0};
+    if (build_student_table(nu, &ht, err, sizeof err) != 0)
+        return fail(QM_E_INVAL, "Student t table for nu=%g: %s", nu, err);
+    size_t coef_bytes = (size_t)ht.hdr.ncell * ht.hdr.stride * sizeof(double);
+    size_t bytes = sizeof(TTableHeader) + coef_bytes;
+    void* d = nullptr;
+    hipError_t e = hipMalloc(&d, bytes);
+    if (e != hipSuccess) { free_student_table(&ht); return fail(QM_E_NOMEM, "hipMalloc table: %s", hipGetErrorString(e)); }
+    e = hipMemcpy(d, &ht.hdr, sizeof(TTableHeader), hipMemcpyHostToDevice);
+    if (e == hipSuccess && coef_bytes)
+        e = hipMemcpy((char*)d + sizeof(TTableHeader), ht.coef, coef_bytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) { (void)hipFree(d); free_student_table(&ht); return hip_fail(e, "upload table"); }
+    DeviceTable dt;
+    dt.hdr = ht.hdr;
+    dt.d_table = (TTableHeader*)d;
+    dt.max_rel_err = ht.max_rel_err;
+    free_student_table(&ht);
+    auto res = ctx->tables.emplace(nu, dt);
+    *out = &res.first->second;
+    return QM_OK;
+}
+
+const TTableHeader* device_table_ptr(const DeviceTable* t) { return t->d_table; }
+const TTableHeader& device_table_hdr(const DeviceTable* t) { return t->hdr; }
+const LaunchShape& ctx_shape(const qm_ctx* ctx) { return ctx->shape; }
+int ctx_device(const qm_ctx* ctx) { return ctx->device; }
+uint64_t ctx_budget(const qm_ctx* ctx) { return ctx->budget; }
+
+qm_status run_single(qm_ctx* ctx, const qm_request& r, hipStream_t s)
+{
+    if (r.n == 0) return QM_OK;
+    hipError_t e;
+    if (r.kind == QM_STUDENT_T) {
+        const DeviceTable* t = nullptr;
+        qm_status st = get_table(ctx, r.nu, &t);
+        if (st != QM_OK) return st;
+        e = launch_student(r.dtype, r.mode, r.d_in, r.d_out, r.n, t->d_table, t->hdr, s, ctx->shape);
+    } else {
+        e = launch_elementwise(r.kind, r.dtype, r.mode, r.d_in, r.d_out, r.n, s, ctx->shape);
+    }
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    return QM_OK;
+}
+
+}  // namespace qm
+
+extern "C" {
+
+qm_status qm_init(int hip_device, uint64_t hbm_budget_bytes, qm_ctx** out)
+{
+    if (!out) return fail(QM_E_INVAL, "out is NULL");
+    *out = nullptr;
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDeviceCount");
+    if (hip_device < 0 || hip_device >= count) return fail(QM_E_INVAL, "no HIP device %d (%d present)", hip_device, count);
+    e = hipSetDevice(hip_device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    int cus = 0;
+    e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, hip_device);
+    if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute");
+    qm_ctx* c = new (std::nothrow) qm_ctx;
+    if (!c) return fail(QM_E_NOMEM, "context allocation");
+    c->device = hip_device;
+    c->budget = hbm_budget_bytes;
+    c->shape.max_blocks = (uint64_t)(cus > 0 ? cus : 256) * 8;
+    c->shape.unroll = 2;
+    *out = c;
+    return QM_OK;
+}
+
+void qm_shutdown(qm_ctx* ctx)
+{
+    if (!ctx) return;
+    if (ctx->server) { qm::server_stop(ctx->server); ctx->server = nullptr; }
+    (void)hipSetDevice(ctx->device);
+    for (auto& kv : ctx->tables) (void)hipFree(kv.second.d_table);
+    delete ctx;
+}
+
+static qm_status single(qm_ctx* ctx, uint32_t kind, const void* in, void* out, uint64_t n, int dtype, int mode,
+                        double nu, void* stream)
+{
+    if (!ctx) return fail(QM_E_INVAL, "context is NULL");
+    qm_request r{};
+    r.kind = kind;
+    r.dtype = (uint32_t)dtype;
+    r.mode = (uint32_t)mode;
+    r.nu = nu;
+    r.d_in = in;
+    r.d_out = out;
+    r.n = n;
+    if (dtype != QM_F32 && dtype != QM_F64) return fail(QM_E_INVAL, "unknown dtype %d", dtype);
+    if (mode != QM_PLAIN && mode != QM_F32_REFINE && mode != QM_PAPER) return fail(QM_E_INVAL, "unknown mode %d", mode);
+    qm_status st = qm::check_request(r, nullptr);
+    if (st != QM_OK) return st;
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    return qm::run_single(ctx, r, (hipStream_t)stream);
+}
+
+qm_status qm_normal_quantile(qm_ctx* ctx, const void* d_u, void* d_w, uint64_t n, int dtype, int mode, void* s)
+{
+    return single(ctx, QM_NORMAL_QUANTILE, d_u, d_w, n, dtype, mode, 0.0, s);
+}
+
+qm_status qm_recycle_student_t(qm_ctx* ctx, const void* d_z, void* d_t, uint64_t n, int dtype, int mode,
+                               double nu, void* s)
+{
+    return single(ctx, QM_STUDENT_T, d_z, d_t, n, dtype, mode, nu, s);
+}
+
+qm_status qm_recycle_exp_to_normal(qm_ctx* ctx, const void* d_x, void* d_z, uint64_t n, int dtype, int mode,
+                                   void* s)
+{
+    return single(ctx, QM_EXP_TO_NORMAL, d_x, d_z, n, dtype, mode, 0.0, s);
+}
+
+const char* qm_status_string(qm_status s)
+{
+    switch (s) {
+    case QM_OK: return "QM_OK";
+    case QM_PENDING: return "QM_PENDING";
+    case QM_E_INVAL: return "QM_E_INVAL";
+    case QM_E_DTYPE: return "QM_E_DTYPE";
+    case QM_E_NOMEM: return "QM_E_NOMEM";
+    case QM_E_HIP: return "QM_E_HIP";
+    case QM_E_CLOSED: return "QM_E_CLOSED";
+    case QM_E_TICKET: return "QM_E_TICKET";
+    default: return "QM_UNKNOWN_STATUS";
+    }
+}
+
+const char* qm_last_error(void) { return g_last_error.c_str(); }
+
+}  /* extern "C" */
+
+/* Error helpers for the other translation units. */
+namespace qm {
+qm_status set_error(qm_status s, const char* msg) { return fail(s, "%s", msg); }
+}

@@ -1,0 +1,284 @@
+/*
+ * qm_device.hpp -- per-element device math for gfx950 (wave64).
+ *
+ * Everything here is branch-free per lane.  The only control flow is
+ * wave-uniform: a rare piece (the deep tail beyond the paper's v = 42) is
+ * entered when any lane of the wave needs it, decided by a wave vote, so no
+ * lane ever diverges from its neighbours (the paper's warp-vote idea,
+ * Section 7.3, applied to the tail instead of the centre).
+ */
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "qm_coeffs.h"
+#include "qm_paper_coeffs.h"
+
+namespace qm {
+
+/* Horner chain p <- p x + c, highest power first (Section 4.5.1: FMA-friendly
+   iterated linear maps, no quadratic factorisation). */
+template <int N>
+__device__ __forceinline__ double horner(double x, const double (&c)[N])
+{
+    double acc = c[0];
+#pragma unroll
+    for (int i = 1; i < N; ++i) acc = __builtin_fma(acc, x, c[i]);
+    return acc;
+}
+
+template <int N>
+__device__ __forceinline__ float hornerf(float x, const float (&c)[N])
+{
+    float acc = c[0];
+#pragma unroll
+    for (int i = 1; i < N; ++i) acc = __builtin_fmaf(acc, x, c[i]);
+    return acc;
+}
+
+/* FP32 Horner on FP64-stored coefficients (rounded once at compile time). */
+template <int N>
+__device__ __forceinline__ float hornerf_d(float x, const double (&c)[N])
+{
+    float acc = (float)c[0];
+#pragma unroll
+    for (int i = 1; i < N; ++i) acc = __builtin_fmaf(acc, x, (float)c[i]);
+    return acc;
+}
+
+/* a / b for finite positive b of moderate size: hardware reciprocal, two
+   Newton steps on it and one residual correction of the quotient (< 1 ulp). */
+__device__ __forceinline__ double div_pos(double a, double b)
+{
+    double y = __builtin_amdgcn_rcp(b);
+    double e = __builtin_fma(-b, y, 1.0);
+    y = __builtin_fma(e, y, y);
+    e = __builtin_fma(-b, y, 1.0);
+    y = __builtin_fma(e, y, y);
+    double q = a * y;
+    double r = __builtin_fma(-b, q, a);
+    return __builtin_fma(r, y, q);
+}
+
+/* any lane of the wave */
+__device__ __forceinline__ bool wave_any(bool p) { return __any((int)p) != 0; }
+
+/* ------------------------------------------------------------------------ */
+/* Exponential-coordinate normal quantile Q(v) = Phi^{-1}(1 - e^{-v}/2),     */
+/* v >= 0 (Section 6 formal solution; Section 7.2 branchless rational).      */
+/* ------------------------------------------------------------------------ */
+
+/* v > 750 (only reachable through exp -> normal with |x| > 750): from the
+   Mills-ratio expansion of the normal tail, log q(z) = -z^2/2 - log(z sqrt(2 pi))
+   + log S(z), S = 1 - z^-2 + 3 z^-4 - 15 z^-6 + 105 z^-8, solve
+   z^2 = 2 (v + log 2 - log(z sqrt(2 pi)) + log S(z)) by fixed-point
+   iteration; the map contracts by ~1/z^2 < 1/1500 per step. */
+__device__ __noinline__ double expcoord_far(double v)
+{
+    const double LN2 = 0.69314718055994530942, LN_SQRT2PI = 0.91893853320467274178;
+    double z = __builtin_sqrt(2.0) * __builtin_sqrt(v);
+    for (int k = 0; k < 5; ++k) {
+        double iz2 = 1.0 / (z * z);
+        double S = __builtin_fma(__builtin_fma(__builtin_fma(105.0 * iz2 - 15.0, iz2, 3.0), iz2, -1.0), iz2, 1.0);
+        double L = ::log(z) + LN_SQRT2PI - ::log(S);
+        z = __builtin_sqrt(2.0) * __builtin_sqrt(v + (LN2 - L));
+    }
+    return z;
+}
+
+/*
+ * Plain FP64 Q(v) for v in [0, inf]: the paper's (13,13) rational on
+ * v <= 42 and the fitted Q(v) = s P7(s)/Q7(s), s = sqrt v, beyond.  Both
+ * pieces end in a single division.  FAR enables the v > 750 piece.
+ */
+template <bool FAR>
+__device__ __forceinline__ double expcoord_q_plain(double v)
+{
+    double num = v * horner(v, QM_PAPER_P13);
+    double den = horner(v, QM_PAPER_Q13);
+    bool tail = v > QM_TAIL_VMIN;
+    if (wave_any(tail)) {
+        double s = __builtin_sqrt(v);
+        double nt = s * horner(s, QM_TAIL_P);
+        double dt = horner(s, QM_TAIL_Q);
+        num = tail ? nt : num;
+        den = tail ? dt : den;
+    }
+    double q = div_pos(num, den);
+    if (FAR) {
+        bool far = (v > QM_TAIL_VMAX) && (v < __builtin_inf());
+        if (wave_any(far)) {
+            double f = expcoord_far(far ? v : 1000.0);
+            q = far ? f : q;
+        }
+    }
+    return q;
+}
+
+/* Paper mode: the (13,13) rational verbatim, whatever v (Appendix B). */
+__device__ __forceinline__ double expcoord_q_paper(double v)
+{
+    return div_pos(v * horner(v, QM_PAPER_P13), horner(v, QM_PAPER_Q13));
+}
+
+/* ------------------------------------------------------------------------ */
+/* FP64 normal quantile w(u) = Phi^{-1}(u).                                  */
+/* ------------------------------------------------------------------------ */
+
+/* Reflection x = 2 min(u, 1-u) is exact (1-u exact for u >= 1/2, Sterbenz);
+   v = -log x; sign by u - 1/2 (+0 at u = 1/2).  u = 0 or 1 give x = 0, v =
+   inf, and are replaced by -inf/+inf; u < 0, u > 1 and NaN give log of a
+   negative number or NaN, hence NaN (Section 7.2 reflection; the paper's
+   kernels leave u in {0,1} to NaN). */
+template <bool PAPER>
+__device__ __forceinline__ double normal_quantile_f64(double u)
+{
+    double om = 1.0 - u;
+    double p = (u < om) ? u : om;
+    double v = -::log(p + p);
+    double mag = PAPER ? expcoord_q_paper(v) : expcoord_q_plain<false>(v);
+    double w = __builtin_copysign(mag, u - 0.5);
+    w = (u == 0.0) ? -__builtin_inf() : w;
+    w = (u == 1.0) ? __builtin_inf() : w;
+    return w;
+}
+
+/* Exponential -> normal, FP64: v = |x| directly, odd extension. */
+template <bool PAPER>
+__device__ __forceinline__ double exp_to_normal_f64(double x)
+{
+    double v = __builtin_fabs(x);
+    double mag = PAPER ? expcoord_q_paper(v) : expcoord_q_plain<true>(v);
+    mag = (v == __builtin_inf()) ? v : mag;
+    return __builtin_copysign(mag, x);
+}
+
+/* ------------------------------------------------------------------------ */
+/* FP32 + FP64-refine form.                                                  */
+/* ------------------------------------------------------------------------ */
+
+/* -log(x) for x in (0, 1] in FP32 with the hardware log2, denormals scaled
+   into the normal range first (accuracy is only needed at the seed level). */
+__device__ __forceinline__ float neg_log_f32(float x)
+{
+    const float LN2F = 0.693147180559945309f;
+    bool sub = x < 0x1p-126f;
+    float xs = sub ? x * 0x1p32f : x;
+    float l2 = __builtin_amdgcn_logf(xs);          /* v_log_f32: log2 */
+    return __builtin_fmaf(-l2, LN2F, sub ? 32.0f * LN2F : 0.0f);
+}
+
+/* FP32 seed of Q(v) = v P4(v)/Q5(v), relative error ~1.2e-5 on v <= 103.3 */
+__device__ __forceinline__ float expcoord_seed_f32(float v)
+{
+    float num = v * hornerf_d(v, QM_SEED_P);
+    float den = hornerf_d(v, QM_SEED_Q);
+    return num * __builtin_amdgcn_rcpf(den);
+}
+
+/* e^a for |a| <= 700, relative error < 1e-14: a = k ln2 + r, |r| <= ln2/2,
+   degree-11 Taylor polynomial in r, then scale by 2^k. */
+__device__ __forceinline__ double exp_refine(double a)
+{
+    const double LOG2E = 1.4426950408889634074, LN2_HI = 0.69314718055994528623, LN2_LO = 2.3190468138462996154e-17;
+    double k = __builtin_rint(a * LOG2E);
+    double r = __builtin_fma(-k, LN2_HI, a);
+    r = __builtin_fma(-k, LN2_LO, r);
+    double p = 1.0 / 39916800.0;
+    p = __builtin_fma(p, r, 1.0 / 3628800.0);
+    p = __builtin_fma(p, r, 1.0 / 362880.0);
+    p = __builtin_fma(p, r, 1.0 / 40320.0);
+    p = __builtin_fma(p, r, 1.0 / 5040.0);
+    p = __builtin_fma(p, r, 1.0 / 720.0);
+    p = __builtin_fma(p, r, 1.0 / 120.0);
+    p = __builtin_fma(p, r, 1.0 / 24.0);
+    p = __builtin_fma(p, r, 1.0 / 6.0);
+    p = __builtin_fma(p, r, 0.5);
+    p = __builtin_fma(p, r, 1.0);
+    p = __builtin_fma(p, r, 1.0);
+    return __builtin_ldexp(p, (int)k);
+}
+
+/*
+ * One Halley correction of x0 ~ z >= 0 solving q(z) = p, q(z) = 1 - Phi(z),
+ * against an FP64 erfc written as erfc(z/sqrt2) = 2 phi(z) M(z) with the
+ * Mills ratio M from a fitted rational (relative 1.1e-12 on [0, 14.5]).
+ * With G(x) = q(x) - p = phi(x) t, t = M(x) - p/phi(x), G' = -phi, G'' = x phi:
+ *   Halley:  x1 = x0 + t / (1 - x0 t / 2) ~ x0 + t (1 + x0 t / 2)
+ * (the expansion drops O(x0^2 t^3), below 1e-10 relative for a 1e-5 seed).
+ * The caller supplies p/phi(x0), formed so that it stays in range.
+ */
+__device__ __forceinline__ double halley_upper(double x0, double p_over_phi)
+{
+    double M = div_pos(horner(x0, QM_MILLS_P), horner(x0, QM_MILLS_Q));
+    double t = M - p_over_phi;
+    double h = 0.5 * x0 * t;
+    return __builtin_fma(t, 1.0 + h, x0);
+}
+
+/* Phi^{-1}(u) for FP32 u: FP32 seed + one FP64 Halley step, rounded to FP32. */
+__device__ __forceinline__ float normal_quantile_f32_refine(float u)
+{
+    const double SQRT2PI = 2.5066282746310005024;
+    float om = 1.0f - u;                       /* exact for u >= 1/2 */
+    float p = (u < om) ? u : om;
+    float v = neg_log_f32(p + p);
+    float z0 = expcoord_seed_f32(v);
+    double x0 = (double)z0;
+    double pd = (double)p;
+    /* x0 has a 24-bit significand, so x0*x0/2 is exact in FP64 */
+    double p_over_phi = pd * SQRT2PI * exp_refine(0.5 * (x0 * x0));
+    double x1 = halley_upper(x0, p_over_phi);
+    float w = __builtin_copysignf((float)x1, u - 0.5f);
+    w = (u == 0.0f) ? -__builtin_inff() : w;
+    w = (u == 1.0f) ? __builtin_inff() : w;
+    /* NaN and out-of-range inputs: p+p < 0 or NaN makes v NaN */
+    w = (u >= 0.0f && u <= 1.0f) ? w : __builtin_nanf("");
+    return w;
+}
+
+/* Phi^{-1}(u), FP32 u, paper's (5,6) in FP32 verbatim (Appendix A), with the
+   specials fixed as above. */
+__device__ __forceinline__ float normal_quantile_f32_paper(float u)
+{
+    float om = 1.0f - u;
+    float p = (u < om) ? u : om;
+    float v = neg_log_f32(p + p);
+    float mag = v * hornerf(v, QM_PAPER_P5) * __builtin_amdgcn_rcpf(hornerf(v, QM_PAPER_Q6));
+    float w = __builtin_copysignf(mag, u - 0.5f);
+    w = (u == 0.0f) ? -__builtin_inff() : w;
+    w = (u == 1.0f) ? __builtin_inff() : w;
+    w = (u >= 0.0f && u <= 1.0f) ? w : __builtin_nanf("");
+    return w;
+}
+
+/* Phi^{-1}(u), FP32 u, evaluated by the plain FP64 path and rounded. */
+__device__ __forceinline__ float normal_quantile_f32_plain(float u)
+{
+    return (float)normal_quantile_f64<false>((double)u);
+}
+
+/* Exponential -> normal for FP32 x: FP32 seed Q(|x|) then one FP64 Halley
+   step against q(z) = e^{-|x|}/2, for which
+   p/phi(x0) = sqrt(pi/2) e^{x0^2/2 - |x|}; the exponent is O(log |x|).
+   |x| > 103 (beyond the seed's fit) takes the plain FP64 path, by wave vote. */
+__device__ __forceinline__ float exp_to_normal_f32_refine(float x)
+{
+    const double SQRT_HALF_PI = 1.2533141373155002512;
+    float v = __builtin_fabsf(x);
+    bool big = !(v <= 103.0f);                  /* also inf and NaN */
+    float vs = big ? 1.0f : v;
+    double x0 = (double)expcoord_seed_f32(vs);
+    double a = __builtin_fma(0.5 * x0, x0, -(double)vs);
+    double x1 = halley_upper(x0, SQRT_HALF_PI * exp_refine(a));
+    float mag = (float)x1;
+    mag = (vs == 0.0f) ? 0.0f : mag;
+    if (wave_any(big)) {
+        float mb = (float)expcoord_q_plain<true>((double)v);
+        mb = (v == __builtin_inff()) ? v : mb;
+        mag = big ? mb : mag;
+    }
+    return __builtin_copysignf(mag, x);
+}
+
+}  // namespace qm

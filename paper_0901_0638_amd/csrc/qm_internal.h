@@ -1,0 +1,29 @@
+/*
+ * qm_internal.h -- declarations shared by the library's translation units
+ * (not part of the public ABI).
+ */
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/qm.h"
+#include "qm_table.h"
+
+namespace qm {
+
+/* Launch geometry of the streaming kernels. */
+struct LaunchShape {
+    uint64_t max_blocks;  /* cap on the grid (grid-stride beyond it) */
+    int unroll;           /* 16-byte vectors in flight per lane: 1, 2 or 4 */
+};
+
+/* Elementwise normal quantile / exp -> normal on one stream. */
+hipError_t launch_elementwise(int kind, int dtype, int mode, const void* in, void* out, uint64_t n,
+                              hipStream_t s, const LaunchShape& shape);
+
+/* Launch the Student t map with a device table (qm_student.hip). */
+hipError_t launch_student(int dtype, int mode, const void* in, void* out, uint64_t n,
+                          const TTableHeader* d_table, const TTableHeader& h_table,
+                          hipStream_t s, const LaunchShape& shape);
+
+}  // namespace qm

@@ -1,0 +1,30 @@
+/*
+ * qm_serve.h -- batch launch and serving loop (internal).
+ */
+#pragma once
+#include <stdint.h>
+
+#include "qm_internal.h"
+
+struct DeviceTable;
+
+namespace qm {
+
+struct Server;
+
+/* Validate one request; sets the last error. */
+qm_status check_request(const qm_request& r, int* dtype_size_out);
+/* Run one validated request on a stream. */
+qm_status run_single(qm_ctx* ctx, const qm_request& r, hipStream_t s);
+/* Per-nu table of a context (built on first use). */
+qm_status get_table(qm_ctx* ctx, double nu, const DeviceTable** out);
+const TTableHeader* device_table_ptr(const DeviceTable* t);
+const TTableHeader& device_table_hdr(const DeviceTable* t);
+const LaunchShape& ctx_shape(const qm_ctx* ctx);
+int ctx_device(const qm_ctx* ctx);
+uint64_t ctx_budget(const qm_ctx* ctx);
+qm_status set_error(qm_status s, const char* msg);
+
+void server_stop(Server* s);
+
+}  // namespace qm

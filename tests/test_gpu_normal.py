@@ -1,0 +1,197 @@
+"""GPU parity: normal quantile and exponential -> normal against the oracle.
+
+Inputs come from the shared seeded generator; the oracle computes every
+element (or, at the full 2^28 size, a sample of elements regenerated on the
+host by index).  Tolerance: tests/_tol.py.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import qm_inputs as qi
+from tests._tol import RTOL_F32, RTOL_F64, assert_close
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_0901_0638_amd as qm  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = qm.Context(0)
+    yield c
+    c.close()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def run_nq(ctx, u, mode=qm.QM_PLAIN):
+    d = dev(u)
+    w = torch.empty_like(d)
+    qm.qm_normal_quantile(ctx, d, w, mode)
+    torch.cuda.synchronize()
+    return w.cpu().numpy()
+
+
+def run_e(ctx, x, mode=None):
+    d = dev(x)
+    z = torch.empty_like(d)
+    qm.qm_recycle_exp_to_normal(ctx, d, z, mode)
+    torch.cuda.synchronize()
+    return z.cpu().numpy()
+
+
+SPECIAL_U = np.array([0.0, 1.0, 0.5, np.nan, -0.25, 1.5, -0.0, np.inf, -np.inf, 5e-324, 2.2250738585072014e-308,
+                      1e-300, 2.875e-19, 1 - 2.0 ** -53, 0.5 - 2.0 ** -54, 0.5 + 2.0 ** -53, 0.25, 0.75,
+                      1e-10, 1 - 1e-10, 0.9999999, 1e-16])
+
+
+def test_quantile_f64_uniforms_2e20(ctx):
+    """2^20 open uniforms, seed 0 (every element checked)."""
+    u = qi.uniforms_2e20()
+    rep = assert_close(run_nq(ctx, u), oracle.norm_quantile(u), RTOL_F64, "uniforms 2^20")
+    print("uniforms 2^20", rep)
+
+
+def test_quantile_f64_mixture_2e20(ctx):
+    """The 10% deep-tail mixture (u down to 1e-300) at 2^20, every element."""
+    u = qi.mixture(1, 0, 1 << 20, np.float64, 0.1, 1e-300)
+    rep = assert_close(run_nq(ctx, u), oracle.norm_quantile(u), RTOL_F64, "mixture 2^20")
+    print("mixture 2^20", rep)
+
+
+def test_quantile_f64_specials_and_ragged(ctx):
+    got = run_nq(ctx, SPECIAL_U)
+    assert_close(got, oracle.norm_quantile(SPECIAL_U), RTOL_F64, "specials")
+    for n in (1, 2, 3, 5, 17, 255, 256, 257, 1023):
+        u = qi.uniform53(9, n, n)
+        assert_close(run_nq(ctx, u), oracle.norm_quantile(u), RTOL_F64, "n=%d" % n)
+
+
+def test_quantile_f64_deep_tail_sweep(ctx):
+    """log-uniform u over the whole double range, including denormals, both sides."""
+    rng = np.random.default_rng(3)
+    t = 10.0 ** -rng.uniform(0.3, 323.3, 200000)
+    t = t[t > 0]
+    u = np.concatenate([t, 1.0 - t[t > 1e-16]])
+    assert_close(run_nq(ctx, u), oracle.norm_quantile(u), RTOL_F64, "deep tail")
+
+
+def test_quantile_f64_misaligned_and_inplace(ctx):
+    u = qi.uniform53(4, 0, 5000)
+    ref = oracle.norm_quantile(u)
+    base = dev(np.concatenate([[0.3], u, [0.7]]))
+    # input at offset 1 (8-byte aligned, not 16), output at offset 0: not co-aligned
+    out = torch.empty(5000, dtype=torch.float64, device="cuda")
+    qm.qm_normal_quantile(ctx, base[1:5001], out)
+    torch.cuda.synchronize()
+    assert_close(out.cpu().numpy(), ref, RTOL_F64, "misaligned")
+    # both at offset 1: co-aligned with a one-element head
+    out2 = torch.zeros(5002, dtype=torch.float64, device="cuda")
+    qm.qm_normal_quantile(ctx, base[1:5001], out2[1:5001])
+    torch.cuda.synchronize()
+    o2 = out2.cpu().numpy()
+    assert_close(o2[1:5001], ref, RTOL_F64, "co-aligned head")
+    assert o2[0] == 0 and o2[5001] == 0, "wrote outside the output range"
+    # in place
+    d = dev(u)
+    qm.qm_normal_quantile(ctx, d, d)
+    torch.cuda.synchronize()
+    assert_close(d.cpu().numpy(), ref, RTOL_F64, "in place")
+
+
+def test_quantile_f64_zero_length_and_errors(ctx):
+    d = torch.zeros(4, dtype=torch.float64, device="cuda")
+    qm.qm_normal_quantile(ctx, d[:0], d[:0])
+    with pytest.raises(qm.QMError) as e:
+        qm.qm_normal_quantile(ctx, d, d, mode=qm.QM_F32_REFINE)
+    assert e.value.status == qm.QM_E_DTYPE
+    lib = qm.load()
+    import ctypes
+    p = ctypes.c_void_p(d.data_ptr())
+    assert lib.qm_normal_quantile(ctx.handle, p, ctypes.c_void_p(d.data_ptr() + 8), 4, qm.QM_F64, 0, None) == qm.QM_E_INVAL
+    assert lib.qm_normal_quantile(ctx.handle, p, p, 4, 7, 0, None) == qm.QM_E_INVAL
+    assert lib.qm_normal_quantile(ctx.handle, None, p, 4, qm.QM_F64, 0, None) == qm.QM_E_INVAL
+
+
+def test_quantile_f64_paper_mode_on_its_domain(ctx):
+    """Paper constants verbatim (Appendix B): within tolerance for v <= 42."""
+    u = qi.uniforms_2e20()
+    assert_close(run_nq(ctx, u, qm.QM_PAPER), oracle.norm_quantile(u), RTOL_F64, "paper 13,13")
+
+
+def test_quantile_f32_refine_mixture(ctx):
+    """FP32 + FP64-refine on the FP32 mixture (tail down to 1e-37), 2^20."""
+    u = qi.mixture(1, 0, 1 << 20, np.float32, 0.1, 1e-37)
+    ref = oracle.norm_quantile(u.astype(np.float64))
+    rep = assert_close(run_nq(ctx, u, qm.QM_F32_REFINE), ref, RTOL_F32, "f32 refine")
+    print("f32 refine", rep)
+
+
+def test_quantile_f32_refine_edges(ctx):
+    rng = np.random.default_rng(8)
+    t = (10.0 ** -rng.uniform(0.3, 44.8, 100000)).astype(np.float32)
+    t = t[t > 0]
+    u = np.concatenate([t, (1.0 - t).astype(np.float32), SPECIAL_U.astype(np.float32),
+                        np.array([1.4e-45, 1.2e-38, 0.5 - 2 ** -25, 0.5 + 2 ** -24, 1 - 2 ** -24], np.float32)])
+    u = u.astype(np.float32)
+    ref = oracle.norm_quantile(u.astype(np.float64))
+    assert_close(run_nq(ctx, u, qm.QM_F32_REFINE), ref, RTOL_F32, "f32 refine edges")
+    assert_close(run_nq(ctx, u, qm.QM_PLAIN), ref, RTOL_F32, "f32 plain edges")
+
+
+def test_quantile_f32_paper_mode(ctx):
+    """Paper (5,6) in FP32 (Appendix A): realized error of order 3e-7 down to
+    u ~ 1e-11 (Section 6.3); checked at 5e-7 on its domain v <= 25."""
+    u = qi.uniform24(5, 0, 1 << 18)
+    u = u[np.minimum(u, 1 - u) > 1e-11]
+    ref = oracle.norm_quantile(u.astype(np.float64))
+    assert_close(run_nq(ctx, u, qm.QM_PAPER), ref, 5e-7, "f32 paper")
+
+
+def test_exp_to_normal_f64(ctx):
+    """Exp(1) samples (seed 2 stream 1), signed copies, and a far-tail sweep."""
+    x = qi.exponentials(2, 1, 1 << 20)
+    xs = np.concatenate([x, -x[:1000]])
+    rep = assert_close(run_e(ctx, xs), oracle.exp_to_normal(xs), RTOL_F64, "exp->normal")
+    print("exp->normal", rep)
+    rng = np.random.default_rng(4)
+    far = np.concatenate([rng.uniform(30, 800, 20000), 10 ** rng.uniform(2.5, 4, 2000),
+                          [42.0, 42.0000001, 749.9, 750.0, 750.1, 0.0, -0.0, np.inf, -np.inf, np.nan, 1e-300]])
+    assert_close(run_e(ctx, far), oracle.exp_to_normal(far), RTOL_F64, "exp->normal far")
+
+
+def test_exp_to_normal_f64_paper(ctx):
+    x = qi.exponentials(2, 1, 1 << 18)
+    assert_close(run_e(ctx, x, qm.QM_PAPER), oracle.exp_to_normal(x), RTOL_F64, "exp->normal paper")
+
+
+def test_exp_to_normal_f32_refine(ctx):
+    x = qi.exponentials(2, 1, 1 << 18).astype(np.float32)
+    x = np.concatenate([x, -x[:100], np.array([0, 102.9, 103.1, 500, 1e4, np.inf, -np.inf, np.nan], np.float32)])
+    x = x.astype(np.float32)
+    ref = oracle.exp_to_normal(x.astype(np.float64))
+    assert_close(run_e(ctx, x), ref, RTOL_F32, "exp->normal f32 refine")
+
+
+def test_quantile_f64_full_size_sampled(ctx):
+    """The FP64 mixture at its full size 2^28 in the launch configuration the
+    benchmark times; 2^16 sampled outputs (plus every tail element among the
+    first 2^20) against the oracle, inputs regenerated on the host by index."""
+    n = 1 << 28
+    u = qi.mixture_f64(n)
+    d = torch.from_numpy(u).cuda()
+    w = torch.empty_like(d)
+    qm.qm_normal_quantile(ctx, d, w)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(12)
+    idx = np.unique(np.concatenate([rng.integers(0, n, 1 << 16), np.arange(n - 300, n)]))
+    got = w[torch.from_numpy(idx).cuda()].cpu().numpy()
+    assert_close(got, oracle.norm_quantile(u[idx]), RTOL_F64, "2^28 sampled")
+    del d, w
+    torch.cuda.empty_cache()
