@@ -41,6 +41,8 @@ def main():
     ap.add_argument("--n", type=int, default=1 << 28, help="samples per pass")
     ap.add_argument("--cpu-sample", type=int, default=1 << 23, help="oracle sample size (elements)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain device copy of the FP64 input (for HBM counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the hot path is elementwise and shards without "
@@ -78,6 +80,10 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+    if args.copy_calibration:
+        # a plain copy of known size: 2^28 doubles read + written (4 GiB)
+        w64.copy_(u64)
+        torch.cuda.synchronize()
 
     events = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
     torch.cuda.synchronize()

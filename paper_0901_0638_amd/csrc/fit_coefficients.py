@@ -17,6 +17,9 @@ Three approximations are fitted here, the rest are the paper's constants:
   * Mills ratio M(x) = (1 - Phi(x))/phi(x) on [0, 14.5] as P6(x)/Q7(x), the
     only non-trivial part of the FP64 erfc used by that correction step
     (erfc(x/sqrt2) = 2 phi(x) M(x)).
+  * The FP64 logarithm of the change of variable v = -log(2 min(u,1-u)):
+    log m = 2 atanh f = 2f + f s R6(s), f = (m-1)/(m+1), s = f^2, for the
+    reduced argument m in [sqrt(1/2), sqrt(2)] (so s <= 0.0294).
 
 Method: relative-error rational fits by linearised least squares (Loeb
 iteration) followed by Lawson reweighting towards minimax, in mpmath at 40
@@ -90,6 +93,39 @@ def rounded_error(p, q, xs, fs):
     return max(abs(mp.polyval(pr[::-1], x) / mp.polyval(qr[::-1], x) / f - 1) for x, f in zip(xs, fs))
 
 
+def fit_log_poly(deg):
+    """R(s) with log m = 2f + f s R(s); minimax in the relative error of log m."""
+    smax = ((mp.sqrt(2) - 1) / (mp.sqrt(2) + 1)) ** 2
+    N = 80
+    xs = [smax * (mp.cos(mp.pi * (k + mp.mpf(1) / 2) / N) + 1) / 2 for k in range(N)]
+    fs = [(2 * mp.atanh(mp.sqrt(x)) - 2 * mp.sqrt(x)) / (mp.sqrt(x) * x) for x in xs]
+    w = [mp.mpf(1)] * N
+    best = None
+    for _ in range(40):
+        rows = [[mp.sqrt(w[i]) * x / 2 * x ** j for j in range(deg + 1)] for i, x in enumerate(xs)]
+        rhs = [mp.sqrt(w[i]) * x / 2 * f for i, (x, f) in enumerate(zip(xs, fs))]
+        c = mp.qr_solve(mp.matrix(rows), mp.matrix(rhs))[0]
+        coef = [c[j] for j in range(deg + 1)]
+        errs = [(mp.polyval(coef[::-1], x) - f) * x / 2 for x, f in zip(xs, fs)]
+        mx = max(abs(e) for e in errs)
+        if best is None or mx < best[0]:
+            best = (mx, coef)
+        w = [w[i] * abs(errs[i]) for i in range(N)]
+        sw = sum(w)
+        w = [wi / sw * N for wi in w]
+    coef = best[1]
+    cr = [mp.mpf(float(x)) for x in coef]
+    worst = 0
+    lo, hi = mp.sqrt(mp.mpf(1) / 2), mp.sqrt(2)
+    for k in range(2001):
+        m = lo + (hi - lo) * k / 2000
+        f = (m - 1) / (m + 1)
+        if f == 0:
+            continue
+        worst = max(worst, abs((2 * f + f * f * f * mp.polyval(cr[::-1], f * f)) / mp.log(m) - 1))
+    return coef, worst
+
+
 def carr(name, coeffs, comment):
     """C array, highest power first (Horner order)."""
     body = ",\n".join("    %s" % repr(float(c)) for c in coeffs[::-1])
@@ -139,6 +175,11 @@ def main():
     print("mills (6,7): max rel %.3e" % e_m, file=sys.stderr)
     out.append(carr("QM_MILLS_P", p, "Mills ratio numerator in x; rel err %.2e on [0,14.5]" % e_m))
     out.append(carr("QM_MILLS_Q", q, "Mills ratio denominator in x (constant term 1)"))
+
+    # --- FP64 log kernel: R6(s) ----------------------------------------------
+    coef, e_log = fit_log_poly(6)
+    print("log R6: max rel %.3e" % e_log, file=sys.stderr)
+    out.append(carr("QM_LOG_R", coef, "log m = 2f + f s R(s), s = f^2 <= 0.0294; rel err %.2e" % e_log))
 
     hdr = [
         "/* qm_coeffs.h -- generated by fit_coefficients.py; do not edit. */\n",

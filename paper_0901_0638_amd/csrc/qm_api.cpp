@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -168,8 +169,15 @@ qm_status qm_init(int hip_device, uint64_t hbm_budget_bytes, qm_ctx** out)
     if (!c) return fail(QM_E_NOMEM, "context allocation");
     c->device = hip_device;
     c->budget = hbm_budget_bytes;
-    c->shape.max_blocks = (uint64_t)(cus > 0 ? cus : 256) * 8;
-    c->shape.unroll = 2;
+    /* streaming launch shape: 8 workgroups of 256 per CU, two 16-byte vectors
+       in flight per lane; QM_BLOCKS_PER_CU / QM_UNROLL override (tuning) */
+    long bpc = 8, unroll = 2;
+    if (const char* ev = getenv("QM_BLOCKS_PER_CU")) bpc = strtol(ev, nullptr, 10);
+    if (const char* ev = getenv("QM_UNROLL")) unroll = strtol(ev, nullptr, 10);
+    if (bpc < 1 || bpc > 64) bpc = 8;
+    if (unroll != 1 && unroll != 2 && unroll != 4) unroll = 2;
+    c->shape.max_blocks = (uint64_t)(cus > 0 ? cus : 256) * (uint64_t)bpc;
+    c->shape.unroll = (int)unroll;
     *out = c;
     return QM_OK;
 }

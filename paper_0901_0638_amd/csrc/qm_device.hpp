@@ -46,18 +46,52 @@ __device__ __forceinline__ float hornerf_d(float x, const double (&c)[N])
     return acc;
 }
 
-/* a / b for finite positive b of moderate size: hardware reciprocal, two
-   Newton steps on it and one residual correction of the quotient (< 1 ulp). */
+/* a / b for finite positive b of moderate size.  The hardware reciprocal is
+   good to ~5e-8, so one Newton step on it (error ~2e-15) and one residual
+   correction of the quotient give a result within an ulp. */
 __device__ __forceinline__ double div_pos(double a, double b)
 {
     double y = __builtin_amdgcn_rcp(b);
     double e = __builtin_fma(-b, y, 1.0);
     y = __builtin_fma(e, y, y);
-    e = __builtin_fma(-b, y, 1.0);
-    y = __builtin_fma(e, y, y);
     double q = a * y;
     double r = __builtin_fma(-b, q, a);
     return __builtin_fma(r, y, q);
+}
+
+/* sqrt(v) for positive normal v, within an ulp: hardware reciprocal square
+   root (~5e-8), one coupled Newton step on (sqrt v, 1/(2 sqrt v)), one
+   residual correction.  Other inputs give unspecified values. */
+__device__ __forceinline__ double sqrt_pos(double v)
+{
+    double r = __builtin_amdgcn_rsq(v);
+    double s = v * r, h = 0.5 * r;
+    double e = __builtin_fma(-s, h, 0.5);
+    s = __builtin_fma(s, e, s);
+    h = __builtin_fma(h, e, h);
+    double d = __builtin_fma(-s, s, v);
+    return __builtin_fma(d, h, s);
+}
+
+/* -log(x) for x in (0, 1], relative error about an ulp.  x = m 2^e with m in
+   [sqrt(1/2), sqrt(2)); log m = 2 atanh f = 2f + f s R(s), f = (m-1)/(m+1)
+   (exact numerator), s = f^2, R a fitted degree-6 polynomial; log 2 is split
+   so that e log2_hi is exact.  Denormal x is handled by frexp.  x = 0,
+   negative or NaN x give unspecified values: callers select their results. */
+__device__ __forceinline__ double neg_log_unit(double x)
+{
+    const double SQRT_HALF = 0.70710678118654752440;
+    const double LN2_HI = 6.93147180369123816490e-01, LN2_LO = 1.90821492927058770002e-10;
+    double m = __builtin_amdgcn_frexp_mant(x);
+    int e = __builtin_amdgcn_frexp_exp(x);
+    bool lo = m < SQRT_HALF;
+    m = lo ? m + m : m;
+    e = lo ? e - 1 : e;
+    double f = div_pos(m - 1.0, m + 1.0);
+    double s = f * f;
+    double lm = __builtin_fma(f * s, horner(s, QM_LOG_R), f + f);
+    double de = (double)e;
+    return -__builtin_fma(de, LN2_HI, __builtin_fma(de, LN2_LO, lm));
 }
 
 /* any lane of the wave */
@@ -98,7 +132,7 @@ __device__ __forceinline__ double expcoord_q_plain(double v)
     double den = horner(v, QM_PAPER_Q13);
     bool tail = v > QM_TAIL_VMIN;
     if (wave_any(tail)) {
-        double s = __builtin_sqrt(v);
+        double s = sqrt_pos(v);
         double nt = s * horner(s, QM_TAIL_P);
         double dt = horner(s, QM_TAIL_Q);
         num = tail ? nt : num;
@@ -126,20 +160,20 @@ __device__ __forceinline__ double expcoord_q_paper(double v)
 /* ------------------------------------------------------------------------ */
 
 /* Reflection x = 2 min(u, 1-u) is exact (1-u exact for u >= 1/2, Sterbenz);
-   v = -log x; sign by u - 1/2 (+0 at u = 1/2).  u = 0 or 1 give x = 0, v =
-   inf, and are replaced by -inf/+inf; u < 0, u > 1 and NaN give log of a
-   negative number or NaN, hence NaN (Section 7.2 reflection; the paper's
-   kernels leave u in {0,1} to NaN). */
+   v = -log x; sign by u - 1/2 (+0 at u = 1/2).  u = 0 -> -inf, u = 1 -> +inf,
+   u outside [0,1] or NaN -> NaN, all by select (Section 7.2 reflection; the
+   paper's kernels leave u in {0,1} to NaN). */
 template <bool PAPER>
 __device__ __forceinline__ double normal_quantile_f64(double u)
 {
     double om = 1.0 - u;
     double p = (u < om) ? u : om;
-    double v = -::log(p + p);
+    double v = neg_log_unit(p + p);
     double mag = PAPER ? expcoord_q_paper(v) : expcoord_q_plain<false>(v);
     double w = __builtin_copysign(mag, u - 0.5);
     w = (u == 0.0) ? -__builtin_inf() : w;
     w = (u == 1.0) ? __builtin_inf() : w;
+    w = (u >= 0.0 && u <= 1.0) ? w : __builtin_nan("");
     return w;
 }
 
