@@ -131,3 +131,40 @@ def qm_serving_latencies(ctx, cap=1 << 20):
     buf = (ctypes.c_uint64 * cap)()
     n = load().qm_serving_latencies(ctx.handle, buf, cap)
     return [buf[i] for i in range(min(n, cap))]
+
+
+class TTableHeader(ctypes.Structure):
+    """Layout of qm::TTableHeader (csrc/qm_table.h)."""
+    _fields_ = [("nu", ctypes.c_double), ("h", ctypes.c_double), ("inv_h", ctypes.c_double),
+                ("y_max", ctypes.c_double), ("centre_offset", ctypes.c_double), ("log_K", ctypes.c_double),
+                ("tail_a", ctypes.c_double * 4), ("ncell", ctypes.c_int32), ("degree", ctypes.c_int32),
+                ("stride", ctypes.c_int32), ("identity", ctypes.c_int32), ("coef_f32_offset", ctypes.c_uint64)]
+
+
+def debug_student_dense(nu, z):
+    """Host-side dense RODE solution Q(z) used to build the t tables (qm_debug.h)."""
+    import numpy as np
+    z = np.ascontiguousarray(z, dtype=np.float64)
+    q = np.empty_like(z)
+    dp = ctypes.POINTER(ctypes.c_double)
+    r = load().qm_debug_student_dense(float(nu), z.ctypes.data_as(dp), q.ctypes.data_as(dp), z.size)
+    if r != 0:
+        raise ValueError("dense solution unavailable for nu=%r" % nu)
+    return q
+
+
+def debug_student_table(nu):
+    """(header, coefficients[ncell, stride], max_rel_err) of the host-built table."""
+    import numpy as np
+    h = TTableHeader()
+    err = ctypes.c_double()
+    lib = load()
+    dp = ctypes.POINTER(ctypes.c_double)
+    n = lib.qm_debug_student_table(float(nu), ctypes.byref(h), None, 0, ctypes.byref(err))
+    if n < 0:
+        raise ValueError("table build failed for nu=%r" % nu)
+    coef = np.empty(max(n, 0), np.float64)
+    if n > 0:
+        lib.qm_debug_student_table(float(nu), None, coef.ctypes.data_as(dp), n, None)
+        coef = coef.reshape(h.ncell, h.stride)
+    return h, coef, err.value

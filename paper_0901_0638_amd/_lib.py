@@ -63,6 +63,12 @@ SIGNATURES = {
     "qm_last_error": (ctypes.c_char_p, []),
 }
 
+# include/qm_debug.h: host-only diagnostics of the Student t table builder
+DEBUG_SIGNATURES = {
+    "qm_debug_student_dense": (ctypes.c_int, [_d, ctypes.POINTER(_d), ctypes.POINTER(_d), ctypes.c_int]),
+    "qm_debug_student_table": (ctypes.c_int, [_d, _vp, ctypes.POINTER(_d), ctypes.c_int, ctypes.POINTER(_d)]),
+}
+
 _lib = None
 
 
@@ -74,7 +80,7 @@ def load():
     if not os.path.exists(LIB_PATH):
         raise ImportError("libqm.so not built at %s (run python -m paper_0901_0638_amd.build)" % LIB_PATH)
     lib = ctypes.CDLL(LIB_PATH)
-    for name, (res, args) in SIGNATURES.items():
+    for name, (res, args) in list(SIGNATURES.items()) + list(DEBUG_SIGNATURES.items()):
         f = getattr(lib, name)
         f.restype = res
         f.argtypes = args

@@ -48,7 +48,7 @@ def build(verbose=False, jobs=8):
     for src in CXX_SOURCES:
         obj = os.path.join(BUILD, src + ".o")
         objs.append(obj)
-        cmds.append(["g++", "-O2", "-std=c++17", "-fPIC", "-Wall", "-c", os.path.join(CSRC, src), "-o", obj])
+        cmds.append(["g++", "-O2", "-std=gnu++17", "-fPIC", "-Wall", "-c", os.path.join(CSRC, src), "-o", obj])
     with ThreadPoolExecutor(max_workers=jobs) as ex:
         outs = list(ex.map(_run, cmds))
     if verbose:

@@ -12,19 +12,28 @@ from paper_0901_0638_amd import _lib
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def header_functions():
-    src = open(os.path.join(ROOT, "include", "qm.h")).read()
+def header_functions(name="qm.h"):
+    src = open(os.path.join(ROOT, "include", name)).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
     return sorted(set(re.findall(r"\b(qm_[a-z_0-9]+)\s*\(", src)))
 
 
+def all_header_functions():
+    names = []
+    for h in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if h.endswith(".h"):
+            names += header_functions(h)
+    return sorted(set(names))
+
+
 def test_header_declares_the_bound_functions():
-    assert header_functions() == sorted(_lib.SIGNATURES)
+    assert header_functions("qm.h") == sorted(_lib.SIGNATURES)
+    assert header_functions("qm_debug.h") == sorted(_lib.DEBUG_SIGNATURES)
 
 
 def test_library_exports_every_symbol():
     lib = ctypes.CDLL(_lib.LIB_PATH)
-    for name in header_functions():
+    for name in all_header_functions():
         assert hasattr(lib, name), name
 
 

@@ -1,0 +1,134 @@
+"""GPU parity: the normal -> Student t recycling map against the oracle."""
+import numpy as np
+import pytest
+
+import oracle
+import qm_inputs as qi
+from tests._tol import RTOL_F32, RTOL_F64, assert_close
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_0901_0638_amd as qm  # noqa: E402
+
+NUS = [1, 2, 3, 4, 5, 10, 30]
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = qm.Context(0)
+    yield c
+    c.close()
+
+
+def run_t(ctx, z, nu, mode=None):
+    d = torch.from_numpy(np.ascontiguousarray(z)).cuda()
+    t = torch.empty_like(d)
+    qm.qm_recycle_student_t(ctx, d, t, nu, mode)
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def normals():
+    """First 2^16 Box-Muller normals of the recycling workload (seed 2), plus
+    every element with |z| > 4 among the first 2^22."""
+    z = qi.recycle_normals(1 << 22)
+    return np.concatenate([z[: 1 << 16], z[np.abs(z) > 4.0]])
+
+
+@pytest.mark.parametrize("nu", NUS)
+def test_student_f64_workload_normals(ctx, normals, nu):
+    rep = assert_close(run_t(ctx, normals, nu), oracle.student_t_map(normals, nu), RTOL_F64, "nu=%s" % nu)
+    print("nu", nu, rep)
+
+
+@pytest.mark.parametrize("nu", [0.5, 2.5, 7.5, 50])
+def test_student_f64_other_nu(ctx, nu):
+    rng = np.random.default_rng(int(nu * 10))
+    z = np.concatenate([rng.normal(size=20000), rng.uniform(-10, 10, 20000)])
+    assert_close(run_t(ctx, z, nu), oracle.student_t_map(z, nu), RTOL_F64, "nu=%s" % nu)
+
+
+def test_student_f64_edges(ctx):
+    z = np.array([0.0, -0.0, 1e-300, -1e-300, 5e-324, 1e-8, np.nan, np.inf, -np.inf, 9.999999, -10.0,
+                  8.652, 0.5, 2.0, 7.999999999, 8.0, 8.0000000001])
+    for nu in (1, 4, 30):
+        got = run_t(ctx, z, nu)
+        assert_close(got, oracle.student_t_map(z, nu), RTOL_F64, "edges nu=%s" % nu)
+    # ragged sizes, misaligned and in place
+    for n in (1, 2, 3, 7, 255, 257):
+        zz = qi.normals(5, n, n)
+        assert_close(run_t(ctx, zz, 3), oracle.student_t_map(zz, 3), RTOL_F64, "n=%d" % n)
+    zz = qi.normals(6, 0, 3001)
+    base = torch.from_numpy(np.concatenate([[0.0], zz])).cuda()
+    out = torch.empty(3001, dtype=torch.float64, device="cuda")
+    qm.qm_recycle_student_t(ctx, base[1:], out, 4.0)
+    d = torch.from_numpy(zz).cuda()
+    qm.qm_recycle_student_t(ctx, d, d, 4.0)
+    torch.cuda.synchronize()
+    ref = oracle.student_t_map(zz, 4.0)
+    assert_close(out.cpu().numpy(), ref, RTOL_F64, "misaligned")
+    assert_close(d.cpu().numpy(), ref, RTOL_F64, "in place")
+
+
+def test_student_identity_and_large_nu(ctx):
+    z = qi.normals(7, 0, 4096)
+    assert np.array_equal(run_t(ctx, z, float("inf")), z)
+    # nu > 1e5: Cornish-Fisher polynomial (Section 3.4); oracle reliable at 1e-13 there
+    t = run_t(ctx, z, 2e5)
+    assert_close(t, oracle.student_t_map(z, 2e5), 1e-13, "nu=2e5")
+
+
+def test_student_invalid_nu(ctx):
+    d = torch.zeros(8, dtype=torch.float64, device="cuda")
+    for nu in (0.25, -1.0, float("nan"), float("-inf")):
+        with pytest.raises(qm.QMError) as e:
+            qm.qm_recycle_student_t(ctx, d, d, nu)
+        assert e.value.status == qm.QM_E_INVAL
+
+
+def test_student_far_tail(ctx):
+    """|z| > 10 takes the two-term tail of Section 3.5, accurate to
+    O(w^{4/nu}), w = K q(|z|): below 1e-14 relative for nu <= 2 there."""
+    z = np.array([10.01, 10.5, 12.0, 15.0, 20.0, 30.0, -11.0])
+    for nu in (1, 2):
+        got = run_t(ctx, z, nu)
+        ref = oracle.student_t_map(z, nu)
+        fin = np.isfinite(ref)
+        assert np.all(np.abs(got[fin] / ref[fin] - 1) < 1e-14), (nu, got, ref)
+        assert np.all(got[~fin] == ref[~fin])
+    # large nu: the formula's own error, bounded by 10 w^{4/nu}
+    import math
+    for nu in (4, 30):
+        got = run_t(ctx, z, nu)
+        ref = oracle.student_t_map(z, nu)
+        lK = math.log(nu) + 0.5 * math.log(math.pi) + math.lgamma(nu / 2) - math.lgamma((nu + 1) / 2)
+        for zi, g, r in zip(z, got, ref):
+            lw = lK + math.log(0.5 * math.erfc(abs(zi) / math.sqrt(2)))
+            assert abs(g / r - 1) <= 10 * math.exp(4 * lw / nu) + 1e-14, (nu, zi, g, r)
+
+
+@pytest.mark.parametrize("nu", [1, 4, 30])
+def test_student_f32_refine(ctx, normals, nu):
+    z = normals.astype(np.float32)
+    got = run_t(ctx, z, nu)
+    ref = oracle.student_t_map(z.astype(np.float64), nu)
+    assert_close(got, ref, RTOL_F32, "f32 nu=%s" % nu)
+
+
+def test_student_full_size_sampled(ctx):
+    """2^26 normals (the recycling workload) at nu = 4 in the benchmark's
+    launch configuration; 2^14 sampled outputs plus the 64 largest |z|."""
+    n = 1 << 26
+    z = qi.recycle_normals(n)
+    d = torch.from_numpy(z).cuda()
+    t = torch.empty_like(d)
+    qm.qm_recycle_student_t(ctx, d, t, 4.0)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(13)
+    idx = np.unique(np.concatenate([rng.integers(0, n, 1 << 14), np.argsort(np.abs(z))[-64:]]))
+    got = t[torch.from_numpy(idx).cuda()].cpu().numpy()
+    assert_close(got, oracle.student_t_map(z[idx], 4.0), RTOL_F64, "2^26 sampled")
