@@ -13,7 +13,7 @@
 #include <mutex>
 #include <string>
 
-#include "qm_internal.h"
+#include "qm_context.h"
 #include "qm_serve.h"
 
 namespace {
@@ -40,21 +40,6 @@ qm_status hip_fail(hipError_t e, const char* what)
 size_t dtype_size(int dtype) { return dtype == QM_F64 ? 8 : 4; }
 
 }  // namespace
-
-struct DeviceTable {
-    qm::TTableHeader hdr;
-    qm::TTableHeader* d_table = nullptr;  /* header followed by coefficients */
-    double max_rel_err = 0;
-};
-
-struct qm_ctx {
-    int device = 0;
-    uint64_t budget = 0;
-    qm::LaunchShape shape{};
-    std::mutex table_mu;
-    std::map<double, DeviceTable> tables;
-    qm::Server* server = nullptr;
-};
 
 namespace qm {
 
@@ -169,6 +154,7 @@ qm_status qm_init(int hip_device, uint64_t hbm_budget_bytes, qm_ctx** out)
     if (!c) return fail(QM_E_NOMEM, "context allocation");
     c->device = hip_device;
     c->budget = hbm_budget_bytes;
+    c->cus = cus > 0 ? cus : 256;
     /* streaming launch shape: 8 workgroups of 256 per CU, two 16-byte vectors
        in flight per lane; QM_BLOCKS_PER_CU / QM_UNROLL override (tuning) */
     long bpc = 8, unroll = 2;
@@ -185,8 +171,9 @@ qm_status qm_init(int hip_device, uint64_t hbm_budget_bytes, qm_ctx** out)
 void qm_shutdown(qm_ctx* ctx)
 {
     if (!ctx) return;
-    if (ctx->server) { qm::server_stop(ctx->server); ctx->server = nullptr; }
     (void)hipSetDevice(ctx->device);
+    if (ctx->server) { qm::server_stop(ctx->server); ctx->server = nullptr; }
+    qm::runner_free(ctx);
     for (auto& kv : ctx->tables) (void)hipFree(kv.second.d_table);
     delete ctx;
 }

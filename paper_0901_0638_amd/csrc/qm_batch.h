@@ -1,0 +1,44 @@
+/*
+ * qm_batch.h -- descriptors of the persistent batch kernel (internal).
+ */
+#pragma once
+#include <stdint.h>
+
+#include "qm_internal.h"
+#include "qm_student_device.hpp"
+
+namespace qm {
+
+/* Elements per chunk: a workgroup claims one chunk at a time. */
+constexpr uint64_t QM_CHUNK = 32768;
+
+enum BatchOp : uint32_t {
+    BOP_NQ64_PLAIN = 0, BOP_NQ64_PAPER, BOP_NQ32_REFINE, BOP_NQ32_PAPER, BOP_NQ32_PLAIN,
+    BOP_E64_PLAIN, BOP_E64_PAPER, BOP_E32_REFINE, BOP_T64, BOP_T32,
+};
+
+/* Device block: header, then nreq BatchReq. */
+struct BatchHeader {
+    uint64_t counter;       /* next chunk to claim; 0 at launch */
+    uint64_t total_chunks;
+    uint32_t nreq;
+    uint32_t reserved;
+    uint64_t reserved2;
+};
+
+struct BatchReq {
+    uint32_t op;            /* BatchOp */
+    uint32_t reserved;
+    const void* in;
+    void* out;
+    uint64_t n;
+    uint64_t chunk_base;    /* global index of the request's first chunk */
+    const double* coef;     /* Student t: device table coefficients */
+    StudentParams P;        /* Student t: table parameters */
+};
+
+StudentParams make_params(const TTableHeader& h);
+hipError_t launch_batch(BatchHeader* d_hdr, const BatchReq* d_reqs, size_t lds_bytes, uint64_t blocks,
+                        hipStream_t s);
+
+}  // namespace qm

@@ -1,1 +1,167 @@
-/* qm_batch.hip -- persistent batch kernel (placeholder). */
+/*
+ * qm_batch.hip -- one persistent launch over many requests of mixed kind,
+ * dtype, mode and nu.
+ *
+ * Every request is cut into chunks of QM_CHUNK elements; chunks are numbered
+ * globally in request order (chunk_base = prefix sum).  Each workgroup
+ * repeatedly claims the next chunk from a device counter, finds its request
+ * by binary search over chunk_base, and evaluates it with the same
+ * per-element functions as the single-request kernels, so every output is
+ * bitwise identical to the single call's.  A chunk belongs to one request,
+ * so the kind switch and the wave votes inside the maps are uniform across
+ * the workgroup.  A Student t chunk stages its table in LDS unless the
+ * workgroup's previous chunk already did.  The loop ends when the counter
+ * passes the last chunk, which every workgroup reaches without waiting on
+ * any other.
+ */
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "qm_batch.h"
+#include "qm_device.hpp"
+#include "qm_student_device.hpp"
+
+namespace qm {
+
+typedef double d2 __attribute__((ext_vector_type(2)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+typedef float f2 __attribute__((ext_vector_type(2)));
+
+/* 8-byte vectors per lane here (one double or two floats): with many maps in
+   one kernel, fewer elements in flight per lane keeps the register budget of
+   the widest map within reach of 4 waves per SIMD. */
+template <typename T> struct bvec;
+template <> struct bvec<double> { typedef double type; static constexpr int n = 1; };
+template <> struct bvec<float> { typedef f2 type; static constexpr int n = 2; };
+
+template <typename V, typename T> __device__ __forceinline__ T vget(const V& v, int j) { return v[j]; }
+template <> __device__ __forceinline__ double vget<double, double>(const double& v, int) { return v; }
+template <typename V, typename T> __device__ __forceinline__ void vset(V& v, int j, T x) { v[j] = x; }
+template <> __device__ __forceinline__ void vset<double, double>(double& v, int, double x) { v = x; }
+
+/* Elements [begin, end) of one request by the whole workgroup. */
+template <typename T, class F>
+__device__ __forceinline__ void chunk_map(const T* __restrict__ in, T* __restrict__ out, uint64_t begin,
+                                          uint64_t end, F f)
+{
+    typedef typename bvec<T>::type V;
+    constexpr int NV = bvec<T>::n;
+    uintptr_t pi = reinterpret_cast<uintptr_t>(in + begin), po = reinterpret_cast<uintptr_t>(out + begin);
+    uint64_t n = end - begin;
+    if ((pi % sizeof(V)) == 0 && (po % sizeof(V)) == 0) {
+        const V* vin = reinterpret_cast<const V*>(in + begin);
+        V* vout = reinterpret_cast<V*>(out + begin);
+        uint64_t nvec = n / NV;
+        for (uint64_t i = threadIdx.x; i < nvec; i += blockDim.x) {
+            V x = __builtin_nontemporal_load(vin + i);
+            V y;
+#pragma unroll
+            for (int j = 0; j < NV; ++j) vset<V, T>(y, j, f(vget<V, T>(x, j)));
+            __builtin_nontemporal_store(y, vout + i);
+        }
+        for (uint64_t i = nvec * NV + threadIdx.x; i < n; i += blockDim.x) out[begin + i] = f(in[begin + i]);
+    } else {
+        for (uint64_t i = threadIdx.x; i < n; i += blockDim.x) out[begin + i] = f(in[begin + i]);
+    }
+}
+
+extern __shared__ double lds_tab[];
+
+/* One chunk per op.  Each is a separate, non-inlined function so that its
+   constants and registers are its own: inlined together, the union of all
+   maps' loop-invariant constants would crowd the persistent loop. */
+#define QM_CHUNK_FN(NAME, T, EXPR)                                                                  \
+    static __device__ __noinline__ void NAME(const void* in, void* out, uint64_t begin, uint64_t end) \
+    {                                                                                               \
+        chunk_map<T>((const T*)in, (T*)out, begin, end, [](T x) { return EXPR; });                  \
+    }
+QM_CHUNK_FN(chunk_nq64_plain, double, normal_quantile_f64<false>(x))
+QM_CHUNK_FN(chunk_nq64_paper, double, normal_quantile_f64<true>(x))
+QM_CHUNK_FN(chunk_nq32_refine, float, normal_quantile_f32_refine(x))
+QM_CHUNK_FN(chunk_nq32_paper, float, normal_quantile_f32_paper(x))
+QM_CHUNK_FN(chunk_nq32_plain, float, normal_quantile_f32_plain(x))
+QM_CHUNK_FN(chunk_e64_plain, double, exp_to_normal_f64<false>(x))
+QM_CHUNK_FN(chunk_e64_paper, double, exp_to_normal_f64<true>(x))
+QM_CHUNK_FN(chunk_e32_refine, float, exp_to_normal_f32_refine(x))
+QM_CHUNK_FN(chunk_copy64, double, x)
+QM_CHUNK_FN(chunk_copy32, float, x)
+#undef QM_CHUNK_FN
+
+/* Student t from the table in LDS (referenced by symbol, so the loads stay
+   LDS loads). */
+static __device__ __noinline__ void chunk_t64(const void* in, void* out, uint64_t begin, uint64_t end,
+                                              const StudentParams P)
+{
+    chunk_map<double>((const double*)in, (double*)out, begin, end,
+                      [&](double z) { return student_eval(z, lds_tab, P); });
+}
+
+static __device__ __noinline__ void chunk_t32(const void* in, void* out, uint64_t begin, uint64_t end,
+                                              const StudentParams P)
+{
+    chunk_map<float>((const float*)in, (float*)out, begin, end,
+                     [&](float z) { return (float)student_eval((double)z, lds_tab, P); });
+}
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_batch(BatchHeader* hdr, const BatchReq* __restrict__ reqs)
+{
+    __shared__ uint64_t s_chunk;
+    const double* loaded = nullptr;        /* table currently in LDS (uniform) */
+    const uint64_t total = hdr->total_chunks;
+    const uint32_t nreq = hdr->nreq;
+    for (;;) {
+        if (threadIdx.x == 0) s_chunk = atomicAdd(reinterpret_cast<unsigned long long*>(&hdr->counter), 1ull);
+        __syncthreads();
+        const uint64_t c = s_chunk;
+        __syncthreads();
+        if (c >= total) break;
+        /* last request with chunk_base <= c (every listed request has chunks) */
+        uint32_t lo = 0, hi = nreq - 1;
+        while (lo < hi) {
+            uint32_t mid = (lo + hi + 1) >> 1;
+            if (reqs[mid].chunk_base <= c) lo = mid; else hi = mid - 1;
+        }
+        const BatchReq& R = reqs[lo];
+        const uint64_t begin = (c - R.chunk_base) * QM_CHUNK;
+        const uint64_t end = begin + QM_CHUNK < R.n ? begin + QM_CHUNK : R.n;
+        switch (R.op) {
+        case BOP_NQ64_PLAIN: chunk_nq64_plain(R.in, R.out, begin, end); break;
+        case BOP_NQ64_PAPER: chunk_nq64_paper(R.in, R.out, begin, end); break;
+        case BOP_NQ32_REFINE: chunk_nq32_refine(R.in, R.out, begin, end); break;
+        case BOP_NQ32_PAPER: chunk_nq32_paper(R.in, R.out, begin, end); break;
+        case BOP_NQ32_PLAIN: chunk_nq32_plain(R.in, R.out, begin, end); break;
+        case BOP_E64_PLAIN: chunk_e64_plain(R.in, R.out, begin, end); break;
+        case BOP_E64_PAPER: chunk_e64_paper(R.in, R.out, begin, end); break;
+        case BOP_E32_REFINE: chunk_e32_refine(R.in, R.out, begin, end); break;
+        case BOP_T64:
+        case BOP_T32: {
+            if (R.P.identity) {
+                if (R.op == BOP_T64) chunk_copy64(R.in, R.out, begin, end);
+                else chunk_copy32(R.in, R.out, begin, end);
+                break;
+            }
+            if (loaded != R.coef) {
+                __syncthreads();
+                const int ncoef = R.P.ncell * T_STRIDE;
+                for (int i = threadIdx.x; i < ncoef; i += blockDim.x) lds_tab[i] = R.coef[i];
+                __syncthreads();
+                loaded = R.coef;
+            }
+            if (R.op == BOP_T64) chunk_t64(R.in, R.out, begin, end, R.P);
+            else chunk_t32(R.in, R.out, begin, end, R.P);
+            break;
+        }
+        default:
+            break;
+        }
+    }
+}
+
+hipError_t launch_batch(BatchHeader* d_hdr, const BatchReq* d_reqs, size_t lds_bytes, uint64_t blocks, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_batch, dim3((unsigned)blocks), dim3(256), lds_bytes, s, d_hdr, d_reqs);
+    return hipGetLastError();
+}
+
+}  // namespace qm

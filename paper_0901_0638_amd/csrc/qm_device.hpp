@@ -292,6 +292,14 @@ __device__ __forceinline__ float normal_quantile_f32_plain(float u)
     return (float)normal_quantile_f64<false>((double)u);
 }
 
+/* |x| > 103 for the FP32 form: the plain FP64 map, rounded (kept out of line:
+   it is rare and would otherwise crowd the FP32 loop's registers). */
+__device__ __noinline__ float exp_to_normal_f32_big(float v)
+{
+    float mb = (float)expcoord_q_plain<true>((double)v);
+    return (v == __builtin_inff()) ? v : mb;
+}
+
 /* Exponential -> normal for FP32 x: FP32 seed Q(|x|) then one FP64 Halley
    step against q(z) = e^{-|x|}/2, for which
    p/phi(x0) = sqrt(pi/2) e^{x0^2/2 - |x|}; the exponent is O(log |x|).
@@ -308,8 +316,7 @@ __device__ __forceinline__ float exp_to_normal_f32_refine(float x)
     float mag = (float)x1;
     mag = (vs == 0.0f) ? 0.0f : mag;
     if (wave_any(big)) {
-        float mb = (float)expcoord_q_plain<true>((double)v);
-        mb = (v == __builtin_inff()) ? v : mb;
+        float mb = exp_to_normal_f32_big(v);
         mag = big ? mb : mag;
     }
     return __builtin_copysignf(mag, x);

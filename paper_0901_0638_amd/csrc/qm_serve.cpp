@@ -1,36 +1,438 @@
 /*
- * qm_serve.cpp -- batch launch and serving loop.
+ * qm_serve.cpp -- batch launch (qm_run_batch) and the continuous-batching
+ * serving loop (qm_submit / qm_poll).
+ *
+ * Batch: requests are validated, Student t tables fetched (built on first
+ * use), descriptors written into a pinned staging buffer, copied to the
+ * device on the caller's stream and consumed by one persistent launch
+ * (qm_batch.hip).  Staging slots are reused once the event recorded after
+ * their launch has completed.
+ *
+ * Serving: qm_submit only validates and queues.  A scheduler thread admits
+ * queued requests in arrival order while the bytes of admitted, unfinished
+ * requests stay within the context's HBM budget, launches everything
+ * admitted since its last launch as one batch on the next of a few streams,
+ * and retires batches whose completion event has fired.  Requests arriving
+ * while batches run are admitted as budget frees up and run concurrently
+ * with them on another stream.
  */
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstdio>
+#include <cstring>
+#include <deque>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "qm_batch.h"
+#include "qm_context.h"
 #include "qm_serve.h"
+
+namespace qm {
+
+/* ------------------------------------------------------------------------ */
+/* Batch runner                                                             */
+/* ------------------------------------------------------------------------ */
+
+struct Staging {
+    void* host = nullptr;
+    void* dev = nullptr;
+    size_t cap = 0;
+    hipEvent_t ev = nullptr;
+    bool busy = false;         /* held by a caller between acquire and event record */
+};
+
+struct BatchRunner {
+    std::mutex mu;
+    std::vector<Staging*> slots;
+};
+
+static BatchRunner* runner_of(qm_ctx* ctx)
+{
+    std::lock_guard<std::mutex> lk(ctx->server_mu);
+    if (!ctx->runner) ctx->runner = new BatchRunner;
+    return ctx->runner;
+}
+
+void runner_free(qm_ctx* ctx)
+{
+    BatchRunner* r = ctx->runner;
+    if (!r) return;
+    for (Staging* s : r->slots) {
+        if (s->ev) {
+            (void)hipEventSynchronize(s->ev);
+            (void)hipEventDestroy(s->ev);
+        }
+        if (s->host) (void)hipHostFree(s->host);
+        if (s->dev) (void)hipFree(s->dev);
+        delete s;
+    }
+    delete r;
+    ctx->runner = nullptr;
+}
+
+/* A staging slot with at least `bytes` of pinned host and device memory
+   whose previous use has completed. */
+static qm_status acquire_slot(BatchRunner* br, size_t bytes, Staging** out)
+{
+    std::unique_lock<std::mutex> lk(br->mu);
+    Staging* slot = nullptr;
+    for (Staging* s : br->slots) {
+        /* the slot's event covers its last launch (a fresh event counts as complete) */
+        if (!s->busy && hipEventQuery(s->ev) == hipSuccess) { slot = s; break; }
+    }
+    if (!slot && br->slots.size() < 32) {
+        slot = new Staging;
+        if (hipEventCreateWithFlags(&slot->ev, hipEventDisableTiming) != hipSuccess) {
+            delete slot;
+            return set_error(QM_E_HIP, "hipEventCreate failed");
+        }
+        br->slots.push_back(slot);
+    }
+    while (!slot) {
+        for (Staging* s : br->slots)
+            if (!s->busy) { slot = s; break; }
+        if (!slot) {            /* all 32 held by other callers right now */
+            lk.unlock();
+            std::this_thread::yield();
+            lk.lock();
+        }
+    }
+    slot->busy = true;
+    lk.unlock();
+    (void)hipEventSynchronize(slot->ev);
+    if (slot->cap < bytes) {
+        if (slot->host) (void)hipHostFree(slot->host);
+        if (slot->dev) (void)hipFree(slot->dev);
+        slot->host = slot->dev = nullptr;
+        slot->cap = 0;
+        size_t cap = std::max(bytes, (size_t)1 << 16);
+        if (hipHostMalloc(&slot->host, cap, hipHostMallocDefault) != hipSuccess ||
+            hipMalloc(&slot->dev, cap) != hipSuccess) {
+            std::lock_guard<std::mutex> g(br->mu);
+            slot->busy = false;
+            return set_error(QM_E_NOMEM, "staging allocation failed");
+        }
+        slot->cap = cap;
+    }
+    *out = slot;
+    return QM_OK;
+}
+
+static uint32_t batch_op(const qm_request& r)
+{
+    switch (r.kind) {
+    case QM_NORMAL_QUANTILE:
+        if (r.dtype == QM_F64) return r.mode == QM_PAPER ? BOP_NQ64_PAPER : BOP_NQ64_PLAIN;
+        if (r.mode == QM_F32_REFINE) return BOP_NQ32_REFINE;
+        return r.mode == QM_PAPER ? BOP_NQ32_PAPER : BOP_NQ32_PLAIN;
+    case QM_EXP_TO_NORMAL:
+        if (r.dtype == QM_F64) return r.mode == QM_PAPER ? BOP_E64_PAPER : BOP_E64_PLAIN;
+        return BOP_E32_REFINE;
+    default:
+        return r.dtype == QM_F64 ? BOP_T64 : BOP_T32;
+    }
+}
+
+/*
+ * Validate and enqueue `count` requests as one persistent launch on s.  If
+ * done is not NULL, an event that completes with the launch is recorded
+ * into it (the caller owns the event).
+ */
+qm_status enqueue_batch(qm_ctx* ctx, const qm_request* reqs, uint64_t count, hipStream_t s, hipEvent_t done)
+{
+    if (!ctx) return set_error(QM_E_INVAL, "context is NULL");
+    if (count > 0 && !reqs) return set_error(QM_E_INVAL, "reqs is NULL");
+    for (uint64_t i = 0; i < count; ++i) {
+        qm_status st = check_request(reqs[i], nullptr);
+        if (st != QM_OK) return st;
+    }
+    if (hipSetDevice(ctx->device) != hipSuccess) return set_error(QM_E_HIP, "hipSetDevice failed");
+    std::vector<BatchReq> d;
+    d.reserve(count);
+    uint64_t chunks = 0;
+    size_t lds = 0;
+    for (uint64_t i = 0; i < count; ++i) {
+        const qm_request& r = reqs[i];
+        if (r.n == 0) continue;
+        BatchReq b;
+        memset(&b, 0, sizeof b);
+        b.op = batch_op(r);
+        b.in = r.d_in;
+        b.out = r.d_out;
+        b.n = r.n;
+        b.chunk_base = chunks;
+        chunks += (r.n + QM_CHUNK - 1) / QM_CHUNK;
+        if (r.kind == QM_STUDENT_T) {
+            const DeviceTable* t = nullptr;
+            qm_status st = get_table(ctx, r.nu, &t);
+            if (st != QM_OK) return st;
+            b.P = make_params(t->hdr);
+            b.coef = reinterpret_cast<const double*>(reinterpret_cast<const char*>(t->d_table) + sizeof(TTableHeader));
+            lds = std::max(lds, (size_t)t->hdr.ncell * T_STRIDE * sizeof(double));
+        }
+        d.push_back(b);
+    }
+    if (d.empty()) {
+        if (done && hipEventRecord(done, s) != hipSuccess) return set_error(QM_E_HIP, "hipEventRecord failed");
+        return QM_OK;
+    }
+    size_t bytes = sizeof(BatchHeader) + d.size() * sizeof(BatchReq);
+    Staging* slot = nullptr;
+    qm_status st = acquire_slot(runner_of(ctx), bytes, &slot);
+    if (st != QM_OK) return st;
+    BatchHeader h;
+    memset(&h, 0, sizeof h);
+    h.counter = 0;
+    h.total_chunks = chunks;
+    h.nreq = (uint32_t)d.size();
+    memcpy(slot->host, &h, sizeof h);
+    memcpy((char*)slot->host + sizeof h, d.data(), d.size() * sizeof(BatchReq));
+    hipError_t e = hipMemcpyAsync(slot->dev, slot->host, bytes, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) {
+        uint64_t blocks = (uint64_t)ctx->cus * 8;
+        if (blocks > chunks) blocks = chunks;
+        e = launch_batch((BatchHeader*)slot->dev, (const BatchReq*)((char*)slot->dev + sizeof h), lds, blocks, s);
+    }
+    hipError_t e2 = hipEventRecord(slot->ev, s);
+    {
+        std::lock_guard<std::mutex> g(runner_of(ctx)->mu);
+        slot->busy = false;
+    }
+    if (e != hipSuccess) return set_error(QM_E_HIP, hipGetErrorString(e));
+    if (e2 != hipSuccess) return set_error(QM_E_HIP, hipGetErrorString(e2));
+    if (done && hipEventRecord(done, s) != hipSuccess) return set_error(QM_E_HIP, "hipEventRecord failed");
+    return QM_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Serving loop                                                             */
+/* ------------------------------------------------------------------------ */
+
+typedef std::chrono::steady_clock clk;
+
+enum TicketState { T_QUEUED = 0, T_RUNNING = 1, T_DONE = 2, T_CLOSED = 3, T_FAILED = 4 };
+
+struct Ticket {
+    qm_request req;
+    uint64_t bytes;
+    int state;
+    clk::time_point t_submit;
+};
+
+struct InFlight {
+    hipEvent_t ev;
+    std::vector<uint64_t> tickets;
+    uint64_t bytes;
+};
+
+constexpr int SERVE_STREAMS = 4;
+
+struct Server {
+    qm_ctx* ctx = nullptr;
+    std::thread th;
+    std::mutex mu;
+    std::condition_variable cv;
+    std::deque<uint64_t> queue;
+    std::unordered_map<uint64_t, Ticket> tickets;
+    uint64_t next_ticket = 1;
+    uint64_t in_flight_bytes = 0;
+    bool stop = false;
+    hipStream_t streams[SERVE_STREAMS] = {};
+    int next_stream = 0;
+    std::vector<InFlight> inflight;
+    std::vector<hipEvent_t> free_events;
+    std::vector<uint64_t> latencies_ns;
+};
+
+static void server_loop(Server* S)
+{
+    (void)hipSetDevice(S->ctx->device);
+    std::vector<uint64_t> admit;
+    std::vector<qm_request> reqs;
+    for (;;) {
+        std::unique_lock<std::mutex> lk(S->mu);
+        /* retire finished batches */
+        clk::time_point now = clk::now();
+        for (size_t i = 0; i < S->inflight.size();) {
+            if (hipEventQuery(S->inflight[i].ev) == hipSuccess) {
+                for (uint64_t t : S->inflight[i].tickets) {
+                    Ticket& tk = S->tickets[t];
+                    tk.state = T_DONE;
+                    S->latencies_ns.push_back(
+                        (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(now - tk.t_submit).count());
+                }
+                S->in_flight_bytes -= S->inflight[i].bytes;
+                S->free_events.push_back(S->inflight[i].ev);
+                S->inflight.erase(S->inflight.begin() + i);
+            } else {
+                ++i;
+            }
+        }
+        /* admit in arrival order while the budget allows */
+        admit.clear();
+        uint64_t bytes = 0;
+        if (!S->stop) {
+            while (!S->queue.empty()) {
+                Ticket& tk = S->tickets[S->queue.front()];
+                if (S->in_flight_bytes + bytes + tk.bytes > S->ctx->budget) break;
+                bytes += tk.bytes;
+                tk.state = T_RUNNING;
+                admit.push_back(S->queue.front());
+                S->queue.pop_front();
+            }
+        }
+        if (S->stop && S->inflight.empty() && admit.empty()) {
+            for (uint64_t t : S->queue) S->tickets[t].state = T_CLOSED;
+            S->queue.clear();
+            return;
+        }
+        if (admit.empty()) {
+            if (S->inflight.empty())
+                S->cv.wait(lk);
+            else
+                S->cv.wait_for(lk, std::chrono::microseconds(20));
+            continue;
+        }
+        reqs.clear();
+        for (uint64_t t : admit) reqs.push_back(S->tickets[t].req);
+        S->in_flight_bytes += bytes;
+        hipEvent_t ev = nullptr;
+        if (!S->free_events.empty()) { ev = S->free_events.back(); S->free_events.pop_back(); }
+        hipStream_t st = S->streams[S->next_stream];
+        S->next_stream = (S->next_stream + 1) % SERVE_STREAMS;
+        lk.unlock();
+        if (!ev) (void)hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        qm_status rc = enqueue_batch(S->ctx, reqs.data(), reqs.size(), st, ev);
+        lk.lock();
+        if (rc != QM_OK) {
+            for (uint64_t t : admit) S->tickets[t].state = T_FAILED;
+            S->in_flight_bytes -= bytes;
+            S->free_events.push_back(ev);
+            continue;
+        }
+        S->inflight.push_back(InFlight{ev, admit, bytes});
+    }
+}
+
+static Server* server_of(qm_ctx* ctx, qm_status* st)
+{
+    std::lock_guard<std::mutex> lk(ctx->server_mu);
+    if (ctx->server) return ctx->server;
+    Server* S = new Server;
+    S->ctx = ctx;
+    (void)hipSetDevice(ctx->device);
+    for (int i = 0; i < SERVE_STREAMS; ++i) {
+        if (hipStreamCreateWithFlags(&S->streams[i], hipStreamNonBlocking) != hipSuccess) {
+            for (int j = 0; j < i; ++j) (void)hipStreamDestroy(S->streams[j]);
+            delete S;
+            *st = set_error(QM_E_HIP, "hipStreamCreate failed");
+            return nullptr;
+        }
+    }
+    S->th = std::thread(server_loop, S);
+    ctx->server = S;
+    return S;
+}
+
+void server_stop(Server* S)
+{
+    if (!S) return;
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->stop = true;
+    }
+    S->cv.notify_all();
+    if (S->th.joinable()) S->th.join();
+    for (InFlight& f : S->inflight) {
+        (void)hipEventSynchronize(f.ev);
+        (void)hipEventDestroy(f.ev);
+    }
+    for (hipEvent_t e : S->free_events) (void)hipEventDestroy(e);
+    for (int i = 0; i < SERVE_STREAMS; ++i)
+        if (S->streams[i]) {
+            (void)hipStreamSynchronize(S->streams[i]);
+            (void)hipStreamDestroy(S->streams[i]);
+        }
+    delete S;
+}
+
+}  // namespace qm
 
 extern "C" {
 
 qm_status qm_run_batch(qm_ctx* ctx, const qm_request* reqs, uint64_t count, void* hip_stream)
 {
-    (void)ctx; (void)reqs; (void)count; (void)hip_stream;
-    return qm::set_error(QM_E_DTYPE, "qm_run_batch: not available in this build");
+    return qm::enqueue_batch(ctx, reqs, count, (hipStream_t)hip_stream, nullptr);
 }
 
 qm_status qm_submit(qm_ctx* ctx, const qm_request* req, uint64_t* ticket)
 {
-    (void)ctx; (void)req; (void)ticket;
-    return qm::set_error(QM_E_DTYPE, "qm_submit: not available in this build");
+    if (!ctx || !req || !ticket) return qm::set_error(QM_E_INVAL, "NULL argument");
+    int es = 0;
+    qm_status st = qm::check_request(*req, &es);
+    if (st != QM_OK) return st;
+    uint64_t bytes = 2 * req->n * (uint64_t)es;
+    if (bytes > ctx->budget) return qm::set_error(QM_E_INVAL, "request larger than the HBM budget");
+    st = QM_OK;
+    qm::Server* S = qm::server_of(ctx, &st);
+    if (!S) return st;
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        if (S->stop) return qm::set_error(QM_E_CLOSED, "serving loop is shutting down");
+        uint64_t t = S->next_ticket++;
+        qm::Ticket tk;
+        tk.req = *req;
+        tk.bytes = bytes;
+        tk.state = qm::T_QUEUED;
+        tk.t_submit = qm::clk::now();
+        S->tickets.emplace(t, tk);
+        S->queue.push_back(t);
+        *ticket = t;
+    }
+    S->cv.notify_one();
+    return QM_OK;
 }
 
 qm_status qm_poll(qm_ctx* ctx, uint64_t ticket)
 {
-    (void)ctx; (void)ticket;
-    return qm::set_error(QM_E_TICKET, "qm_poll: unknown ticket");
+    if (!ctx) return qm::set_error(QM_E_INVAL, "context is NULL");
+    qm::Server* S;
+    {
+        std::lock_guard<std::mutex> lk(ctx->server_mu);
+        S = ctx->server;
+    }
+    if (!S) return qm::set_error(QM_E_TICKET, "unknown ticket");
+    std::lock_guard<std::mutex> lk(S->mu);
+    auto it = S->tickets.find(ticket);
+    if (it == S->tickets.end()) return qm::set_error(QM_E_TICKET, "unknown ticket");
+    switch (it->second.state) {
+    case qm::T_DONE: return QM_OK;
+    case qm::T_CLOSED: return qm::set_error(QM_E_CLOSED, "request failed by shutdown");
+    case qm::T_FAILED: return qm::set_error(QM_E_HIP, "request launch failed");
+    default: return QM_PENDING;
+    }
 }
 
 uint64_t qm_serving_latencies(qm_ctx* ctx, uint64_t* lat_ns, uint64_t cap)
 {
-    (void)ctx; (void)lat_ns; (void)cap;
-    return 0;
+    if (!ctx) return 0;
+    qm::Server* S;
+    {
+        std::lock_guard<std::mutex> lk(ctx->server_mu);
+        S = ctx->server;
+    }
+    if (!S) return 0;
+    std::lock_guard<std::mutex> lk(S->mu);
+    uint64_t n = S->latencies_ns.size();
+    if (lat_ns)
+        for (uint64_t i = 0; i < n && i < cap; ++i) lat_ns[i] = S->latencies_ns[i];
+    return n;
 }
 
-}
-
-namespace qm {
-void server_stop(Server* s) { (void)s; }
-}
+}  /* extern "C" */

@@ -25,6 +25,10 @@ int ctx_device(const qm_ctx* ctx);
 uint64_t ctx_budget(const qm_ctx* ctx);
 qm_status set_error(qm_status s, const char* msg);
 
+/* Validate and enqueue requests as one persistent launch (done: optional
+   event recorded after it). */
+qm_status enqueue_batch(qm_ctx* ctx, const qm_request* reqs, uint64_t count, hipStream_t s, hipEvent_t done);
+void runner_free(qm_ctx* ctx);
 void server_stop(Server* s);
 
 }  // namespace qm

@@ -125,3 +125,41 @@ def recycle_normals(n=1 << 26, threads=0):
 def recycle_exponentials(n=1 << 26, threads=0):
     """Exp(1) samples for the exponential -> normal map, seed 2 stream 1."""
     return exponentials(2, 1, n, threads)
+
+
+# Batched / serving request mix: per request r, three parameter uniforms from
+# streams 100-102 of the seed; inputs of request r from stream 1000 + r.
+MIX = (("nq_f32_refine", 0.4), ("nq_f64", 0.2), ("student_f64", 0.3), ("exp_f64", 0.1))
+
+
+def request_mix(seed, count, log2_lo, log2_hi):
+    """List of dicts {kind, n, nu, stream} for a heterogeneous batch:
+    sizes log-uniform in [2^log2_lo, 2^log2_hi], kinds 40% quantile
+    FP32+refine, 20% quantile FP64, 30% Student t FP64 with nu uniform-integer
+    in [1, 50], 10% exponential -> normal FP64."""
+    us = uniform53(seed, 100, count)
+    uk = uniform53(seed, 101, count)
+    un = uniform53(seed, 102, count)
+    out = []
+    for r in range(count):
+        n = int(2.0 ** (log2_lo + (log2_hi - log2_lo) * us[r]))
+        acc, kind = 0.0, MIX[-1][0]
+        for name, p in MIX:
+            acc += p
+            if uk[r] < acc:
+                kind = name
+                break
+        out.append({"kind": kind, "n": n, "nu": float(1 + int(50 * un[r])), "stream": 1000 + r})
+    return out
+
+
+def request_input(seed, req):
+    """The input array of one request of request_mix."""
+    k, n, s = req["kind"], req["n"], req["stream"]
+    if k == "nq_f32_refine":
+        return uniform24(seed, s, n)
+    if k == "nq_f64":
+        return uniform53(seed, s, n)
+    if k == "student_f64":
+        return normals(seed, s, n)
+    return exponentials(seed, s, n)

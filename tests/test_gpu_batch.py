@@ -1,0 +1,151 @@
+"""GPU: the persistent batch launch and the serving loop.  Every request's
+output must be bitwise identical to the single-request call with the same
+kind, dtype and mode, and within tolerance of the oracle."""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+import qm_inputs as qi
+from tests._tol import RTOL_F32, RTOL_F64, assert_close
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_0901_0638_amd as qm  # noqa: E402
+
+KIND = {"nq_f32_refine": (qm.QM_NORMAL_QUANTILE, qm.QM_F32_REFINE),
+        "nq_f64": (qm.QM_NORMAL_QUANTILE, qm.QM_PLAIN),
+        "student_f64": (qm.QM_STUDENT_T, qm.QM_PLAIN),
+        "exp_f64": (qm.QM_EXP_TO_NORMAL, qm.QM_PLAIN)}
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = qm.Context(0, hbm_budget_bytes=256 << 20)
+    yield c
+    c.close()
+
+
+def single(ctx, kind, mode, nu, inp):
+    out = torch.empty_like(inp)
+    if kind == qm.QM_NORMAL_QUANTILE:
+        qm.qm_normal_quantile(ctx, inp, out, mode)
+    elif kind == qm.QM_STUDENT_T:
+        qm.qm_recycle_student_t(ctx, inp, out, nu, mode)
+    else:
+        qm.qm_recycle_exp_to_normal(ctx, inp, out, mode)
+    return out
+
+
+def oracle_of(req, x):
+    k = req["kind"]
+    if k in ("nq_f32_refine", "nq_f64"):
+        return oracle.norm_quantile(x.astype(np.float64))
+    if k == "student_f64":
+        return oracle.student_t_map(x, req["nu"])
+    return oracle.exp_to_normal(x)
+
+
+def build(seed, count, lo, hi, extra_sizes=()):
+    reqs = qi.request_mix(seed, count, lo, hi)
+    for i, n in enumerate(extra_sizes):
+        reqs[i % len(reqs)]["n"] = n
+    ins, outs, qreqs = [], [], []
+    for r in reqs:
+        x = qi.request_input(seed, r)
+        d = torch.from_numpy(x).cuda()
+        o = torch.full_like(d, float("nan"))
+        kind, mode = KIND[r["kind"]]
+        qreqs.append(qm.qm_request(kind, qm.QM_F32 if x.dtype == np.float32 else qm.QM_F64, mode, 0,
+                                   r["nu"], d.data_ptr(), o.data_ptr(), x.size, 0))
+        ins.append(d)
+        outs.append(o)
+    return reqs, ins, outs, qreqs
+
+
+def check_against_single_and_oracle(ctx, reqs, ins, outs, rng):
+    for r, d, o, in zip(reqs, ins, outs):
+        kind, mode = KIND[r["kind"]]
+        ref_single = single(ctx, kind, mode, r["nu"], d)
+        torch.cuda.synchronize()
+        a, b = o.cpu().numpy(), ref_single.cpu().numpy()
+        assert np.array_equal(a.view(np.uint8), b.view(np.uint8)), ("not bitwise equal", r)
+        if a.size:
+            idx = np.unique(rng.integers(0, a.size, 64))
+            x = d.cpu().numpy()[idx]
+            rtol = RTOL_F32 if a.dtype == np.float32 else RTOL_F64
+            assert_close(a[idx], oracle_of(r, x), rtol, str(r))
+
+
+def test_batch_mixed_bitwise_equal_to_single(ctx):
+    edge = (0, 1, 3, 32767, 32768, 32769, 65537)
+    reqs, ins, outs, qreqs = build(3, 160, 10, 16, edge)
+    qm.qm_run_batch(ctx, qreqs, device_tensor=ins[0])
+    torch.cuda.synchronize()
+    check_against_single_and_oracle(ctx, reqs, ins, outs, np.random.default_rng(0))
+
+
+def test_batch_misaligned_and_repeat(ctx):
+    x = qi.uniform53(3, 7, 100001)
+    base = torch.from_numpy(np.concatenate([[0.5], x])).cuda()
+    out = torch.empty(100001, dtype=torch.float64, device="cuda")
+    r = qm.qm_request(qm.QM_NORMAL_QUANTILE, qm.QM_F64, qm.QM_PLAIN, 0, 0.0, base.data_ptr() + 8,
+                      out.data_ptr(), 100001, 0)
+    for _ in range(3):
+        qm.qm_run_batch(ctx, [r, r], device_tensor=base)
+    torch.cuda.synchronize()
+    assert_close(out.cpu().numpy(), oracle.norm_quantile(x), RTOL_F64, "misaligned batch")
+
+
+def test_batch_validation_rejects_whole_batch(ctx):
+    reqs, ins, outs, qreqs = build(4, 8, 10, 12)
+    bad = qm.qm_request(qm.QM_STUDENT_T, qm.QM_F64, qm.QM_PLAIN, 0, 0.1, ins[0].data_ptr(), outs[0].data_ptr(), 10, 0)
+    with pytest.raises(qm.QMError) as e:
+        qm.qm_run_batch(ctx, qreqs + [bad], device_tensor=ins[0])
+    assert e.value.status == qm.QM_E_INVAL
+    torch.cuda.synchronize()
+    for o in outs:
+        assert torch.isnan(o).all(), "nothing may run when validation fails"
+
+
+def test_serving_results_equal_single_calls(ctx):
+    reqs, ins, outs, qreqs = build(5, 120, 10, 18)
+    tickets = [qm.qm_submit(ctx, q) for q in qreqs]
+    deadline = time.time() + 60
+    pending = set(tickets)
+    while pending and time.time() < deadline:
+        pending = {t for t in pending if qm.qm_poll(ctx, t) == qm.QM_PENDING}
+        time.sleep(0.001)
+    assert not pending, "requests did not complete"
+    for t in tickets:
+        assert qm.qm_poll(ctx, t) == qm.QM_OK
+    lat = qm.qm_serving_latencies(ctx)
+    assert len(lat) >= len(tickets)
+    check_against_single_and_oracle(ctx, reqs, ins, outs, np.random.default_rng(1))
+
+
+def test_serving_errors(ctx):
+    with pytest.raises(qm.QMError) as e:
+        qm.qm_poll(ctx, 10 ** 12)
+    assert e.value.status == qm.QM_E_TICKET
+    d = torch.zeros(64 << 20, dtype=torch.float64, device="cuda")   # 512 MiB in + out > 256 MiB budget
+    big = qm.make_request(qm.QM_NORMAL_QUANTILE, d, d)
+    with pytest.raises(qm.QMError) as e:
+        qm.qm_submit(ctx, big)
+    assert e.value.status == qm.QM_E_INVAL
+
+
+def test_serving_shutdown_with_work_in_flight():
+    c = qm.Context(0, hbm_budget_bytes=64 << 20)
+    xs = [torch.from_numpy(qi.uniform53(6, i, 1 << 20)).cuda() for i in range(16)]
+    ys = [torch.empty_like(x) for x in xs]
+    for x, y in zip(xs, ys):
+        qm.qm_submit(c, qm.make_request(qm.QM_NORMAL_QUANTILE, x, y))
+    t0 = time.time()
+    c.close()                       # drains admitted work, fails the rest
+    assert time.time() - t0 < 30
+    torch.cuda.synchronize()
