@@ -29,6 +29,7 @@ static __device__ __noinline__ double student_far(double s, const StudentParams&
 {
 #pragma clang fp contract(off)
     const double INV_SQRT2 = 0.70710678118654752440, LN2 = 0.69314718055994530942;
+    if (!(s < __builtin_inf())) return s;              /* z = +-inf -> +-inf; NaN -> NaN */
     double hs = -0.5 * s;                              /* exact */
     double e_hi = hs * s;
     double e_lo = __builtin_fma(hs, s, -e_hi);         /* -s^2/2 = e_hi + e_lo exactly */
