@@ -1,21 +1,32 @@
 #!/usr/bin/env python3
 """Benchmark of the quantile-mechanics hot path on one MI355X.
 
-Workload (one "step"): the Gaussian quantile on 2^28 samples, once in FP64
-(plain, 2e-15) and once in FP32 + FP64 refine (2e-7): u is 90% open uniform,
-10% tail stratum log-uniform in [1e-300, 1e-2] (FP64) or [1e-37, 1e-2]
-(FP32), mirrored to 1-u with probability 1/2, seed 1.  Inputs are resident in
-HBM before the timed region.  value = samples of both passes / wall time of
-the timed steps.
+Default workload (one "step"): the Gaussian quantile on 2^28 samples, once in
+FP64 (plain, 2e-15) and once in FP32 + FP64 refine (2e-7): u is 90% open
+uniform, 10% tail stratum log-uniform in [1e-300, 1e-2] (FP64) or
+[1e-37, 1e-2] (FP32), mirrored to 1-u with probability 1/2, seed 1.  Inputs
+are resident in HBM before the timed region.  value = samples of both passes
+/ wall time of the timed steps.  The JSON line also carries, outside the
+timed region, the normal -> Student t map (2^26 normals, nu in
+{1,2,3,4,5,10,30}) and exponential -> normal (2^26) rates, the roofline of
+the dominant kernel (FP64 quantile: 16 algorithmic bytes per sample, timed
+per launch with HIP events on its stream) and the CPU oracle on a bounded
+sample.
 
-Prints one JSON line (see the keys below), with the roofline of the dominant
-kernel (FP64 quantile: 16 algorithmic bytes per sample, timed per launch by
-HIP events on its stream) and the CPU oracle's rate on a bounded sample.
+    --workload batch   4096 mixed requests (sizes log-uniform 2^10..2^22,
+                       40% quantile FP32+refine, 20% quantile FP64, 30%
+                       Student t nu in 1..50, 10% exp -> normal), seed 3:
+                       one persistent launch vs one launch per request.
+    --workload serve   Poisson arrivals at swept rates, sizes 2^12..2^24,
+                       same mix, HBM budget 64 GB: p50/p99 latency and
+                       Gsamples/s, vs the same trace as sequential launches.
 """
 import argparse
 import json
+import math
 import os
 import sys
+import threading
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -23,38 +34,56 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Gsamples/s Φ^{-1} & t-recycle (FP64 vs FP32+refine) at stated max err; p50/p99"
 HBM_PEAK_GBS = 8000.0
+T_NUS = (1, 2, 3, 4, 5, 10, 30)
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("qm_kernels.hip", "qm_device.hpp", "qm_coeffs.h", "qm_paper_coeffs.h"):
+        with open(os.path.join(ROOT, "paper_0901_0638_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def counted_traffic():
+    """HBM bytes per launch of the FP64 quantile kernel from the committed
+    rocprofv3 FETCH_SIZE/WRITE_SIZE summary, or None if the kernel sources
+    changed since those counters were taken."""
+    import re
+    path = os.path.join(ROOT, "profiles", "quantile_mixture_2e28_hbm_counters.md")
+    try:
+        text = open(path).read()
+    except OSError:
+        return None
+    m = re.search(r"Kernel source hash: `([0-9a-f]+)`", text)
+    t = re.search(r"traffic_bytes_per_launch k_nq64_compact: ([0-9]+)", text)
+    if not m or not t or m.group(1) != kernel_source_hash():
+        return None
+    return int(t.group(1))
 
 
 def percentile(xs, p):
     xs = sorted(xs)
     if not xs:
         return None
-    k = min(len(xs) - 1, max(0, int(round(p / 100.0 * (len(xs) - 1)))))
+    k = min(len(xs) - 1, max(0, int(math.ceil(p / 100.0 * len(xs))) - 1))
     return xs[k]
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--n", type=int, default=1 << 28, help="samples per pass")
-    ap.add_argument("--cpu-sample", type=int, default=1 << 23, help="oracle sample size (elements)")
-    ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--copy-calibration", action="store_true",
-                    help="also run a plain device copy of the FP64 input (for HBM counter scaling)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print("bench.py measures one GPU only: the hot path is elementwise and shards without "
-              "communication, so --gpus %d is not run (see DESIGN.md)." % args.gpus, file=sys.stderr)
-        return 2
+def timed_launches(torch, stream, fn, reps):
+    """Per-launch durations (ms) with HIP events on the launch stream."""
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for a, b in ev:
+        a.record(stream)
+        fn()
+        b.record(stream)
+    torch.cuda.synchronize()
+    return [a.elapsed_time(b) for a, b in ev]
 
-    import numpy as np
-    import torch
 
-    import paper_0901_0638_amd as qm
-    import qm_inputs as qi
-
+# ---------------------------------------------------------------------------
+def run_quantile(args, torch, qm, qi):
     n = args.n
     t0 = time.time()
     u64 = torch.from_numpy(qi.mixture_f64(n)).cuda()
@@ -92,28 +121,22 @@ def main():
         step(events[k])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
+    print("timed %d steps in %.3f s" % (args.steps, wall), file=sys.stderr, flush=True)
 
     d64 = [e[0].elapsed_time(e[1]) for e in events]  # ms
     d32 = [e[1].elapsed_time(e[2]) for e in events]
-    ms_step = wall * 1e3 / args.steps
-    value = 2.0 * n * args.steps / wall / 1e9
-
     avg64 = sum(d64) / len(d64)
+    avg32 = sum(d32) / len(d32)
     bytes64 = 16.0 * n
     achieved = bytes64 / (avg64 * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "k_map<double, VECTOR, 2, OpNQ64Plain> (FP64 quantile)",
-                "algorithmic_bytes_per_launch": bytes64, "avg_launch_ms": round(avg64, 4)}
-
     result = {
         "metric": METRIC,
-        "value": round(value, 3),
+        "value": round(2.0 * n * args.steps / wall / 1e9, 3),
         "unit": "Gsamples/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_step, 4),
+        "ms_per_step": round(wall * 1e3 / args.steps, 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -124,25 +147,268 @@ def main():
                    "n_per_pass": n, "passes_per_step": 2},
         "fp64": {"gsamples_s": round(n / (avg64 * 1e-3) / 1e9, 2), "p50_ms": percentile(d64, 50),
                  "p99_ms": percentile(d64, 99), "max_rel_err_bound": 2e-15},
-        "fp32_refine": {"gsamples_s": round(n / (sum(d32) / len(d32) * 1e-3) / 1e9, 2),
-                        "p50_ms": percentile(d32, 50), "p99_ms": percentile(d32, 99),
-                        "gbs": round(8.0 * n / (sum(d32) / len(d32) * 1e-3) / 1e9, 1), "max_rel_err_bound": 2e-7},
-        "roofline": roofline,
+        "fp32_refine": {"gsamples_s": round(n / (avg32 * 1e-3) / 1e9, 2), "p50_ms": percentile(d32, 50),
+                        "p99_ms": percentile(d32, 99), "gbs": round(8.0 * n / (avg32 * 1e-3) / 1e9, 1),
+                        "max_rel_err_bound": 2e-7},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": counted_traffic() if n == (1 << 28) else None,
+                     "kernel": "qm::k_nq64_compact<2> (FP64 quantile, deep tail compacted per wave)",
+                     "algorithmic_bytes_per_launch": bytes64, "avg_launch_ms": round(avg64, 4)},
     }
+    del u64, u32, w64, w32
+    torch.cuda.empty_cache()
+
+    if not args.no_extra:
+        # secondary maps, outside the timed region (normals / Exp(1), seed 2)
+        m = 1 << 26
+        z = torch.from_numpy(qi.recycle_normals(m)).cuda()
+        x = torch.from_numpy(qi.recycle_exponentials(m)).cuda()
+        o = torch.empty_like(z)
+        extra = {"student_t_f64": {}, "n": m}
+        for nu in T_NUS:
+            qm.qm_recycle_student_t(ctx, z, o, nu)  # builds and caches the table
+            ds = timed_launches(torch, stream, lambda nu=nu: qm.qm_recycle_student_t(ctx, z, o, nu), 10)
+            avg = sum(ds) / len(ds)
+            extra["student_t_f64"][str(nu)] = {"gsamples_s": round(m / (avg * 1e-3) / 1e9, 2),
+                                               "gbs": round(16.0 * m / (avg * 1e-3) / 1e9, 1),
+                                               "p50_ms": percentile(ds, 50), "p99_ms": percentile(ds, 99)}
+        ds = timed_launches(torch, stream, lambda: qm.qm_recycle_exp_to_normal(ctx, x, o), 10)
+        avg = sum(ds) / len(ds)
+        extra["exp_to_normal_f64"] = {"gsamples_s": round(m / (avg * 1e-3) / 1e9, 2),
+                                      "gbs": round(16.0 * m / (avg * 1e-3) / 1e9, 1),
+                                      "p50_ms": percentile(ds, 50), "p99_ms": percentile(ds, 99)}
+        z32 = z.float()
+        o32 = torch.empty_like(z32)
+        ds = timed_launches(torch, stream, lambda: qm.qm_recycle_student_t(ctx, z32, o32, 4.0), 10)
+        avg = sum(ds) / len(ds)
+        extra["student_t_f32_refine_nu4"] = {"gsamples_s": round(m / (avg * 1e-3) / 1e9, 2),
+                                             "gbs": round(8.0 * m / (avg * 1e-3) / 1e9, 1)}
+        result["extra"] = extra
+        del z, x, o, z32, o32
+        torch.cuda.empty_cache()
 
     if not args.no_cpu:
         import oracle
-        m = args.cpu_sample
-        us = qi.mixture_f64(m)
+        mm = args.cpu_sample
+        us = qi.mixture_f64(mm)
         threads = oracle.threads_used(0)
         c0 = time.perf_counter()
         oracle.norm_quantile(us, threads)
         cdt = time.perf_counter() - c0
-        result["cpu_baseline"] = {"value": round(m / cdt / 1e9, 6), "unit": "Gsamples/s", "cores": threads,
-                                  "kind": "oracle", "sample": "first %d elements of the FP64 mixture workload, "
-                                  "FP64 quantile, %.1f s wall on %d threads" % (m, cdt, threads)}
-    print(json.dumps(result))
+        result["cpu_baseline"] = {"value": round(mm / cdt / 1e9, 6), "unit": "Gsamples/s", "cores": threads,
+                                  "kind": "oracle",
+                                  "sample": "first %d elements of the FP64 mixture workload, FP64 quantile, "
+                                            "%.1f s wall on %d threads (%s)" % (mm, cdt, threads, cpu_model())}
     ctx.close()
+    return result
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown CPU"
+
+
+# ---------------------------------------------------------------------------
+def make_requests(qm, qi, torch, seed, count, lo, hi):
+    """Device inputs and outputs for a request mix (inputs generated per request)."""
+    kinds = {"nq_f32_refine": (qm.QM_NORMAL_QUANTILE, qm.QM_F32, qm.QM_F32_REFINE),
+             "nq_f64": (qm.QM_NORMAL_QUANTILE, qm.QM_F64, qm.QM_PLAIN),
+             "student_f64": (qm.QM_STUDENT_T, qm.QM_F64, qm.QM_PLAIN),
+             "exp_f64": (qm.QM_EXP_TO_NORMAL, qm.QM_F64, qm.QM_PLAIN)}
+    spec = qi.request_mix(seed, count, lo, hi)
+    reqs, keep = [], []
+    for r in spec:
+        x = torch.from_numpy(qi.request_input(seed, r)).cuda()
+        y = torch.empty_like(x)
+        kind, dt, mode = kinds[r["kind"]]
+        reqs.append(qm.qm_request(kind, dt, mode, 0, r["nu"], x.data_ptr(), y.data_ptr(), x.numel(), 0))
+        keep.append((x, y))
+    return spec, reqs, keep
+
+
+def single_call(qm, ctx, r, stream_ptr):
+    lib = qm.load()
+    import ctypes
+    s = ctypes.c_void_p(stream_ptr)
+    if r.kind == qm.QM_NORMAL_QUANTILE:
+        st = lib.qm_normal_quantile(ctx.handle, r.d_in, r.d_out, r.n, r.dtype, r.mode, s)
+    elif r.kind == qm.QM_STUDENT_T:
+        st = lib.qm_recycle_student_t(ctx.handle, r.d_in, r.d_out, r.n, r.dtype, r.mode, r.nu, s)
+    else:
+        st = lib.qm_recycle_exp_to_normal(ctx.handle, r.d_in, r.d_out, r.n, r.dtype, r.mode, s)
+    qm.check(st)
+
+
+def run_batch(args, torch, qm, qi):
+    t0 = time.time()
+    spec, reqs, keep = make_requests(qm, qi, torch, 3, args.batch_count, 10, 22)
+    total = sum(r.n for r in reqs)
+    print("batch inputs ready in %.1f s (%d requests, %d elements)" % (time.time() - t0, len(reqs), total),
+          file=sys.stderr, flush=True)
+    ctx = qm.Context(0)
+    stream = torch.cuda.current_stream()
+    sp = stream.cuda_stream
+    qm.qm_run_batch(ctx, reqs, stream=sp)       # builds the nu tables
+    for r in reqs:
+        single_call(qm, ctx, r, sp)
+    torch.cuda.synchronize()
+    db = timed_launches(torch, stream, lambda: qm.qm_run_batch(ctx, reqs, stream=sp), args.steps)
+
+    def seq():
+        for r in reqs:
+            single_call(qm, ctx, r, sp)
+    ds = timed_launches(torch, stream, seq, max(2, args.steps // 4))
+    ab, aseq = sum(db) / len(db), sum(ds) / len(ds)
+    nbytes = sum(r.n * (4 if r.dtype == qm.QM_F32 else 8) * 2 for r in reqs)
+    ctx.close()
+    return {"metric": "Gsamples/s batched heterogeneous launch", "value": round(total / (ab * 1e-3) / 1e9, 3),
+            "unit": "Gsamples/s", "n_gpus": 1, "steps": args.steps, "warmup": 1, "higher_is_better": True,
+            "dtype": "f64+f32", "data": "synthetic",
+            "config": {"workload": "batch: %d requests, sizes log-uniform 2^10..2^22, mix 40/20/30/10, seed 3"
+                                   % len(reqs), "elements": total, "bytes": nbytes},
+            "batch": {"p50_ms": percentile(db, 50), "p99_ms": percentile(db, 99),
+                      "gbs": round(nbytes / (ab * 1e-3) / 1e9, 1)},
+            "sequential_launches": {"gsamples_s": round(total / (aseq * 1e-3) / 1e9, 3),
+                                    "p50_ms": percentile(ds, 50)},
+            "speedup_vs_sequential": round(aseq / ab, 3)}
+
+
+def run_serve(args, torch, qm, qi):
+    """Open-loop Poisson arrivals through qm_submit/qm_poll at swept rates."""
+    import numpy as np
+    seed = 5
+    count = args.serve_count
+    spec = qi.request_mix(seed, count, 12, 24)
+    pools = {}
+    maxn = 1 << 24
+    # shared read-only input pools, one per kind (the content is workload-shaped)
+    pools["nq_f32_refine"] = torch.from_numpy(qi.uniform24(seed, 1, maxn)).cuda()
+    pools["nq_f64"] = torch.from_numpy(qi.uniform53(seed, 2, maxn)).cuda()
+    pools["student_f64"] = torch.from_numpy(qi.normals(seed, 3, maxn)).cuda()
+    pools["exp_f64"] = torch.from_numpy(qi.exponentials(seed, 4, maxn)).cuda()
+    budget = 64 << 30
+    out_ring_bytes = 40 << 30
+    out_ring = torch.empty(out_ring_bytes // 8, dtype=torch.float64, device="cuda")
+    kinds = {"nq_f32_refine": (qm.QM_NORMAL_QUANTILE, qm.QM_F32, qm.QM_F32_REFINE, 4),
+             "nq_f64": (qm.QM_NORMAL_QUANTILE, qm.QM_F64, qm.QM_PLAIN, 8),
+             "student_f64": (qm.QM_STUDENT_T, qm.QM_F64, qm.QM_PLAIN, 8),
+             "exp_f64": (qm.QM_EXP_TO_NORMAL, qm.QM_F64, qm.QM_PLAIN, 8)}
+    reqs = []
+    off = 0
+    base = out_ring.data_ptr()
+    for r in spec:
+        kind, dt, mode, es = kinds[r["kind"]]
+        nbytes = r["n"] * es
+        if off + nbytes > out_ring_bytes:
+            off = 0
+        reqs.append(qm.qm_request(kind, dt, mode, 0, r["nu"], pools[r["kind"]].data_ptr(), base + off, r["n"], 0))
+        off += (nbytes + 255) // 256 * 256
+    total = sum(r.n for r in reqs)
+    rng = np.random.default_rng(seed)
+    results = []
+    warm = qm.Context(0, hbm_budget_bytes=budget)
+    for nu in range(1, 51):                  # warm the table builder's cache path
+        qm.qm_recycle_student_t(warm, pools["student_f64"][:1024], out_ring[:1024], float(nu))
+    warm.close()
+    for rate in args.rates:
+        ctx = qm.Context(0, hbm_budget_bytes=budget)
+        for nu in range(1, 51):
+            qm.qm_recycle_student_t(ctx, pools["student_f64"][:1024], out_ring[:1024], float(nu))
+        torch.cuda.synchronize()
+        gaps = rng.exponential(1.0 / rate, count)
+        arrivals = np.cumsum(gaps)
+        tickets = [None] * count
+        lib = qm.load()
+        import ctypes
+
+        def submitter():
+            t0 = time.perf_counter()
+            for i in range(count):
+                while time.perf_counter() - t0 < arrivals[i]:
+                    pass
+                tk = ctypes.c_uint64()
+                qm.check(lib.qm_submit(ctx.handle, ctypes.byref(reqs[i]), ctypes.byref(tk)))
+                tickets[i] = tk.value
+
+        th = threading.Thread(target=submitter)
+        t_start = time.perf_counter()
+        th.start()
+        th.join()
+        done = 0
+        while done < count:
+            done = sum(1 for t in tickets if lib.qm_poll(ctx.handle, t) == qm.QM_OK)
+            if done < count:
+                time.sleep(0.0005)
+        wall = time.perf_counter() - t_start
+        lat = qm.qm_serving_latencies(ctx)
+        ctx.close()
+        lat_ms = [x / 1e6 for x in lat]
+        results.append({"rate_req_s": rate, "requests": count, "elements": total, "wall_s": round(wall, 4),
+                        "gsamples_s": round(total / wall / 1e9, 3),
+                        "offered_gsamples_s": round(total / arrivals[-1] / 1e9, 3),
+                        "p50_ms": round(percentile(lat_ms, 50), 4), "p99_ms": round(percentile(lat_ms, 99), 4),
+                        "max_ms": round(max(lat_ms), 4)})
+        print(json.dumps(results[-1]), file=sys.stderr, flush=True)
+    # the same trace as sequential launches, one request at a time on one stream
+    ctx = qm.Context(0)
+    for nu in range(1, 51):                  # tables built before timing
+        qm.qm_recycle_student_t(ctx, pools["student_f64"][:1024], out_ring[:1024], float(nu))
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for r in reqs:
+        single_call(qm, ctx, r, stream.cuda_stream)
+    torch.cuda.synchronize()
+    seq_wall = time.perf_counter() - t0
+    ctx.close()
+    return {"metric": "serving p50/p99 latency and Gsamples/s (continuous batching)", "value": results[-1]["gsamples_s"],
+            "unit": "Gsamples/s", "n_gpus": 1, "higher_is_better": True, "dtype": "f64+f32", "data": "synthetic",
+            "config": {"workload": "serving: Poisson arrivals, %d requests per rate, sizes log-uniform 2^12..2^24, "
+                                   "mix 40/20/30/10, HBM budget 64 GB, seed 5" % count},
+            "rates": results,
+            "sequential_launches": {"wall_s": round(seq_wall, 4), "gsamples_s": round(total / seq_wall / 1e9, 3)}}
+
+
+# ---------------------------------------------------------------------------
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", choices=["quantile", "batch", "serve"], default="quantile")
+    ap.add_argument("--n", type=int, default=1 << 28, help="samples per pass (quantile workload)")
+    ap.add_argument("--cpu-sample", type=int, default=1 << 24, help="oracle sample size (elements)")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="skip the secondary maps")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain device copy of the FP64 input (for HBM counter scaling)")
+    ap.add_argument("--batch-count", type=int, default=4096)
+    ap.add_argument("--serve-count", type=int, default=2000)
+    ap.add_argument("--rates", type=float, nargs="+", default=[1000, 2000, 5000, 10000, 20000, 50000])
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the hot path is elementwise and shards without "
+              "communication, so --gpus %d is not run (see DESIGN.md)." % args.gpus, file=sys.stderr)
+        return 2
+
+    import torch
+
+    import paper_0901_0638_amd as qm
+    import qm_inputs as qi
+
+    if args.workload == "batch":
+        result = run_batch(args, torch, qm, qi)
+    elif args.workload == "serve":
+        result = run_serve(args, torch, qm, qi)
+    else:
+        result = run_quantile(args, torch, qm, qi)
+    print(json.dumps(result), flush=True)
     return 0
 
 

@@ -79,7 +79,7 @@ typedef struct qm_ctx qm_ctx;
  * flight; 0 means no serving budget (qm_submit then rejects every request).
  * The context owns the per-nu Student t tables and the serving state.
  * The streaming kernels' launch shape (workgroups of 256 per compute unit,
- * default 8; 16-byte vectors in flight per lane, 1, 2 or 4, default 2) is
+ * default 32; 16-byte vectors in flight per lane, 1, 2 or 4, default 2) is
  * read here from the environment variables QM_BLOCKS_PER_CU and QM_UNROLL.
  * Errors: QM_E_INVAL (out == NULL or no such device), QM_E_HIP, QM_E_NOMEM.
  */

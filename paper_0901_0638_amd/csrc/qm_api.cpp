@@ -155,15 +155,19 @@ qm_status qm_init(int hip_device, uint64_t hbm_budget_bytes, qm_ctx** out)
     c->device = hip_device;
     c->budget = hbm_budget_bytes;
     c->cus = cus > 0 ? cus : 256;
-    /* streaming launch shape: 8 workgroups of 256 per CU, two 16-byte vectors
-       in flight per lane; QM_BLOCKS_PER_CU / QM_UNROLL override (tuning) */
-    long bpc = 8, unroll = 2;
+    /* streaming launch shape: 32 workgroups of 256 per CU (four rounds of the
+       8 resident ones), two 16-byte vectors in flight per lane -- the best of
+       a measured sweep over 2..32 x 1..4; QM_BLOCKS_PER_CU / QM_UNROLL
+       override (tuning) */
+    long bpc = 32, unroll = 2;
     if (const char* ev = getenv("QM_BLOCKS_PER_CU")) bpc = strtol(ev, nullptr, 10);
     if (const char* ev = getenv("QM_UNROLL")) unroll = strtol(ev, nullptr, 10);
-    if (bpc < 1 || bpc > 64) bpc = 8;
+    if (bpc < 1 || bpc > 64) bpc = 32;
     if (unroll != 1 && unroll != 2 && unroll != 4) unroll = 2;
     c->shape.max_blocks = (uint64_t)(cus > 0 ? cus : 256) * (uint64_t)bpc;
     c->shape.unroll = (int)unroll;
+    const char* ec = getenv("QM_COMPACT_TAIL");
+    c->shape.compact = ec ? (int)strtol(ec, nullptr, 10) != 0 : 1;
     *out = c;
     return QM_OK;
 }

@@ -120,6 +120,25 @@ __device__ __noinline__ double expcoord_far(double v)
     return z;
 }
 
+/* The deep-tail piece alone: Q(v) = s P7(s)/Q7(s), s = sqrt v, 42 < v <= 750. */
+__device__ __forceinline__ double expcoord_tail(double v)
+{
+    double s = sqrt_pos(v);
+    return div_pos(s * horner(s, QM_TAIL_P), horner(s, QM_TAIL_Q));
+}
+
+/* The paper's (13,13) piece alone (Appendix B), v <= 42. */
+__device__ __forceinline__ double expcoord_main(double v)
+{
+    return div_pos(v * horner(v, QM_PAPER_P13), horner(v, QM_PAPER_Q13));
+}
+
+/* v > 42 and finite: the lanes that need the deep-tail piece. */
+__device__ __forceinline__ bool expcoord_needs_tail(double v)
+{
+    return (v > QM_TAIL_VMIN) && (v < __builtin_inf());
+}
+
 /*
  * Plain FP64 Q(v) for v in [0, inf]: the paper's (13,13) rational on
  * v <= 42 and the fitted Q(v) = s P7(s)/Q7(s), s = sqrt v, beyond.  Both
@@ -163,18 +182,28 @@ __device__ __forceinline__ double expcoord_q_paper(double v)
    v = -log x; sign by u - 1/2 (+0 at u = 1/2).  u = 0 -> -inf, u = 1 -> +inf,
    u outside [0,1] or NaN -> NaN, all by select (Section 7.2 reflection; the
    paper's kernels leave u in {0,1} to NaN). */
-template <bool PAPER>
-__device__ __forceinline__ double normal_quantile_f64(double u)
+__device__ __forceinline__ double quantile_v(double u)
 {
     double om = 1.0 - u;
     double p = (u < om) ? u : om;
-    double v = neg_log_unit(p + p);
-    double mag = PAPER ? expcoord_q_paper(v) : expcoord_q_plain<false>(v);
+    return neg_log_unit(p + p);
+}
+
+__device__ __forceinline__ double quantile_finish(double u, double mag)
+{
     double w = __builtin_copysign(mag, u - 0.5);
     w = (u == 0.0) ? -__builtin_inf() : w;
     w = (u == 1.0) ? __builtin_inf() : w;
     w = (u >= 0.0 && u <= 1.0) ? w : __builtin_nan("");
     return w;
+}
+
+template <bool PAPER>
+__device__ __forceinline__ double normal_quantile_f64(double u)
+{
+    double v = quantile_v(u);
+    double mag = PAPER ? expcoord_q_paper(v) : expcoord_q_plain<false>(v);
+    return quantile_finish(u, mag);
 }
 
 /* Exponential -> normal, FP64: v = |x| directly, odd extension. */

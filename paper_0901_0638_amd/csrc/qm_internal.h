@@ -15,6 +15,7 @@ namespace qm {
 struct LaunchShape {
     uint64_t max_blocks;  /* cap on the grid (grid-stride beyond it) */
     int unroll;           /* 16-byte vectors in flight per lane: 1, 2 or 4 */
+    int compact;          /* FP64 quantile: compact deep-tail lanes across the wave */
 };
 
 /* Elementwise normal quantile / exp -> normal on one stream. */
