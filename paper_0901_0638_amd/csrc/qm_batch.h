@@ -38,6 +38,7 @@ struct BatchReq {
 };
 
 StudentParams make_params(const TTableHeader& h);
+int student_lds_stride();
 hipError_t launch_batch(BatchHeader* d_hdr, const BatchReq* d_reqs, size_t lds_bytes, uint64_t blocks,
                         hipStream_t s);
 

@@ -143,8 +143,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
             }
             if (loaded != R.coef) {
                 __syncthreads();
-                const int ncoef = R.P.ncell * T_STRIDE;
-                for (int i = threadIdx.x; i < ncoef; i += blockDim.x) lds_tab[i] = R.coef[i];
+                stage_table(lds_tab, R.coef, R.P);
                 __syncthreads();
                 loaded = R.coef;
             }

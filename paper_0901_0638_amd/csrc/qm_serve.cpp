@@ -174,10 +174,11 @@ qm_status enqueue_batch(qm_ctx* ctx, const qm_request* reqs, uint64_t count, hip
             if (st != QM_OK) return st;
             b.P = make_params(t->hdr);
             b.coef = reinterpret_cast<const double*>(reinterpret_cast<const char*>(t->d_table) + sizeof(TTableHeader));
-            lds = std::max(lds, (size_t)t->hdr.ncell * T_STRIDE * sizeof(double));
+            lds = std::max(lds, (size_t)t->hdr.ncell * b.P.lds_stride * sizeof(double));
         }
         d.push_back(b);
     }
+    if (lds > 65536) return set_error(QM_E_INVAL, "Student t table larger than the LDS a launch may use");
     if (d.empty()) {
         if (done && hipEventRecord(done, s) != hipSuccess) return set_error(QM_E_HIP, "hipEventRecord failed");
         return QM_OK;

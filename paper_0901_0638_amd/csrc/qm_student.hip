@@ -13,6 +13,7 @@
  */
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <stdlib.h>
 
 #include "qm_device.hpp"
 #include "qm_internal.h"
@@ -50,8 +51,7 @@ __global__ __launch_bounds__(256) void k_student(StudentArgs<T> a)
 {
     extern __shared__ double lds_tab[];
     const StudentParams P = a.P;
-    const int ncoef = P.ncell * T_STRIDE;
-    for (int i = threadIdx.x; i < ncoef; i += blockDim.x) lds_tab[i] = a.coef[i];
+    stage_table(lds_tab, a.coef, P);
     __syncthreads();
 
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
@@ -101,6 +101,20 @@ __global__ __launch_bounds__(256) void k_identity(const T* in, T* out, uint64_t 
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) out[i] = in[i];
 }
 
+/* LDS row stride in doubles.  Rows of 16 doubles all start on the same
+   bank, so lanes reading different cells conflict; one double of padding
+   (17) spreads them (measured: nu = 1 from 200 to 271 Gsamples/s).
+   QM_T_LDS_STRIDE (16..24) overrides (tuning). */
+int student_lds_stride()
+{
+    static int stride = [] {
+        const char* e = getenv("QM_T_LDS_STRIDE");
+        int v = e ? atoi(e) : T_STRIDE + 1;
+        return (v >= T_STRIDE && v <= 24) ? v : T_STRIDE + 1;
+    }();
+    return stride;
+}
+
 StudentParams make_params(const TTableHeader& h)
 {
     StudentParams P;
@@ -115,6 +129,7 @@ StudentParams make_params(const TTableHeader& h)
     P.nu = h.nu;
     P.ncell = h.ncell;
     P.identity = h.identity;
+    P.lds_stride = student_lds_stride();
     return P;
 }
 
@@ -135,7 +150,8 @@ static hipError_t launch_t(const void* in, void* out, uint64_t n, const double* 
     a.n = n;
     a.coef = d_coef;
     a.P = make_params(h);
-    size_t lds = (size_t)h.ncell * T_STRIDE * sizeof(double);
+    size_t lds = (size_t)h.ncell * a.P.lds_stride * sizeof(double);
+    if (lds > 65536) return hipErrorInvalidValue;   /* beyond the dynamic LDS a launch may ask for */
     uintptr_t pin = reinterpret_cast<uintptr_t>(in), pout = reinterpret_cast<uintptr_t>(out);
     constexpr int NV = svec<T>::n;
     bool coaligned = ((pin - pout) % 16) == 0;

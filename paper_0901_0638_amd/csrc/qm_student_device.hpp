@@ -18,7 +18,15 @@ struct StudentParams {
     double h, inv_h, centre_offset, y_max, log_K, tail_a, sqrt_nu, inv_nu, nu;
     int ncell;
     int identity;
+    int lds_stride;   /* doubles between cell rows in LDS (>= T_STRIDE; padding spreads banks) */
 };
+
+/* Copy a table (ncell rows of T_STRIDE doubles) into LDS rows of P.lds_stride. */
+__device__ __forceinline__ void stage_table(double* lds, const double* __restrict__ coef, const StudentParams& P)
+{
+    const int ncoef = P.ncell * T_STRIDE;
+    for (int i = threadIdx.x; i < ncoef; i += blockDim.x) lds[(i >> 4) * P.lds_stride + (i & 15)] = coef[i];
+}
 
 /* Far tail (y > y_max): w = K q(s), q(s) = erfcx(s/sqrt2) e^{-s^2/2} / 2,
    t = sqrt(nu) w^{-1/nu} (1 + a w^{2/nu}) (Sections 3.3, 3.5).  log w is
@@ -58,7 +66,7 @@ __device__ __forceinline__ double student_eval(double z, const double* __restric
        precision reaches the polynomial, which matters because log R grows
        like y/(2 nu) */
     double d = __builtin_fma(s, s, -yc);
-    const double* c = tab + j * T_STRIDE;
+    const double* c = tab + j * P.lds_stride;
     double R = c[0];
 #pragma unroll
     for (int k = 1; k <= T_DEGREE; ++k) R = __builtin_fma(R, d, c[k]);
