@@ -239,17 +239,16 @@ __device__ __forceinline__ float expcoord_seed_f32(float v)
     return num * __builtin_amdgcn_rcpf(den);
 }
 
-/* e^a for |a| <= 700, relative error < 1e-14: a = k ln2 + r, |r| <= ln2/2,
-   degree-11 Taylor polynomial in r, then scale by 2^k. */
+/* e^a for |a| <= 700, relative error < 1e-11 (all the correction step
+   needs): a = k ln2 + r, |r| <= ln2/2, degree-9 Taylor polynomial in r
+   (remainder r^10/10! < 7e-12), then scale by 2^k. */
 __device__ __forceinline__ double exp_refine(double a)
 {
     const double LOG2E = 1.4426950408889634074, LN2_HI = 0.69314718055994528623, LN2_LO = 2.3190468138462996154e-17;
     double k = __builtin_rint(a * LOG2E);
     double r = __builtin_fma(-k, LN2_HI, a);
     r = __builtin_fma(-k, LN2_LO, r);
-    double p = 1.0 / 39916800.0;
-    p = __builtin_fma(p, r, 1.0 / 3628800.0);
-    p = __builtin_fma(p, r, 1.0 / 362880.0);
+    double p = 1.0 / 362880.0;
     p = __builtin_fma(p, r, 1.0 / 40320.0);
     p = __builtin_fma(p, r, 1.0 / 5040.0);
     p = __builtin_fma(p, r, 1.0 / 720.0);
@@ -260,6 +259,17 @@ __device__ __forceinline__ double exp_refine(double a)
     p = __builtin_fma(p, r, 1.0);
     p = __builtin_fma(p, r, 1.0);
     return __builtin_ldexp(p, (int)k);
+}
+
+/* a / b to ~3e-15 for positive b of moderate size: hardware reciprocal and
+   one Newton step, no residual correction (enough for the correction step's
+   1e-11 needs). */
+__device__ __forceinline__ double div_pos_fast(double a, double b)
+{
+    double y = __builtin_amdgcn_rcp(b);
+    double e = __builtin_fma(-b, y, 1.0);
+    y = __builtin_fma(e, y, y);
+    return a * y;
 }
 
 /*
@@ -273,7 +283,7 @@ __device__ __forceinline__ double exp_refine(double a)
  */
 __device__ __forceinline__ double halley_upper(double x0, double p_over_phi)
 {
-    double M = div_pos(horner(x0, QM_MILLS_P), horner(x0, QM_MILLS_Q));
+    double M = div_pos_fast(horner(x0, QM_MILLS_P), horner(x0, QM_MILLS_Q));
     double t = M - p_over_phi;
     double h = 0.5 * x0 * t;
     return __builtin_fma(t, 1.0 + h, x0);
@@ -295,8 +305,8 @@ __device__ __forceinline__ float normal_quantile_f32_refine(float u)
     float w = __builtin_copysignf((float)x1, u - 0.5f);
     w = (u == 0.0f) ? -__builtin_inff() : w;
     w = (u == 1.0f) ? __builtin_inff() : w;
-    /* NaN and out-of-range inputs: p+p < 0 or NaN makes v NaN */
-    w = (u >= 0.0f && u <= 1.0f) ? w : __builtin_nanf("");
+    /* NaN and out-of-range inputs need no select: p + p is then negative or
+       NaN, the hardware log returns NaN, and NaN propagates to w */
     return w;
 }
 

@@ -322,7 +322,7 @@ int build_student_table(double nu_d, HostTTable* out, char* err, int errlen)
     const fq tol = 2e-17Q;
     for (double h = 8.0; h >= 1.0 / 64; h /= 2) {
         int ncell = (int)std::ceil(Y_TABLE / h);
-        if (ncell > 512) break;
+        if (ncell > 480) break;   /* 480 rows of 17 doubles fit the 64 KB of LDS a launch may use */
         std::vector<double> coef((size_t)ncell * H.stride, 0.0);
         fq worst = 0;
         bool ok = true;
