@@ -133,12 +133,19 @@ def qm_serving_latencies(ctx, cap=1 << 20):
     return [buf[i] for i in range(min(n, cap))]
 
 
+class TCells(ctypes.Structure):
+    """Layout of qm::TCells (csrc/qm_table.h): one cell approximation of R(y) = t/z."""
+    _fields_ = [("h", ctypes.c_double), ("inv_h", ctypes.c_double), ("y_max", ctypes.c_double),
+                ("y_lds", ctypes.c_double), ("centre_offset", ctypes.c_double), ("max_rel_err", ctypes.c_double),
+                ("ncell", ctypes.c_int32), ("nlds", ctypes.c_int32), ("degree", ctypes.c_int32),
+                ("stride", ctypes.c_int32), ("coef_offset", ctypes.c_uint64)]
+
+
 class TTableHeader(ctypes.Structure):
     """Layout of qm::TTableHeader (csrc/qm_table.h)."""
-    _fields_ = [("nu", ctypes.c_double), ("h", ctypes.c_double), ("inv_h", ctypes.c_double),
-                ("y_max", ctypes.c_double), ("centre_offset", ctypes.c_double), ("log_K", ctypes.c_double),
-                ("tail_a", ctypes.c_double * 4), ("ncell", ctypes.c_int32), ("degree", ctypes.c_int32),
-                ("stride", ctypes.c_int32), ("identity", ctypes.c_int32), ("coef_f32_offset", ctypes.c_uint64)]
+    _fields_ = [("nu", ctypes.c_double), ("log_K", ctypes.c_double), ("tail_a", ctypes.c_double * 4),
+                ("identity", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("f64", TCells), ("f32", TCells)]
 
 
 def debug_student_dense(nu, z):
@@ -153,18 +160,20 @@ def debug_student_dense(nu, z):
     return q
 
 
-def debug_student_table(nu):
-    """(header, coefficients[ncell, stride], max_rel_err) of the host-built table."""
+def debug_student_table(nu, which="f64"):
+    """(header, cells, coefficients[ncell, stride]) of the host-built table;
+    `which` selects the cell approximation for FP64 ("f64") or FP32 ("f32")
+    outputs."""
     import numpy as np
     h = TTableHeader()
-    err = ctypes.c_double()
     lib = load()
     dp = ctypes.POINTER(ctypes.c_double)
-    n = lib.qm_debug_student_table(float(nu), ctypes.byref(h), None, 0, ctypes.byref(err))
+    n = lib.qm_debug_student_table(float(nu), ctypes.byref(h), None, 0)
     if n < 0:
         raise ValueError("table build failed for nu=%r" % nu)
-    coef = np.empty(max(n, 0), np.float64)
+    c = getattr(h, which)
+    block = np.empty(max(n, 0), np.float64)
     if n > 0:
-        lib.qm_debug_student_table(float(nu), None, coef.ctypes.data_as(dp), n, None)
-        coef = coef.reshape(h.ncell, h.stride)
-    return h, coef, err.value
+        lib.qm_debug_student_table(float(nu), None, block.ctypes.data_as(dp), n)
+    coef = block[c.coef_offset:c.coef_offset + c.ncell * c.stride].reshape(c.ncell, c.stride)
+    return h, c, coef

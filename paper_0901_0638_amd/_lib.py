@@ -66,7 +66,7 @@ SIGNATURES = {
 # include/qm_debug.h: host-only diagnostics of the Student t table builder
 DEBUG_SIGNATURES = {
     "qm_debug_student_dense": (ctypes.c_int, [_d, ctypes.POINTER(_d), ctypes.POINTER(_d), ctypes.c_int]),
-    "qm_debug_student_table": (ctypes.c_int, [_d, _vp, ctypes.POINTER(_d), ctypes.c_int, ctypes.POINTER(_d)]),
+    "qm_debug_student_table": (ctypes.c_int, [_d, _vp, ctypes.POINTER(_d), ctypes.c_int]),
 }
 
 _lib = None

@@ -92,7 +92,7 @@ qm_status get_table(qm_ctx* ctx, double nu, const DeviceTable** out)
     char err[256] = {0};
     if (build_student_table(nu, &ht, err, sizeof err) != 0)
         return fail(QM_E_INVAL, "Student t table for nu=%g: %s", nu, err);
-    size_t coef_bytes = (size_t)ht.hdr.ncell * ht.hdr.stride * sizeof(double);
+    size_t coef_bytes = (size_t)ht.ncoef * sizeof(double);
     size_t bytes = sizeof(TTableHeader) + coef_bytes;
     void* d = nullptr;
     hipError_t e = hipMalloc(&d, bytes);
@@ -104,7 +104,6 @@ qm_status get_table(qm_ctx* ctx, double nu, const DeviceTable** out)
     DeviceTable dt;
     dt.hdr = ht.hdr;
     dt.d_table = (TTableHeader*)d;
-    dt.max_rel_err = ht.max_rel_err;
     free_student_table(&ht);
     auto res = ctx->tables.emplace(nu, dt);
     *out = &res.first->second;

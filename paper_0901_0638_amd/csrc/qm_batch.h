@@ -33,12 +33,11 @@ struct BatchReq {
     void* out;
     uint64_t n;
     uint64_t chunk_base;    /* global index of the request's first chunk */
-    const double* coef;     /* Student t: device table coefficients */
+    const double* coef;     /* Student t: device cell rows of the request's dtype */
     StudentParams P;        /* Student t: table parameters */
 };
 
-StudentParams make_params(const TTableHeader& h);
-int student_lds_stride();
+StudentParams make_params(const TTableHeader& h, const TCells& c, const double* d_rows);
 hipError_t launch_batch(BatchHeader* d_hdr, const BatchReq* d_reqs, size_t lds_bytes, uint64_t blocks,
                         hipStream_t s);
 

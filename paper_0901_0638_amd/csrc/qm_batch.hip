@@ -94,14 +94,14 @@ static __device__ __noinline__ void chunk_t64(const void* in, void* out, uint64_
                                               const StudentParams P)
 {
     chunk_map<double>((const double*)in, (double*)out, begin, end,
-                      [&](double z) { return student_eval(z, lds_tab, P); });
+                      [&](double z) { return student_eval<T_DEGREE_F64>(z, lds_tab, P); });
 }
 
 static __device__ __noinline__ void chunk_t32(const void* in, void* out, uint64_t begin, uint64_t end,
                                               const StudentParams P)
 {
     chunk_map<float>((const float*)in, (float*)out, begin, end,
-                     [&](float z) { return (float)student_eval((double)z, lds_tab, P); });
+                     [&](float z) { return (float)student_eval<T_DEGREE_F32>((double)z, lds_tab, P); });
 }
 
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_batch(BatchHeader* hdr, const BatchReq* __restrict__ reqs)

@@ -16,7 +16,6 @@ struct BatchRunner;
 struct DeviceTable {
     qm::TTableHeader hdr;
     qm::TTableHeader* d_table = nullptr;  /* header followed by coefficients */
-    double max_rel_err = 0;
 };
 
 struct qm_ctx {

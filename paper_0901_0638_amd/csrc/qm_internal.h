@@ -22,7 +22,14 @@ struct LaunchShape {
 hipError_t launch_elementwise(int kind, int dtype, int mode, const void* in, void* out, uint64_t n,
                               hipStream_t s, const LaunchShape& shape);
 
-/* Launch the Student t map with a device table (qm_student.hip). */
+/* The coefficient block that follows a device table's header. */
+inline const double* table_block(const TTableHeader* d_table)
+{
+    return reinterpret_cast<const double*>(reinterpret_cast<const char*>(d_table) + sizeof(TTableHeader));
+}
+
+/* Launch the Student t map with a device table (qm_student.hip): FP64
+   outputs use the table's f64 cells, FP32 outputs its f32 cells. */
 hipError_t launch_student(int dtype, int mode, const void* in, void* out, uint64_t n,
                           const TTableHeader* d_table, const TTableHeader& h_table,
                           hipStream_t s, const LaunchShape& shape);

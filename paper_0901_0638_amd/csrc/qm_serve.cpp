@@ -50,6 +50,7 @@ struct Staging {
 struct BatchRunner {
     std::mutex mu;
     std::vector<Staging*> slots;
+    size_t next = 0;           /* ring position: the oldest use is tried first */
 };
 
 static BatchRunner* runner_of(qm_ctx* ctx)
@@ -82,22 +83,34 @@ static qm_status acquire_slot(BatchRunner* br, size_t bytes, Staging** out)
 {
     std::unique_lock<std::mutex> lk(br->mu);
     Staging* slot = nullptr;
-    for (Staging* s : br->slots) {
-        /* the slot's event covers its last launch (a fresh event counts as complete) */
-        if (!s->busy && hipEventQuery(s->ev) == hipSuccess) { slot = s; break; }
+    /* slots are used in ring order, so the one at `next` holds the oldest
+       launch: one event query usually settles it; otherwise add a slot */
+    const size_t ns = br->slots.size();
+    for (size_t k = 0; k < ns && k < 2 && !slot; ++k) {
+        Staging* s = br->slots[(br->next + k) % ns];
+        if (!s->busy && hipEventQuery(s->ev) == hipSuccess) {
+            slot = s;
+            br->next = (br->next + k + 1) % ns;
+        }
     }
-    if (!slot && br->slots.size() < 32) {
+    if (!slot && ns < 32) {
         slot = new Staging;
         if (hipEventCreateWithFlags(&slot->ev, hipEventDisableTiming) != hipSuccess) {
             delete slot;
             return set_error(QM_E_HIP, "hipEventCreate failed");
         }
-        br->slots.push_back(slot);
+        br->slots.insert(br->slots.begin() + br->next, slot);
+        br->next = (br->next + 1) % br->slots.size();
     }
-    while (!slot) {
-        for (Staging* s : br->slots)
-            if (!s->busy) { slot = s; break; }
-        if (!slot) {            /* all 32 held by other callers right now */
+    while (!slot) {             /* all 32 in use: take the oldest that no caller holds */
+        for (size_t k = 0; k < br->slots.size() && !slot; ++k) {
+            Staging* s = br->slots[(br->next + k) % br->slots.size()];
+            if (!s->busy) {
+                slot = s;
+                br->next = (br->next + k + 1) % br->slots.size();
+            }
+        }
+        if (!slot) {
             lk.unlock();
             std::this_thread::yield();
             lk.lock();
@@ -172,9 +185,10 @@ qm_status enqueue_batch(qm_ctx* ctx, const qm_request* reqs, uint64_t count, hip
             const DeviceTable* t = nullptr;
             qm_status st = get_table(ctx, r.nu, &t);
             if (st != QM_OK) return st;
-            b.P = make_params(t->hdr);
-            b.coef = reinterpret_cast<const double*>(reinterpret_cast<const char*>(t->d_table) + sizeof(TTableHeader));
-            lds = std::max(lds, (size_t)t->hdr.ncell * b.P.lds_stride * sizeof(double));
+            const TCells& c = r.dtype == QM_F64 ? t->hdr.f64 : t->hdr.f32;
+            b.coef = table_block(t->d_table) + c.coef_offset;
+            b.P = make_params(t->hdr, c, b.coef);
+            if (!t->hdr.identity) lds = std::max(lds, (size_t)c.nlds * b.P.lds_stride * sizeof(double));
         }
         d.push_back(b);
     }

@@ -3,13 +3,15 @@
  *
  * t = F_nu^{-1}(Phi(z)) = z R(y), y = z^2, with R the per-cell polynomial
  * built on the host from the recycling ODE (qm_table.cpp).  Each workgroup
- * stages the table in LDS once, then streams 16-byte vectors as the other
- * elementwise kernels do.  Per element: the cell index from y = s^2 by one
- * multiply, the offset d = s^2 - y_c by one fused multiply-add (so the full
- * input precision reaches the polynomial: log R grows like y/(2 nu)), the cell's coefficients from LDS, Horner in d, one multiply by
- * z.  Elements beyond the table (|z| > 10, probability below 1e-23 for a
- * normal sample) take the two-term tail formula of Section 3.5 in log space,
- * entered by a wave vote.
+ * stages the cells of y <= 100 in LDS once, then streams 16-byte vectors as
+ * the other elementwise kernels do.  Per element: the cell index from
+ * y = s^2 by one multiply, the offset d = s^2 - y_c by one fused
+ * multiply-add (so the full input precision reaches the polynomial: log R
+ * grows like y/(2 nu)), the cell's coefficients from LDS, Horner in d, one
+ * multiply by z.  FP64 outputs use degree-15 cells, FP32 outputs degree-7
+ * cells.  Elements beyond (|z| > 10, probability below 1e-23 for a normal
+ * sample) are entered by a wave vote: the table's further cells from global
+ * memory, then the two-term tail formula of Section 3.5 in log space.
  */
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -29,7 +31,7 @@ struct StudentArgs {
     const T* in;
     T* out;
     uint64_t head, nvec, tail_begin, n;
-    const double* coef;       /* device table coefficients (ncell * T_STRIDE) */
+    const double* coef;       /* device cell rows (ncell << P.row_shift doubles) */
     StudentParams P;
 };
 
@@ -40,10 +42,11 @@ template <> struct svec<float> { typedef f4 type; static constexpr int n = 4; };
 template <typename T>
 __device__ __forceinline__ T student_op(T z, const double* tab, const StudentParams& P)
 {
-    if (sizeof(T) == 8) return (T)student_eval((double)z, tab, P);
-    /* FP32 in/out: the FP64 evaluation rounded once (the input is exact in
-       FP64, so y = z^2 is exact and the table's full accuracy carries over) */
-    return (T)student_eval((double)z, tab, P);
+    if (sizeof(T) == 8) return (T)student_eval<T_DEGREE_F64>((double)z, tab, P);
+    /* FP32 in/out: the FP64 evaluation of the degree-7 cells (R to 1e-10)
+       rounded once; the input is exact in FP64, so the cell offset carries
+       the input's full precision */
+    return (T)student_eval<T_DEGREE_F32>((double)z, tab, P);
 }
 
 template <typename T, bool VECTOR, int UNROLL>
@@ -101,40 +104,54 @@ __global__ __launch_bounds__(256) void k_identity(const T* in, T* out, uint64_t 
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) out[i] = in[i];
 }
 
-/* LDS row stride in doubles.  Rows of 16 doubles all start on the same
-   bank, so lanes reading different cells conflict; one double of padding
-   (17) spreads them (measured: nu = 1 from 200 to 271 Gsamples/s).
-   QM_T_LDS_STRIDE (16..24) overrides (tuning). */
-int student_lds_stride()
+/* LDS row stride in doubles for rows of `row` coefficients.  Rows of a
+   power-of-2 length all start on the same bank, so lanes reading different
+   cells conflict; one double of padding spreads them (measured, rows of 16:
+   nu = 1 from 200 to 271 Gsamples/s).  QM_T_LDS_STRIDE (row..24) overrides
+   the FP64 rows' stride, QM_T32_LDS_STRIDE (row..24) the FP32 rows' (tuning). */
+static int stride_from_env(const char* name, int row)
 {
-    static int stride = [] {
-        const char* e = getenv("QM_T_LDS_STRIDE");
-        int v = e ? atoi(e) : T_STRIDE + 1;
-        return (v >= T_STRIDE && v <= 24) ? v : T_STRIDE + 1;
-    }();
-    return stride;
+    const char* e = getenv(name);
+    int v = e ? atoi(e) : row + 1;
+    return (v >= row && v <= 24) ? v : row + 1;
 }
 
-StudentParams make_params(const TTableHeader& h)
+int student_lds_stride(int row)
+{
+    static const int s16 = stride_from_env("QM_T_LDS_STRIDE", T_DEGREE_F64 + 1);
+    static const int s8 = stride_from_env("QM_T32_LDS_STRIDE", T_DEGREE_F32 + 1);
+    return row == T_DEGREE_F64 + 1 ? s16 : s8;
+}
+
+static bool cells_valid(const TCells& c, int degree)
+{
+    return c.degree == degree && c.stride == degree + 1 && c.nlds >= 1 && c.ncell >= c.nlds;
+}
+
+StudentParams make_params(const TTableHeader& h, const TCells& c, const double* d_rows)
 {
     StudentParams P;
-    P.h = h.h;
-    P.inv_h = h.inv_h;
-    P.centre_offset = h.centre_offset;
-    P.y_max = h.y_max;
+    P.h = c.h;
+    P.inv_h = c.inv_h;
+    P.centre_offset = c.centre_offset;
+    P.y_lds = c.y_lds;
+    P.y_max = c.y_max;
+    P.gcoef = d_rows;
     P.log_K = h.log_K;
     P.tail_a = h.tail_a[0];
     P.sqrt_nu = __builtin_sqrt(h.nu);
     P.inv_nu = 1.0 / h.nu;
     P.nu = h.nu;
-    P.ncell = h.ncell;
+    P.ncell = c.ncell;
+    P.nlds = c.nlds;
     P.identity = h.identity;
-    P.lds_stride = student_lds_stride();
+    P.row_shift = c.stride == 16 ? 4 : 3;
+    P.lds_stride = student_lds_stride(c.stride);
     return P;
 }
 
 template <typename T>
-static hipError_t launch_t(const void* in, void* out, uint64_t n, const double* d_coef, const TTableHeader& h,
+static hipError_t launch_t(const void* in, void* out, uint64_t n, const double* d_block, const TTableHeader& h,
                            hipStream_t s, const LaunchShape& shape)
 {
     if (h.identity) {
@@ -148,9 +165,10 @@ static hipError_t launch_t(const void* in, void* out, uint64_t n, const double* 
     a.in = static_cast<const T*>(in);
     a.out = static_cast<T*>(out);
     a.n = n;
-    a.coef = d_coef;
-    a.P = make_params(h);
-    size_t lds = (size_t)h.ncell * a.P.lds_stride * sizeof(double);
+    const TCells& c = sizeof(T) == 8 ? h.f64 : h.f32;
+    a.coef = d_block + c.coef_offset;
+    a.P = make_params(h, c, a.coef);
+    size_t lds = (size_t)c.nlds * a.P.lds_stride * sizeof(double);
     if (lds > 65536) return hipErrorInvalidValue;   /* beyond the dynamic LDS a launch may ask for */
     uintptr_t pin = reinterpret_cast<uintptr_t>(in), pout = reinterpret_cast<uintptr_t>(out);
     constexpr int NV = svec<T>::n;
@@ -186,11 +204,11 @@ hipError_t launch_student(int dtype, int mode, const void* in, void* out, uint64
                           const TTableHeader* d_table, const TTableHeader& h_table,
                           hipStream_t s, const LaunchShape& shape)
 {
-    if (h_table.degree != T_DEGREE && !h_table.identity) return hipErrorInvalidValue;
-    if (!h_table.identity && (h_table.ncell < 1 || h_table.stride != T_STRIDE)) return hipErrorInvalidValue;
-    const double* d_coef = reinterpret_cast<const double*>(reinterpret_cast<const char*>(d_table) + sizeof(TTableHeader));
-    if (dtype == QM_F64 && mode == QM_PLAIN) return launch_t<double>(in, out, n, d_coef, h_table, s, shape);
-    if (dtype == QM_F32 && mode == QM_F32_REFINE) return launch_t<float>(in, out, n, d_coef, h_table, s, shape);
+    if (!h_table.identity && !(cells_valid(h_table.f64, T_DEGREE_F64) && cells_valid(h_table.f32, T_DEGREE_F32)))
+        return hipErrorInvalidValue;
+    const double* d_block = table_block(d_table);
+    if (dtype == QM_F64 && mode == QM_PLAIN) return launch_t<double>(in, out, n, d_block, h_table, s, shape);
+    if (dtype == QM_F32 && mode == QM_F32_REFINE) return launch_t<float>(in, out, n, d_block, h_table, s, shape);
     return hipErrorInvalidValue;
 }
 

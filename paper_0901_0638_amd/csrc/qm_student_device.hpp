@@ -10,34 +10,71 @@
 
 namespace qm {
 
-constexpr int T_DEGREE = 15;
-constexpr int T_STRIDE = 16;
-
-/* Uniform per-launch parameters (copied from the host-side header). */
+/* Uniform per-launch parameters: the tail constants of the table header and
+   the layout of the cell approximation in use. */
 struct StudentParams {
-    double h, inv_h, centre_offset, y_max, log_K, tail_a, sqrt_nu, inv_nu, nu;
-    int ncell;
+    double h, inv_h, centre_offset, y_lds, y_max, log_K, tail_a, sqrt_nu, inv_nu, nu;
+    const double* gcoef;  /* all ncell rows in global memory (the rare path reads them) */
+    int ncell;        /* rows covering y <= y_max */
+    int nlds;         /* rows staged in LDS, covering y <= y_lds */
     int identity;
-    int lds_stride;   /* doubles between cell rows in LDS (>= T_STRIDE; padding spreads banks) */
+    int row_shift;    /* log2 of the coefficients per row in memory (degree + 1) */
+    int lds_stride;   /* doubles between cell rows in LDS (> row; padding spreads banks) */
 };
 
-/* Copy a table (ncell rows of T_STRIDE doubles) into LDS rows of P.lds_stride. */
+/* Copy the first nlds cell rows (2^row_shift doubles each) into LDS rows of
+   P.lds_stride doubles. */
 __device__ __forceinline__ void stage_table(double* lds, const double* __restrict__ coef, const StudentParams& P)
 {
-    const int ncoef = P.ncell * T_STRIDE;
-    for (int i = threadIdx.x; i < ncoef; i += blockDim.x) lds[(i >> 4) * P.lds_stride + (i & 15)] = coef[i];
+    const int ncoef = P.nlds << P.row_shift;
+    const int mask = (1 << P.row_shift) - 1;
+    for (int i = threadIdx.x; i < ncoef; i += blockDim.x) lds[(i >> P.row_shift) * P.lds_stride + (i & mask)] = coef[i];
 }
 
-/* Far tail (y > y_max): w = K q(s), q(s) = erfcx(s/sqrt2) e^{-s^2/2} / 2,
-   t = sqrt(nu) w^{-1/nu} (1 + a w^{2/nu}) (Sections 3.3, 3.5).  log w is
-   carried as a double-double (s^2/2 exactly, the division by nu with its
-   remainder), because an absolute error e in it is a relative error e/nu
-   in t and |log w| reaches several hundred. */
+/* R(y) of cell j by Horner in d = y - y_c (rows of DEG + 1 doubles). */
+template <int DEG>
+__device__ __forceinline__ double cell_poly(const double* __restrict__ c, double d)
+{
+    double R = c[0];
+#pragma unroll
+    for (int k = 1; k <= DEG; ++k) R = __builtin_fma(R, d, c[k]);
+    return R;
+}
+
+/* Cell index and offset for s = |z|: j from y = s^2 by one multiply,
+   clamped to jmax (NaN and inf clamp too), and d = s^2 - y_c with a single
+   rounding (|d| <= h/2), so the full input precision reaches the
+   polynomial, which matters because log R grows like y/(2 nu). */
+__device__ __forceinline__ int cell_of(double s, double yh, int jmax, const StudentParams& P, double* d)
+{
+    double jd = yh * P.inv_h;
+    const double jm = (double)jmax;
+    jd = (jd < jm) ? jd : jm;
+    int j = (int)jd;
+    double yc = __builtin_fma((double)j, P.h, P.centre_offset);   /* exact: h is a power of 2 */
+    *d = __builtin_fma(s, s, -yc);
+    return j;
+}
+
+/* Beyond the LDS cells (y > y_lds, |z| above about 10).  Up to y_max the
+   remaining cells, from global memory.  Beyond: w = K q(s),
+   q(s) = erfcx(s/sqrt2) e^{-s^2/2} / 2, t = sqrt(nu) w^{-1/nu} (1 + a w^{2/nu})
+   (Sections 3.3, 3.5), which the table builder has checked to be as accurate
+   as the cells there.  log w is carried as a double-double (s^2/2 exactly,
+   the division by nu with its remainder), because an absolute error e in it
+   is a relative error e/nu in t and |log w| reaches several hundred. */
+template <int DEG>
 static __device__ __noinline__ double student_far(double s, const StudentParams& P)
 {
 #pragma clang fp contract(off)
     const double INV_SQRT2 = 0.70710678118654752440, LN2 = 0.69314718055994530942;
     if (!(s < __builtin_inf())) return s;              /* z = +-inf -> +-inf; NaN -> NaN */
+    double yh = s * s;
+    if (yh <= P.y_max) {
+        double d;
+        int j = cell_of(s, yh, P.ncell - 1, P, &d);
+        return s * cell_poly<DEG>(P.gcoef + j * (DEG + 1), d);
+    }
     double hs = -0.5 * s;                              /* exact */
     double e_hi = hs * s;
     double e_lo = __builtin_fma(hs, s, -e_hi);         /* -s^2/2 = e_hi + e_lo exactly */
@@ -52,28 +89,18 @@ static __device__ __noinline__ double student_far(double s, const StudentParams&
     return t * (1.0 + P.tail_a * ::exp(2.0 * q_hi));
 }
 
-/* t(z) in FP64 from the LDS table. */
+/* t(z) in FP64 from the LDS table, cells of degree DEG. */
+template <int DEG>
 __device__ __forceinline__ double student_eval(double z, const double* __restrict__ tab, const StudentParams& P)
 {
     double s = __builtin_fabs(z);
     double yh = s * s;                      /* only selects the cell */
-    double jd = yh * P.inv_h;
-    const double jmax = (double)(P.ncell - 1);
-    jd = (jd < jmax) ? jd : jmax;           /* NaN and inf clamp to the last cell */
-    int j = (int)jd;
-    double yc = __builtin_fma((double)j, P.h, P.centre_offset);   /* exact: h is a power of 2 */
-    /* d = s^2 - y_c with a single rounding (|d| <= h/2): the full input
-       precision reaches the polynomial, which matters because log R grows
-       like y/(2 nu) */
-    double d = __builtin_fma(s, s, -yc);
-    const double* c = tab + j * P.lds_stride;
-    double R = c[0];
-#pragma unroll
-    for (int k = 1; k <= T_DEGREE; ++k) R = __builtin_fma(R, d, c[k]);
-    double t = z * R;
-    bool far = !(yh <= P.y_max);            /* also NaN: NaN propagates either way */
+    double d;
+    int j = cell_of(s, yh, P.nlds - 1, P, &d);
+    double t = z * cell_poly<DEG>(tab + j * P.lds_stride, d);
+    bool far = !(yh <= P.y_lds);            /* also NaN: NaN propagates either way */
     if (wave_any(far)) {
-        double tf = __builtin_copysign(student_far(far ? s : 1.0, P), z);
+        double tf = __builtin_copysign(student_far<DEG>(far ? s : 1.0, P), z);
         t = far ? tf : t;
     }
     return t;

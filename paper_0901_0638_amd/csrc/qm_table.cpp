@@ -17,18 +17,23 @@
  * solution like 1/(1 - Phi(z)).  So the solution is built from both ends:
  *
  *   forward  from the centre conditions to z_m = 4,
- *   backward from z_far = 10.5 down to z_m, starting from the tail
+ *   backward from z_far (10.5, or past the last cell) down to z_m, from the tail
  *            condition: Q(z_far) solves 1 - F_nu(Q) = 1 - Phi(z_far) with the
  *            Student tail written as a convergent hypergeometric series
  *            (DLMF 8.17.8), Q'(z_far) = phi(z_far) / f_nu(Q) (the centre/tail
  *            boundary data of Sections 3.1 and 3.3),
  *
- * and the two legs must agree at z_m (checked).  The device table then holds,
- * for y = z^2 in [0, 100], cells of width h in y with the Chebyshev
- * interpolant of R(y) = Q(z)/z (an even function of z, like the paper's
- * series in y = z^2, Section 3.5), stored as monomial coefficients in
- * d = y - y_centre.  For nu > 1e5 the map is within 1e-19 of the
- * Cornish-Fisher series of Section 3.4 (A&S 26.7.5), used directly.
+ * and the two legs must agree at z_m (checked).  The device table then holds
+ * cells of width h in y = z^2 with the Chebyshev interpolant of
+ * R(y) = Q(z)/z (an even function of z, like the paper's series in y = z^2,
+ * Section 3.5), stored as monomial coefficients in d = y - y_centre, twice:
+ * degree 15 for FP64 outputs and degree 7 on narrower cells for FP32
+ * outputs.  The cells cover y <= 100 and then as far as the two-term tail
+ * formula of Section 3.5 falls short of the same accuracy (it is
+ * O(w^{4/nu}), so for large nu it needs very large |z|), but never past
+ * |z| = 40, beyond the normal quantile of any positive double.  For
+ * nu > 1e5 the map is within 1e-19 of the Cornish-Fisher series of
+ * Section 3.4 (A&S 26.7.5), used directly.
  */
 #include <quadmath.h>
 
@@ -47,8 +52,11 @@ typedef __float128 fq;
 
 constexpr int TAYLOR_M = 32;        /* Taylor order of the integrator */
 constexpr double Z_MATCH = 4.0;     /* forward/backward meeting point */
-constexpr double Z_FAR = 10.5;      /* backward anchor */
-constexpr double Y_TABLE = 100.0;   /* table covers y = z^2 in [0, Y_TABLE] */
+constexpr double Z_FAR = 10.5;      /* backward anchor, at least */
+constexpr double Y_LDS = 100.0;     /* cells staged in LDS cover y = z^2 in [0, Y_LDS] at least */
+constexpr double Z_TAIL0 = 10.0;    /* the tail formula is never used below |z| = Z_TAIL0 */
+constexpr double Z_CAP = 40.0;      /* ... and always beyond Z_CAP (past every normal
+                                       quantile of a positive double, |z| <= 38.5) */
 constexpr double NU_CF = 1e5;       /* above: Cornish-Fisher polynomial */
 
 struct Node {
@@ -184,7 +192,7 @@ fq anchor_value(fq nu, fq zf, fq lbeta, fq logq_target)
     return t;
 }
 
-/* Dense output Q(z), 0 <= z <= Z_FAR, from the recorded nodes. */
+/* Dense output Q(z), 0 <= z <= z_far, from the recorded nodes. */
 struct Solution {
     std::vector<Node> fwd, bwd;
     fq eval(fq z) const
@@ -202,6 +210,53 @@ struct Solution {
         return horner_q(v[best].a, TAYLOR_M, z - v[best].z0);
     }
 };
+
+/*
+ * The two legs of the RODE solution on [0, z_far]: forward from the centre
+ * conditions Q(0) = 0, Q'(0) = gamma to z_m, backward from the tail
+ * condition at z_far; they must agree in value and slope at z_m.
+ */
+bool solve_rode(fq nu, fq lbeta, fq gamma, fq z_far, Solution& sol, char* err, int errlen)
+{
+    integrate(nu, 0, 0, gamma, Z_MATCH, sol.fwd);
+    const fq logq_far = logq(erfcq(z_far / sqrtq(2)) / 2);
+    const fq Qf = anchor_value(nu, z_far, lbeta, logq_far);
+    const fq phi_far = expq(-z_far * z_far / 2) / sqrtq(2 * M_PIq);
+    const fq dQf = phi_far / expq(log_student_pdf(nu, Qf, lbeta));
+    integrate(nu, z_far, Qf, dQf, Z_MATCH, sol.bwd);
+    const Node& f = sol.fwd.back();
+    const Node& b = sol.bwd.back();
+    fq qf = horner_q(f.a, TAYLOR_M, f.h), qb = horner_q(b.a, TAYLOR_M, b.h);
+    fq df = horner_qd(f.a, TAYLOR_M, f.h), db = horner_qd(b.a, TAYLOR_M, b.h);
+    fq mis = fabsq(qf / qb - 1) + fabsq(df / db - 1);
+    if (!(mis < 1e-22Q)) {
+        snprintf(err, errlen, "forward/backward legs disagree at z=%g by %.3e", Z_MATCH, (double)mis);
+        return false;
+    }
+    return true;
+}
+
+/*
+ * Where the two-term tail of Section 3.5, t = sqrt(nu) w^{-1/nu}
+ * (1 + a w^{2/nu}), w = K q(z), is accurate to tol: the smallest z on a
+ * grid of 1/2 in [Z_TAIL0, Z_CAP] from which on its relative error against
+ * the exact map (the tail-condition solve at z) stays below tol; Z_CAP if
+ * none.  The error falls monotonically with z (it is O(w^{4/nu})), so the
+ * scan runs down from Z_CAP and stops at the first failure.
+ */
+fq tail_formula_z(fq nu, fq lbeta, fq logK, fq a, fq tol)
+{
+    fq z_ok = Z_CAP;
+    for (fq z = Z_CAP; z >= (fq)Z_TAIL0; z -= 0.5Q) {
+        fq lq = logq(erfcq(z / sqrtq(2)) / 2);
+        fq exact = anchor_value(nu, z, lbeta, lq);
+        fq lw = logK + lq;
+        fq tf = sqrtq(nu) * expq(-lw / nu) * (1 + a * expq(2 * lw / nu));
+        if (!(fabsq(tf / exact - 1) <= tol)) break;
+        z_ok = z;
+    }
+    return z_ok;
+}
 
 /* Chebyshev interpolant of f on [y0 - hw, y0 + hw] as monomials in d = y - y0. */
 void cheb_to_monomial(const fq* fv, int K, fq hw, fq* mono)
@@ -239,91 +294,25 @@ int fail(char* err, int errlen, const char* msg)
     return -1;
 }
 
-}  // namespace
-
-int build_student_table(double nu_d, HostTTable* out, char* err, int errlen)
+/*
+ * Cells of degree K for R(y) = Q(z)/z on y in [0, max(y_need, Y_LDS)]: the
+ * widest power-of-2 width h <= 8 whose Chebyshev interpolants have
+ * truncation error below tol (checked with the exact coefficients on 4K+1
+ * points per cell) and whose cells up to Y_LDS number at most max_lds; the
+ * error after rounding the coefficients to FP64 is measured as well and
+ * recorded.  Appends the rows to `coef` and fills `c`.  Returns false if
+ * no width qualifies.
+ */
+bool fit_cells(const Solution& sol, fq gamma, int K, fq tol, double y_need, int max_lds, std::vector<double>& coef,
+               TCells* c)
 {
-    memset(out, 0, sizeof *out);
-    if (!(nu_d >= 0.5)) return fail(err, errlen, "nu must be >= 0.5");
-    TTableHeader& H = out->hdr;
-    H.nu = nu_d;
-    if (std::isinf(nu_d)) {
-        H.identity = 1;
-        H.ncell = 0;
-        H.degree = 0;
-        H.stride = 0;
-        H.h = 1;
-        H.inv_h = 1;
-        H.y_max = 0;
-        return 0;
-    }
-    const fq nu = nu_d;
-    const fq lbeta = lgamma_q(nu / 2) + lgamma_q(0.5Q) - lgamma_q(nu / 2 + 0.5Q);
-    H.log_K = (double)(logq(nu) + 0.5Q * logq(M_PIq) + lgamma_q(nu / 2) - lgamma_q((nu + 1) / 2));
-    /* two-term tail of Section 3.5: t = sqrt(nu) w^{-1/nu} (1 - (nu+1)/(2(nu+2)) w^{2/nu}) */
-    H.tail_a[0] = -(double)((nu + 1) / (2 * (nu + 2)));
-
-    const int K = 15;                     /* polynomial degree per cell */
-    H.degree = K;
-    H.stride = K + 1;
-
-    if (nu_d > NU_CF) {
-        /* Section 3.4 (A&S 26.7.5): t = z (1 + (y+1)/(4n) + (5y^2+16y+3)/(96n^2)
-           + (3y^3+19y^2+17y-15)/(384n^3) + (79y^4+776y^3+1482y^2-1920y-945)/(92160n^4)),
-           one cell whose polynomial in d = y (y_centre = 0) covers all y. */
-        H.identity = 0;
-        H.ncell = 1;
-        H.h = 1e300;
-        H.inv_h = 0;
-        H.y_max = 1e300;
-        H.centre_offset = 0;
-        out->coef = (double*)calloc(H.stride, sizeof(double));
-        if (!out->coef) return fail(err, errlen, "out of memory");
-        fq n = nu, c[5] = {0, 0, 0, 0, 0};
-        c[0] = 1 + 1 / (4 * n) + 3 / (96 * n * n) - 15 / (384 * n * n * n) - 945 / (92160 * n * n * n * n);
-        c[1] = 1 / (4 * n) + 16 / (96 * n * n) + 17 / (384 * n * n * n) - 1920 / (92160 * n * n * n * n);
-        c[2] = 5 / (96 * n * n) + 19 / (384 * n * n * n) + 1482 / (92160 * n * n * n * n);
-        c[3] = 3 / (384 * n * n * n) + 776 / (92160 * n * n * n * n);
-        c[4] = 79 / (92160 * n * n * n * n);
-        /* stored highest power first, degree K */
-        for (int k = 0; k <= 4; ++k) out->coef[K - k] = (double)c[k];
-        out->max_rel_err = 0;
-        return 0;
-    }
-
-    /* --- the two legs of the RODE solution ------------------------------- */
-    Solution sol;
-    const fq gamma = sqrtq(nu / 2) * expq(lgamma_q(nu / 2) - lgamma_q((nu + 1) / 2));
-    integrate(nu, 0, 0, gamma, Z_MATCH, sol.fwd);
-    const fq zf = Z_FAR;
-    const fq logq_far = logq(erfcq(zf / sqrtq(2)) / 2);
-    const fq Qf = anchor_value(nu, zf, lbeta, logq_far);
-    const fq phi_far = expq(-zf * zf / 2) / sqrtq(2 * M_PIq);
-    const fq dQf = phi_far / expq(log_student_pdf(nu, Qf, lbeta));
-    integrate(nu, zf, Qf, dQf, Z_MATCH, sol.bwd);
-    /* the legs meet at z_m: value and slope must agree */
-    {
-        const Node& f = sol.fwd.back();
-        const Node& b = sol.bwd.back();
-        fq qf = horner_q(f.a, TAYLOR_M, f.h), qb = horner_q(b.a, TAYLOR_M, b.h);
-        fq df = horner_qd(f.a, TAYLOR_M, f.h), db = horner_qd(b.a, TAYLOR_M, b.h);
-        fq mis = fabsq(qf / qb - 1) + fabsq(df / db - 1);
-        if (!(mis < 1e-22Q)) {
-            char buf[128];
-            snprintf(buf, sizeof buf, "forward/backward legs disagree at z=%g by %.3e", Z_MATCH, (double)mis);
-            return fail(err, errlen, buf);
-        }
-    }
-
-    /* --- cells: the widest h (power of 2) whose Chebyshev interpolants have
-       truncation error < 2e-17 (checked with the exact coefficients); the
-       error after rounding the coefficients to FP64 (about an ulp of R) is
-       measured as well and reported ------------------------------------- */
-    const fq tol = 2e-17Q;
-    for (double h = 8.0; h >= 1.0 / 64; h /= 2) {
-        int ncell = (int)std::ceil(Y_TABLE / h);
-        if (ncell > 480) break;   /* 480 rows of 17 doubles fit the 64 KB of LDS a launch may use */
-        std::vector<double> coef((size_t)ncell * H.stride, 0.0);
+    const int stride = K + 1;
+    const double y_top = y_need > Y_LDS ? y_need : Y_LDS;
+    for (double h = 8.0; h >= 1.0 / 256; h /= 2) {
+        const int nlds = (int)std::ceil(Y_LDS / h);
+        if (nlds > max_lds) break;
+        const int ncell = (int)std::ceil(y_top / h);
+        std::vector<double> rows((size_t)ncell * stride, 0.0);
         fq worst = 0;
         bool ok = true;
         for (int j = 0; j < ncell && ok; ++j) {
@@ -336,7 +325,8 @@ int build_student_table(double nu_d, HostTTable* out, char* err, int errlen)
                 fv[i] = z > 0 ? sol.eval(z) / z : gamma;
             }
             cheb_to_monomial(fv, K, hw, mono);
-            for (int k = 0; k <= K; ++k) coef[(size_t)j * H.stride + (K - k)] = (double)mono[k];
+            double* row = &rows[(size_t)j * stride];
+            for (int k = 0; k <= K; ++k) row[K - k] = (double)mono[k];
             for (int t = 0; t <= 4 * K; ++t) {
                 fq d = -hw + h * (fq)t / (4 * K);
                 fq y = yc + d;
@@ -344,29 +334,113 @@ int build_student_table(double nu_d, HostTTable* out, char* err, int errlen)
                 fq ref = z > 0 ? sol.eval(z) / z : gamma;
                 fq pe = 0, pr = 0;
                 for (int k = K; k >= 0; --k) pe = pe * d + mono[k];
-                for (int k = 0; k <= K; ++k) pr = pr * d + (fq)coef[(size_t)j * H.stride + k];
+                for (int k = 0; k <= K; ++k) pr = pr * d + (fq)row[k];
                 fq et = fabsq(pe / ref - 1), er = fabsq(pr / ref - 1);
                 if (er > worst) worst = er;
 #ifdef QM_TABLE_VERBOSE
-                if (et > tol) fprintf(stderr, "h %g cell %d y %g trunc err %.3e\n", h, j, (double)y, (double)et);
+                if (et > tol) fprintf(stderr, "K %d h %g cell %d y %g trunc err %.3e\n", K, h, j, (double)y, (double)et);
 #endif
                 if (et > tol) { ok = false; break; }
             }
         }
         if (!ok) continue;
-        H.identity = 0;
-        H.ncell = ncell;
-        H.h = h;
-        H.inv_h = 1.0 / h;
-        H.y_max = ncell * h;
-        H.centre_offset = 0.5 * h;
-        out->coef = (double*)malloc(coef.size() * sizeof(double));
-        if (!out->coef) return fail(err, errlen, "out of memory");
-        memcpy(out->coef, coef.data(), coef.size() * sizeof(double));
-        out->max_rel_err = (double)worst;
+        c->h = h;
+        c->inv_h = 1.0 / h;
+        c->y_max = ncell * h;
+        c->y_lds = nlds * h;
+        c->centre_offset = 0.5 * h;
+        c->max_rel_err = (double)worst;
+        c->ncell = ncell;
+        c->nlds = nlds;
+        c->degree = K;
+        c->stride = stride;
+        c->coef_offset = coef.size();
+        coef.insert(coef.end(), rows.begin(), rows.end());
+        return true;
+    }
+    return false;
+}
+
+/* nu > NU_CF: one cell whose polynomial in d = y (centre 0) is the series of
+   Section 3.4 (A&S 26.7.5), covering every y,
+     t = z (1 + (y+1)/(4n) + (5y^2+16y+3)/(96n^2) + (3y^3+19y^2+17y-15)/(384n^3)
+            + (79y^4+776y^3+1482y^2-1920y-945)/(92160n^4)). */
+void cornish_fisher_cells(fq n, int K, std::vector<double>& coef, TCells* c)
+{
+    fq a[5];
+    a[0] = 1 + 1 / (4 * n) + 3 / (96 * n * n) - 15 / (384 * n * n * n) - 945 / (92160 * n * n * n * n);
+    a[1] = 1 / (4 * n) + 16 / (96 * n * n) + 17 / (384 * n * n * n) - 1920 / (92160 * n * n * n * n);
+    a[2] = 5 / (96 * n * n) + 19 / (384 * n * n * n) + 1482 / (92160 * n * n * n * n);
+    a[3] = 3 / (384 * n * n * n) + 776 / (92160 * n * n * n * n);
+    a[4] = 79 / (92160 * n * n * n * n);
+    c->h = 1e300;
+    c->inv_h = 0;
+    c->y_max = 1e300;
+    c->y_lds = 1e300;
+    c->centre_offset = 0;
+    c->max_rel_err = 0;
+    c->ncell = 1;
+    c->nlds = 1;
+    c->degree = K;
+    c->stride = K + 1;
+    c->coef_offset = coef.size();
+    std::vector<double> row(K + 1, 0.0);
+    for (int k = 0; k <= 4; ++k) row[K - k] = (double)a[k];   /* highest power first */
+    coef.insert(coef.end(), row.begin(), row.end());
+}
+
+}  // namespace
+
+int build_student_table(double nu_d, HostTTable* out, char* err, int errlen)
+{
+    memset(out, 0, sizeof *out);
+    if (!(nu_d >= 0.5)) return fail(err, errlen, "nu must be >= 0.5");
+    TTableHeader& H = out->hdr;
+    H.nu = nu_d;
+    if (std::isinf(nu_d)) {
+        H.identity = 1;
         return 0;
     }
-    return fail(err, errlen, "no cell width met the accuracy target");
+    const fq nu = nu_d;
+    const fq lbeta = lgamma_q(nu / 2) + lgamma_q(0.5Q) - lgamma_q(nu / 2 + 0.5Q);
+    H.log_K = (double)(logq(nu) + 0.5Q * logq(M_PIq) + lgamma_q(nu / 2) - lgamma_q((nu + 1) / 2));
+    /* two-term tail of Section 3.5: t = sqrt(nu) w^{-1/nu} (1 - (nu+1)/(2(nu+2)) w^{2/nu}) */
+    H.tail_a[0] = -(double)((nu + 1) / (2 * (nu + 2)));
+
+    std::vector<double> coef;
+    if (nu_d > NU_CF) {
+        cornish_fisher_cells(nu, T_DEGREE_F64, coef, &H.f64);
+        cornish_fisher_cells(nu, T_DEGREE_F32, coef, &H.f32);
+    } else {
+        /* Tolerances: FP64 outputs, truncation below 2e-17, so the rounded
+           coefficients (about an ulp of R) dominate; FP32 outputs, 1e-10.
+           The cells reach as far as the tail formula needs to meet the same
+           tolerance; those up to Y_LDS (at most 480 rows of 17 doubles, the
+           64 KB of LDS a launch may use) are the ones staged in LDS. */
+        const fq tol64 = 2e-17Q, tol32 = 1e-10Q;
+        /* the formula's truncation error, with its constants exact (their
+           rounding to FP64 is part of the device's evaluation error) */
+        const fq logK = logq(nu) + 0.5Q * logq(M_PIq) + lgamma_q(nu / 2) - lgamma_q((nu + 1) / 2);
+        const fq a = -(nu + 1) / (2 * (nu + 2));
+        const fq z64 = tail_formula_z(nu, lbeta, logK, a, tol64);
+        const fq z32 = tail_formula_z(nu, lbeta, logK, a, tol32);
+        const double y64 = (double)(z64 * z64), y32 = (double)(z32 * z32);
+        /* the solution must reach the last cell's upper edge (y rounded up by < 8) */
+        fq z_far = sqrtq((fq)(y64 > Y_LDS ? y64 : Y_LDS) + 8) + 0.25Q;
+        if (z_far < (fq)Z_FAR) z_far = Z_FAR;
+        Solution sol;
+        const fq gamma = sqrtq(nu / 2) * expq(lgamma_q(nu / 2) - lgamma_q((nu + 1) / 2));
+        if (!solve_rode(nu, lbeta, gamma, z_far, sol, err, errlen)) return -1;
+        if (!fit_cells(sol, gamma, T_DEGREE_F64, tol64, y64, 480, coef, &H.f64))
+            return fail(err, errlen, "no cell width met the FP64 accuracy target");
+        if (!fit_cells(sol, gamma, T_DEGREE_F32, tol32, y32, 720, coef, &H.f32))
+            return fail(err, errlen, "no cell width met the FP32 accuracy target");
+    }
+    out->coef = (double*)malloc(coef.size() * sizeof(double));
+    if (!out->coef) return fail(err, errlen, "out of memory");
+    memcpy(out->coef, coef.data(), coef.size() * sizeof(double));
+    out->ncoef = coef.size();
+    return 0;
 }
 
 void free_student_table(HostTTable* t)
@@ -384,31 +458,33 @@ extern "C" int qm_debug_student_dense(double nu_d, const double* z, double* q, i
 {
     using namespace qm;
     if (!(nu_d >= 0.5) || nu_d > NU_CF) return -1;
+    fq zmax = 0;
+    for (int i = 0; i < n; ++i) {
+        fq a = fabsq((fq)z[i]);
+        if (!(a <= (fq)Z_CAP)) return -1;
+        if (a > zmax) zmax = a;
+    }
     const fq nu = nu_d;
     const fq lbeta = lgamma_q(nu / 2) + lgamma_q(0.5Q) - lgamma_q(nu / 2 + 0.5Q);
-    Solution sol;
     const fq gamma = sqrtq(nu / 2) * expq(lgamma_q(nu / 2) - lgamma_q((nu + 1) / 2));
-    integrate(nu, 0, 0, gamma, Z_MATCH, sol.fwd);
-    const fq zf = Z_FAR;
-    const fq logq_far = logq(erfcq(zf / sqrtq(2)) / 2);
-    const fq Qf = anchor_value(nu, zf, lbeta, logq_far);
-    const fq dQf = expq(-zf * zf / 2) / sqrtq(2 * M_PIq) / expq(log_student_pdf(nu, Qf, lbeta));
-    integrate(nu, zf, Qf, dQf, Z_MATCH, sol.bwd);
+    fq z_far = zmax + 0.5Q;
+    if (z_far < (fq)Z_FAR) z_far = Z_FAR;
+    Solution sol;
+    char err[160];
+    if (!solve_rode(nu, lbeta, gamma, z_far, sol, err, sizeof err)) return -1;
     for (int i = 0; i < n; ++i) q[i] = (double)sol.eval(fabsq((fq)z[i])) * (z[i] < 0 ? -1 : 1);
     return 0;
 }
 
 /* Host copy of a table (include/qm_debug.h). */
-extern "C" int qm_debug_student_table(double nu, void* header_out, double* coef_out, int coef_cap,
-                                      double* max_rel_err)
+extern "C" int qm_debug_student_table(double nu, void* header_out, double* coef_out, int coef_cap)
 {
     qm::HostTTable t;
     char err[256];
     if (qm::build_student_table(nu, &t, err, sizeof err) != 0) return -1;
-    int need = t.hdr.ncell * t.hdr.stride;
+    int need = (int)t.ncoef;
     if (header_out) memcpy(header_out, &t.hdr, sizeof t.hdr);
     if (coef_out && coef_cap >= need && need > 0) memcpy(coef_out, t.coef, sizeof(double) * need);
-    if (max_rel_err) *max_rel_err = t.max_rel_err;
     qm::free_student_table(&t);
     return need;
 }

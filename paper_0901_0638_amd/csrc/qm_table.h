@@ -7,37 +7,60 @@
 
 namespace qm {
 
+/* Polynomial degrees per cell: FP64 outputs need R to about an ulp of FP64;
+   FP32 outputs are rounded once from an FP64 evaluation, so R to 1e-10
+   relative (far below the 6e-8 half-ulp of FP32) is enough and a lower
+   degree on narrower cells halves the table reads per element. */
+constexpr int T_DEGREE_F64 = 15;
+constexpr int T_DEGREE_F32 = 7;
+
 /*
- * Device-side table of the normal -> Student t map for one nu.
- *
- * For y = z^2 <= y_max the map is t = z R(y), with R evaluated per cell:
- * j = floor(y / h) (clamped to ncell - 1), R = sum_k c_{j,k} d^k with
- * d = y - (j h + centre_offset).  Coefficients are stored cell-major,
- * highest power first, with a row stride of `stride` doubles (>= degree + 1);
- * an FP32 copy of the same array follows at byte offset coef_f32_offset.
- * Beyond y_max the two-term tail t = sqrt(nu) w^{-1/nu} (1 + a w^{2/nu}),
- * w = K q(|z|) (Sections 3.3, 3.5), is used with log K and a = tail_a[0].
+ * One piecewise-polynomial approximation of R(y) = t(z)/z, y = z^2 <= y_max:
+ * cell j = floor(y / h) (clamped to ncell - 1) holds R = sum_k c_{j,k} d^k,
+ * d = y - (j h + centre_offset).  Rows are cell-major, highest power first,
+ * `stride` = degree + 1 doubles each, starting `coef_offset` doubles into
+ * the table's coefficient block.  The first nlds cells (y <= y_lds, about
+ * 100: every sample of a normal below 10 in magnitude) are the ones staged
+ * in LDS; the rest extend the table to where the two-term tail formula
+ * meets the same accuracy (at most y = 1600), read from global memory on
+ * the rare path.
+ */
+struct TCells {
+    double h;             /* cell width in y (a power of 2, so j h is exact) */
+    double inv_h;
+    double y_max;         /* = ncell * h; beyond it the far-tail formula */
+    double y_lds;         /* = nlds * h */
+    double centre_offset; /* cell centre = j h + centre_offset */
+    double max_rel_err;   /* builder's check of the rounded coefficients */
+    int32_t ncell;
+    int32_t nlds;
+    int32_t degree;
+    int32_t stride;
+    uint64_t coef_offset;
+};
+
+/*
+ * Device-side table of the normal -> Student t map for one nu: two cell
+ * approximations of the same map (FP64 outputs, FP32 outputs), and the
+ * two-term tail t = sqrt(nu) w^{-1/nu} (1 + a w^{2/nu}), w = K q(|z|)
+ * (Sections 3.3, 3.5), with log K and a = tail_a[0], used beyond y_max.
+ * On the device the header is followed by the coefficient block.
  */
 struct TTableHeader {
     double nu;
-    double h;           /* cell width in y = z^2 */
-    double inv_h;
-    double y_max;       /* = ncell * h */
-    double centre_offset; /* cell centre = j h + centre_offset */
-    double log_K;       /* log of n sqrt(pi) Gamma(n/2)/Gamma((n+1)/2) */
+    double log_K;       /* log of nu sqrt(pi) Gamma(nu/2)/Gamma((nu+1)/2) */
     double tail_a[4];   /* far-tail series t = sqrt(nu) w^{-1/nu} (1 + sum a_k w^{2k/nu}) */
-    int32_t ncell;
-    int32_t degree;
-    int32_t stride;
     int32_t identity;   /* nu = +inf: t = z */
-    uint64_t coef_f32_offset; /* bytes from the table start to the FP32 copy */
+    int32_t reserved;
+    TCells f64;         /* degree T_DEGREE_F64 */
+    TCells f32;         /* degree T_DEGREE_F32 */
 };
 
-/* Host-built table: header + ncell*stride coefficients (doubles). */
+/* Host-built table: header + coefficient block (doubles). */
 struct HostTTable {
     TTableHeader hdr;
     double* coef;       /* host copy, malloc'd */
-    double max_rel_err; /* builder's self-check against its own dense output */
+    uint64_t ncoef;     /* doubles in the block (both approximations) */
 };
 
 /* Build the table for nu on the host (qm_table.cpp). Returns 0 on success. */

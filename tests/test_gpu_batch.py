@@ -140,6 +140,8 @@ def test_serving_errors(ctx):
 
 
 def test_serving_shutdown_with_work_in_flight():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
     c = qm.Context(0, hbm_budget_bytes=64 << 20)
     xs = [torch.from_numpy(qi.uniform53(6, i, 1 << 20)).cuda() for i in range(16)]
     ys = [torch.empty_like(x) for x in xs]
@@ -149,3 +151,78 @@ def test_serving_shutdown_with_work_in_flight():
     c.close()                       # drains admitted work, fails the rest
     assert time.time() - t0 < 30
     torch.cuda.synchronize()
+
+
+ALL_COMBOS = [
+    (qm.QM_NORMAL_QUANTILE, np.float64, qm.QM_PLAIN), (qm.QM_NORMAL_QUANTILE, np.float64, qm.QM_PAPER),
+    (qm.QM_NORMAL_QUANTILE, np.float32, qm.QM_F32_REFINE), (qm.QM_NORMAL_QUANTILE, np.float32, qm.QM_PAPER),
+    (qm.QM_NORMAL_QUANTILE, np.float32, qm.QM_PLAIN), (qm.QM_EXP_TO_NORMAL, np.float64, qm.QM_PLAIN),
+    (qm.QM_EXP_TO_NORMAL, np.float64, qm.QM_PAPER), (qm.QM_EXP_TO_NORMAL, np.float32, qm.QM_F32_REFINE),
+    (qm.QM_STUDENT_T, np.float64, qm.QM_PLAIN), (qm.QM_STUDENT_T, np.float32, qm.QM_F32_REFINE),
+]
+
+
+def combo_input(kind, dtype, n, seed):
+    if kind == qm.QM_NORMAL_QUANTILE:
+        x = qi.mixture(seed, 0, n, dtype, 0.1, 1e-300 if dtype == np.float64 else 1e-37)
+    elif kind == qm.QM_EXP_TO_NORMAL:
+        x = qi.exponentials(seed, 1, n).astype(dtype)
+        x[::7] *= -1
+    else:
+        x = qi.normals(seed, 2, n).astype(dtype)
+    return np.ascontiguousarray(x)
+
+
+def test_batch_every_kind_dtype_mode_bitwise(ctx):
+    """One batch holding every supported (kind, dtype, mode), several nu and
+    ragged sizes: each output equals its single call bit for bit."""
+    rng = np.random.default_rng(17)
+    qreqs, cases = [], []
+    for c, (kind, dtype, mode) in enumerate(ALL_COMBOS):
+        for j, n in enumerate((1, 777, 32768 + 5, 70001)):
+            x = combo_input(kind, dtype, n, 40 + 4 * c + j)
+            d = torch.from_numpy(x).cuda()
+            o = torch.full_like(d, float("nan"))
+            nu = float(rng.choice([1.0, 2.5, 4.0, 17.0, float("inf")])) if kind == qm.QM_STUDENT_T else 0.0
+            qreqs.append(qm.qm_request(kind, qm.QM_F32 if dtype == np.float32 else qm.QM_F64, mode, 0, nu,
+                                       d.data_ptr(), o.data_ptr(), n, 0))
+            cases.append((kind, mode, nu, d, o))
+    qm.qm_run_batch(ctx, qreqs, device_tensor=cases[0][3])
+    torch.cuda.synchronize()
+    for kind, mode, nu, d, o in cases:
+        ref = single(ctx, kind, mode, nu, d)
+        torch.cuda.synchronize()
+        a, b = o.cpu().numpy(), ref.cpu().numpy()
+        assert np.array_equal(a.view(np.uint8), b.view(np.uint8)), (kind, mode, nu, a.size)
+
+
+def test_batch_full_size_mix_sampled(ctx):
+    """The 4096-request mix at its full size (sizes 2^10..2^22, about 2.1e9
+    elements, 27 GB), one persistent launch as the benchmark times it;
+    sampled outputs of every request against the oracle."""
+    reqs = qi.request_mix(3, 4096, 10, 22)
+    kinds = {"nq_f32_refine": (qm.QM_NORMAL_QUANTILE, qm.QM_F32, qm.QM_F32_REFINE),
+             "nq_f64": (qm.QM_NORMAL_QUANTILE, qm.QM_F64, qm.QM_PLAIN),
+             "student_f64": (qm.QM_STUDENT_T, qm.QM_F64, qm.QM_PLAIN),
+             "exp_f64": (qm.QM_EXP_TO_NORMAL, qm.QM_F64, qm.QM_PLAIN)}
+    ins, outs, qreqs = [], [], []
+    for r in reqs:
+        x = qi.request_input(3, r)
+        d = torch.from_numpy(x).cuda()
+        o = torch.empty_like(d)
+        kind, dt, mode = kinds[r["kind"]]
+        qreqs.append(qm.qm_request(kind, dt, mode, 0, r["nu"], d.data_ptr(), o.data_ptr(), x.size, 0))
+        ins.append(d)
+        outs.append(o)
+    qm.qm_run_batch(ctx, qreqs, device_tensor=ins[0])
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(23)
+    for r, d, o in zip(reqs, ins, outs):
+        idx = np.unique(rng.integers(0, d.numel(), 8))
+        ti = torch.from_numpy(idx).cuda()
+        x = d[ti].cpu().numpy()
+        got = o[ti].cpu().numpy()
+        rtol = RTOL_F32 if got.dtype == np.float32 else RTOL_F64
+        assert_close(got, oracle_of(r, x), rtol, str(r))
+    del ins, outs
+    torch.cuda.empty_cache()

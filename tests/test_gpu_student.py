@@ -90,24 +90,40 @@ def test_student_invalid_nu(ctx):
         assert e.value.status == qm.QM_E_INVAL
 
 
-def test_student_far_tail(ctx):
-    """|z| > 10 takes the two-term tail of Section 3.5, accurate to
-    O(w^{4/nu}), w = K q(|z|): below 1e-14 relative for nu <= 2 there."""
-    z = np.array([10.01, 10.5, 12.0, 15.0, 20.0, 30.0, -11.0])
-    for nu in (1, 2):
-        got = run_t(ctx, z, nu)
+@pytest.mark.parametrize("nu", [0.5, 1, 2, 4, 8, 10, 20, 30, 50, 80, 100, 1000, 1e5])
+def test_student_far_tail(ctx, nu):
+    """|z| > 10: the table's further cells (read from global memory) and,
+    beyond them, the two-term tail of Section 3.5, which the builder only
+    uses where it is as accurate as the cells; up to |z| = 38.5 (the normal
+    quantile of the smallest double) that holds for every nu.  Both output
+    precisions, and a wave mixing far and table elements."""
+    rng = np.random.default_rng(int(nu) + 5)
+    far = np.concatenate([np.linspace(10.0, 38.5, 229), -rng.uniform(10.0, 38.5, 64),
+                          [10.000000001, 10.198039027185569, 10.198039027185571, 12.0, 12.000000001]])
+    mixed = np.concatenate([rng.normal(size=192), far[:64]])     # one far lane per four
+    for z in (far, mixed):
         ref = oracle.student_t_map(z, nu)
-        fin = np.isfinite(ref)
-        assert np.all(np.abs(got[fin] / ref[fin] - 1) < 1e-14), (nu, got, ref)
-        assert np.all(got[~fin] == ref[~fin])
-    # large nu: the formula's own error, bounded by 10 w^{4/nu}
+        assert_close(run_t(ctx, z, nu), ref, RTOL_F64, "far f64 nu=%s" % nu)
+        z32 = z.astype(np.float32)
+        ref32 = oracle.student_t_map(z32.astype(np.float64), nu)
+        assert_close(run_t(ctx, z32, nu), ref32, RTOL_F32, "far f32 nu=%s" % nu)
+
+
+def test_student_beyond_cells_formula_bound(ctx):
+    """|z| > 40 (no normal quantile of a double lies there): the two-term
+    formula alone, within its own O(w^{4/nu}) error, w = K q(|z|)."""
     import math
-    for nu in (4, 30):
+    z = np.array([40.5, 45.0, 60.0, -50.0, 100.0])
+    for nu in (4, 30, 100):
         got = run_t(ctx, z, nu)
         ref = oracle.student_t_map(z, nu)
         lK = math.log(nu) + 0.5 * math.log(math.pi) + math.lgamma(nu / 2) - math.lgamma((nu + 1) / 2)
         for zi, g, r in zip(z, got, ref):
-            lw = lK + math.log(0.5 * math.erfc(abs(zi) / math.sqrt(2)))
+            if np.isinf(r):
+                assert g == r, (nu, zi, g)
+                continue
+            lw = lK + math.log(0.5) + math.log(math.erfc(abs(zi) / math.sqrt(2))) if abs(zi) < 26 else \
+                lK - zi * zi / 2 - math.log(abs(zi) * math.sqrt(2 * math.pi))
             assert abs(g / r - 1) <= 10 * math.exp(4 * lw / nu) + 1e-14, (nu, zi, g, r)
 
 
@@ -117,6 +133,43 @@ def test_student_f32_refine(ctx, normals, nu):
     got = run_t(ctx, z, nu)
     ref = oracle.student_t_map(z.astype(np.float64), nu)
     assert_close(got, ref, RTOL_F32, "f32 nu=%s" % nu)
+
+
+@pytest.mark.parametrize("nu", [0.5, 0.75, 1.5, 2.5, 7.5, 50, 1000, 2e5, float("inf")])
+def test_student_f32_refine_other_nu(ctx, nu):
+    """FP32 outputs from the degree-7 cells: bulk, the whole table range, and
+    the far tail (|z| > 10) including the largest finite floats."""
+    rng = np.random.default_rng(7 + int(min(nu, 1e6) * 4))
+    z = np.concatenate([rng.normal(size=20000), rng.uniform(-10.5, 10.5, 20000),
+                        rng.uniform(10, 38, 2000) * rng.choice([-1, 1], 2000)]).astype(np.float32)
+    ref = oracle.student_t_map(z.astype(np.float64), nu)
+    assert_close(run_t(ctx, z, nu), ref, RTOL_F32, "f32 nu=%s" % nu)
+
+
+def test_student_f32_edges(ctx):
+    z = np.array([0.0, -0.0, 1e-45, -1e-45, 1e-38, 1e-8, np.nan, np.inf, -np.inf, 9.999999, -10.0, 10.000001,
+                  0.5, 2.0, 7.999999, 8.0, 8.000001, 3.4e38, -3.4e38], dtype=np.float32)
+    for nu in (0.5, 1, 4, 30):
+        got = run_t(ctx, z, nu)
+        ref = oracle.student_t_map(z.astype(np.float64), nu)
+        assert_close(got, ref, RTOL_F32, "f32 edges nu=%s" % nu)
+        assert np.signbit(got[1]) and np.signbit(got[3])
+
+
+@pytest.mark.parametrize("nu", [1, 4, 30])
+def test_student_f32_correctly_rounded(ctx, normals, nu):
+    """R is accurate to 1e-10, so the FP32 output is the oracle value rounded
+    to nearest except where that value lies within 1e-9 (relative) of a
+    midpoint between two floats."""
+    z = normals.astype(np.float32)
+    got = run_t(ctx, z, nu)
+    ref = oracle.student_t_map(z.astype(np.float64), nu)
+    r32 = ref.astype(np.float32)
+    other = np.nextafter(r32, np.where(ref > r32, np.float32(np.inf), np.float32(-np.inf)))
+    mid = (r32.astype(np.float64) + other.astype(np.float64)) / 2
+    near_mid = np.abs(ref - mid) <= 1e-9 * np.abs(ref)
+    bad = (got != r32) & ~near_mid & np.isfinite(ref)
+    assert not bad.any(), (nu, int(bad.sum()), z[bad][:5], got[bad][:5], r32[bad][:5])
 
 
 def test_student_full_size_sampled(ctx):
