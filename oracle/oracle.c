@@ -204,10 +204,34 @@ double oracle_exp_to_normal1(double x)
 /*   F_nu(t) - 1/2 = I_{t^2/(nu+t^2)}(1/2, nu/2) / 2.                          */
 /* I_x(a,b) is evaluated from its continued fraction (DLMF 8.17.22) with the */
 /* modified Lentz method where x < (a+1)/(a+b+2), else through the symmetry  */
-/* I_x(a,b) = 1 - I_{1-x}(b,a) (DLMF 8.17.4).  Both x and 1-x are passed in  */
-/* so that neither is formed by cancellation.                                */
+/* I_x(a,b) = 1 - I_{1-x}(b,a) (DLMF 8.17.4).  Both x and 1-x, and their     */
+/* logarithms, are passed in so that none is formed by cancellation: with    */
+/* x = nu/(nu+t^2), log x = -log1p(t^2/nu), since the prefactor raises x to  */
+/* the power nu/2 and would multiply a rounding of x by nu/2.                */
 /* ------------------------------------------------------------------------- */
 static ld lbeta(ld a, ld b) { return lgammal(a) + lgammal(b) - lgammal(a + b); }
+
+/*
+ * log B(a, 1/2) = log Gamma(1/2) - D(a), D(a) = log Gamma(a+1/2) - log Gamma(a).
+ * For large a the difference of two lgamma values near a log a would lose
+ * its last digits times a log a; instead a = r + k with r in [1, 2) and, by
+ * Gamma(x+1) = x Gamma(x) (DLMF 5.5.1),
+ *   D(a) = D(r) + sum_{j<k} log(1 + 1/(2(r+j))),
+ * summed with compensation (Kahan).
+ */
+static ld lbeta_half(ld a)
+{
+    if (a < 16.0L) return lbeta(a, 0.5L);
+    ld k = floorl(a) - 1.0L, r = a - k;
+    ld sum = lgammal(r + 0.5L) - lgammal(r), comp = 0.0L;
+    for (ld j = 0.0L; j < k; j += 1.0L) {
+        ld term = log1pl(0.5L / (r + j)) - comp;
+        ld t = sum + term;
+        comp = (t - sum) - term;
+        sum = t;
+    }
+    return lgammal(0.5L) - sum;
+}
 
 /* K = 1 + d1/(1 + d2/(1 + ...)), so that I_x(a,b) = prefactor / K. */
 static ld beta_cf(ld a, ld b, ld x)
@@ -231,43 +255,47 @@ static ld beta_cf(ld a, ld b, ld x)
     return f;
 }
 
-/* x^a (1-x)^b / (a B(a,b)), with log B supplied by the caller */
-static ld beta_prefactor(ld a, ld b, ld x, ld omx, ld lb)
+/* x^a (1-x)^b / (a B(a,b)) from lx = log x, lomx = log(1-x), lb = log B */
+static ld beta_prefactor(ld a, ld b, ld lx, ld lomx, ld lb)
 {
-    return expl(a * logl(x) + b * logl(omx) - lb) / a;
+    return expl(a * lx + b * lomx - lb) / a;
 }
 
-/* I_x(a,b) with omx = 1 - x; lbab = log B(a,b) (symmetric in a,b). */
-static ld betainc_reg(ld a, ld b, ld x, ld omx, ld lbab)
+/* I_x(a,b) with omx = 1 - x, lx = log x, lomx = log(1-x); lbab = log B(a,b)
+   (symmetric in a,b). */
+static ld betainc_reg(ld a, ld b, ld x, ld omx, ld lx, ld lomx, ld lbab)
 {
     if (x <= 0.0L) return 0.0L;
     if (omx <= 0.0L) return 1.0L;
     if (x < (a + 1.0L) / (a + b + 2.0L))
-        return beta_prefactor(a, b, x, omx, lbab) / beta_cf(a, b, x);
-    return 1.0L - beta_prefactor(b, a, omx, x, lbab) / beta_cf(b, a, omx);
+        return beta_prefactor(a, b, lx, lomx, lbab) / beta_cf(a, b, x);
+    return 1.0L - beta_prefactor(b, a, lomx, lx, lbab) / beta_cf(b, a, omx);
 }
 
 double oracle_betainc(double a, double b, double x)
 {
     if (!(a > 0) || !(b > 0) || !(x >= 0) || !(x <= 1)) return NAN;
-    return (double)betainc_reg(a, b, x, 1.0L - (ld)x, lbeta(a, b));
+    return (double)betainc_reg(a, b, x, 1.0L - (ld)x, logl(x), log1pl(-(ld)x), lbeta(a, b));
 }
 
 /* 1 - F_nu(t) for t >= 0, and F_nu(t) - 1/2 for t >= 0 */
 typedef struct { ld nu, lb; } tctx;
 
+/* with s = t^2/nu: log(nu/(nu+t^2)) = -log1p(s), log(t^2/(nu+t^2)) = -log1p(1/s) */
 static ld t_upper(const tctx* c, ld t)
 {
     ld t2 = t * t;
     ld x = c->nu / (c->nu + t2), omx = t2 / (c->nu + t2);
-    return 0.5L * betainc_reg(0.5L * c->nu, 0.5L, x, omx, c->lb);
+    ld lx = -log1pl(t2 / c->nu), lomx = -log1pl(c->nu / t2);
+    return 0.5L * betainc_reg(0.5L * c->nu, 0.5L, x, omx, lx, lomx, c->lb);
 }
 
 static ld t_central(const tctx* c, ld t)
 {
     ld t2 = t * t;
     ld y = t2 / (c->nu + t2), omy = c->nu / (c->nu + t2);
-    return 0.5L * betainc_reg(0.5L, 0.5L * c->nu, y, omy, c->lb);
+    ld ly = -log1pl(c->nu / t2), lomy = -log1pl(t2 / c->nu);
+    return 0.5L * betainc_reg(0.5L, 0.5L * c->nu, y, omy, ly, lomy, c->lb);
 }
 
 static uint64_t dbits(double d) { uint64_t b; memcpy(&b, &d, 8); return b; }
@@ -307,7 +335,7 @@ double oracle_student_t_map1(double z, double nu)
 {
     if (isnan(nu) || !(nu > 0.0)) return NAN;
     if (isinf(nu)) return z;
-    tctx c = { (ld)nu, lbeta(0.5L * (ld)nu, 0.5L) };
+    tctx c = { (ld)nu, lbeta_half(0.5L * (ld)nu) };
     return student_map1(&c, z);
 }
 
@@ -334,7 +362,7 @@ static void* run_job(void* p)
             for (size_t i = j->begin; i < j->end; ++i) j->out[i] = j->in[i];
             return NULL;
         }
-        tctx c = { (ld)j->nu, lbeta(0.5L * (ld)j->nu, 0.5L) };
+        tctx c = { (ld)j->nu, lbeta_half(0.5L * (ld)j->nu) };
         for (size_t i = j->begin; i < j->end; ++i) j->out[i] = student_map1(&c, j->in[i]);
         return NULL;
     }

@@ -288,6 +288,26 @@ def test_student_vs_mpmath_betainc_root(nu):
             assert abs(T / r - 1) <= 1.2e-16, (nu, zi, ti)
 
 
+@pytest.mark.parametrize("nu", [1e3, 1e4, 1e5])
+def test_student_large_nu_vs_mpmath_betainc_root(nu):
+    """Large nu: the prefactor of I_x(nu/2, 1/2) raises x to the power nu/2
+    and log B(nu/2, 1/2) is a difference of two lgamma values near
+    (nu/2) log(nu/2), so both must be formed without cancellation; checked
+    against mpmath roots at 40 digits, both sides of the central/tail switch.
+    Within one ulp (the long continued fraction's residual decides the last
+    bit, not always the nearer neighbour)."""
+    z = np.array([1e-3, 0.33, 0.67, 0.7, 1.0, 1.7, 3.0, 7.5, 10.0, 25.0, 38.0])
+    t = oracle.student_t_map(z, nu)
+    a = mp.mpf(nu) / 2
+    with mp.workdps(40):
+        for zi, ti in zip(z, t):
+            q = mp.erfc(mp.mpf(zi) / mp.sqrt(2)) / 2
+            f = lambda tt: mp.betainc(a, mp.mpf(1) / 2, 0, nu / (nu + tt ** 2), regularized=True) / 2 - q
+            T = mp.mpf(ti)
+            r = mp.findroot(f, (T * (1 - mp.mpf("1e-10")), T * (1 + mp.mpf("1e-10"))), solver="illinois")
+            assert abs(T / r - 1) <= 2.3e-16, (nu, zi, ti)
+
+
 def _paper_t4_series():
     """Printed coefficients; convert inside a workdps block for full digits."""
     return [mp.mpf(c[0]) for c in _golden.keyed("paper_t4_series.txt")["c"]]
@@ -368,14 +388,17 @@ def test_student_tail_formula(nu, z0):
 
 def test_student_large_nu_cornish_fisher():
     """Section 3.4 (A&S 26.7.5): t = z + (z^3+z)/(4n) + ... to 1/n^4; at
-    n = 2000 the truncation is O(n^-5)."""
-    n = 2000.0
-    for z in (0.3, 1.0, 2.0):
-        t = oracle.student_t_map([z], n)[0]
-        cf = (z + (z ** 3 + z) / (4 * n) + (5 * z ** 5 + 16 * z ** 3 + 3 * z) / (96 * n ** 2)
-              + (3 * z ** 7 + 19 * z ** 5 + 17 * z ** 3 - 15 * z) / (384 * n ** 3)
-              + (79 * z ** 9 + 776 * z ** 7 + 1482 * z ** 5 - 1920 * z ** 3 - 945 * z) / (92160 * n ** 4))
-        assert abs(t / cf - 1) < 2e-15, (z, t, cf)
+    n = 2000 the truncation is O(n^-5) (below 2e-15 for |z| <= 2), at
+    n = 2e5 below the rounding."""
+    for n, tol in ((2000.0, 2e-15), (2e5, 3.4e-16)):
+        for z in (0.3, 1.0, 2.0, 5.0):
+            if n == 2000.0 and z > 2:
+                continue
+            t = oracle.student_t_map([z], n)[0]
+            cf = (z + (z ** 3 + z) / (4 * n) + (5 * z ** 5 + 16 * z ** 3 + 3 * z) / (96 * n ** 2)
+                  + (3 * z ** 7 + 19 * z ** 5 + 17 * z ** 3 - 15 * z) / (384 * n ** 3)
+                  + (79 * z ** 9 + 776 * z ** 7 + 1482 * z ** 5 - 1920 * z ** 3 - 945 * z) / (92160 * n ** 4))
+            assert abs(t / cf - 1) < tol, (n, z, t, cf)
 
 
 def test_student_odd_and_specials():
