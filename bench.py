@@ -186,6 +186,20 @@ def run_quantile(args, torch, qm, qi):
             avg = sum(ds) / len(ds)
             extra["student_t_f32_refine"][str(nu)] = {"gsamples_s": round(m / (avg * 1e-3) / 1e9, 2),
                                                       "gbs": round(8.0 * m / (avg * 1e-3) / 1e9, 1)}
+        # fused Philox generation + quantile (write-only), vs generation alone
+        g64 = torch.empty(n, dtype=torch.float64, device="cuda")
+        g32 = torch.empty(n, dtype=torch.float32, device="cuda")
+        fused = {"n": n}
+        for name, buf, kind in (("uniform_f64", g64, qm.QM_UNIFORM), ("quantile_f64", g64, qm.QM_NORMAL_QUANTILE),
+                                ("uniform_f32", g32, qm.QM_UNIFORM),
+                                ("quantile_f32_refine", g32, qm.QM_NORMAL_QUANTILE)):
+            ds = timed_launches(torch, stream, lambda buf=buf, kind=kind: qm.qm_generate(ctx, 1, 0, 0, buf, kind), 10)
+            avg = sum(ds) / len(ds)
+            fused[name] = {"gsamples_s": round(n / (avg * 1e-3) / 1e9, 2),
+                           "gbs": round(buf.element_size() * n / (avg * 1e-3) / 1e9, 1),
+                           "p50_ms": percentile(ds, 50), "p99_ms": percentile(ds, 99)}
+        extra["generate_fused"] = fused
+        del g64, g32
         result["extra"] = extra
         del z, x, o, z32, o32
         torch.cuda.empty_cache()

@@ -10,6 +10,8 @@
  *                                                         (Section 6)
  *   qm_recycle_student_t      t = F_nu^{-1}(Phi(z))       (Section 1 recycling
  *                                composite, Section 3 recycling ODE)
+ *   qm_generate               the uniforms of a counter-based stream, or w
+ *                             of them, drawn and mapped in one pass
  *   qm_run_batch              many such requests in one persistent launch
  *   qm_submit / qm_poll       continuous-batching serving loop
  *
@@ -59,8 +61,9 @@ enum qm_dtype { QM_F32 = 0, QM_F64 = 1 };
  *                  whole double range.  F32: the FP64 evaluation rounded to
  *                  float.
  *   QM_F32_REFINE  dtype QM_F32 only: FP32 rational seed plus one FP64
- *                  correction step against an FP64 erfc; relative error within
- *                  2e-7 (absolute 2e-10 near 0).
+ *                  correction step against an FP64 erf (|u - 1/2| <= 0.45)
+ *                  or erfc (beyond); relative error within 2e-7 (absolute
+ *                  2e-10 near 0).
  *   QM_PAPER       the paper's constants verbatim, valid only on the paper's
  *                  domain: F64 the (13,13) rational of Section 7.2 / Appendix
  *                  B (v <= 42, u >= 2.875e-19), F32 the (5,6) rational of
@@ -69,7 +72,8 @@ enum qm_dtype { QM_F32 = 0, QM_F64 = 1 };
  */
 enum qm_mode { QM_PLAIN = 0, QM_F32_REFINE = 1, QM_PAPER = 2 };
 
-enum qm_kind { QM_NORMAL_QUANTILE = 0, QM_STUDENT_T = 1, QM_EXP_TO_NORMAL = 2 };
+/* QM_UNIFORM (the uniforms themselves) is accepted by qm_generate only. */
+enum qm_kind { QM_NORMAL_QUANTILE = 0, QM_STUDENT_T = 1, QM_EXP_TO_NORMAL = 2, QM_UNIFORM = 3 };
 
 typedef struct qm_ctx qm_ctx;
 
@@ -80,7 +84,9 @@ typedef struct qm_ctx qm_ctx;
  * The context owns the per-nu Student t tables and the serving state.
  * The streaming kernels' launch shape (workgroups of 256 per compute unit,
  * default 32; 16-byte vectors in flight per lane, 1, 2 or 4, default 2) is
- * read here from the environment variables QM_BLOCKS_PER_CU and QM_UNROLL.
+ * read here from the environment variables QM_BLOCKS_PER_CU and QM_UNROLL;
+ * QM_COMPACT=0 turns off the FP64 quantile's gathering of non-central lanes
+ * across the wave (the results are bitwise the same either way).
  * Errors: QM_E_INVAL (out == NULL or no such device), QM_E_HIP, QM_E_NOMEM.
  */
 qm_status qm_init(int hip_device, uint64_t hbm_budget_bytes, qm_ctx** out);
@@ -93,9 +99,13 @@ qm_status qm_init(int hip_device, uint64_t hbm_budget_bytes, qm_ctx** out);
 void qm_shutdown(qm_ctx* ctx);
 
 /*
- * w[i] = Phi^{-1}(u[i]) (Section 1, eq. 1), evaluated through the paper's
- * exponential change of variable v = -log(2 min(u, 1-u)) and a rational in v
- * (Section 7.2), with a fitted rational in sqrt(v) for 42 < v (beyond the
+ * w[i] = Phi^{-1}(u[i]) (Section 1, eq. 1).  QM_PAPER: the paper's
+ * exponential change of variable v = -log(2 min(u, 1-u)) and its rational
+ * in v (Section 7.2) for every u.  QM_PLAIN and QM_F32_REFINE: the hybrid of
+ * Section 7.3 / Appendix C -- a central piece for |u - 1/2| <= 0.45 (a
+ * fitted rational in 0.2025 - (u - 1/2)^2, no logarithm; in place of the
+ * paper's T2 intermediate variable), and the exponential-coordinate path
+ * elsewhere, with a fitted rational in sqrt(v) for 42 < v (beyond the
  * paper's domain, Section 4.3).  u = 0 -> -inf, u = 1 -> +inf, u outside
  * [0,1] or NaN -> NaN, u = 1/2 -> +0.
  * dtype/mode: F64 {PLAIN, PAPER}; F32 {PLAIN, F32_REFINE, PAPER}.
@@ -110,10 +120,13 @@ qm_status qm_normal_quantile(qm_ctx* ctx, const void* d_u, void* d_w, uint64_t n
  * the solution of the Gaussian-background recycling ODE (Section 3.1) with
  * centre conditions Q(0) = 0, Q'(0) = gamma (Section 3.1); the library
  * integrates it on the host once per nu (cached in the context) and
- * evaluates piecewise polynomials on the device.  Accuracy: relative 2e-15
- * for |z| <= 9 (every normal drawn from a 53-bit uniform); beyond, the
- * tail form of Section 3.3 with reduced but bounded accuracy.  z = +-inf ->
- * +-inf, NaN -> NaN, and t may overflow to +-inf for small nu.
+ * evaluates piecewise polynomials on the device (degree 15 for F64,
+ * degree 7 for F32 outputs).  Accuracy: relative 2e-15 (F64) / 2e-7 (F32)
+ * for |z| <= 40, which holds the normal quantile of every positive double;
+ * the two-term tail of Sections 3.3/3.5 takes over only where it is as
+ * accurate, and beyond |z| = 40 for every nu, with error O(w^{4/nu}),
+ * w = K q(|z|).  z = +-inf -> +-inf, NaN -> NaN, and t may overflow to
+ * +-inf for small nu.
  * dtype/mode: F64 PLAIN; F32 F32_REFINE.
  * Errors: QM_E_INVAL for nu < 0.5, NaN or -inf.
  */
@@ -131,6 +144,27 @@ qm_status qm_recycle_student_t(qm_ctx* ctx, const void* d_z, void* d_t, uint64_t
  */
 qm_status qm_recycle_exp_to_normal(qm_ctx* ctx, const void* d_x, void* d_z, uint64_t n,
                                    int dtype, int mode, void* hip_stream);
+
+/*
+ * Fused generation and transform.  Draws the open uniforms of elements
+ * first .. first+n-1 of the counter-based stream Philox4x32-10 (Salmon et
+ * al., SC'11) with key (seed, stream), maps them, and writes only the
+ * results to d_out (n elements of dtype).  Element e of the stream:
+ *   F64: block e/2 (counter (e/2 mod 2^32, e/2 div 2^32, 0, 0)); the 64-bit
+ *        value of words (0,1) for even e, (2,3) for odd e (low word
+ *        first); its top 53 bits k give u = (k + 1/2) 2^-53.
+ *   F32: word e mod 4 of block e/4; its top 24 bits k give
+ *        u = (k + 1/2) 2^-24.
+ * kind QM_UNIFORM writes u (mode QM_PLAIN); kind QM_NORMAL_QUANTILE writes
+ * Phi^{-1}(u), bitwise equal to qm_normal_quantile of the same u, with the
+ * dtype/mode pairs of qm_normal_quantile.  Any sub-range of a stream can be
+ * generated independently; the results do not depend on the launch.
+ * Errors: QM_E_INVAL for seed or stream >= 2^32, first + n beyond 2^63, a
+ * NULL d_out (n > 0), an unaligned d_out or another kind; QM_E_DTYPE for a
+ * mode the dtype does not offer.
+ */
+qm_status qm_generate(qm_ctx* ctx, uint64_t seed, uint64_t stream, uint64_t first, void* d_out, uint64_t n,
+                      int kind, int dtype, int mode, void* hip_stream);
 
 /* One request of a batch or of the serving loop. */
 typedef struct {

@@ -233,12 +233,20 @@ static ld lbeta_half(ld a)
     return lgammal(0.5L) - sum;
 }
 
-/* K = 1 + d1/(1 + d2/(1 + ...)), so that I_x(a,b) = prefactor / K. */
-static ld beta_cf(ld a, ld b, ld x)
+/*
+ * K = 1 + d1/(1 + d2/(1 + ...)), so that I_x(a,b) = prefactor / K, with the
+ * partial numerators d_j of DLMF 8.17.22.  For large a near the switch point
+ * d1 = -(a+b)x/(a+1) is close to -1 and K ~ 1/a: forming 1 + d1/T (T the
+ * rest of the fraction) would lose the digits of K.  So c1 = 1 + d1 =
+ * ((a+1)(1-x) + (1-b)x)/(a+1) is formed directly from 1-x, the rest
+ * R = T - 1 = d2/(1 + d3/(1 + ...)) by the modified Lentz method, and
+ * K = (c1 + R)/(1 + R).
+ */
+static ld beta_cf(ld a, ld b, ld x, ld omx)
 {
     const ld tiny = 1e-4000L, eps = 1e-21L;
-    ld f = 1.0L, C = 1.0L, D = 0.0L;
-    for (int j = 1; j < 20000; ++j) {
+    ld f = tiny, C = tiny, D = 0.0L;
+    for (int j = 2; j < 40000; ++j) {
         int m = j / 2;
         ld dj;
         if (j & 1) dj = -(a + m) * (a + b + m) * x / ((a + 2 * m) * (a + 2 * m + 1));
@@ -252,7 +260,8 @@ static ld beta_cf(ld a, ld b, ld x)
         f *= delta;
         if (fabsl(delta - 1.0L) < eps) break;
     }
-    return f;
+    ld c1 = ((a + 1.0L) * omx + (1.0L - b) * x) / (a + 1.0L);
+    return (c1 + f) / (1.0L + f);
 }
 
 /* x^a (1-x)^b / (a B(a,b)) from lx = log x, lomx = log(1-x), lb = log B */
@@ -268,8 +277,8 @@ static ld betainc_reg(ld a, ld b, ld x, ld omx, ld lx, ld lomx, ld lbab)
     if (x <= 0.0L) return 0.0L;
     if (omx <= 0.0L) return 1.0L;
     if (x < (a + 1.0L) / (a + b + 2.0L))
-        return beta_prefactor(a, b, lx, lomx, lbab) / beta_cf(a, b, x);
-    return 1.0L - beta_prefactor(b, a, lomx, lx, lbab) / beta_cf(b, a, omx);
+        return beta_prefactor(a, b, lx, lomx, lbab) / beta_cf(a, b, x, omx);
+    return 1.0L - beta_prefactor(b, a, lomx, lx, lbab) / beta_cf(b, a, omx, x);
 }
 
 double oracle_betainc(double a, double b, double x)

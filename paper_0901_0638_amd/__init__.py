@@ -8,12 +8,13 @@ step of the maps runs in the library's HIP kernels.
     qm_normal_quantile(ctx, u, w)                 # w = Phi^{-1}(u)
     qm_recycle_student_t(ctx, z, t, nu=4.0)       # t = F_nu^{-1}(Phi(z))
     qm_recycle_exp_to_normal(ctx, x, z)           # z = sign(x) Phi^{-1}(1 - e^{-|x|}/2)
+    qm_generate(ctx, seed, stream, first, w, QM_NORMAL_QUANTILE)   # w = Phi^{-1}(Philox uniforms)
 """
 import ctypes
 
 from ._lib import (  # noqa: F401
     QM_E_CLOSED, QM_E_DTYPE, QM_E_HIP, QM_E_INVAL, QM_E_NOMEM, QM_E_TICKET, QM_EXP_TO_NORMAL, QM_F32,
-    QM_F32_REFINE, QM_F64, QM_NORMAL_QUANTILE, QM_OK, QM_PAPER, QM_PENDING, QM_PLAIN, QM_STUDENT_T, QMError,
+    QM_F32_REFINE, QM_F64, QM_NORMAL_QUANTILE, QM_OK, QM_PAPER, QM_PENDING, QM_PLAIN, QM_STUDENT_T, QM_UNIFORM, QMError,
     check, load, qm_request,
 )
 
@@ -82,6 +83,19 @@ def qm_normal_quantile(ctx, u, w, mode=QM_PLAIN, stream=None):
     """w = Phi^{-1}(u) on the device (FP64: PLAIN/PAPER; FP32: PLAIN/F32_REFINE/PAPER)."""
     pi, po, n, dt = _io(u, w)
     check(load().qm_normal_quantile(ctx.handle, pi, po, n, dt, mode, _stream(stream, u)))
+
+
+def qm_generate(ctx, seed, stream_id, first, out, kind=QM_NORMAL_QUANTILE, mode=None, stream=None):
+    """out[i] = map of the open uniform of element first + i of the Philox4x32-10
+    stream with key (seed, stream_id): kind QM_UNIFORM (u itself) or
+    QM_NORMAL_QUANTILE (Phi^{-1}(u); FP64 PLAIN/PAPER, FP32 F32_REFINE/PLAIN/PAPER)."""
+    if out.device.type != "cuda" or not out.is_contiguous():
+        raise ValueError("output must be a contiguous tensor on a HIP device")
+    dt = _dtype_of(out)
+    if mode is None:
+        mode = QM_F32_REFINE if (dt == QM_F32 and kind == QM_NORMAL_QUANTILE) else QM_PLAIN
+    check(load().qm_generate(ctx.handle, int(seed), int(stream_id), int(first), ctypes.c_void_p(out.data_ptr()),
+                             out.numel(), int(kind), dt, int(mode), _stream(stream, out)))
 
 
 def qm_recycle_student_t(ctx, z, t, nu, mode=None, stream=None):

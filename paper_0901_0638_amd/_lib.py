@@ -30,6 +30,7 @@ QM_PAPER = 2
 QM_NORMAL_QUANTILE = 0
 QM_STUDENT_T = 1
 QM_EXP_TO_NORMAL = 2
+QM_UNIFORM = 3
 
 
 class qm_request(ctypes.Structure):
@@ -55,6 +56,7 @@ SIGNATURES = {
     "qm_normal_quantile": (_st, [_vp, _vp, _vp, _u64, _i, _i, _vp]),
     "qm_recycle_student_t": (_st, [_vp, _vp, _vp, _u64, _i, _i, _d, _vp]),
     "qm_recycle_exp_to_normal": (_st, [_vp, _vp, _vp, _u64, _i, _i, _vp]),
+    "qm_generate": (_st, [_vp, _u64, _u64, _u64, _vp, _u64, _i, _i, _i, _vp]),
     "qm_run_batch": (_st, [_vp, ctypes.POINTER(qm_request), _u64, _vp]),
     "qm_submit": (_st, [_vp, ctypes.POINTER(qm_request), ctypes.POINTER(_u64)]),
     "qm_poll": (_st, [_vp, _u64]),

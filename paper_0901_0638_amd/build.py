@@ -23,7 +23,7 @@ HIP_FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function", "-I", os.path.join(ROOT, "include"),
 ]
-HIP_SOURCES = ["qm_kernels.hip", "qm_student.hip", "qm_batch.hip", "qm_api.cpp", "qm_serve.cpp"]
+HIP_SOURCES = ["qm_kernels.hip", "qm_student.hip", "qm_batch.hip", "qm_generate.hip", "qm_api.cpp", "qm_serve.cpp"]
 CXX_SOURCES = ["qm_table.cpp"]
 
 

@@ -3,7 +3,7 @@
 
 Run from the repository root:  python paper_0901_0638_amd/csrc/fit_coefficients.py
 
-Three approximations are fitted here, the rest are the paper's constants:
+These approximations are fitted here, the rest are the paper's constants:
 
   * Deep-tail piece of the exponential-coordinate normal quantile.  The
     paper's branchless FP64 rational Q(v) = v p13(v)/q13(v) (Section 7.2,
@@ -17,6 +17,16 @@ Three approximations are fitted here, the rest are the paper's constants:
   * Mills ratio M(x) = (1 - Phi(x))/phi(x) on [0, 14.5] as P6(x)/Q7(x), the
     only non-trivial part of the FP64 erfc used by that correction step
     (erfc(x/sqrt2) = 2 phi(x) M(x)).
+  * Central piece of the FP64 quantile (the hybrid of Section 7.3 /
+    Appendix C, with a log-free central variable): for |q| <= 0.45,
+    q = u - 1/2, Phi^{-1}(u) = q P8(r)/Q8(r), r = 0.2025 - q^2.  All
+    coefficients come out positive in r, so their FP64 rounding costs about
+    an ulp.  Outside, the exponential-coordinate path above.
+  * Central piece of the FP32+refine form, |q| <= 0.45: an FP32 seed
+    q S2(r)/S3(r) (2.6e-6), then one FP64 Newton step against
+    Phi(z) - u = erf(z/sqrt2)/2 - q with erf(z/sqrt2)/(2z) = E8(z^2) and
+    1/phi(z) = G5(z^2), polynomials good to 1.1e-11 and 4.2e-6 on
+    |z| <= 1.646.
   * The FP64 logarithm of the change of variable v = -log(2 min(u,1-u)):
     log m = 2 atanh f = 2f + f s R6(s), f = (m-1)/(m+1), s = f^2, for the
     reduced argument m in [sqrt(1/2), sqrt(2)] (so s <= 0.0294).
@@ -28,6 +38,7 @@ The coefficients are then rounded to FP64 and the error of the rounded
 rational is measured exactly on a dense grid and written into the header.
 """
 import os
+import struct
 import sys
 
 import mpmath as mp
@@ -126,6 +137,30 @@ def fit_log_poly(deg):
     return coef, worst
 
 
+def fit_poly(fun, a, b, deg, nodes=200, rounds=30):
+    """Polynomial minimising max |p/f - 1| (Lawson-reweighted least squares)."""
+    xs = cheb_nodes(a, b, nodes)
+    fv = [fun(x) for x in xs]
+    w = [mp.mpf(1)] * nodes
+    best = None
+    for _ in range(rounds):
+        rows = [[mp.sqrt(w[i]) / fv[i] * x ** j for j in range(deg + 1)] for i, x in enumerate(xs)]
+        rhs = [mp.sqrt(w[i]) for i in range(nodes)]
+        c = mp.qr_solve(mp.matrix(rows), mp.matrix(rhs))[0]
+        coef = [c[j] for j in range(deg + 1)]
+        errs = [mp.polyval(coef[::-1], x) / f - 1 for x, f in zip(xs, fv)]
+        mx = max(abs(e) for e in errs)
+        if best is None or mx < best[0]:
+            best = (mx, coef)
+        w = [w[i] * abs(errs[i]) for i in range(nodes)]
+        sw = sum(w)
+        w = [wi / sw * nodes for wi in w]
+    coef = best[1]
+    cr = [mp.mpf(float(x)) for x in coef]
+    dense = [a + (b - a) * k / 1500 for k in range(1501)]
+    return coef, max(abs(mp.polyval(cr[::-1], x) / fun(x) - 1) for x in dense)
+
+
 def carr(name, coeffs, comment):
     """C array, highest power first (Horner order)."""
     body = ",\n".join("    %s" % repr(float(c)) for c in coeffs[::-1])
@@ -175,6 +210,44 @@ def main():
     print("mills (6,7): max rel %.3e" % e_m, file=sys.stderr)
     out.append(carr("QM_MILLS_P", p, "Mills ratio numerator in x; rel err %.2e on [0,14.5]" % e_m))
     out.append(carr("QM_MILLS_Q", q, "Mills ratio denominator in x (constant term 1)"))
+
+    # --- central piece, Phi^{-1}(1/2 + q)/q = P8(r)/Q8(r), r = X - q^2 ---------
+    QC, X = mp.mpf(float(0.45)), mp.mpf(float(0.2025))
+    r_lo = X - QC * QC - mp.mpf("1e-12")          # |q| <= 0.45 as FP64 values, with margin
+    g = lambda r: mp.sqrt(2 * mp.pi) if r == X else mp.sqrt(2) * mp.erfinv(2 * mp.sqrt(X - r)) / mp.sqrt(X - r)
+    xs = cheb_nodes(r_lo, X, 160)
+    fs = [g(x) for x in xs]
+    _, p, q = fit_rational(xs, fs, 8, 8)
+    dense = [r_lo + (X - r_lo) * k / 1500 for k in range(1501)]
+    dfs = [g(x) for x in dense]
+    e_c = rounded_error(p, q, dense, dfs)
+    print("central (8,8): max rel %.3e" % e_c, file=sys.stderr)
+    assert all(c > 0 for c in p) and all(c > 0 for c in q)
+    out.append("static constexpr double QM_CENTRAL_QMAX = 0.45;\n")
+    out.append("static constexpr double QM_CENTRAL_X = 0.2025;\n")
+    out.append(carr("QM_CENTRAL_P", p, "Phi^{-1}(1/2 + q)/q numerator in r = 0.2025 - q^2; rel err %.2e for |q| <= 0.45" % e_c))
+    out.append(carr("QM_CENTRAL_Q", q, "central denominator in r (constant term 1)"))
+
+    # --- FP32+refine central piece ----------------------------------------
+    xs = cheb_nodes(r_lo, X, 120)
+    fs = [g(x) for x in xs]
+    _, p, q = fit_rational(xs, fs, 2, 3)
+    # the seed is evaluated in FP32: measure it with FP32-rounded coefficients
+    f32 = lambda c: mp.mpf(struct.unpack("f", struct.pack("f", float(c)))[0])
+    e_s = max(abs(mp.polyval([f32(c) for c in p][::-1], x) / mp.polyval([f32(c) for c in q][::-1], x) / f - 1)
+              for x, f in zip(dense, dfs))
+    print("central FP32 seed (2,3): max rel %.3e" % e_s, file=sys.stderr)
+    out.append(carr("QM_C32_SP", p, "FP32 central seed numerator in r = 0.2025 - q^2; rel err %.2e (FP32 coefficients)" % e_s))
+    out.append(carr("QM_C32_SQ", q, "FP32 central seed denominator in r (constant term 1)"))
+    zmax = mp.sqrt(2) * mp.erfinv(2 * QC) * (1 + mp.mpf("1e-3"))
+    Y = zmax * zmax
+    erfh = lambda y: mp.erf(mp.sqrt(y / 2)) / (2 * mp.sqrt(y)) if y > 0 else 1 / mp.sqrt(2 * mp.pi)
+    coef, e_e = fit_poly(erfh, mp.mpf(0), Y, 8)
+    print("central erf E8: max rel %.3e" % e_e, file=sys.stderr)
+    out.append(carr("QM_C32_E", coef, "erf(z/sqrt2)/(2z) in y = z^2 <= %.4f; rel err %.2e" % (float(Y), e_e)))
+    coef, e_g = fit_poly(lambda y: mp.sqrt(2 * mp.pi) * mp.exp(y / 2), mp.mpf(0), Y, 5)
+    print("central 1/phi G5: max rel %.3e" % e_g, file=sys.stderr)
+    out.append(carr("QM_C32_G", coef, "1/phi(z) = sqrt(2 pi) e^{y/2} in y = z^2 <= %.4f; rel err %.2e" % (float(Y), e_g)))
 
     # --- FP64 log kernel: R6(s) ----------------------------------------------
     coef, e_log = fit_log_poly(6)

@@ -165,7 +165,7 @@ qm_status qm_init(int hip_device, uint64_t hbm_budget_bytes, qm_ctx** out)
     if (unroll != 1 && unroll != 2 && unroll != 4) unroll = 2;
     c->shape.max_blocks = (uint64_t)(cus > 0 ? cus : 256) * (uint64_t)bpc;
     c->shape.unroll = (int)unroll;
-    const char* ec = getenv("QM_COMPACT_TAIL");
+    const char* ec = getenv("QM_COMPACT");
     c->shape.compact = ec ? (int)strtol(ec, nullptr, 10) != 0 : 1;
     *out = c;
     return QM_OK;
@@ -217,6 +217,32 @@ qm_status qm_recycle_exp_to_normal(qm_ctx* ctx, const void* d_x, void* d_z, uint
                                    void* s)
 {
     return single(ctx, QM_EXP_TO_NORMAL, d_x, d_z, n, dtype, mode, 0.0, s);
+}
+
+qm_status qm_generate(qm_ctx* ctx, uint64_t seed, uint64_t stream, uint64_t first, void* d_out, uint64_t n,
+                      int kind, int dtype, int mode, void* hs)
+{
+    if (!ctx) return fail(QM_E_INVAL, "context is NULL");
+    if (seed > 0xFFFFFFFFull || stream > 0xFFFFFFFFull) return fail(QM_E_INVAL, "seed and stream must be < 2^32");
+    if (dtype != QM_F32 && dtype != QM_F64) return fail(QM_E_INVAL, "unknown dtype %d", dtype);
+    if (mode != QM_PLAIN && mode != QM_F32_REFINE && mode != QM_PAPER) return fail(QM_E_INVAL, "unknown mode %d", mode);
+    if (kind == QM_UNIFORM) {
+        if (mode != QM_PLAIN) return fail(QM_E_DTYPE, "QM_UNIFORM takes mode QM_PLAIN");
+    } else if (kind == QM_NORMAL_QUANTILE) {
+        if (dtype == QM_F64 && mode == QM_F32_REFINE) return fail(QM_E_DTYPE, "QM_F32_REFINE needs dtype QM_F32");
+    } else {
+        return fail(QM_E_INVAL, "qm_generate: kind must be QM_UNIFORM or QM_NORMAL_QUANTILE (got %d)", kind);
+    }
+    if (first > (1ull << 63) || n > (1ull << 63) - first) return fail(QM_E_INVAL, "first + n beyond 2^63");
+    if (n == 0) return QM_OK;
+    if (!d_out) return fail(QM_E_INVAL, "NULL output with n > 0");
+    if ((uintptr_t)d_out % dtype_size(dtype)) return fail(QM_E_INVAL, "output must be aligned to the element size");
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    e = qm::launch_generate(kind, dtype, mode, (uint32_t)seed, (uint32_t)stream, first, d_out, n, (hipStream_t)hs,
+                            ctx->shape);
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    return QM_OK;
 }
 
 const char* qm_status_string(qm_status s)

@@ -120,25 +120,6 @@ __device__ __noinline__ double expcoord_far(double v)
     return z;
 }
 
-/* The deep-tail piece alone: Q(v) = s P7(s)/Q7(s), s = sqrt v, 42 < v <= 750. */
-__device__ __forceinline__ double expcoord_tail(double v)
-{
-    double s = sqrt_pos(v);
-    return div_pos(s * horner(s, QM_TAIL_P), horner(s, QM_TAIL_Q));
-}
-
-/* The paper's (13,13) piece alone (Appendix B), v <= 42. */
-__device__ __forceinline__ double expcoord_main(double v)
-{
-    return div_pos(v * horner(v, QM_PAPER_P13), horner(v, QM_PAPER_Q13));
-}
-
-/* v > 42 and finite: the lanes that need the deep-tail piece. */
-__device__ __forceinline__ bool expcoord_needs_tail(double v)
-{
-    return (v > QM_TAIL_VMIN) && (v < __builtin_inf());
-}
-
 /*
  * Plain FP64 Q(v) for v in [0, inf]: the paper's (13,13) rational on
  * v <= 42 and the fitted Q(v) = s P7(s)/Q7(s), s = sqrt v, beyond.  Both
@@ -198,12 +179,49 @@ __device__ __forceinline__ double quantile_finish(double u, double mag)
     return w;
 }
 
+/* The exponential-coordinate path for any u (plain mode): v = -log(2 min(u,
+   1-u)), Q(v), sign and specials. */
+__device__ __forceinline__ double outer_quantile_f64(double u)
+{
+    return quantile_finish(u, expcoord_q_plain<false>(quantile_v(u)));
+}
+
+/* Central piece, |q| <= 0.45 with q = u - 1/2 (90% of uniform draws):
+   w = q P8(r)/Q8(r), r = 0.2025 - q^2, relative error 6e-17 after rounding;
+   no logarithm.  q is exact for u >= 1/4 and within half an ulp below, which
+   moves w by at most 2.3e-16 relative at |q| = 0.45.  Other q give
+   unspecified values. */
+__device__ __forceinline__ bool is_central(double q) { return __builtin_fabs(q) <= QM_CENTRAL_QMAX; }
+
+__device__ __forceinline__ double central_quantile(double q)
+{
+    double r = __builtin_fma(-q, q, QM_CENTRAL_X);
+    return div_pos(q * horner(r, QM_CENTRAL_P), horner(r, QM_CENTRAL_Q));
+}
+
+/*
+ * FP64 w(u).  Paper mode: the (13,13) rational of Appendix B in the
+ * exponential coordinate for every u.  Plain mode: the hybrid of
+ * Section 7.3 / Appendix C -- a central piece where most samples fall, the
+ * branchless exponential-coordinate path elsewhere -- with the paper's T2
+ * central variable (chosen there for a fast single-precision-grade rsqrt)
+ * replaced by q itself, which needs no transcendental at all.  Lanes
+ * outside the centre take the outer path by wave vote here; the streaming
+ * kernel instead gathers them across the wave (k_nq64_compact), with the
+ * same arithmetic per element.
+ */
 template <bool PAPER>
 __device__ __forceinline__ double normal_quantile_f64(double u)
 {
-    double v = quantile_v(u);
-    double mag = PAPER ? expcoord_q_paper(v) : expcoord_q_plain<false>(v);
-    return quantile_finish(u, mag);
+    if (PAPER) return quantile_finish(u, expcoord_q_paper(quantile_v(u)));
+    double q = u - 0.5;
+    bool central = is_central(q);           /* NaN: false */
+    double w = central_quantile(q);
+    if (wave_any(!central)) {
+        double wo = outer_quantile_f64(u);
+        w = central ? w : wo;
+    }
+    return w;
 }
 
 /* Exponential -> normal, FP64: v = |x| directly, odd extension. */
@@ -289,8 +307,9 @@ __device__ __forceinline__ double halley_upper(double x0, double p_over_phi)
     return __builtin_fma(t, 1.0 + h, x0);
 }
 
-/* Phi^{-1}(u) for FP32 u: FP32 seed + one FP64 Halley step, rounded to FP32. */
-__device__ __forceinline__ float normal_quantile_f32_refine(float u)
+/* Phi^{-1}(u) for FP32 u outside the centre: FP32 seed in the exponential
+   coordinate + one FP64 Halley step, rounded to FP32. */
+__device__ __forceinline__ float outer_quantile_f32_refine(float u)
 {
     const double SQRT2PI = 2.5066282746310005024;
     float om = 1.0f - u;                       /* exact for u >= 1/2 */
@@ -307,6 +326,41 @@ __device__ __forceinline__ float normal_quantile_f32_refine(float u)
     w = (u == 1.0f) ? __builtin_inff() : w;
     /* NaN and out-of-range inputs need no select: p + p is then negative or
        NaN, the hardware log returns NaN, and NaN propagates to w */
+    return w;
+}
+
+/*
+ * Central piece of the FP32+refine form, |q| <= 0.45, q = u - 1/2 (exact in
+ * FP64 for FP32 u): the FP32 seed z0 = q S2(r)/S3(r), r = 0.2025 - q^2
+ * (2.6e-6 relative), then one FP64 Newton step on Phi(z) = u,
+ *   z1 = z0 - (erf(z0/sqrt2)/2 - q) / phi(z0),
+ * with erf(z/sqrt2)/2 = z E8(z^2) (1.1e-11) and 1/phi(z) = G5(z^2) (4.2e-6:
+ * the step is about 2.6e-6 z, so this costs 1.1e-11 z).  Newton's own error
+ * is (z0/2) e0^2, below 1e-11 z here.  No logarithm and no exponential.
+ */
+__device__ __forceinline__ float central_quantile_f32_refine(double qd)
+{
+    float qf = (float)qd;
+    float rf = __builtin_fmaf(-qf, qf, (float)QM_CENTRAL_X);
+    float z0 = qf * hornerf_d(rf, QM_C32_SP) * __builtin_amdgcn_rcpf(hornerf_d(rf, QM_C32_SQ));
+    double x0 = (double)z0;
+    double y = x0 * x0;
+    double res = __builtin_fma(x0, horner(y, QM_C32_E), -qd);
+    return (float)__builtin_fma(-res, horner(y, QM_C32_G), x0);
+}
+
+/* Phi^{-1}(u) for FP32 u, FP32+refine form: the hybrid of the FP64 path
+   (central piece; the outer path by wave vote here, gathered across the
+   wave by the streaming kernel, with the same arithmetic per element). */
+__device__ __forceinline__ float normal_quantile_f32_refine(float u)
+{
+    double qd = (double)u - 0.5;
+    bool central = is_central(qd);          /* NaN: false */
+    float w = central_quantile_f32_refine(qd);
+    if (wave_any(!central)) {
+        float wo = outer_quantile_f32_refine(u);
+        w = central ? w : wo;
+    }
     return w;
 }
 

@@ -15,12 +15,16 @@ namespace qm {
 struct LaunchShape {
     uint64_t max_blocks;  /* cap on the grid (grid-stride beyond it) */
     int unroll;           /* 16-byte vectors in flight per lane: 1, 2 or 4 */
-    int compact;          /* FP64 quantile: compact deep-tail lanes across the wave */
+    int compact;          /* FP64 quantile: gather non-central lanes across the wave */
 };
 
 /* Elementwise normal quantile / exp -> normal on one stream. */
 hipError_t launch_elementwise(int kind, int dtype, int mode, const void* in, void* out, uint64_t n,
                               hipStream_t s, const LaunchShape& shape);
+
+/* Fused Philox4x32-10 generation and transform (qm_generate.hip). */
+hipError_t launch_generate(int kind, int dtype, int mode, uint32_t seed, uint32_t stream, uint64_t first,
+                           void* out, uint64_t n, hipStream_t s, const LaunchShape& shape);
 
 /* The coefficient block that follows a device table's header. */
 inline const double* table_block(const TTableHeader* d_table)

@@ -15,25 +15,10 @@
 #include <type_traits>
 
 #include "qm_device.hpp"
+#include "qm_hybrid.hpp"
 #include "qm_internal.h"
 
 namespace qm {
-
-typedef double d2 __attribute__((ext_vector_type(2)));
-typedef float f4 __attribute__((ext_vector_type(4)));
-
-template <typename T> struct vec16;
-template <> struct vec16<double> { typedef d2 type; static constexpr int n = 2; };
-template <> struct vec16<float> { typedef f4 type; static constexpr int n = 4; };
-
-struct OpNQ64Plain { __device__ double operator()(double u) const { return normal_quantile_f64<false>(u); } };
-struct OpNQ64Paper { __device__ double operator()(double u) const { return normal_quantile_f64<true>(u); } };
-struct OpE64Plain  { __device__ double operator()(double x) const { return exp_to_normal_f64<false>(x); } };
-struct OpE64Paper  { __device__ double operator()(double x) const { return exp_to_normal_f64<true>(x); } };
-struct OpNQ32Refine { __device__ float operator()(float u) const { return normal_quantile_f32_refine(u); } };
-struct OpNQ32Paper  { __device__ float operator()(float u) const { return normal_quantile_f32_paper(u); } };
-struct OpNQ32Plain  { __device__ float operator()(float u) const { return normal_quantile_f32_plain(u); } };
-struct OpE32Refine  { __device__ float operator()(float x) const { return exp_to_normal_f32_refine(x); } };
 
 /*
  * in/out: the whole arrays.  [0, head) and [tail_begin, n) are done element
@@ -96,81 +81,40 @@ __global__ __launch_bounds__(256) void k_map(MapArgs<T> a)
     }
 }
 
-/*
- * FP64 quantile, plain mode, with the deep-tail piece compacted across the
- * wave.  On inputs with a tail stratum nearly every wave holds a lane with
- * v > 42, so evaluating the tail piece by wave vote costs every lane the
- * sqrt, the (7,7) rational and a division.  Here each lane keeps K = 2 UNROLL
- * elements; the wave counts its tail elements (ballots), writes their v to a
- * per-wave LDS list at prefix-sum positions, evaluates that list with one
- * element per lane (one pass per 64), and reads each result back.  The
- * arithmetic on every element is the same as normal_quantile_f64<false>,
- * so the results are bitwise identical.
- */
-template <int UNROLL>
-__global__ __launch_bounds__(256) void k_nq64_compact(MapArgs<double> a)
+/* The hybrid quantile over a memory stream (see qm_hybrid.hpp). */
+template <typename T, int UNROLL, class H>
+__global__ __launch_bounds__(256) void k_hybrid(MapArgs<T> a)
 {
-    constexpr int K = 2 * UNROLL;
-    __shared__ double tail_buf[4][64 * K];
-    double* buf = tail_buf[threadIdx.x >> 6];
+    typedef typename vec16<T>::type V;
+    constexpr int NV = vec16<T>::n;
+    constexpr int K = NV * UNROLL;
+    __shared__ T outer_buf[4][64 * K];
+    T* buf = outer_buf[threadIdx.x >> 6];
     const uint32_t lane = __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const d2* vin = reinterpret_cast<const d2*>(a.in + a.head);
-    d2* vout = reinterpret_cast<d2*>(a.out + a.head);
+    const V* vin = reinterpret_cast<const V*>(a.in + a.head);
+    V* vout = reinterpret_cast<V*>(a.out + a.head);
     /* whole waves iterate together: the trip count is uniform per wave because
        the bound is tested on the wave's first lane */
     const uint64_t wave_first = tid - lane;
     for (uint64_t i0 = wave_first; i0 < a.nvec; i0 += UNROLL * stride) {
         const uint64_t i = i0 + lane;
-        double u[K], v[K], mag[K];
-        bool tl[K];
+        T u[K], w[K];
 #pragma unroll
         for (int k = 0; k < UNROLL; ++k) {
             uint64_t idx = i + k * stride;
-            d2 x = idx < a.nvec ? __builtin_nontemporal_load(vin + idx) : d2{0.5, 0.5};
-            u[2 * k] = x[0];
-            u[2 * k + 1] = x[1];
-        }
-        uint64_t cnt = 0;
+            V x = idx < a.nvec ? __builtin_nontemporal_load(vin + idx) : (V)(T)0.5;
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
-            v[k] = quantile_v(u[k]);
-            mag[k] = expcoord_main(v[k]);
-            tl[k] = expcoord_needs_tail(v[k]);
-            cnt += __popcll(__ballot(tl[k]));
+            for (int j = 0; j < NV; ++j) u[NV * k + j] = x[j];
         }
-        if (cnt) {
-            uint32_t pos[K];
-            uint32_t base = 0;
-#pragma unroll
-            for (int k = 0; k < K; ++k) {
-                uint64_t m = __ballot(tl[k]);
-                pos[k] = base + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-                if (tl[k]) buf[pos[k]] = v[k];
-                base += (uint32_t)__popcll(m);
-            }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            for (uint32_t r = 0; r < base; r += 64) {
-                if (r + lane < base) buf[r + lane] = expcoord_tail(buf[r + lane]);
-            }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-#pragma unroll
-            for (int k = 0; k < K; ++k)
-                if (tl[k]) mag[k] = buf[pos[k]];
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-        }
+        hybrid_eval<T, K, H>(u, w, buf, lane);
 #pragma unroll
         for (int k = 0; k < UNROLL; ++k) {
             uint64_t idx = i + k * stride;
-            d2 y;
-            y[0] = quantile_finish(u[2 * k], mag[2 * k]);
-            y[1] = quantile_finish(u[2 * k + 1], mag[2 * k + 1]);
+            V y;
+#pragma unroll
+            for (int j = 0; j < NV; ++j) y[j] = w[NV * k + j];
             if (idx < a.nvec) __builtin_nontemporal_store(y, vout + idx);
         }
     }
@@ -178,10 +122,34 @@ __global__ __launch_bounds__(256) void k_nq64_compact(MapArgs<double> a)
         uint64_t extra = a.head + (a.n - a.tail_begin);
         for (uint64_t e = threadIdx.x; e < extra; e += blockDim.x) {
             uint64_t idx = e < a.head ? e : a.tail_begin + (e - a.head);
-            a.out[idx] = normal_quantile_f64<false>(a.in[idx]);
+            a.out[idx] = H::whole(a.in[idx]);
         }
     }
 }
+
+template <typename T, class H>
+static void launch_hybrid(const MapArgs<T>& a, uint64_t blocks, hipStream_t s, int unroll)
+{
+    if (unroll == 4)
+        hipLaunchKernelGGL((k_hybrid<T, 4, H>), dim3((unsigned)blocks), dim3(256), 0, s, a);
+    else if (unroll == 1)
+        hipLaunchKernelGGL((k_hybrid<T, 1, H>), dim3((unsigned)blocks), dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_hybrid<T, 2, H>), dim3((unsigned)blocks), dim3(256), 0, s, a);
+}
+
+template <typename T, class H, bool HAS>
+struct HybridLaunch {
+    static bool run(const MapArgs<T>&, uint64_t, hipStream_t, int) { return false; }
+};
+template <typename T, class H>
+struct HybridLaunch<T, H, true> {
+    static bool run(const MapArgs<T>& a, uint64_t blocks, hipStream_t s, int unroll)
+    {
+        launch_hybrid<T, H>(a, blocks, s, unroll);
+        return true;
+    }
+};
 
 template <typename T, class Op>
 static hipError_t launch_op(const void* in, void* out, uint64_t n, hipStream_t s, const LaunchShape& shape)
@@ -202,16 +170,9 @@ static hipError_t launch_op(const void* in, void* out, uint64_t n, hipStream_t s
         uint64_t blocks = (a.nvec + per_block - 1) / per_block;
         if (blocks > shape.max_blocks) blocks = shape.max_blocks;
         if (blocks < 1) blocks = 1;
-        if (std::is_same<Op, OpNQ64Plain>::value && shape.compact) {
-            if (shape.unroll == 4)
-                hipLaunchKernelGGL((k_nq64_compact<4>), dim3((unsigned)blocks), dim3(256), 0, s,
-                                   *reinterpret_cast<MapArgs<double>*>(&a));
-            else if (shape.unroll == 1)
-                hipLaunchKernelGGL((k_nq64_compact<1>), dim3((unsigned)blocks), dim3(256), 0, s,
-                                   *reinterpret_cast<MapArgs<double>*>(&a));
-            else
-                hipLaunchKernelGGL((k_nq64_compact<2>), dim3((unsigned)blocks), dim3(256), 0, s,
-                                   *reinterpret_cast<MapArgs<double>*>(&a));
+        typedef typename HybridOf<Op>::type H;
+        if (shape.compact && HybridLaunch<T, H, !std::is_void<H>::value>::run(a, blocks, s, shape.unroll)) {
+            /* launched the gathering kernel */
         } else if (shape.unroll == 4)
             hipLaunchKernelGGL((k_map<T, true, 4, Op>), dim3((unsigned)blocks), dim3(256), 0, s, a);
         else if (shape.unroll == 1)

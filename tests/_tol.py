@@ -42,3 +42,12 @@ def assert_close(got, ref, rtol, what=""):
     ok, rep = compare(got, ref, rtol)
     assert rep["fails"] == 0, "%s: %r" % (what, rep)
     return rep
+
+
+def as_f32_output(ref):
+    """An FP64 reference for FP32 outputs: a magnitude that rounds beyond
+    FLT_MAX is +-inf in FP32, as the output itself must then be."""
+    r = np.asarray(ref, dtype=np.float64)
+    with np.errstate(over="ignore"):
+        r32 = r.astype(np.float32)
+    return np.where(np.isinf(r32) & np.isfinite(r), r32.astype(np.float64), r)

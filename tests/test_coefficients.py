@@ -1,0 +1,152 @@
+"""CPU checks of the fitted rationals the kernels evaluate (qm_coeffs.h),
+each against the oracle: the coefficients as stored (FP64), evaluated
+exactly in mpmath, so only the fit and the rounding of its coefficients are
+under test, not the device's arithmetic."""
+import math
+import os
+import re
+
+import mpmath as mp
+import numpy as np
+
+import oracle
+
+HDR = os.path.join(os.path.dirname(__file__), "..", "paper_0901_0638_amd", "csrc", "qm_coeffs.h")
+
+
+def arrays():
+    s = open(HDR).read()
+    out = {}
+    for m in re.finditer(r"static constexpr double (\w+)\[\d+\] = \{([^}]*)\};", s):
+        out[m.group(1)] = [float(x) for x in m.group(2).replace("\n", " ").split(",") if x.strip()]
+    for m in re.finditer(r"static constexpr double (\w+) = ([0-9.eE+-]+);", s):
+        out[m.group(1)] = float(m.group(2))
+    return out
+
+
+def horner(c, x):
+    r = mp.mpf(0)
+    for ck in c:
+        r = r * x + mp.mpf(ck)
+    return r
+
+
+def test_central_piece_against_oracle():
+    """w = q P8(r)/Q8(r), r = 0.2025 - q^2, for |q| <= 0.45: within 1e-16
+    of the oracle (plus the oracle's own half-ulp) across the whole piece."""
+    c = arrays()
+    assert c["QM_CENTRAL_QMAX"] == 0.45 and c["QM_CENTRAL_X"] == 0.2025
+    u = np.concatenate([np.linspace(0.05, 0.95, 2001), [0.05, 0.95, 0.5 + 1e-12, 0.5 - 1e-300]])
+    ref = oracle.norm_quantile(u)
+    with mp.workdps(40):
+        for ui, wi in zip(u, ref):
+            q = mp.mpf(ui) - mp.mpf("0.5")          # exact in mpmath
+            if q == 0:
+                continue
+            r = mp.mpf(c["QM_CENTRAL_X"]) - q * q
+            w = q * horner(c["QM_CENTRAL_P"], r) / horner(c["QM_CENTRAL_Q"], r)
+            assert abs(w / mp.mpf(wi) - 1) <= 1e-16 + 2 ** -53, (ui, float(w), wi)
+
+
+def test_deep_tail_piece_against_oracle():
+    """Q(v) = s P7(s)/Q7(s), s = sqrt(v), on 42 < v <= 745 (u down to the
+    smallest double)."""
+    c = arrays()
+    v = np.linspace(42.0, 744.0, 400)
+    u = np.exp(-v) / 2
+    ref = -oracle.norm_quantile(u)
+    with mp.workdps(40):
+        for vi, ui, wi in zip(v, u, ref):
+            if ui == 0:
+                continue
+            vv = -mp.log(2 * mp.mpf(ui))            # the v of the stored u, exactly
+            s = mp.sqrt(vv)
+            w = s * horner(c["QM_TAIL_P"], s) / horner(c["QM_TAIL_Q"], s)
+            assert abs(w / mp.mpf(wi) - 1) <= 5e-17 + 2 ** -53, (vi, float(w), wi)
+
+
+def test_fp32_seed_and_mills_ratio():
+    """The FP32 seed is a seed (1.2e-5); the Mills ratio M(x) = (1 - Phi(x))/phi(x)
+    behind the correction step's erfc is good to 1.1e-12 on [0, 14.5]."""
+    c = arrays()
+    with mp.workdps(30):
+        for v in np.linspace(0.01, 103.0, 300):
+            u = math.exp(-v) / 2
+            ref = -oracle.norm_quantile(np.array([u]))[0]
+            vv = -mp.log(2 * mp.mpf(u))
+            z = vv * horner(c["QM_SEED_P"], vv) / horner(c["QM_SEED_Q"], vv)
+            assert abs(z / ref - 1) <= 1.2e-5
+        for x in np.linspace(0.0, 14.5, 300):
+            m = horner(c["QM_MILLS_P"], x) / horner(c["QM_MILLS_Q"], x)
+            ref = mp.erfc(mp.mpf(x) / mp.sqrt(2)) / 2 * mp.sqrt(2 * mp.pi) * mp.exp(mp.mpf(x) ** 2 / 2)
+            assert abs(m / ref - 1) <= 1.1e-12
+
+
+def test_log_kernel_polynomial():
+    """log m = 2f + f s R6(s), f = (m-1)/(m+1), s = f^2, on [sqrt(1/2), sqrt(2)]."""
+    c = arrays()
+    with mp.workdps(40):
+        for m in np.linspace(math.sqrt(0.5), math.sqrt(2.0), 500):
+            mm = mp.mpf(m)
+            if mm == 1:
+                continue
+            f = (mm - 1) / (mm + 1)
+            s = f * f
+            lm = 2 * f + f * s * horner(c["QM_LOG_R"], s)
+            assert abs(lm / mp.log(mm) - 1) <= 2e-18
+
+
+def f32(x):
+    return float(np.float32(x))
+
+
+def test_fp32_central_pieces():
+    """FP32+refine central piece: the seed (with FP32 coefficients) within
+    2.7e-6, erf(z/sqrt2)/(2z) = E8(z^2) within 1.2e-11 and
+    1/phi(z) = G5(z^2) within 4.3e-6, over |q| <= 0.45 (|z| <= 1.646)."""
+    c = arrays()
+    u = np.linspace(0.05, 0.95, 901)
+    ref = oracle.norm_quantile(u)
+    with mp.workdps(30):
+        for ui, wi in zip(u, ref):
+            q = mp.mpf(ui) - mp.mpf("0.5")
+            if q == 0:
+                continue
+            r = mp.mpf(0.2025) - q * q
+            z0 = q * horner([f32(x) for x in c["QM_C32_SP"]], r) / horner([f32(x) for x in c["QM_C32_SQ"]], r)
+            assert abs(z0 / mp.mpf(wi) - 1) <= 2.7e-6, (ui, float(z0), wi)
+            y = mp.mpf(wi) ** 2
+            e = horner(c["QM_C32_E"], y) * 2 * mp.mpf(wi)
+            assert abs(e / mp.erf(mp.mpf(wi) / mp.sqrt(2)) - 1) <= 1.2e-11
+            g = horner(c["QM_C32_G"], y)
+            assert abs(g / (mp.sqrt(2 * mp.pi) * mp.exp(y / 2)) - 1) <= 4.3e-6
+
+
+def test_fp32_central_newton_step_emulated():
+    """The whole central FP32+refine evaluation emulated in float32/float64
+    (plain numpy, no FMA): within 1e-9 of the oracle before the final
+    rounding, so the FP32 result is the oracle value rounded (or, within
+    1e-9 of a midpoint, its neighbour)."""
+    c = arrays()
+    u = np.linspace(0.05, 0.95, 20001).astype(np.float32).astype(np.float64)
+    qd = u - 0.5
+    qf = qd.astype(np.float32)
+    rf = np.float32(0.2025) - qf * qf
+    sp = np.zeros_like(rf)
+    for x in c["QM_C32_SP"]:
+        sp = sp * rf + np.float32(x)
+    sq = np.zeros_like(rf)
+    for x in c["QM_C32_SQ"]:
+        sq = sq * rf + np.float32(x)
+    z0 = (qf * sp / sq).astype(np.float64)
+    y = z0 * z0
+    e = np.zeros_like(y)
+    for x in c["QM_C32_E"]:
+        e = e * y + x
+    g = np.zeros_like(y)
+    for x in c["QM_C32_G"]:
+        g = g * y + x
+    z1 = z0 - (z0 * e - qd) * g
+    ref = oracle.norm_quantile(u)
+    nz = ref != 0
+    assert np.max(np.abs(z1[nz] / ref[nz] - 1)) <= 1e-9

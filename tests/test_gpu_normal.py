@@ -82,6 +82,30 @@ def test_quantile_f64_deep_tail_sweep(ctx):
     assert_close(run_nq(ctx, u), oracle.norm_quantile(u), RTOL_F64, "deep tail")
 
 
+def test_quantile_f64_central_outer_boundary(ctx):
+    """Plain mode switches between the central piece (|u - 1/2| <= 0.45) and
+    the exponential-coordinate path; both sides of the switch, the switch
+    points themselves, and u near 1/4 (where u - 1/2 stops being exact), in
+    waves that mix both pieces and waves that hold only one."""
+    edges = []
+    for c in (0.05, 0.95, 0.25, 0.75):
+        x = np.float64(c)
+        for _ in range(40):
+            edges += [x]
+            x = np.nextafter(x, 2.0)
+        x = np.float64(c)
+        for _ in range(40):
+            x = np.nextafter(x, -1.0)
+            edges += [x]
+    rng = np.random.default_rng(17)
+    near = np.concatenate([rng.uniform(0.04, 0.06, 5000), rng.uniform(0.94, 0.96, 5000),
+                           rng.uniform(0.2, 0.3, 2000)])
+    central_only = rng.uniform(0.06, 0.94, 4096)
+    outer_only = np.concatenate([rng.uniform(1e-9, 0.049, 2048), rng.uniform(0.951, 1 - 1e-9, 2048)])
+    for name, u in (("edges", np.array(edges)), ("near", near), ("central", central_only), ("outer", outer_only)):
+        assert_close(run_nq(ctx, u), oracle.norm_quantile(u), RTOL_F64, name)
+
+
 def test_quantile_f64_misaligned_and_inplace(ctx):
     u = qi.uniform53(4, 0, 5000)
     ref = oracle.norm_quantile(u)
