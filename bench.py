@@ -40,7 +40,7 @@ T_NUS = (1, 2, 3, 4, 5, 10, 30)
 def kernel_source_hash():
     import hashlib
     h = hashlib.sha256()
-    for f in ("qm_kernels.hip", "qm_device.hpp", "qm_coeffs.h", "qm_paper_coeffs.h"):
+    for f in ("qm_kernels.hip", "qm_hybrid.hpp", "qm_device.hpp", "qm_coeffs.h", "qm_paper_coeffs.h"):
         with open(os.path.join(ROOT, "paper_0901_0638_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -57,7 +57,7 @@ def counted_traffic():
     except OSError:
         return None
     m = re.search(r"Kernel source hash: `([0-9a-f]+)`", text)
-    t = re.search(r"traffic_bytes_per_launch k_nq64_compact: ([0-9]+)", text)
+    t = re.search(r"traffic_bytes_per_launch k_hybrid<double>: ([0-9]+)", text)
     if not m or not t or m.group(1) != kernel_source_hash():
         return None
     return int(t.group(1))
@@ -153,7 +153,8 @@ def run_quantile(args, torch, qm, qi):
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": counted_traffic() if n == (1 << 28) else None,
-                     "kernel": "qm::k_nq64_compact<2> (FP64 quantile, deep tail compacted per wave)",
+                     "kernel": "qm::k_hybrid<double, 2, qm::HybridNQ64> (FP64 quantile: central piece, "
+                               "outer elements gathered per wave)",
                      "algorithmic_bytes_per_launch": bytes64, "avg_launch_ms": round(avg64, 4)},
     }
     del u64, u32, w64, w32
