@@ -403,7 +403,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", choices=["quantile", "batch", "serve"], default="quantile")
     ap.add_argument("--n", type=int, default=1 << 28, help="samples per pass (quantile workload)")
-    ap.add_argument("--cpu-sample", type=int, default=1 << 24, help="oracle sample size (elements)")
+    ap.add_argument("--cpu-sample", type=int, default=1 << 28, help="oracle sample size (elements)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the secondary maps")
     ap.add_argument("--copy-calibration", action="store_true",
