@@ -12,6 +12,10 @@ namespace qm {
 /* Elements per chunk: a workgroup claims one chunk at a time. */
 constexpr uint64_t QM_CHUNK = 32768;
 
+/* Dynamic LDS (the largest Student t table of the batch) the batch kernel
+   may ask for: 64 KB less its static 8 KB gather list and claim slot. */
+constexpr size_t QM_BATCH_DYNAMIC_LDS_MAX = 65536 - 8192 - 256;
+
 enum BatchOp : uint32_t {
     BOP_NQ64_PLAIN = 0, BOP_NQ64_PAPER, BOP_NQ32_REFINE, BOP_NQ32_PAPER, BOP_NQ32_PLAIN,
     BOP_E64_PLAIN, BOP_E64_PAPER, BOP_E32_REFINE, BOP_T64, BOP_T32,

@@ -19,12 +19,10 @@
 
 #include "qm_batch.h"
 #include "qm_device.hpp"
+#include "qm_hybrid.hpp"
 #include "qm_student_device.hpp"
 
 namespace qm {
-
-typedef double d2 __attribute__((ext_vector_type(2)));
-typedef float f4 __attribute__((ext_vector_type(4)));
 
 typedef float f2 __attribute__((ext_vector_type(2)));
 
@@ -76,9 +74,7 @@ extern __shared__ double lds_tab[];
     {                                                                                               \
         chunk_map<T>((const T*)in, (T*)out, begin, end, [](T x) { return EXPR; });                  \
     }
-QM_CHUNK_FN(chunk_nq64_plain, double, normal_quantile_f64<false>(x))
 QM_CHUNK_FN(chunk_nq64_paper, double, normal_quantile_f64<true>(x))
-QM_CHUNK_FN(chunk_nq32_refine, float, normal_quantile_f32_refine(x))
 QM_CHUNK_FN(chunk_nq32_paper, float, normal_quantile_f32_paper(x))
 QM_CHUNK_FN(chunk_nq32_plain, float, normal_quantile_f32_plain(x))
 QM_CHUNK_FN(chunk_e64_plain, double, exp_to_normal_f64<false>(x))
@@ -87,6 +83,66 @@ QM_CHUNK_FN(chunk_e32_refine, float, exp_to_normal_f32_refine(x))
 QM_CHUNK_FN(chunk_copy64, double, x)
 QM_CHUNK_FN(chunk_copy32, float, x)
 #undef QM_CHUNK_FN
+
+/* LDS list of the hybrid quantiles' gather: 64 K elements per wave (K = 4
+   FP64 or 8 FP32 per lane), 8 KB per workgroup of four waves. */
+constexpr int GATHER_DOUBLES_PER_WAVE = 64 * 4;
+
+/*
+ * Hybrid quantile chunk (FP64 plain, FP32+refine): the streaming kernel's
+ * gather (hybrid_eval) over two 16-byte vectors per lane, so that the outer
+ * path runs once per 64 outer elements rather than on every lane of a wave
+ * holding one; bitwise the per-element function.  Whole waves iterate
+ * together, as the gather needs.  Elements before the first co-aligned
+ * 16-byte boundary, after the last whole vector, or of arrays that are not
+ * co-aligned take the per-element function.
+ */
+template <typename T, class H>
+static __device__ __noinline__ void chunk_hybrid(const void* vin_, void* vout_, uint64_t begin, uint64_t end,
+                                                 double* gather)
+{
+    typedef typename vec16<T>::type V;
+    constexpr int NV = vec16<T>::n;
+    constexpr int UNROLL = 2;
+    constexpr int K = NV * UNROLL;
+    const T* in = (const T*)vin_ + begin;
+    T* out = (T*)vout_ + begin;
+    const uint64_t n = end - begin;
+    uintptr_t pi = reinterpret_cast<uintptr_t>(in), po = reinterpret_cast<uintptr_t>(out);
+    uint64_t head = ((16 - (pi % 16)) % 16) / sizeof(T);
+    if ((pi - po) % 16 != 0 || head > n) head = n;          /* not co-aligned: all element-wise */
+    const uint64_t nvec = (n - head) / NV;
+    const uint64_t tail_begin = head + nvec * NV;
+    const uint32_t lane = __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+    T* buf = reinterpret_cast<T*>(gather + (threadIdx.x >> 6) * GATHER_DOUBLES_PER_WAVE);
+    const V* vin = reinterpret_cast<const V*>(in + head);
+    V* vout = reinterpret_cast<V*>(out + head);
+    for (uint64_t i0 = threadIdx.x - lane; i0 < nvec; i0 += UNROLL * blockDim.x) {
+        const uint64_t i = i0 + lane;
+        T u[K], w[K];
+#pragma unroll
+        for (int k = 0; k < UNROLL; ++k) {
+            uint64_t idx = i + k * blockDim.x;
+            V x = idx < nvec ? __builtin_nontemporal_load(vin + idx) : (V)(T)0.5;
+#pragma unroll
+            for (int j = 0; j < NV; ++j) u[NV * k + j] = x[j];
+        }
+        hybrid_eval<T, K, H>(u, w, buf, lane);
+#pragma unroll
+        for (int k = 0; k < UNROLL; ++k) {
+            uint64_t idx = i + k * blockDim.x;
+            V y;
+#pragma unroll
+            for (int j = 0; j < NV; ++j) y[j] = w[NV * k + j];
+            if (idx < nvec) __builtin_nontemporal_store(y, vout + idx);
+        }
+    }
+    const uint64_t extra = head + (n - tail_begin);
+    for (uint64_t e = threadIdx.x; e < extra; e += blockDim.x) {
+        uint64_t idx = e < head ? e : tail_begin + (e - head);
+        out[idx] = H::whole(in[idx]);
+    }
+}
 
 /* Student t from the table in LDS (referenced by symbol, so the loads stay
    LDS loads). */
@@ -107,6 +163,7 @@ static __device__ __noinline__ void chunk_t32(const void* in, void* out, uint64_
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_batch(BatchHeader* hdr, const BatchReq* __restrict__ reqs)
 {
     __shared__ uint64_t s_chunk;
+    __shared__ double gather[4 * GATHER_DOUBLES_PER_WAVE];
     const double* loaded = nullptr;        /* table currently in LDS (uniform) */
     const uint64_t total = hdr->total_chunks;
     const uint32_t nreq = hdr->nreq;
@@ -126,9 +183,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
         const uint64_t begin = (c - R.chunk_base) * QM_CHUNK;
         const uint64_t end = begin + QM_CHUNK < R.n ? begin + QM_CHUNK : R.n;
         switch (R.op) {
-        case BOP_NQ64_PLAIN: chunk_nq64_plain(R.in, R.out, begin, end); break;
+        case BOP_NQ64_PLAIN: chunk_hybrid<double, HybridNQ64>(R.in, R.out, begin, end, gather); break;
         case BOP_NQ64_PAPER: chunk_nq64_paper(R.in, R.out, begin, end); break;
-        case BOP_NQ32_REFINE: chunk_nq32_refine(R.in, R.out, begin, end); break;
+        case BOP_NQ32_REFINE: chunk_hybrid<float, HybridNQ32>(R.in, R.out, begin, end, gather); break;
         case BOP_NQ32_PAPER: chunk_nq32_paper(R.in, R.out, begin, end); break;
         case BOP_NQ32_PLAIN: chunk_nq32_plain(R.in, R.out, begin, end); break;
         case BOP_E64_PLAIN: chunk_e64_plain(R.in, R.out, begin, end); break;

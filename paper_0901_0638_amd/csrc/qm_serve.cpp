@@ -192,7 +192,7 @@ qm_status enqueue_batch(qm_ctx* ctx, const qm_request* reqs, uint64_t count, hip
         }
         d.push_back(b);
     }
-    if (lds > 65536) return set_error(QM_E_INVAL, "Student t table larger than the LDS a launch may use");
+    if (lds > QM_BATCH_DYNAMIC_LDS_MAX) return set_error(QM_E_INVAL, "Student t table larger than the LDS a launch may use");
     if (d.empty()) {
         if (done && hipEventRecord(done, s) != hipSuccess) return set_error(QM_E_HIP, "hipEventRecord failed");
         return QM_OK;
