@@ -82,11 +82,15 @@ typedef struct qm_ctx qm_ctx;
  * bytes (input + output of admitted requests) that the serving loop keeps in
  * flight; 0 means no serving budget (qm_submit then rejects every request).
  * The context owns the per-nu Student t tables and the serving state.
- * The streaming kernels' launch shape (workgroups of 256 per compute unit,
- * default 32; 16-byte vectors in flight per lane, 1, 2 or 4, default 2) is
- * read here from the environment variables QM_BLOCKS_PER_CU and QM_UNROLL;
- * QM_COMPACT=0 turns off the FP64 quantile's gathering of non-central lanes
- * across the wave (the results are bitwise the same either way).
+ * Each kernel family has its own launch shape (workgroups of 256 per compute
+ * unit x 16-byte vectors in flight per lane, from measured sweeps: light
+ * maps 2 x 4, FP64 quantile 64 x 4, FP32+refine quantile 32 x 2, Student t
+ * 2 x 4 (FP64) and 3 x 4 (FP32)); the environment variables
+ * QM_BLOCKS_PER_CU (1..64) and QM_UNROLL (1, 2 or 4), read here, override
+ * every family, and QM_SHAPE_STREAM, QM_SHAPE_NQ64, QM_SHAPE_NQ32,
+ * QM_SHAPE_T64, QM_SHAPE_T32 ("blocks,unroll") one family each.  QM_COMPACT=0 turns off the quantiles' gathering of
+ * non-central lanes across the wave (the results are bitwise the same
+ * either way).
  * Errors: QM_E_INVAL (out == NULL or no such device), QM_E_HIP, QM_E_NOMEM.
  */
 qm_status qm_init(int hip_device, uint64_t hbm_budget_bytes, qm_ctx** out);

@@ -154,17 +154,32 @@ qm_status qm_init(int hip_device, uint64_t hbm_budget_bytes, qm_ctx** out)
     c->device = hip_device;
     c->budget = hbm_budget_bytes;
     c->cus = cus > 0 ? cus : 256;
-    /* streaming launch shape: 32 workgroups of 256 per CU (four rounds of the
-       8 resident ones), two 16-byte vectors in flight per lane -- the best of
-       a measured sweep over 2..32 x 1..4; QM_BLOCKS_PER_CU / QM_UNROLL
-       override (tuning) */
-    long bpc = 32, unroll = 2;
-    if (const char* ev = getenv("QM_BLOCKS_PER_CU")) bpc = strtol(ev, nullptr, 10);
-    if (const char* ev = getenv("QM_UNROLL")) unroll = strtol(ev, nullptr, 10);
-    if (bpc < 1 || bpc > 64) bpc = 32;
-    if (unroll != 1 && unroll != 2 && unroll != 4) unroll = 2;
-    c->shape.max_blocks = (uint64_t)(cus > 0 ? cus : 256) * (uint64_t)bpc;
-    c->shape.unroll = (int)unroll;
+    /* launch shapes per kernel family (workgroups of 256 per CU x vectors
+       per lane), the best of measured sweeps over 1..64 x 1..4 on MI355X;
+       QM_BLOCKS_PER_CU / QM_UNROLL override every family (tuning) */
+    const uint64_t ncu = (uint64_t)(cus > 0 ? cus : 256);
+    struct { qm::KernelShape* ks; const char* env; long bpc, unroll; } fam[] = {
+        {&c->shape.stream, "QM_SHAPE_STREAM", 2, 4},   /* light maps: few workgroups, deep unroll */
+        {&c->shape.hybrid[0], "QM_SHAPE_NQ32", 32, 2}, /* FP32+refine quantile */
+        {&c->shape.hybrid[1], "QM_SHAPE_NQ64", 64, 4}, /* FP64 quantile */
+        {&c->shape.student[0], "QM_SHAPE_T32", 3, 4},  /* Student t, FP32 outputs */
+        {&c->shape.student[1], "QM_SHAPE_T64", 2, 4},  /* Student t, FP64 outputs */
+    };
+    long env_bpc = 0, env_unroll = 0;
+    if (const char* ev = getenv("QM_BLOCKS_PER_CU")) env_bpc = strtol(ev, nullptr, 10);
+    if (const char* ev = getenv("QM_UNROLL")) env_unroll = strtol(ev, nullptr, 10);
+    for (auto& f : fam) {
+        long bpc = f.bpc, unroll = f.unroll, eb = env_bpc, eu = env_unroll;
+        if (const char* ev = getenv(f.env)) {       /* "bpc,unroll" for this family alone */
+            char* end = nullptr;
+            eb = strtol(ev, &end, 10);
+            eu = (end && *end == ',') ? strtol(end + 1, nullptr, 10) : 0;
+        }
+        if (eb >= 1 && eb <= 64) bpc = eb;
+        if (eu == 1 || eu == 2 || eu == 4) unroll = eu;
+        f.ks->max_blocks = ncu * (uint64_t)bpc;
+        f.ks->unroll = (int)unroll;
+    }
     const char* ec = getenv("QM_COMPACT");
     c->shape.compact = ec ? (int)strtol(ec, nullptr, 10) != 0 : 1;
     *out = c;

@@ -146,11 +146,12 @@ static __device__ __noinline__ void chunk_hybrid(const void* vin_, void* vout_, 
 
 /* Student t from the table in LDS (referenced by symbol, so the loads stay
    LDS loads). */
+template <int DEG>
 static __device__ __noinline__ void chunk_t64(const void* in, void* out, uint64_t begin, uint64_t end,
                                               const StudentParams P)
 {
     chunk_map<double>((const double*)in, (double*)out, begin, end,
-                      [&](double z) { return student_eval<T_DEGREE_F64>(z, lds_tab, P); });
+                      [&](double z) { return student_eval<DEG>(z, lds_tab, P); });
 }
 
 static __device__ __noinline__ void chunk_t32(const void* in, void* out, uint64_t begin, uint64_t end,
@@ -204,7 +205,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
                 __syncthreads();
                 loaded = R.coef;
             }
-            if (R.op == BOP_T64) chunk_t64(R.in, R.out, begin, end, R.P);
+            if (R.op == BOP_T64) {
+                if (R.P.row_shift == 4) chunk_t64<T_DEGREE_HIGH>(R.in, R.out, begin, end, R.P);
+                else chunk_t64<T_DEGREE_LOW>(R.in, R.out, begin, end, R.P);
+            }
             else chunk_t32(R.in, R.out, begin, end, R.P);
             break;
         }

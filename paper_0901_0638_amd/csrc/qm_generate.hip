@@ -116,8 +116,9 @@ __global__ __launch_bounds__(256) void k_generate(GenArgs<T> a)
 }
 
 template <typename T, class H, bool GATHER>
-static hipError_t launch_gen(GenArgs<T> a, hipStream_t s, const LaunchShape& shape)
+static hipError_t launch_gen(GenArgs<T> a, hipStream_t s, const LaunchShape& shape_all)
 {
+    const KernelShape shape = shape_all.hybrid[sizeof(T) == 8];
     constexpr int NV = vec16<T>::n;
     a.head = (NV - a.first % NV) % NV;
     bool vector = a.head <= a.n && (a.n - a.head) >= (uint64_t)NV &&

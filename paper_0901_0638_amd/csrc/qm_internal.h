@@ -11,11 +11,23 @@
 
 namespace qm {
 
-/* Launch geometry of the streaming kernels. */
+/* Launch geometry of one kernel family: the grid is capped at max_blocks
+   workgroups of 256 (grid-stride beyond), each lane keeps `unroll` 16-byte
+   vectors in flight (1, 2 or 4). */
+struct KernelShape {
+    uint64_t max_blocks;
+    int unroll;
+};
+
+/* Per family, measured on MI355X (launch-shape sweeps over 1..64
+   workgroups per CU x 1..4 vectors): light HBM-bound maps stream best from
+   few workgroups with deep unrolling, the VALU-heavy hybrid quantiles from
+   many. */
 struct LaunchShape {
-    uint64_t max_blocks;  /* cap on the grid (grid-stride beyond it) */
-    int unroll;           /* 16-byte vectors in flight per lane: 1, 2 or 4 */
-    int compact;          /* FP64 quantile: gather non-central lanes across the wave */
+    KernelShape stream;      /* k_map: exp -> normal, paper modes, FP32 plain */
+    KernelShape hybrid[2];   /* [0] FP32+refine, [1] FP64 quantile: k_hybrid, k_generate */
+    KernelShape student[2];  /* [0] FP32, [1] FP64 outputs: k_student */
+    int compact;             /* quantiles: gather non-central lanes across the wave */
 };
 
 /* Elementwise normal quantile / exp -> normal on one stream. */

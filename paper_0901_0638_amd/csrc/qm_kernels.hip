@@ -154,6 +154,9 @@ struct HybridLaunch<T, H, true> {
 template <typename T, class Op>
 static hipError_t launch_op(const void* in, void* out, uint64_t n, hipStream_t s, const LaunchShape& shape)
 {
+    typedef typename HybridOf<Op>::type H;
+    const bool gather = shape.compact && !std::is_void<H>::value;
+    const KernelShape ks = gather ? shape.hybrid[sizeof(T) == 8] : shape.stream;
     MapArgs<T> a;
     a.in = static_cast<const T*>(in);
     a.out = static_cast<T*>(out);
@@ -166,16 +169,15 @@ static hipError_t launch_op(const void* in, void* out, uint64_t n, hipStream_t s
         a.head = head;
         a.nvec = (n - head) / NV;
         a.tail_begin = head + a.nvec * NV;
-        uint64_t per_block = 256ull * shape.unroll;
+        uint64_t per_block = 256ull * ks.unroll;
         uint64_t blocks = (a.nvec + per_block - 1) / per_block;
-        if (blocks > shape.max_blocks) blocks = shape.max_blocks;
+        if (blocks > ks.max_blocks) blocks = ks.max_blocks;
         if (blocks < 1) blocks = 1;
-        typedef typename HybridOf<Op>::type H;
-        if (shape.compact && HybridLaunch<T, H, !std::is_void<H>::value>::run(a, blocks, s, shape.unroll)) {
+        if (gather && HybridLaunch<T, H, !std::is_void<H>::value>::run(a, blocks, s, ks.unroll)) {
             /* launched the gathering kernel */
-        } else if (shape.unroll == 4)
+        } else if (ks.unroll == 4)
             hipLaunchKernelGGL((k_map<T, true, 4, Op>), dim3((unsigned)blocks), dim3(256), 0, s, a);
-        else if (shape.unroll == 1)
+        else if (ks.unroll == 1)
             hipLaunchKernelGGL((k_map<T, true, 1, Op>), dim3((unsigned)blocks), dim3(256), 0, s, a);
         else
             hipLaunchKernelGGL((k_map<T, true, 2, Op>), dim3((unsigned)blocks), dim3(256), 0, s, a);
@@ -184,7 +186,7 @@ static hipError_t launch_op(const void* in, void* out, uint64_t n, hipStream_t s
         a.nvec = n;
         a.tail_begin = n;
         uint64_t blocks = (n + 255) / 256;
-        if (blocks > shape.max_blocks) blocks = shape.max_blocks;
+        if (blocks > ks.max_blocks) blocks = ks.max_blocks;
         if (blocks < 1) blocks = 1;
         hipLaunchKernelGGL((k_map<T, false, 1, Op>), dim3((unsigned)blocks), dim3(256), 0, s, a);
     }

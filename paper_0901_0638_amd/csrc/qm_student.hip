@@ -39,17 +39,16 @@ template <typename T> struct svec;
 template <> struct svec<double> { typedef d2 type; static constexpr int n = 2; };
 template <> struct svec<float> { typedef f4 type; static constexpr int n = 4; };
 
-template <typename T>
+/* FP32 in/out: the FP64 evaluation of the table's FP32 cells (R to 1e-10)
+   rounded once; the input is exact in FP64, so the cell offset carries the
+   input's full precision. */
+template <typename T, int DEG>
 __device__ __forceinline__ T student_op(T z, const double* tab, const StudentParams& P)
 {
-    if (sizeof(T) == 8) return (T)student_eval<T_DEGREE_F64>((double)z, tab, P);
-    /* FP32 in/out: the FP64 evaluation of the degree-7 cells (R to 1e-10)
-       rounded once; the input is exact in FP64, so the cell offset carries
-       the input's full precision */
-    return (T)student_eval<T_DEGREE_F32>((double)z, tab, P);
+    return (T)student_eval<DEG>((double)z, tab, P);
 }
 
-template <typename T, bool VECTOR, int UNROLL>
+template <typename T, bool VECTOR, int UNROLL, int DEG>
 __global__ __launch_bounds__(256) void k_student(StudentArgs<T> a)
 {
     extern __shared__ double lds_tab[];
@@ -73,7 +72,7 @@ __global__ __launch_bounds__(256) void k_student(StudentArgs<T> a)
             for (int k = 0; k < UNROLL; ++k) {
                 V y;
 #pragma unroll
-                for (int j = 0; j < NV; ++j) y[j] = student_op<T>(x[k][j], lds_tab, P);
+                for (int j = 0; j < NV; ++j) y[j] = student_op<T, DEG>(x[k][j], lds_tab, P);
                 __builtin_nontemporal_store(y, vout + i + k * stride);
             }
         }
@@ -81,18 +80,18 @@ __global__ __launch_bounds__(256) void k_student(StudentArgs<T> a)
             V x = __builtin_nontemporal_load(vin + i);
             V y;
 #pragma unroll
-            for (int j = 0; j < NV; ++j) y[j] = student_op<T>(x[j], lds_tab, P);
+            for (int j = 0; j < NV; ++j) y[j] = student_op<T, DEG>(x[j], lds_tab, P);
             __builtin_nontemporal_store(y, vout + i);
         }
         if (blockIdx.x == 0) {
             uint64_t extra = a.head + (a.n - a.tail_begin);
             for (uint64_t e = threadIdx.x; e < extra; e += blockDim.x) {
                 uint64_t idx = e < a.head ? e : a.tail_begin + (e - a.head);
-                a.out[idx] = student_op<T>(a.in[idx], lds_tab, P);
+                a.out[idx] = student_op<T, DEG>(a.in[idx], lds_tab, P);
             }
         }
     } else {
-        for (uint64_t i = tid; i < a.n; i += stride) a.out[i] = student_op<T>(a.in[i], lds_tab, P);
+        for (uint64_t i = tid; i < a.n; i += stride) a.out[i] = student_op<T, DEG>(a.in[i], lds_tab, P);
     }
 }
 
@@ -107,8 +106,9 @@ __global__ __launch_bounds__(256) void k_identity(const T* in, T* out, uint64_t 
 /* LDS row stride in doubles for rows of `row` coefficients.  Rows of a
    power-of-2 length all start on the same bank, so lanes reading different
    cells conflict; one double of padding spreads them (measured, rows of 16:
-   nu = 1 from 200 to 271 Gsamples/s).  QM_T_LDS_STRIDE (row..24) overrides
-   the FP64 rows' stride, QM_T32_LDS_STRIDE (row..24) the FP32 rows' (tuning). */
+   nu = 1 from 200 to 271 Gsamples/s).  QM_T_LDS_STRIDE (16..24) overrides
+   the stride of rows of 16, QM_T8_LDS_STRIDE (8..24) that of rows of 8
+   (tuning). */
 static int stride_from_env(const char* name, int row)
 {
     const char* e = getenv(name);
@@ -118,9 +118,9 @@ static int stride_from_env(const char* name, int row)
 
 int student_lds_stride(int row)
 {
-    static const int s16 = stride_from_env("QM_T_LDS_STRIDE", T_DEGREE_F64 + 1);
-    static const int s8 = stride_from_env("QM_T32_LDS_STRIDE", T_DEGREE_F32 + 1);
-    return row == T_DEGREE_F64 + 1 ? s16 : s8;
+    static const int s16 = stride_from_env("QM_T_LDS_STRIDE", T_DEGREE_HIGH + 1);
+    static const int s8 = stride_from_env("QM_T8_LDS_STRIDE", T_DEGREE_LOW + 1);
+    return row == T_DEGREE_HIGH + 1 ? s16 : s8;
 }
 
 static bool cells_valid(const TCells& c, int degree)
@@ -150,10 +150,11 @@ StudentParams make_params(const TTableHeader& h, const TCells& c, const double* 
     return P;
 }
 
-template <typename T>
+template <typename T, int DEG>
 static hipError_t launch_t(const void* in, void* out, uint64_t n, const double* d_block, const TTableHeader& h,
-                           hipStream_t s, const LaunchShape& shape)
+                           hipStream_t s, const LaunchShape& shape_all)
 {
+    const KernelShape shape = shape_all.student[sizeof(T) == 8];
     if (h.identity) {
         uint64_t blocks = (n + 255) / 256;
         if (blocks > shape.max_blocks) blocks = shape.max_blocks;
@@ -183,11 +184,11 @@ static hipError_t launch_t(const void* in, void* out, uint64_t n, const double* 
         if (blocks > shape.max_blocks) blocks = shape.max_blocks;
         if (blocks < 1) blocks = 1;
         if (shape.unroll == 4)
-            hipLaunchKernelGGL((k_student<T, true, 4>), dim3((unsigned)blocks), dim3(256), lds, s, a);
+            hipLaunchKernelGGL((k_student<T, true, 4, DEG>), dim3((unsigned)blocks), dim3(256), lds, s, a);
         else if (shape.unroll == 1)
-            hipLaunchKernelGGL((k_student<T, true, 1>), dim3((unsigned)blocks), dim3(256), lds, s, a);
+            hipLaunchKernelGGL((k_student<T, true, 1, DEG>), dim3((unsigned)blocks), dim3(256), lds, s, a);
         else
-            hipLaunchKernelGGL((k_student<T, true, 2>), dim3((unsigned)blocks), dim3(256), lds, s, a);
+            hipLaunchKernelGGL((k_student<T, true, 2, DEG>), dim3((unsigned)blocks), dim3(256), lds, s, a);
     } else {
         a.head = 0;
         a.nvec = n;
@@ -195,7 +196,7 @@ static hipError_t launch_t(const void* in, void* out, uint64_t n, const double* 
         uint64_t blocks = (n + 255) / 256;
         if (blocks > shape.max_blocks) blocks = shape.max_blocks;
         if (blocks < 1) blocks = 1;
-        hipLaunchKernelGGL((k_student<T, false, 1>), dim3((unsigned)blocks), dim3(256), lds, s, a);
+        hipLaunchKernelGGL((k_student<T, false, 1, DEG>), dim3((unsigned)blocks), dim3(256), lds, s, a);
     }
     return hipGetLastError();
 }
@@ -204,11 +205,17 @@ hipError_t launch_student(int dtype, int mode, const void* in, void* out, uint64
                           const TTableHeader* d_table, const TTableHeader& h_table,
                           hipStream_t s, const LaunchShape& shape)
 {
-    if (!h_table.identity && !(cells_valid(h_table.f64, T_DEGREE_F64) && cells_valid(h_table.f32, T_DEGREE_F32)))
+    if (!h_table.identity && !((cells_valid(h_table.f64, T_DEGREE_LOW) || cells_valid(h_table.f64, T_DEGREE_HIGH)) &&
+                               cells_valid(h_table.f32, T_DEGREE_F32)))
         return hipErrorInvalidValue;
     const double* d_block = table_block(d_table);
-    if (dtype == QM_F64 && mode == QM_PLAIN) return launch_t<double>(in, out, n, d_block, h_table, s, shape);
-    if (dtype == QM_F32 && mode == QM_F32_REFINE) return launch_t<float>(in, out, n, d_block, h_table, s, shape);
+    if (dtype == QM_F64 && mode == QM_PLAIN) {
+        if (h_table.identity || h_table.f64.degree == T_DEGREE_LOW)
+            return launch_t<double, T_DEGREE_LOW>(in, out, n, d_block, h_table, s, shape);
+        return launch_t<double, T_DEGREE_HIGH>(in, out, n, d_block, h_table, s, shape);
+    }
+    if (dtype == QM_F32 && mode == QM_F32_REFINE)
+        return launch_t<float, T_DEGREE_F32>(in, out, n, d_block, h_table, s, shape);
     return hipErrorInvalidValue;
 }
 

@@ -27,8 +27,8 @@
  * cells of width h in y = z^2 with the Chebyshev interpolant of
  * R(y) = Q(z)/z (an even function of z, like the paper's series in y = z^2,
  * Section 3.5), stored as monomial coefficients in d = y - y_centre, twice:
- * degree 15 for FP64 outputs and degree 7 on narrower cells for FP32
- * outputs.  The cells cover y <= 100 and then as far as the two-term tail
+ * for FP64 outputs (degree 7 where at most 200 cells cover y <= 100, else
+ * degree 15 on wider cells) and for FP32 outputs (degree 7, to 1e-10).  The cells cover y <= 100 and then as far as the two-term tail
  * formula of Section 3.5 falls short of the same accuracy (it is
  * O(w^{4/nu}), so for large nu it needs very large |z|), but never past
  * |z| = 40, beyond the normal quantile of any positive double.  For
@@ -409,14 +409,15 @@ int build_student_table(double nu_d, HostTTable* out, char* err, int errlen)
 
     std::vector<double> coef;
     if (nu_d > NU_CF) {
-        cornish_fisher_cells(nu, T_DEGREE_F64, coef, &H.f64);
+        cornish_fisher_cells(nu, T_DEGREE_LOW, coef, &H.f64);
         cornish_fisher_cells(nu, T_DEGREE_F32, coef, &H.f32);
     } else {
         /* Tolerances: FP64 outputs, truncation below 2e-17, so the rounded
            coefficients (about an ulp of R) dominate; FP32 outputs, 1e-10.
            The cells reach as far as the tail formula needs to meet the same
-           tolerance; those up to Y_LDS (at most 480 rows of 17 doubles, the
-           64 KB of LDS a launch may use) are the ones staged in LDS. */
+           tolerance; those up to Y_LDS are the ones staged in LDS (for FP64,
+           degree 7 if at most 200 rows of 9 doubles do, else degree 15 in at
+           most 480 rows of 17 doubles, the 64 KB of LDS a launch may use). */
         const fq tol64 = 2e-17Q, tol32 = 1e-10Q;
         /* the formula's truncation error, with its constants exact (their
            rounding to FP64 is part of the device's evaluation error) */
@@ -431,7 +432,8 @@ int build_student_table(double nu_d, HostTTable* out, char* err, int errlen)
         Solution sol;
         const fq gamma = sqrtq(nu / 2) * expq(lgamma_q(nu / 2) - lgamma_q((nu + 1) / 2));
         if (!solve_rode(nu, lbeta, gamma, z_far, sol, err, errlen)) return -1;
-        if (!fit_cells(sol, gamma, T_DEGREE_F64, tol64, y64, 480, coef, &H.f64))
+        if (!fit_cells(sol, gamma, T_DEGREE_LOW, tol64, y64, T_LDS_CELLS_LOW, coef, &H.f64) &&
+            !fit_cells(sol, gamma, T_DEGREE_HIGH, tol64, y64, 480, coef, &H.f64))
             return fail(err, errlen, "no cell width met the FP64 accuracy target");
         if (!fit_cells(sol, gamma, T_DEGREE_F32, tol32, y32, 720, coef, &H.f32))
             return fail(err, errlen, "no cell width met the FP32 accuracy target");

@@ -7,12 +7,16 @@
 
 namespace qm {
 
-/* Polynomial degrees per cell: FP64 outputs need R to about an ulp of FP64;
-   FP32 outputs are rounded once from an FP64 evaluation, so R to 1e-10
-   relative (far below the 6e-8 half-ulp of FP32) is enough and a lower
-   degree on narrower cells halves the table reads per element. */
-constexpr int T_DEGREE_F64 = 15;
-constexpr int T_DEGREE_F32 = 7;
+/* Polynomial degrees per cell.  FP64 outputs need R to about an ulp of
+   FP64: degree 7 on narrower cells where at most T_LDS_CELLS_LOW of them
+   cover y <= 100 (nu >= 3 or so), else degree 15 on wider ones.  FP32
+   outputs are rounded once from an FP64 evaluation, so R to 1e-10 relative
+   (far below the 6e-8 half-ulp of FP32) is enough: degree 7.  Degree 7
+   halves the table reads and the Horner chain per element. */
+constexpr int T_DEGREE_LOW = 7;
+constexpr int T_DEGREE_HIGH = 15;
+constexpr int T_DEGREE_F32 = T_DEGREE_LOW;
+constexpr int T_LDS_CELLS_LOW = 200;
 
 /*
  * One piecewise-polynomial approximation of R(y) = t(z)/z, y = z^2 <= y_max:
@@ -52,7 +56,7 @@ struct TTableHeader {
     double tail_a[4];   /* far-tail series t = sqrt(nu) w^{-1/nu} (1 + sum a_k w^{2k/nu}) */
     int32_t identity;   /* nu = +inf: t = z */
     int32_t reserved;
-    TCells f64;         /* degree T_DEGREE_F64 */
+    TCells f64;         /* degree T_DEGREE_LOW or T_DEGREE_HIGH */
     TCells f32;         /* degree T_DEGREE_F32 */
 };
 

@@ -100,11 +100,14 @@ def table_grid(c):
 
 @pytest.mark.parametrize("nu", NUS + [100, 1e3, 1e5])
 def test_table_polynomials_match_oracle(nu):
-    """FP64 cells (degree 15): within a few FP64 rounding errors of the
-    oracle's incomplete-beta inversion everywhere in the table's range."""
+    """FP64 cells (degree 7 where at most 200 of them cover y <= 100, which
+    holds from nu = 3 on, else degree 15): within a few FP64 rounding errors
+    of the oracle's incomplete-beta inversion everywhere in the table's
+    range."""
     h, c, coef = qm.debug_student_table(nu)
     assert h.identity == 0
-    check_cells(c, 15)
+    check_cells(c, 7 if nu >= 3 else 15)
+    assert c.nlds <= (200 if c.degree == 7 else 480)
     assert c.max_rel_err < 3e-16
     z = table_grid(c)
     t = eval_table_exact(c, coef, z)
@@ -115,13 +118,14 @@ def test_table_polynomials_match_oracle(nu):
 
 @pytest.mark.parametrize("nu", NUS + [0.75, 1.5])
 def test_fp32_cells_match_oracle(nu):
-    """FP32-output cells (degree 7 on cells at most as wide as the FP64
-    ones): R within 1e-10 of the oracle, far below FP32's half-ulp of 6e-8,
-    so the one rounding to FP32 decides the result."""
+    """FP32-output cells (degree 7, fitted to 1e-10): R within 1e-10 of the
+    oracle, far below FP32's half-ulp of 6e-8, so the one rounding to FP32
+    decides the result."""
     h, c, coef = qm.debug_student_table(nu, "f32")
     _, c64, _ = qm.debug_student_table(nu)
     check_cells(c, 7)
-    assert c.h <= c64.h
+    if c64.degree == 7:          # same degree, looser tolerance: cells at least as wide
+        assert c.h >= c64.h
     assert c.max_rel_err < 1e-10
     z = table_grid(c)
     t = eval_table_exact(c, coef, z)
@@ -198,7 +202,7 @@ def test_table_identity_and_cornish_fisher():
     h, c, coef = qm.debug_student_table(float("inf"))
     assert h.identity == 1 and c.ncell == 0 and coef.size == 0
     nu = 2e5
-    for which, degree in (("f64", 15), ("f32", 7)):
+    for which, degree in (("f64", 7), ("f32", 7)):
         h, c, coef = qm.debug_student_table(nu, which)
         assert c.ncell == 1 and c.inv_h == 0 and c.degree == degree
         # the cell polynomial is A&S 26.7.5 (Section 3.4) in y = z^2
