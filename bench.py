@@ -153,8 +153,8 @@ def run_quantile(args, torch, qm, qi):
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": counted_traffic() if n == (1 << 28) else None,
-                     "kernel": "qm::k_hybrid<double, 2, qm::HybridNQ64> (FP64 quantile: central piece, "
-                               "outer elements gathered per wave)",
+                     "kernel": "qm::k_hybrid<double, 4, qm::HybridNQ64> (FP64 quantile: central piece, "
+                               "outer elements gathered per wave; 64 workgroups/CU x 4 vectors)",
                      "algorithmic_bytes_per_launch": bytes64, "avg_launch_ms": round(avg64, 4)},
     }
     del u64, u32, w64, w32
