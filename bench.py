@@ -410,7 +410,7 @@ def main():
                     help="also run a plain device copy of the FP64 input (for HBM counter scaling)")
     ap.add_argument("--batch-count", type=int, default=4096)
     ap.add_argument("--serve-count", type=int, default=2000)
-    ap.add_argument("--rates", type=float, nargs="+", default=[1000, 2000, 5000, 10000, 20000, 50000, 0],
+    ap.add_argument("--rates", type=float, nargs="+", default=[1000, 2000, 5000, 10000, 20000, 50000, 100000, 0],
                     help="arrival rates in requests/s; 0 = burst (all requests at once)")
     args = ap.parse_args()
     if args.gpus != 1:

@@ -9,8 +9,13 @@
 
 namespace qm {
 
-/* Elements per chunk: a workgroup claims one chunk at a time. */
-constexpr uint64_t QM_CHUNK = 32768;
+/* Elements per chunk (a workgroup claims one chunk at a time), carried in
+   the batch header: QM_CHUNK_MAX unless tuning lowers the floor, when small
+   batches get chunks of about total / (4 x workgroups), between these
+   bounds (multiples of QM_CHUNK_MIN keep every chunk start 16-byte aligned
+   within an aligned request). */
+constexpr uint64_t QM_CHUNK_MIN = 2048;
+constexpr uint64_t QM_CHUNK_MAX = 32768;
 
 /* Dynamic LDS (the largest Student t table of the batch) the batch kernel
    may ask for: 64 KB less its static 8 KB gather list and claim slot. */
@@ -27,7 +32,7 @@ struct BatchHeader {
     uint64_t total_chunks;
     uint32_t nreq;
     uint32_t reserved;
-    uint64_t reserved2;
+    uint64_t chunk;         /* elements per chunk */
 };
 
 struct BatchReq {

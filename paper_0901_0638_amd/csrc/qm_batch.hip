@@ -2,7 +2,7 @@
  * qm_batch.hip -- one persistent launch over many requests of mixed kind,
  * dtype, mode and nu.
  *
- * Every request is cut into chunks of QM_CHUNK elements; chunks are numbered
+ * Every request is cut into chunks of hdr->chunk elements; chunks are numbered
  * globally in request order (chunk_base = prefix sum).  Each workgroup
  * repeatedly claims the next chunk from a device counter, finds its request
  * by binary search over chunk_base, and evaluates it with the same
@@ -167,6 +167,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
     __shared__ double gather[4 * GATHER_DOUBLES_PER_WAVE];
     const double* loaded = nullptr;        /* table currently in LDS (uniform) */
     const uint64_t total = hdr->total_chunks;
+    const uint64_t chunk = hdr->chunk;
     const uint32_t nreq = hdr->nreq;
     for (;;) {
         if (threadIdx.x == 0) s_chunk = atomicAdd(reinterpret_cast<unsigned long long*>(&hdr->counter), 1ull);
@@ -181,8 +182,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
             if (reqs[mid].chunk_base <= c) lo = mid; else hi = mid - 1;
         }
         const BatchReq& R = reqs[lo];
-        const uint64_t begin = (c - R.chunk_base) * QM_CHUNK;
-        const uint64_t end = begin + QM_CHUNK < R.n ? begin + QM_CHUNK : R.n;
+        const uint64_t begin = (c - R.chunk_base) * chunk;
+        const uint64_t end = begin + chunk < R.n ? begin + chunk : R.n;
         switch (R.op) {
         case BOP_NQ64_PLAIN: chunk_hybrid<double, HybridNQ64>(R.in, R.out, begin, end, gather); break;
         case BOP_NQ64_PAPER: chunk_nq64_paper(R.in, R.out, begin, end); break;
