@@ -207,7 +207,7 @@ __device__ __forceinline__ double central_quantile(double q)
  * central variable (chosen there for a fast single-precision-grade rsqrt)
  * replaced by q itself, which needs no transcendental at all.  Lanes
  * outside the centre take the outer path by wave vote here; the streaming
- * kernel instead gathers them across the wave (k_nq64_compact), with the
+ * kernel instead gathers them across the wave (k_hybrid), with the
  * same arithmetic per element.
  */
 template <bool PAPER>

@@ -169,6 +169,36 @@ def test_quantile_f32_refine_edges(ctx):
     assert_close(run_nq(ctx, u, qm.QM_PLAIN), ref, RTOL_F32, "f32 plain edges")
 
 
+def test_quantile_f32_refine_central_outer_boundary(ctx):
+    """FP32+refine switches between its central piece (FP32 seed + FP64
+    Newton against erf) and the exponential-coordinate seed + Halley against
+    erfc at |u - 1/2| = 0.45; both sides and the switch points, every float
+    in a window around them, in mixed and single-piece waves.  The result is
+    the oracle value rounded to float except within 1e-9 of a midpoint."""
+    edges = []
+    for c in (0.05, 0.95, 0.25, 0.75, 0.5):
+        x = np.float32(c)
+        for _ in range(300):
+            edges.append(x)
+            x = np.nextafter(x, np.float32(2))
+        x = np.float32(c)
+        for _ in range(300):
+            x = np.nextafter(x, np.float32(-1))
+            edges.append(x)
+    rng = np.random.default_rng(23)
+    u = np.concatenate([np.array(edges, np.float32), rng.uniform(0.04, 0.96, 20000).astype(np.float32),
+                        qi.uniform24(6, 0, 1 << 16)])
+    ref = oracle.norm_quantile(u.astype(np.float64))
+    got = run_nq(ctx, u, qm.QM_F32_REFINE)
+    assert_close(got, ref, RTOL_F32, "f32 refine centre/outer")
+    r32 = ref.astype(np.float32)
+    other = np.nextafter(r32, np.where(ref > r32, np.float32(np.inf), np.float32(-np.inf)))
+    mid = (r32.astype(np.float64) + other.astype(np.float64)) / 2
+    near = np.abs(ref - mid) <= 1e-9 * np.abs(ref)
+    bad = (got != r32) & ~near & (ref != 0)
+    assert not bad.any(), (int(bad.sum()), u[bad][:5], got[bad][:5], r32[bad][:5])
+
+
 def test_quantile_f32_paper_mode(ctx):
     """Paper (5,6) in FP32 (Appendix A): realized error of order 3e-7 down to
     u ~ 1e-11 (Section 6.3); checked at 5e-7 on its domain v <= 25."""
