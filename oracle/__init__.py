@@ -12,6 +12,11 @@ precision, see oracle.c):
   exp_to_normal(x)        sign(x) Phi^{-1}(1 - e^{-|x|}/2)     (Section 6)
   student_t_map(z, nu)    F_nu^{-1}(Phi(z))                    (Sections 1, 3.1)
   betainc(a, b, x)        regularized incomplete beta I_x(a,b) (used by the t map)
+  hyperbolic_map(v, alpha, beta, delta)
+                          F^{-1}(F0(v)), two-sided exponential base -> hyperbolic
+                          target (Section 8.1; hyperbolic.c)
+  hyperbolic_masses(...)  (log p+, log p-, log C) of the hyperbolic target
+  hyperbolic_log_tail(x, ...)  log(1 - F(x)) for x >= 0, log F(x) for x < 0
 """
 import ctypes
 import os
@@ -20,7 +25,7 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRC = os.path.join(_HERE, "oracle.c")
+_SRC = [os.path.join(_HERE, "oracle.c"), os.path.join(_HERE, "hyperbolic.c")]
 _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
@@ -29,7 +34,7 @@ def build(force=True):
     """Compile liboracle.so with gcc (no fast-math: the oracle needs IEEE semantics)."""
     if not force and os.path.exists(_LIB):
         return _LIB
-    cmd = ["gcc", "-O2", "-Wall", "-shared", "-fPIC", "-o", _LIB + ".tmp", _SRC, "-lm", "-lpthread"]
+    cmd = ["gcc", "-O2", "-Wall", "-shared", "-fPIC", "-o", _LIB + ".tmp"] + _SRC + ["-lm", "-lpthread"]
     subprocess.run(cmd, check=True)
     os.replace(_LIB + ".tmp", _LIB)
     return _LIB
@@ -57,6 +62,13 @@ def _load():
         f.restype = ctypes.c_double
     lib.oracle_student_t_map1.argtypes = [ctypes.c_double, ctypes.c_double]
     lib.oracle_student_t_map1.restype = ctypes.c_double
+    d = ctypes.c_double
+    lib.oracle_hyperbolic_map.argtypes = [dp, dp, ctypes.c_size_t, d, d, d, ctypes.c_int]
+    lib.oracle_hyperbolic_map.restype = ctypes.c_int
+    lib.oracle_hyperbolic_masses.argtypes = [d, d, d, dp, dp, dp]
+    lib.oracle_hyperbolic_masses.restype = ctypes.c_int
+    lib.oracle_hyperbolic_log_tail.argtypes = [d, d, d, d]
+    lib.oracle_hyperbolic_log_tail.restype = d
     _lib = lib
     return lib
 
@@ -101,3 +113,26 @@ def betainc(a, b, x):
 def threads_used(threads=0):
     """Number of threads the array drivers use for a given request."""
     return threads if threads > 0 else (os.cpu_count() or 1)
+
+
+def hyperbolic_map(v, alpha, beta, delta, threads=0):
+    """x = F^{-1}(F0(v)): two-sided exponential base -> hyperbolic target (Section 8.1)."""
+    v = _as_f64(v)
+    out = np.empty_like(v)
+    _load().oracle_hyperbolic_map(_ptr(v), _ptr(out), v.size, float(alpha), float(beta), float(delta),
+                                  threads_used(threads))
+    return out
+
+
+def hyperbolic_masses(alpha, beta, delta):
+    """(log p+, log p-, log C) of the hyperbolic density with these parameters."""
+    a, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    if _load().oracle_hyperbolic_masses(float(alpha), float(beta), float(delta), ctypes.byref(a), ctypes.byref(b),
+                                        ctypes.byref(c)) != 0:
+        raise ValueError("invalid hyperbolic parameters")
+    return a.value, b.value, c.value
+
+
+def hyperbolic_log_tail(x, alpha, beta, delta):
+    """log(1 - F(x)) for x >= 0, log F(x) for x < 0."""
+    return _load().oracle_hyperbolic_log_tail(float(x), float(alpha), float(beta), float(delta))
