@@ -187,6 +187,27 @@ def run_quantile(args, torch, qm, qi):
             avg = sum(ds) / len(ds)
             extra["student_t_f32_refine"][str(nu)] = {"gsamples_s": round(m / (avg * 1e-3) / 1e9, 2),
                                                       "gbs": round(8.0 * m / (avg * 1e-3) / 1e9, 1)}
+        # exponential -> hyperbolic (Section 8.1), base samples with the target's masses
+        extra["exp_to_hyperbolic_f64"] = {}
+        extra["exp_to_hyperbolic_f32"] = {}
+        for hp in (qi.HYPERBOLIC_PARAMS, (1.0, 0.5, 1.0)):
+            tb = time.perf_counter()
+            lp, lm = qm.qm_hyperbolic_masses(ctx, *hp)   # builds and caches the table
+            tb = time.perf_counter() - tb
+            hv = torch.from_numpy(qi.recycle_two_sided(m, hp[0], hp[1], math.exp(lm))).cuda()
+            ds = timed_launches(torch, stream, lambda: qm.qm_recycle_exp_to_hyperbolic(ctx, hv, o, *hp), 10)
+            avg = sum(ds) / len(ds)
+            key = "a%g_b%g_d%g" % hp
+            extra["exp_to_hyperbolic_f64"][key] = {"gsamples_s": round(m / (avg * 1e-3) / 1e9, 2),
+                                                  "gbs": round(16.0 * m / (avg * 1e-3) / 1e9, 1),
+                                                  "p50_ms": percentile(ds, 50), "p99_ms": percentile(ds, 99),
+                                                  "table_build_s": round(tb, 3)}
+            hv32 = hv.float()
+            ds = timed_launches(torch, stream, lambda: qm.qm_recycle_exp_to_hyperbolic(ctx, hv32, o32, *hp), 10)
+            avg = sum(ds) / len(ds)
+            extra["exp_to_hyperbolic_f32"][key] = {"gsamples_s": round(m / (avg * 1e-3) / 1e9, 2),
+                                                  "gbs": round(8.0 * m / (avg * 1e-3) / 1e9, 1)}
+            del hv, hv32
         # fused Philox generation + quantile (write-only), vs generation alone
         g64 = torch.empty(n, dtype=torch.float64, device="cuda")
         g32 = torch.empty(n, dtype=torch.float32, device="cuda")

@@ -10,6 +10,9 @@
  *                                                         (Section 6)
  *   qm_recycle_student_t      t = F_nu^{-1}(Phi(z))       (Section 1 recycling
  *                                composite, Section 3 recycling ODE)
+ *   qm_recycle_exp_to_hyperbolic
+ *                             x = F^{-1}(F0(v)), two-sided exponential base
+ *                             -> hyperbolic target        (Section 8.1)
  *   qm_generate               the uniforms of a counter-based stream, or w
  *                             of them, drawn and mapped in one pass
  *   qm_run_batch              many such requests in one persistent launch
@@ -148,6 +151,37 @@ qm_status qm_recycle_student_t(qm_ctx* ctx, const void* d_z, void* d_t, uint64_t
  */
 qm_status qm_recycle_exp_to_normal(qm_ctx* ctx, const void* d_x, void* d_z, uint64_t n,
                                    int dtype, int mode, void* hip_stream);
+
+/*
+ * x[i] = mu + Q(v[i]), the exponential -> hyperbolic recycling map
+ * (Section 8.1).  Target: the hyperbolic density
+ *   f(x) = gamma / (2 alpha delta K_1(delta gamma)) exp(-alpha sqrt(delta^2 + (x-mu)^2) + beta (x-mu)),
+ * gamma = sqrt(alpha^2 - beta^2).  Base: the two-sided exponential with the
+ * target's masses p+ (x > mu) and p- (x < mu), density
+ * p+ (alpha-beta) e^{-(alpha-beta) v} on v > 0 and p- (alpha+beta) e^{(alpha+beta) v}
+ * on v < 0 (qm_hyperbolic_masses gives log p+ and log p-; a base sample is
+ * -log(U)/(alpha-beta) with probability p+, log(U)/(alpha+beta) otherwise).
+ * Q = F^{-1}(F0(v)) is the solution of the left and right recycling ODEs
+ * with Q(0) = 0 and Q'(0) = f0(0+-)/f(0) (Section 8.1); the library
+ * integrates them on the host once per (alpha, beta, delta) (cached in the
+ * context, about a second) and evaluates piecewise polynomials of degree 11
+ * on the device.  Accuracy: relative 2e-15 in x - mu (F64), 2e-7 (F32, the
+ * F64 evaluation rounded once) for every v.  v = +-inf -> +-inf, NaN -> NaN.
+ * dtype/mode: F64 PLAIN; F32 F32_REFINE.
+ * Errors: QM_E_INVAL for alpha <= |beta|, delta <= 0, a non-finite
+ * parameter or mu, NULL, unaligned or partially overlapping buffers.
+ */
+qm_status qm_recycle_exp_to_hyperbolic(qm_ctx* ctx, const void* d_v, void* d_x, uint64_t n, int dtype, int mode,
+                                       double alpha, double beta, double delta, double mu, void* hip_stream);
+
+/*
+ * log p+ and log p- (host doubles; either pointer may be NULL): the
+ * hyperbolic target's masses on each side of mu (Section 8.1), which the
+ * base of qm_recycle_exp_to_hyperbolic carries.  Builds and caches the
+ * table like that call.  Errors as for it.
+ */
+qm_status qm_hyperbolic_masses(qm_ctx* ctx, double alpha, double beta, double delta, double* log_p_plus,
+                               double* log_p_minus);
 
 /*
  * Fused generation and transform.  Draws the open uniforms of elements

@@ -1,7 +1,8 @@
 /*
  * qm_debug.h -- host-only diagnostic entry points of libqm (no device work).
- * They expose the Student t table builder's intermediate results so that its
- * accuracy can be checked on a machine without a GPU.
+ * They expose the table builders' intermediate results (Student t, and the
+ * exponential -> hyperbolic map) so that their accuracy can be checked on a
+ * machine without a GPU.
  */
 #ifndef QM_DEBUG_H
 #define QM_DEBUG_H
@@ -30,6 +31,29 @@ int qm_debug_student_dense(double nu, const double* z, double* q, int n);
  * the build failed.
  */
 int qm_debug_student_table(double nu, void* header_out, double* coef_out, int coef_cap);
+
+/*
+ * The hyperbolic builder's solution of the exponential-background recycling
+ * ODE (Section 8.1), q[i] = Q(v[i]) for |v[i]| <= 1e12: the Taylor-series
+ * legs of each side within its anchor, the direct solution of the tail
+ * condition beyond (in __float128, rounded).  Parameters as for
+ * qm_hyperbolic_table_build.  Host arrays of n doubles.  Returns 0, or -1
+ * for invalid parameters, |v[i]| > 1e12 or a failed solve (reason on
+ * stderr).
+ */
+int qm_debug_hyperbolic_dense(double alpha, double beta, double delta, const double* v, double* q, int n);
+
+/*
+ * Build the hyperbolic table on the host.  header_out (may be NULL)
+ * receives the header (struct qm::HypTableHeader of csrc/qm_hyp_table.h,
+ * 184 bytes: parameters, the two sides' masses, and for each side the cell
+ * layout, large-v constants and the builder's check of its rounded rows);
+ * coef_out (may be NULL) receives the rows of both sides, at their
+ * coef_offset, if coef_cap doubles are enough.  Returns the number of
+ * doubles, or -1 if the build failed.
+ */
+int qm_debug_hyperbolic_table(double alpha, double beta, double delta, void* header_out, double* coef_out,
+                              int coef_cap);
 
 #ifdef __cplusplus
 }

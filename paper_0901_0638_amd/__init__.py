@@ -8,6 +8,7 @@ step of the maps runs in the library's HIP kernels.
     qm_normal_quantile(ctx, u, w)                 # w = Phi^{-1}(u)
     qm_recycle_student_t(ctx, z, t, nu=4.0)       # t = F_nu^{-1}(Phi(z))
     qm_recycle_exp_to_normal(ctx, x, z)           # z = sign(x) Phi^{-1}(1 - e^{-|x|}/2)
+    qm_recycle_exp_to_hyperbolic(ctx, v, x, alpha, beta, delta)   # x = F_hyp^{-1}(F0(v))
     qm_generate(ctx, seed, stream, first, w, QM_NORMAL_QUANTILE)   # w = Phi^{-1}(Philox uniforms)
 """
 import ctypes
@@ -22,7 +23,7 @@ _DTYPES = {"torch.float64": QM_F64, "torch.float32": QM_F32}
 
 
 class Context:
-    """Owns a qm_ctx (per-nu tables, serving state) on one HIP device."""
+    """Owns a qm_ctx (Student t and hyperbolic tables, serving state) on one HIP device."""
 
     def __init__(self, device=0, hbm_budget_bytes=0):
         lib = load()
@@ -114,6 +115,23 @@ def qm_recycle_exp_to_normal(ctx, x, z, mode=None, stream=None):
     check(load().qm_recycle_exp_to_normal(ctx.handle, pi, po, n, dt, mode, _stream(stream, x)))
 
 
+def qm_recycle_exp_to_hyperbolic(ctx, v, x, alpha, beta, delta, mu=0.0, mode=None, stream=None):
+    """x = mu + F^{-1}(F0(v)), two-sided exponential base -> hyperbolic (FP64 PLAIN or FP32 F32_REFINE)."""
+    pi, po, n, dt = _io(v, x)
+    if mode is None:
+        mode = QM_PLAIN if dt == QM_F64 else QM_F32_REFINE
+    check(load().qm_recycle_exp_to_hyperbolic(ctx.handle, pi, po, n, dt, mode, float(alpha), float(beta),
+                                              float(delta), float(mu), _stream(stream, v)))
+
+
+def qm_hyperbolic_masses(ctx, alpha, beta, delta):
+    """(log p+, log p-) of the hyperbolic target: the base's masses on each side."""
+    lp, lm = ctypes.c_double(), ctypes.c_double()
+    check(load().qm_hyperbolic_masses(ctx.handle, float(alpha), float(beta), float(delta), ctypes.byref(lp),
+                                      ctypes.byref(lm)))
+    return lp.value, lm.value
+
+
 def make_request(kind, inp, out, mode=None, nu=0.0, user_tag=0):
     """qm_request for qm_run_batch / qm_submit from a pair of device tensors."""
     pi, po, n, dt = _io(inp, out)
@@ -191,3 +209,51 @@ def debug_student_table(nu, which="f64"):
         lib.qm_debug_student_table(float(nu), None, block.ctypes.data_as(dp), n)
     coef = block[c.coef_offset:c.coef_offset + c.ncell * c.stride].reshape(c.ncell, c.stride)
     return h, c, coef
+
+
+class HypSide(ctypes.Structure):
+    """Layout of qm::HypSide (csrc/qm_hyp_table.h): the cells of one side of the hyperbolic map."""
+    _fields_ = [("v0", ctypes.c_double), ("inv_v0", ctypes.c_double), ("v_top", ctypes.c_double),
+                ("far_c0", ctypes.c_double), ("far_c1", ctypes.c_double), ("far_c2", ctypes.c_double),
+                ("max_rel_err", ctypes.c_double), ("noct", ctypes.c_int32), ("ncell", ctypes.c_int32),
+                ("coef_offset", ctypes.c_uint64)]
+
+
+class HypTableHeader(ctypes.Structure):
+    """Layout of qm::HypTableHeader (csrc/qm_hyp_table.h)."""
+    _fields_ = [("alpha", ctypes.c_double), ("beta", ctypes.c_double), ("delta", ctypes.c_double),
+                ("log_p_plus", ctypes.c_double), ("log_p_minus", ctypes.c_double),
+                ("right", HypSide), ("left", HypSide)]
+
+
+HYP_DEGREE = 11
+HYP_SUB = 8
+
+
+def debug_hyperbolic_dense(alpha, beta, delta, v):
+    """Host-side solution Q(v) that the hyperbolic tables are fitted to (qm_debug.h)."""
+    import numpy as np
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    q = np.empty_like(v)
+    dp = ctypes.POINTER(ctypes.c_double)
+    r = load().qm_debug_hyperbolic_dense(float(alpha), float(beta), float(delta), v.ctypes.data_as(dp),
+                                         q.ctypes.data_as(dp), v.size)
+    if r != 0:
+        raise ValueError("dense solution unavailable for %r" % ((alpha, beta, delta),))
+    return q
+
+
+def debug_hyperbolic_table(alpha, beta, delta):
+    """(header, right rows[ncell, HYP_DEGREE+1], left rows) of the host-built table."""
+    import numpy as np
+    h = HypTableHeader()
+    lib = load()
+    dp = ctypes.POINTER(ctypes.c_double)
+    n = lib.qm_debug_hyperbolic_table(float(alpha), float(beta), float(delta), ctypes.byref(h), None, 0)
+    if n < 0:
+        raise ValueError("table build failed for %r" % ((alpha, beta, delta),))
+    block = np.empty(n, np.float64)
+    lib.qm_debug_hyperbolic_table(float(alpha), float(beta), float(delta), None, block.ctypes.data_as(dp), n)
+    W = HYP_DEGREE + 1
+    rows = [block[s.coef_offset:s.coef_offset + s.ncell * W].reshape(s.ncell, W) for s in (h.right, h.left)]
+    return h, rows[0], rows[1]

@@ -56,6 +56,8 @@ SIGNATURES = {
     "qm_normal_quantile": (_st, [_vp, _vp, _vp, _u64, _i, _i, _vp]),
     "qm_recycle_student_t": (_st, [_vp, _vp, _vp, _u64, _i, _i, _d, _vp]),
     "qm_recycle_exp_to_normal": (_st, [_vp, _vp, _vp, _u64, _i, _i, _vp]),
+    "qm_recycle_exp_to_hyperbolic": (_st, [_vp, _vp, _vp, _u64, _i, _i, _d, _d, _d, _d, _vp]),
+    "qm_hyperbolic_masses": (_st, [_vp, _d, _d, _d, ctypes.POINTER(_d), ctypes.POINTER(_d)]),
     "qm_generate": (_st, [_vp, _u64, _u64, _u64, _vp, _u64, _i, _i, _i, _vp]),
     "qm_run_batch": (_st, [_vp, ctypes.POINTER(qm_request), _u64, _vp]),
     "qm_submit": (_st, [_vp, ctypes.POINTER(qm_request), ctypes.POINTER(_u64)]),
@@ -65,10 +67,12 @@ SIGNATURES = {
     "qm_last_error": (ctypes.c_char_p, []),
 }
 
-# include/qm_debug.h: host-only diagnostics of the Student t table builder
+# include/qm_debug.h: host-only diagnostics of the table builders
 DEBUG_SIGNATURES = {
     "qm_debug_student_dense": (ctypes.c_int, [_d, ctypes.POINTER(_d), ctypes.POINTER(_d), ctypes.c_int]),
     "qm_debug_student_table": (ctypes.c_int, [_d, _vp, ctypes.POINTER(_d), ctypes.c_int]),
+    "qm_debug_hyperbolic_dense": (ctypes.c_int, [_d, _d, _d, ctypes.POINTER(_d), ctypes.POINTER(_d), ctypes.c_int]),
+    "qm_debug_hyperbolic_table": (ctypes.c_int, [_d, _d, _d, _vp, ctypes.POINTER(_d), ctypes.c_int]),
 }
 
 _lib = None

@@ -4,7 +4,8 @@
 
 Device code is compiled by hipcc for gfx950 only, with packed-FP32 VALU
 instructions disabled; the Student t table builder (plain C++ with
-__float128) is compiled by g++ and linked in.
+__float128), and that of the hyperbolic tables, are compiled by g++ and
+linked in.
 """
 import os
 import subprocess
@@ -23,8 +24,9 @@ HIP_FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function", "-I", os.path.join(ROOT, "include"),
 ]
-HIP_SOURCES = ["qm_kernels.hip", "qm_student.hip", "qm_batch.hip", "qm_generate.hip", "qm_api.cpp", "qm_serve.cpp"]
-CXX_SOURCES = ["qm_table.cpp"]
+HIP_SOURCES = ["qm_kernels.hip", "qm_student.hip", "qm_batch.hip", "qm_generate.hip", "qm_hyp.hip", "qm_api.cpp",
+               "qm_serve.cpp"]
+CXX_SOURCES = ["qm_table.cpp", "qm_hyp_table.cpp"]
 
 
 def _run(cmd):

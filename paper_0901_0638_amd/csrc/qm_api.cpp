@@ -1,6 +1,7 @@
 /*
  * qm_api.cpp -- the C ABI of libqm (include/qm.h): argument validation,
- * context, per-nu table cache, and dispatch to the kernels.
+ * context, per-nu and per-(alpha, beta, delta) table caches, and dispatch
+ * to the kernels.
  */
 #include <hip/hip_runtime.h>
 
@@ -110,6 +111,35 @@ qm_status get_table(qm_ctx* ctx, double nu, const DeviceTable** out)
     return QM_OK;
 }
 
+/* Look up (or build and upload) the hyperbolic table for (alpha, beta, delta). */
+qm_status get_hyp_table(qm_ctx* ctx, double alpha, double beta, double delta, const DeviceHypTable** out)
+{
+    std::lock_guard<std::mutex> lk(ctx->table_mu);
+    auto key = std::make_tuple(alpha, beta, delta);
+    auto it = ctx->hyp_tables.find(key);
+    if (it != ctx->hyp_tables.end()) { *out = &it->second; return QM_OK; }
+    HostHypTable ht{};
+    char err[256] = {0};
+    if (build_hyperbolic_table(alpha, beta, delta, &ht, err, sizeof err) != 0)
+        return fail(QM_E_INVAL, "hyperbolic table for alpha=%g beta=%g delta=%g: %s", alpha, beta, delta, err);
+    size_t coef_bytes = (size_t)ht.ncoef * sizeof(double);
+    void* d = nullptr;
+    hipError_t e = hipMalloc(&d, sizeof(HypTableHeader) + coef_bytes);
+    if (e != hipSuccess) { free_hyperbolic_table(&ht); return fail(QM_E_NOMEM, "hipMalloc table: %s", hipGetErrorString(e)); }
+    e = hipMemcpy(d, &ht.hdr, sizeof(HypTableHeader), hipMemcpyHostToDevice);
+    if (e == hipSuccess && coef_bytes)
+        e = hipMemcpy((char*)d + sizeof(HypTableHeader), ht.coef, coef_bytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) { (void)hipFree(d); free_hyperbolic_table(&ht); return hip_fail(e, "upload table"); }
+    DeviceHypTable dt;
+    dt.hdr = ht.hdr;
+    dt.d_table = (HypTableHeader*)d;
+    dt.ncoef = ht.ncoef;
+    free_hyperbolic_table(&ht);
+    auto res = ctx->hyp_tables.emplace(key, dt);
+    *out = &res.first->second;
+    return QM_OK;
+}
+
 const TTableHeader* device_table_ptr(const DeviceTable* t) { return t->d_table; }
 const TTableHeader& device_table_hdr(const DeviceTable* t) { return t->hdr; }
 const LaunchShape& ctx_shape(const qm_ctx* ctx) { return ctx->shape; }
@@ -164,6 +194,8 @@ qm_status qm_init(int hip_device, uint64_t hbm_budget_bytes, qm_ctx** out)
         {&c->shape.hybrid[1], "QM_SHAPE_NQ64", 64, 4}, /* FP64 quantile */
         {&c->shape.student[0], "QM_SHAPE_T32", 3, 4},  /* Student t, FP32 outputs */
         {&c->shape.student[1], "QM_SHAPE_T64", 2, 4},  /* Student t, FP64 outputs */
+        {&c->shape.hyperbolic[0], "QM_SHAPE_H32", 2, 4}, /* exp -> hyperbolic, FP32 */
+        {&c->shape.hyperbolic[1], "QM_SHAPE_H64", 2, 4}, /* exp -> hyperbolic, FP64 */
     };
     long env_bpc = 0, env_unroll = 0;
     if (const char* ev = getenv("QM_BLOCKS_PER_CU")) env_bpc = strtol(ev, nullptr, 10);
@@ -193,6 +225,7 @@ void qm_shutdown(qm_ctx* ctx)
     if (ctx->server) { qm::server_stop(ctx->server); ctx->server = nullptr; }
     qm::runner_free(ctx);
     for (auto& kv : ctx->tables) (void)hipFree(kv.second.d_table);
+    for (auto& kv : ctx->hyp_tables) (void)hipFree(kv.second.d_table);
     delete ctx;
 }
 
@@ -232,6 +265,57 @@ qm_status qm_recycle_exp_to_normal(qm_ctx* ctx, const void* d_x, void* d_z, uint
                                    void* s)
 {
     return single(ctx, QM_EXP_TO_NORMAL, d_x, d_z, n, dtype, mode, 0.0, s);
+}
+
+static bool hyp_params_ok(double alpha, double beta, double delta)
+{
+    return std::isfinite(alpha) && std::isfinite(beta) && std::isfinite(delta) && delta > 0 && alpha > std::fabs(beta);
+}
+
+qm_status qm_recycle_exp_to_hyperbolic(qm_ctx* ctx, const void* d_v, void* d_x, uint64_t n, int dtype, int mode,
+                                       double alpha, double beta, double delta, double mu, void* s)
+{
+    if (!ctx) return fail(QM_E_INVAL, "context is NULL");
+    if (dtype != QM_F32 && dtype != QM_F64) return fail(QM_E_INVAL, "unknown dtype %d", dtype);
+    if (mode != QM_PLAIN && mode != QM_F32_REFINE && mode != QM_PAPER) return fail(QM_E_INVAL, "unknown mode %d", mode);
+    if (!(dtype == QM_F64 && mode == QM_PLAIN) && !(dtype == QM_F32 && mode == QM_F32_REFINE))
+        return fail(QM_E_DTYPE, "exp->hyperbolic: F64 QM_PLAIN or F32 QM_F32_REFINE");
+    if (!hyp_params_ok(alpha, beta, delta))
+        return fail(QM_E_INVAL, "need |beta| < alpha, delta > 0, all finite (got %g, %g, %g)", alpha, beta, delta);
+    if (!std::isfinite(mu)) return fail(QM_E_INVAL, "mu must be finite");
+    const size_t es = dtype_size(dtype);
+    if (n > 0) {
+        if (!d_v || !d_x) return fail(QM_E_INVAL, "NULL buffer with n > 0");
+        uintptr_t a = (uintptr_t)d_v, b = (uintptr_t)d_x;
+        if (a % es || b % es) return fail(QM_E_INVAL, "buffers must be aligned to the element size");
+        if (n > (UINT64_MAX / 2) / es) return fail(QM_E_INVAL, "n too large");
+        uint64_t bytes = n * es;
+        if (a != b && a < b + bytes && b < a + bytes) return fail(QM_E_INVAL, "input and output partially overlap");
+    }
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    const DeviceHypTable* t = nullptr;
+    qm_status st = qm::get_hyp_table(ctx, alpha, beta, delta, &t);
+    if (st != QM_OK || n == 0) return st;
+    e = qm::launch_hyperbolic(dtype, mode, d_v, d_x, n, t->d_table, t->hdr, t->ncoef, mu, (hipStream_t)s, ctx->shape);
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    return QM_OK;
+}
+
+qm_status qm_hyperbolic_masses(qm_ctx* ctx, double alpha, double beta, double delta, double* log_p_plus,
+                               double* log_p_minus)
+{
+    if (!ctx) return fail(QM_E_INVAL, "context is NULL");
+    if (!hyp_params_ok(alpha, beta, delta))
+        return fail(QM_E_INVAL, "need |beta| < alpha, delta > 0, all finite (got %g, %g, %g)", alpha, beta, delta);
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    const DeviceHypTable* t = nullptr;
+    qm_status st = qm::get_hyp_table(ctx, alpha, beta, delta, &t);
+    if (st != QM_OK) return st;
+    if (log_p_plus) *log_p_plus = t->hdr.log_p_plus;
+    if (log_p_minus) *log_p_minus = t->hdr.log_p_minus;
+    return QM_OK;
 }
 
 qm_status qm_generate(qm_ctx* ctx, uint64_t seed, uint64_t stream, uint64_t first, void* d_out, uint64_t n,

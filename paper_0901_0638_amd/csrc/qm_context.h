@@ -4,6 +4,7 @@
 #pragma once
 #include <map>
 #include <mutex>
+#include <tuple>
 #include <vector>
 
 #include "qm_internal.h"
@@ -18,12 +19,19 @@ struct DeviceTable {
     qm::TTableHeader* d_table = nullptr;  /* header followed by coefficients */
 };
 
+struct DeviceHypTable {
+    qm::HypTableHeader hdr;
+    qm::HypTableHeader* d_table = nullptr;  /* header followed by both sides' rows */
+    uint64_t ncoef = 0;
+};
+
 struct qm_ctx {
     int device = 0;
     uint64_t budget = 0;
     qm::LaunchShape shape{};
     std::mutex table_mu;
     std::map<double, DeviceTable> tables;
+    std::map<std::tuple<double, double, double>, DeviceHypTable> hyp_tables;  /* (alpha, beta, delta) */
     std::mutex server_mu;
     qm::Server* server = nullptr;
     qm::BatchRunner* runner = nullptr;

@@ -1,0 +1,684 @@
+/*
+ * qm_hyp_table.cpp -- host builder of the exponential -> hyperbolic tables.
+ *
+ * Section 8.1: the hyperbolic target (mu = 0)
+ *     f(x) = C exp(-alpha sqrt(delta^2 + x^2) + beta x),
+ *     C = gamma / (2 alpha delta K_1(delta gamma)),  gamma = sqrt(alpha^2 - beta^2),
+ * is reached from the two-sided exponential base with the target's masses
+ * p+ and p- on each side and rates alpha - beta (right), alpha + beta
+ * (left), so that Q(0) = 0.  With H(x) = alpha x / sqrt(delta^2 + x^2) - beta
+ * (minus the log-derivative of f), the right map solves the recycling ODE
+ *     Q'' + (alpha - beta) Q' = H(Q) Q'^2,  Q(0) = 0,
+ *     Q'(0) = p+ (alpha - beta) / f(0) = 2 p+ (alpha - beta) (alpha delta / gamma) K_1(delta gamma) e^{alpha delta},
+ * and the left map is the right map of the mirrored target (beta -> -beta),
+ * reflected: Q(v) = -Q~(-v).
+ *
+ * As for the Student t builder, the ODE is integrated by the Taylor-series
+ * method in __float128 -- here the series of H(Q) comes from those of
+ * Q^2 + delta^2 and of its inverse square root (J. C. P. Miller's
+ * recurrence for a power of a series) -- and from both ends: outwards from
+ * the centre conditions, and inwards from an anchor v_a, where Q solves the
+ * tail condition log(1 - F(Q)) = log p+ - (alpha - beta) v_a directly;
+ * outward integration would amplify any error by e^{(alpha-beta) v}.
+ * Beyond v_a, Q is that direct solution (Newton), with the tail mass in
+ * closed form up to one smooth integral: with s = asinh(x/delta) and
+ * c = cosh(s - s_peak) (alpha = gamma cosh s_peak, beta = gamma sinh s_peak),
+ *     1 - F(x) = (C delta / z) e^{-z c0} (e^{s_peak} + cosh(s_peak) K),
+ *     K = int_0^inf e^{-t} (h(c0 + t/z) - 1) dt,  h(c) = c / sqrt(c^2 - 1),
+ * z = delta gamma, c0 = c at x, z c0 = alpha sqrt(delta^2 + x^2) - beta x;
+ * K by Gauss-Laguerre quadrature, accurate once D = z (c0 - 1) is large
+ * (the singularity of h at c = 1 lies a distance D to the left of t = 0).
+ * An explicit integrator cannot take steps much longer than 1/(alpha - beta)
+ * there (the decaying mode of the backward direction limits them), which
+ * would make the far range, out to where the large-v form below holds,
+ * cost millions of steps.  The table holds R(v) = Q(v)/v in
+ * cells of t = v / v0: eight uniform cells on [0, 1), then eight per octave
+ * of t, so that the relative width of a cell is the same at every scale
+ * (Q is nearly v + const far out, and curved on the scale delta near 0).
+ * Each cell holds the degree-11 Chebyshev interpolant of R as monomials in
+ * d = v - centre, checked against the solution.  Beyond the last
+ * octave, Q = v + c0 + c1/v + c2/v^2 (the expansion of the tail condition
+ * for large v, derived at solve_side), checked there too.
+ */
+#include <quadmath.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <vector>
+
+#include "qm_hyp_table.h"
+
+namespace qm {
+namespace {
+
+typedef __float128 fq;
+
+constexpr int TM = 32;              /* Taylor order of the integrator */
+constexpr int GLN = 24;             /* Gauss-Legendre nodes per panel */
+
+struct GL {
+    fq x[GLN], w[GLN];
+    GL()
+    {
+        for (int i = 0; i < GLN; ++i) {
+            fq x0 = cosq(M_PIq * (i + 0.75Q) / (GLN + 0.5Q)), dp = 0;
+            for (int it = 0; it < 100; ++it) {
+                fq p0 = 1, p1 = x0;
+                for (int k = 2; k <= GLN; ++k) {
+                    fq p2 = ((2 * k - 1) * x0 * p1 - (k - 1) * p0) / k;
+                    p0 = p1;
+                    p1 = p2;
+                }
+                dp = GLN * (x0 * p1 - p0) / (x0 * x0 - 1);
+                fq dx = p1 / dp;
+                x0 -= dx;
+                if (fabsq(dx) < 1e-33Q) break;
+            }
+            x[i] = x0;
+            w[i] = 2 / ((1 - x0 * x0) * dp * dp);
+        }
+    }
+};
+
+const GL& gl()
+{
+    static const GL g;
+    return g;
+}
+
+/* One side of the target: parameters and its tail masses. */
+struct Side {
+    fq alpha, beta, delta, gamma, rate;
+    fq ad, bd, dg, speak;   /* alpha delta, beta delta, delta gamma, peak of E in s */
+    fq log_c;               /* log C */
+    fq log_p;               /* log of this side's mass */
+
+    /* E(s) = -alpha delta cosh s + beta delta sinh s + delta gamma <= 0 */
+    fq E(fq s) const { return -ad * coshq(s) + bd * sinhq(s) + dg; }
+
+    fq panel(fq a, fq b, fq shift) const
+    {
+        const GL& g = gl();
+        fq c = (a + b) / 2, r = (b - a) / 2, sum = 0;
+        for (int i = 0; i < GLN; ++i) {
+            fq s = c + r * g.x[i];
+            sum += g.w[i] * expq(E(s) - shift) * coshq(s);
+        }
+        return sum * r;
+    }
+
+    fq adapt(fq a, fq b, fq shift, fq whole, fq tol, int depth) const
+    {
+        fq m = (a + b) / 2;
+        fq l = panel(a, m, shift), r = panel(m, b, shift);
+        fq diff = fabsq(l + r - whole);
+        fq noise = 1e-32Q * (1 + fabsq(E(a)) + fabsq(E(b)));
+        if (depth >= 30 || diff <= tol || diff <= noise * (l + r)) return l + r;
+        return adapt(a, m, shift, l, tol / 2, depth + 1) + adapt(m, b, shift, r, tol / 2, depth + 1);
+    }
+
+    /* int_a^b e^{E(s) - shift} cosh s ds */
+    fq integral(fq a, fq b, fq shift, fq floor_tol = 0) const
+    {
+        if (!(b > a)) return 0;
+        fq whole = panel(a, b, shift);
+        fq tol = 1e-31Q * fabsq(whole);
+        if (tol < floor_tol) tol = floor_tol;
+        return adapt(a, b, shift, whole, tol, 0);
+    }
+
+    /* int_a^inf, by panels 1/|E'(a)| wide past the peak (the decay length) */
+    fq integral_to_inf(fq a, fq shift) const
+    {
+        fq slope = ad * sinhq(a) - bd * coshq(a);
+        fq w = (a > speak && slope > 1) ? 1 / slope : 1;
+        fq sum = 0;
+        for (int k = 0; k < 100000; ++k) {
+            fq p = integral(a + k * w, a + (k + 1) * w, shift, 1e-33Q * sum);
+            sum += p;
+            if (a + k * w > speak && p <= 1e-36Q * sum) break;
+        }
+        return sum;
+    }
+
+    /* f dx = C delta e^{-delta gamma} e^{E(s)} cosh s ds */
+    fq log_scale() const { return log_c + logq(delta) - dg; }
+
+    /* log(1 - F(x)), x >= 0 */
+    fq log_upper(fq x) const
+    {
+        fq S = asinhq(x / delta);
+        if (S > speak) {
+            fq e = E(S);
+            return log_scale() + e + logq(integral_to_inf(S, e));
+        }
+        return log_scale() + logq(integral(S, speak, 0) + integral_to_inf(speak, 0));
+    }
+
+    fq log_f(fq x) const { return log_c - alpha * sqrtq(delta * delta + x * x) + beta * x; }
+};
+
+/* K_1(z) = int_0^inf e^{-z cosh t} cosh t dt, scaled by e^{z} (DLMF 10.32.8) */
+fq log_bessel_k1(fq z)
+{
+    Side k{};
+    k.ad = z;
+    k.bd = 0;
+    k.dg = z;     /* E(t) = -z cosh t + z = -z (cosh t - 1) */
+    k.speak = 0;
+    return logq(k.integral(0, 1, 0) + k.integral_to_inf(1, 0)) - z;
+}
+
+Side make_side(fq alpha, fq beta, fq delta)
+{
+    Side s{};
+    s.alpha = alpha;
+    s.beta = beta;
+    s.delta = delta;
+    s.gamma = sqrtq((alpha - beta) * (alpha + beta));
+    s.rate = alpha - beta;
+    s.ad = alpha * delta;
+    s.bd = beta * delta;
+    s.dg = delta * s.gamma;
+    s.speak = atanhq(beta / alpha);
+    s.log_c = logq(s.gamma / (2 * alpha * delta)) - log_bessel_k1(delta * s.gamma);
+    s.log_p = s.log_upper(0);
+    return s;
+}
+
+/*
+ * Taylor coefficients of the right map about v0 from a[0] = Q(v0),
+ * a[1] = Q'(v0): with P = Q'^2, S = delta^2 + Q^2, R = S^{-1/2} (Miller:
+ * R_k = (1/(k S_0)) sum_{j=1..k} ((1/2) j - k) S_j R_{k-j}) and
+ * H = alpha Q R - beta, the power d^k of Q'' + rate Q' = H P gives
+ * (k+2)(k+1) a_{k+2} = (H P)_k - rate (k+1) a_{k+1}.
+ */
+void taylor_step(const Side& sd, fq* a)
+{
+    fq P[TM + 1], S[TM + 1], R[TM + 1], H[TM + 1];
+    for (int k = 0; k + 2 <= TM; ++k) {
+        fq p = 0, s2 = 0;
+        for (int i = 0; i <= k; ++i) {
+            p += (fq)(i + 1) * a[i + 1] * (fq)(k - i + 1) * a[k - i + 1];
+            s2 += a[i] * a[k - i];
+        }
+        P[k] = p;
+        S[k] = s2 + (k == 0 ? sd.delta * sd.delta : (fq)0);
+        if (k == 0) {
+            R[0] = 1 / sqrtq(S[0]);
+        } else {
+            fq acc = 0;
+            for (int j = 1; j <= k; ++j) acc += ((fq)j / 2 - (fq)k) * S[j] * R[k - j];
+            R[k] = acc / ((fq)k * S[0]);
+        }
+        fq qr = 0;
+        for (int i = 0; i <= k; ++i) qr += a[i] * R[k - i];
+        H[k] = sd.alpha * qr - (k == 0 ? sd.beta : (fq)0);
+        fq hp = 0;
+        for (int i = 0; i <= k; ++i) hp += H[i] * P[k - i];
+        a[k + 2] = (hp - sd.rate * (fq)(k + 1) * a[k + 1]) / ((fq)(k + 2) * (fq)(k + 1));
+    }
+}
+
+struct Node {
+    fq v0, h;
+    fq a[TM + 1];
+};
+
+fq horner(const fq* a, fq d)
+{
+    fq r = a[TM];
+    for (int k = TM - 1; k >= 0; --k) r = r * d + a[k];
+    return r;
+}
+
+fq horner_d(const fq* a, fq d)
+{
+    fq r = TM * a[TM];
+    for (int k = TM - 1; k >= 1; --k) r = r * d + k * a[k];
+    return r;
+}
+
+/* Largest step with the last two Taylor terms below 1e-36 |Q| (at most hmax) */
+fq step_size(const fq* a, fq hmax)
+{
+    fq scale = fabsq(a[0]) + fabsq(a[1]) * 1e-3Q + 1e-300Q, h = hmax;
+    for (int k = TM - 1; k <= TM; ++k) {
+        if (a[k] == 0) continue;
+        fq hk = powq(1e-36Q * scale / fabsq(a[k]), 1.0Q / k);
+        if (hk < h) h = hk;
+    }
+    return h;
+}
+
+void integrate(const Side& sd, fq v, fq Q, fq dQ, fq v1, std::vector<Node>& out)
+{
+    fq dir = v1 > v ? 1 : -1;
+    for (int guard = 0; guard < 1000000; ++guard) {
+        Node n;
+        n.v0 = v;
+        n.a[0] = Q;
+        n.a[1] = dQ;
+        taylor_step(sd, n.a);
+        fq hmax = 0.25Q + 0.05Q * fabsq(v);
+        fq h = step_size(n.a, hmax);
+        bool last = fabsq(v1 - v) <= h;
+        if (last) h = fabsq(v1 - v);
+        n.h = dir * h;
+        out.push_back(n);
+        Q = horner(n.a, n.h);
+        dQ = horner_d(n.a, n.h);
+        v += n.h;
+        if (last) break;
+    }
+}
+
+/*
+ * Gauss-Laguerre rule (weight e^{-t} on [0, inf)): the nodes are the
+ * eigenvalues of the Jacobi matrix of the Laguerre polynomials (diagonal
+ * 2i + 1, off-diagonal i + 1), found one by one by bisection on the Sturm
+ * count of negative pivots of J - lambda I; weights
+ * w_i = t_i / ((n + 1)^2 L_{n+1}(t_i)^2) (Abramowitz and Stegun 25.4.45).
+ */
+constexpr int GLAG = 48;
+
+struct Laguerre {
+    fq t[GLAG], w[GLAG];
+    static int below(fq lam)
+    {
+        int neg = 0;
+        fq d = 1 - lam;
+        if (d < 0) ++neg;
+        for (int i = 1; i < GLAG; ++i) {
+            if (d == 0) d = 1e-60Q;
+            d = (2 * i + 1 - lam) - (fq)i * (fq)i / d;
+            if (d < 0) ++neg;
+        }
+        return neg;
+    }
+    Laguerre()
+    {
+        for (int i = 0; i < GLAG; ++i) {
+            fq lo = 0, hi = 4 * GLAG + 2;
+            for (int it = 0; it < 240; ++it) {
+                fq mid = (lo + hi) / 2;
+                if (below(mid) > i) hi = mid; else lo = mid;
+                if (hi - lo <= 1e-33Q * hi) break;
+            }
+            fq x = (lo + hi) / 2;
+            fq p0 = 1, p1 = 1 - x;
+            for (int k = 1; k <= GLAG; ++k) {
+                fq p2 = ((2 * k + 1 - x) * p1 - k * p0) / (k + 1);
+                p0 = p1;
+                p1 = p2;
+            }
+            t[i] = x;
+            w[i] = x / ((fq)(GLAG + 1) * (fq)(GLAG + 1) * p1 * p1);
+        }
+    }
+};
+
+const Laguerre& laguerre()
+{
+    static const Laguerre g;
+    return g;
+}
+
+/* D = alpha sqrt(delta^2 + x^2) - beta x - delta gamma (the depth below the
+   density's peak), with z c0 = r x + alpha delta^2 / (sqrt(delta^2 + x^2) + x)
+   formed without cancellation for x >= 0. */
+fq depth(const Side& sd, fq x, fq* zc0)
+{
+    fq rt = sqrtq(sd.delta * sd.delta + x * x);
+    fq zc = sd.rate * x + sd.alpha * sd.delta * sd.delta / (rt + x);
+    if (zc0) *zc0 = zc;
+    return zc - sd.dg;
+}
+
+/* log(1 - F(x)) and the ratio m = (1 - F)/f at x past the peak (D large). */
+void far_tail(const Side& sd, fq x, fq* log_t, fq* m)
+{
+    const Laguerre& L = laguerre();
+    fq zc0, D = depth(sd, x, &zc0);
+    const fq z = sd.dg;
+    fq K = 0;
+    for (int i = 0; i < GLAG; ++i) {
+        fq a = (D + L.t[i]) / z;            /* c - 1 */
+        fq ra = sqrtq(a * (a + 2));         /* sqrt(c^2 - 1) */
+        K += L.w[i] / (ra * (1 + a + ra));  /* h(c) - 1 */
+    }
+    fq br = expq(sd.speak) + coshq(sd.speak) * K;
+    *log_t = sd.log_c + logq(sd.delta / z) - zc0 + logq(br);
+    *m = sd.delta / z * br;
+}
+
+constexpr fq D_MIN = 24;   /* Laguerre error ~ e^{-4 sqrt(GLAG D)} << 1e-34 */
+
+/* Q(v) for v past the anchor: Newton on log(1 - F(Q)) = log p - r v, from x0. */
+fq solve_far(const Side& sd, fq v, fq x0)
+{
+    const fq target = sd.log_p - sd.rate * v;
+    fq x = x0;
+    for (int it = 0; it < 40; ++it) {
+        fq lt, m;
+        far_tail(sd, x, &lt, &m);
+        fq dx = m * (lt - target);
+        x += dx;
+        if (fabsq(dx) <= 1e-22Q * x) break;     /* the next step would be below 1e-40 */
+    }
+    return x;
+}
+
+/* The solution of one side: ODE legs on [0, v_a], direct solves beyond. */
+struct SideSolution {
+    const Side* sd;
+    std::vector<Node> fwd, bwd;
+    fq v_match, v_a;
+    fq slope0;          /* Q'(0) */
+    fq c0, c1, c2;      /* Q = v + c0 + c1/v + c2/v^2 + O(v^-3) */
+
+    fq far(fq v) const { return v + c0 + (c1 + c2 / v) / v; }
+
+    fq eval(fq v) const
+    {
+        if (v > v_a) return solve_far(*sd, v, far(v));
+        const std::vector<Node>& nd = v <= v_match ? fwd : bwd;
+        /* fwd nodes increase in v0, bwd nodes decrease */
+        size_t lo = 0, hi = nd.size() - 1;
+        const bool up = nd.front().h > 0;
+        while (lo < hi) {
+            size_t mid = (lo + hi) / 2;
+            fq a = nd[mid].v0, b = nd[mid].v0 + nd[mid].h;
+            fq lo_v = up ? a : b, hi_v = up ? b : a;
+            if (v < lo_v) {
+                if (up) hi = mid; else lo = mid + 1;
+            } else if (v > hi_v) {
+                if (up) lo = mid + 1; else hi = mid;
+            } else {
+                lo = hi = mid;
+            }
+        }
+        return horner(nd[lo].a, v - nd[lo].v0);
+    }
+};
+
+int fail(char* err, int errlen, const char* msg)
+{
+    snprintf(err, errlen, "%s", msg);
+    return -1;
+}
+
+/* Chebyshev interpolant of fv (values at the K+1 Chebyshev points of
+   [c - hw, c + hw]) as monomials in d = v - c. */
+void cheb_to_monomial(const fq* fv, int K, fq hw, fq* mono)
+{
+    const int N = K + 1;
+    fq ck[64], Tp[64], Tc[64], Tn[64];
+    for (int j = 0; j < N; ++j) {
+        fq s = 0;
+        for (int i = 0; i < N; ++i) s += fv[i] * cosq(M_PIq * j * (i + 0.5Q) / N);
+        ck[j] = s * 2 / N;
+    }
+    ck[0] /= 2;
+    for (int i = 0; i < N; ++i) {
+        mono[i] = 0;
+        Tp[i] = 0;
+        Tc[i] = 0;
+    }
+    Tp[0] = 1;
+    Tc[1] = 1;
+    for (int i = 0; i < N; ++i) mono[i] += ck[0] * Tp[i] + ck[1] * Tc[i];
+    for (int j = 2; j < N; ++j) {
+        for (int i = 0; i < N; ++i) Tn[i] = -Tp[i] + (i > 0 ? 2 * Tc[i - 1] : (fq)0);
+        for (int i = 0; i < N; ++i) mono[i] += ck[j] * Tn[i];
+        memcpy(Tp, Tc, sizeof(fq) * N);
+        memcpy(Tc, Tn, sizeof(fq) * N);
+    }
+    fq sc = 1;
+    for (int i = 0; i < N; ++i) {
+        mono[i] /= sc;
+        sc *= hw;
+    }
+}
+
+/*
+ * Large-v form.  With phi = log f - log C = -alpha sqrt(delta^2 + x^2) + beta x
+ * = -r x - alpha delta^2/(2x) + O(x^-3) (r = alpha - beta), the tail mass is
+ * T = C e^phi / (-phi') (1 + O(phi''/phi'^2)) with -phi' = r - alpha delta^2/(2x^2)
+ * + O(x^-4) and phi'' = O(x^-3), so log T = log(C/r) - r x - a/x + a/(r x^2)
+ * + O(x^-3), a = alpha delta^2 / 2.  Solving log T(Q) = log p - r v for Q
+ * and expanding 1/Q gives c0 = log(C/(r p))/r, c1 = -a/r,
+ * c2 = (a/r)(c0 + 1/r).
+ */
+bool solve_side(const Side& sd, SideSolution* ss, char* err, int errlen)
+{
+    const fq r = sd.rate;
+    ss->sd = &sd;
+    ss->c0 = (sd.log_c - logq(r) - sd.log_p) / r;
+    const fq a = sd.alpha * sd.delta * sd.delta / 2;
+    ss->c1 = -a / r;
+    ss->c2 = (a / r) * (ss->c0 + 1 / r);
+    ss->slope0 = expq(sd.log_p - sd.log_f(0)) * r;
+    /* the anchor: far enough for the forward leg to stop at 20/r and for
+       the direct solve to be accurate (D >= D_MIN) */
+    fq va = 40 / r;
+    for (int it = 0; it < 200; ++it) {
+        fq x = solve_far(sd, va, ss->far(va) > 0 ? ss->far(va) : va);
+        if (depth(sd, x, nullptr) >= D_MIN && x > 0) break;
+        va *= 1.25Q;
+    }
+    ss->v_a = va;
+    ss->v_match = 20 / r;
+    integrate(sd, 0, 0, ss->slope0, ss->v_match, ss->fwd);
+    const fq Qa = solve_far(sd, va, ss->far(va));
+    const fq dQa = expq(sd.log_p - r * va + logq(r) - sd.log_f(Qa));
+    integrate(sd, va, Qa, dQa, ss->v_match, ss->bwd);
+    const Node& f = ss->fwd.back();
+    const Node& b = ss->bwd.back();
+    fq qf = horner(f.a, f.h), qb = horner(b.a, b.h);
+    fq df = horner_d(f.a, f.h), db = horner_d(b.a, b.h);
+    fq mis = fabsq(qf / qb - 1) + fabsq(df / db - 1);
+    if (!(mis < 1e-22Q)) {
+        snprintf(err, errlen, "legs disagree at v=%g by %.3e", (double)ss->v_match, (double)mis);
+        return false;
+    }
+    return true;
+}
+
+/* The smallest power of 2, P, from which on the large-v form meets tol
+   (checked on [P, 3P]). */
+bool far_start(const SideSolution& ss, fq tol, fq* P)
+{
+    fq p = ldexpq(1, (int)ceilq(log2q(ldexpq(1, 30) / ss.sd->rate)));
+    auto holds = [&](fq q) {
+        for (int i = 0; i <= 16; ++i) {
+            fq v = q * (1 + (fq)i / 8);
+            if (fabsq(ss.far(v) / ss.eval(v) - 1) > tol) return false;
+        }
+        return true;
+    };
+    if (!holds(p)) return false;
+    while (p > ldexpq(1, -40) && holds(p / 2)) p /= 2;
+    *P = p;
+    return true;
+}
+
+/*
+ * Fit R = Q/v on [lo, hi] (degree HYP_DEGREE, Chebyshev points), rounded to
+ * double, highest power first.  Returns the largest relative error of the
+ * interpolant at 2 HYP_DEGREE + 1 points against the solution; *rounded
+ * gets that of the double row (which includes the rounding of R itself).
+ */
+fq fit_cell(const SideSolution& ss, fq lo, fq hi, double* row, fq* rounded)
+{
+    fq c = (lo + hi) / 2, hw = (hi - lo) / 2;
+    fq fv[64], mono[64];
+    for (int i = 0; i <= HYP_DEGREE; ++i) {
+        fq v = c + hw * cosq(M_PIq * (i + 0.5Q) / (HYP_DEGREE + 1));
+        fv[i] = ss.eval(v) / v;
+    }
+    cheb_to_monomial(fv, HYP_DEGREE, hw, mono);
+    for (int k = 0; k <= HYP_DEGREE; ++k) row[HYP_DEGREE - k] = (double)mono[k];
+    fq worst = 0, worst_r = 0;
+    const int NT = 2 * HYP_DEGREE;
+    for (int t = 0; t <= NT; ++t) {
+        fq d = -hw + 2 * hw * t / NT;
+        fq v = c + d;
+        fq ref = v > 0 ? ss.eval(v) / v : ss.slope0;
+        fq pe = 0, pr = 0;
+        for (int k = HYP_DEGREE; k >= 0; --k) pe = pe * d + mono[k];
+        for (int k = 0; k <= HYP_DEGREE; ++k) pr = pr * d + (fq)row[k];
+        fq et = fabsq(pe / ref - 1), er = fabsq(pr / ref - 1);
+        if (et > worst) worst = et;
+        if (er > worst_r) worst_r = er;
+    }
+    *rounded = worst_r;
+    return worst;
+}
+
+/*
+ * Cells of one side.  The octave cells [2^e (1 + i/S), 2^e (1 + (i+1)/S))
+ * do not depend on v0, so they are fitted once, from the top octave down;
+ * v0 = 2^e is the largest power of 2 whose uniform cells on [0, v0) meet
+ * the tolerance.  Returns false if none does.
+ */
+bool fit_side(const SideSolution& ss, std::vector<double>& coef, HypSide* hs, char* err, int errlen)
+{
+    const fq tol = 2e-17Q;
+    fq v_top;
+    if (!far_start(ss, tol / 4, &v_top)) {
+        snprintf(err, errlen, "large-v form not accurate at 2^30 / (alpha - beta)");
+        return false;
+    }
+    const int top_exp = (int)lrintq(log2q(v_top));
+    const int W = HYP_DEGREE + 1;
+    std::vector<double> oct;    /* octave rows, top octave first */
+    fq worst = 0;   /* of the rounded rows */
+    for (int e = top_exp; e >= top_exp - HYP_MAX_OCT; --e) {
+        /* try v0 = 2^e: uniform cells on [0, 2^e) */
+        const fq v0 = ldexpq(1, e);
+        std::vector<double> uni((size_t)HYP_SUB * W);
+        fq wu = 0, wu_r = 0;
+        for (int j = 0; j < HYP_SUB && wu <= tol; ++j) {
+            fq rj, ej = fit_cell(ss, v0 * j / HYP_SUB, v0 * (j + 1) / HYP_SUB, &uni[(size_t)j * W], &rj);
+            if (ej > wu) wu = ej;
+            if (rj > wu_r) wu_r = rj;
+        }
+        if (wu <= tol) {
+            const int noct = top_exp - e;
+            hs->v0 = (double)v0;
+            hs->inv_v0 = (double)(1 / v0);
+            hs->v_top = (double)v_top;
+            hs->far_c0 = (double)ss.c0;
+            hs->far_c1 = (double)ss.c1;
+            hs->far_c2 = (double)ss.c2;
+            hs->max_rel_err = (double)(wu_r > worst ? wu_r : worst);
+            hs->noct = noct;
+            hs->ncell = HYP_SUB * (noct + 1);
+            hs->coef_offset = coef.size();
+            coef.insert(coef.end(), uni.begin(), uni.end());
+            /* octaves in increasing order: octave k covers [v0 2^k, v0 2^(k+1)) */
+            for (int k = 0; k < noct; ++k) {
+                size_t at = (size_t)(noct - 1 - k) * HYP_SUB * W;
+                coef.insert(coef.end(), oct.begin() + at, oct.begin() + at + (size_t)HYP_SUB * W);
+            }
+            return true;
+        }
+        /* otherwise the octave [2^(e-1), 2^e) joins the table */
+        const fq base = ldexpq(1, e - 1);
+        std::vector<double> rows((size_t)HYP_SUB * W);
+        for (int i = 0; i < HYP_SUB; ++i) {
+            fq ri, ei = fit_cell(ss, base * (1 + (fq)i / HYP_SUB), base * (1 + (fq)(i + 1) / HYP_SUB),
+                                 &rows[(size_t)i * W], &ri);
+            if (ei > tol) {
+                snprintf(err, errlen, "cell near v=%g misses the accuracy target (%.2e)", (double)base, (double)ei);
+                return false;
+            }
+            if (ri > worst) worst = ri;
+        }
+        oct.insert(oct.end(), rows.begin(), rows.end());
+    }
+    snprintf(err, errlen, "more than %d octaves needed", HYP_MAX_OCT);
+    return false;
+}
+
+bool check_params(double alpha, double beta, double delta)
+{
+    return std::isfinite(alpha) && std::isfinite(beta) && std::isfinite(delta) && delta > 0 &&
+           alpha > std::fabs(beta);
+}
+
+}  // namespace
+
+int build_hyperbolic_table(double alpha, double beta, double delta, HostHypTable* out, char* err, int errlen)
+{
+    memset(out, 0, sizeof *out);
+    if (!check_params(alpha, beta, delta)) return fail(err, errlen, "need |beta| < alpha and delta > 0, all finite");
+    HypTableHeader& H = out->hdr;
+    H.alpha = alpha;
+    H.beta = beta;
+    H.delta = delta;
+    const Side right = make_side(alpha, beta, delta);
+    const Side left = make_side(alpha, -(fq)beta, delta);
+    H.log_p_plus = (double)right.log_p;
+    H.log_p_minus = (double)left.log_p;
+    std::vector<double> coef;
+    SideSolution rs, ls;
+    if (!solve_side(right, &rs, err, errlen) || !fit_side(rs, coef, &H.right, err, errlen)) return -1;
+    if (!solve_side(left, &ls, err, errlen) || !fit_side(ls, coef, &H.left, err, errlen)) return -1;
+    out->coef = (double*)malloc(coef.size() * sizeof(double));
+    if (!out->coef) return fail(err, errlen, "out of memory");
+    memcpy(out->coef, coef.data(), coef.size() * sizeof(double));
+    out->ncoef = coef.size();
+    return 0;
+}
+
+void free_hyperbolic_table(HostHypTable* t)
+{
+    if (t && t->coef) {
+        free(t->coef);
+        t->coef = nullptr;
+    }
+}
+
+}  // namespace qm
+
+/* Host copy of a table (include/qm_debug.h). */
+extern "C" int qm_debug_hyperbolic_table(double alpha, double beta, double delta, void* header_out, double* coef_out,
+                                         int coef_cap)
+{
+    qm::HostHypTable t;
+    char err[256];
+    if (qm::build_hyperbolic_table(alpha, beta, delta, &t, err, sizeof err) != 0) return -1;
+    int need = (int)t.ncoef;
+    if (header_out) memcpy(header_out, &t.hdr, sizeof t.hdr);
+    if (coef_out && coef_cap >= need && need > 0) memcpy(coef_out, t.coef, sizeof(double) * need);
+    qm::free_hyperbolic_table(&t);
+    return need;
+}
+
+/* Dense ODE solution (include/qm_debug.h). */
+extern "C" int qm_debug_hyperbolic_dense(double alpha, double beta, double delta, const double* v, double* q, int n)
+{
+    using namespace qm;
+    if (!check_params(alpha, beta, delta) || n < 0) return -1;
+    char err[256];
+    const Side right = make_side(alpha, beta, delta);
+    const Side left = make_side(alpha, -(fq)beta, delta);
+    SideSolution rs, ls;
+    if (!solve_side(right, &rs, err, sizeof err) || !solve_side(left, &ls, err, sizeof err)) {
+        fprintf(stderr, "qm_debug_hyperbolic_dense: %s\n", err);
+        return -1;
+    }
+    for (int i = 0; i < n; ++i) {
+        fq x = v[i];
+        const SideSolution& ss = x >= 0 ? rs : ls;
+        fq a = fabsq(x);
+        if (!(a <= 1e12Q)) return -1;
+        fq Q = a == 0 ? (fq)0 : ss.eval(a);
+        q[i] = (double)(x >= 0 ? Q : -Q);
+    }
+    return 0;
+}

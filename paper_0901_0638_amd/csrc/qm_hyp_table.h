@@ -1,0 +1,53 @@
+/*
+ * qm_hyp_table.h -- layout of the exponential -> hyperbolic tables and their
+ * host builder (plain C++ with __float128, no HIP dependency).
+ */
+#pragma once
+#include <stdint.h>
+
+namespace qm {
+
+constexpr int HYP_DEGREE = 11;      /* polynomial degree per cell */
+constexpr int HYP_SUB = 8;          /* cells per octave (a power of 2) */
+constexpr int HYP_MAX_OCT = 40;     /* octaves per side at most */
+
+/*
+ * One side of the map (v >= 0 with beta, or the mirrored v < 0 side with
+ * -beta): Q(v) = v R(v) for 0 <= v < v_top, R in cells of the variable
+ * t = v / v0 (v0 a power of 2): HYP_SUB uniform cells on [0, 1), then
+ * HYP_SUB equal cells in each octave [2^k, 2^(k+1)), k < noct.  Cell j
+ * holds R = sum_k c_{j,k} d^k, d = v - centre_j, highest power first,
+ * HYP_DEGREE + 1 doubles per row, starting coef_offset doubles into the
+ * table's coefficient block.  From v_top (= v0 2^noct) on:
+ * Q = v + far_c0 + (far_c1 + far_c2 / v) / v, the large-v expansion of the
+ * tail condition (Section 8.1: both H and the base have constant rates far
+ * out, so Q - v tends to a constant).
+ */
+struct HypSide {
+    double v0, inv_v0, v_top;
+    double far_c0, far_c1, far_c2;
+    double max_rel_err;      /* builder's check of the rounded coefficients */
+    int32_t noct;
+    int32_t ncell;           /* HYP_SUB (noct + 1) */
+    uint64_t coef_offset;
+};
+
+struct HypTableHeader {
+    double alpha, beta, delta;
+    double log_p_plus, log_p_minus;   /* target masses on x > 0 and x < 0 */
+    HypSide right;                    /* v >= 0 */
+    HypSide left;                     /* v < 0, as -Q(-v) of the mirrored side */
+};
+
+struct HostHypTable {
+    HypTableHeader hdr;
+    double* coef;            /* malloc'd block of both sides' rows */
+    uint64_t ncoef;
+};
+
+/* Build the table for (alpha, beta, delta), |beta| < alpha, delta > 0
+   (qm_hyp_table.cpp).  Returns 0 on success. */
+int build_hyperbolic_table(double alpha, double beta, double delta, HostHypTable* out, char* err, int errlen);
+void free_hyperbolic_table(HostHypTable* t);
+
+}  // namespace qm

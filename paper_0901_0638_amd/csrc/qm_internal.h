@@ -7,6 +7,7 @@
 #include <stdint.h>
 
 #include "../../include/qm.h"
+#include "qm_hyp_table.h"
 #include "qm_table.h"
 
 namespace qm {
@@ -27,6 +28,7 @@ struct LaunchShape {
     KernelShape stream;      /* k_map: exp -> normal, paper modes, FP32 plain */
     KernelShape hybrid[2];   /* [0] FP32+refine, [1] FP64 quantile: k_hybrid, k_generate */
     KernelShape student[2];  /* [0] FP32, [1] FP64 outputs: k_student */
+    KernelShape hyperbolic[2]; /* [0] FP32, [1] FP64: k_hyperbolic */
     int compact;             /* quantiles: gather non-central lanes across the wave */
 };
 
@@ -49,5 +51,11 @@ inline const double* table_block(const TTableHeader* d_table)
 hipError_t launch_student(int dtype, int mode, const void* in, void* out, uint64_t n,
                           const TTableHeader* d_table, const TTableHeader& h_table,
                           hipStream_t s, const LaunchShape& shape);
+
+/* Launch the exponential -> hyperbolic map with a device table
+   (qm_hyp.hip); ncoef doubles follow the header. */
+hipError_t launch_hyperbolic(int dtype, int mode, const void* in, void* out, uint64_t n, const HypTableHeader* d_table,
+                             const HypTableHeader& h, uint64_t ncoef, double mu, hipStream_t s,
+                             const LaunchShape& shape);
 
 }  // namespace qm

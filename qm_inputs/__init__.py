@@ -12,6 +12,11 @@ Workloads (sizes and seeds as used by the tests and the benchmark):
                  mirrored to 1 - t with probability 1/2
   normals        Box-Muller pairs from two open uniforms
   exponentials   -log(u) of an open uniform
+  two_sided_exponentials
+                 log(u/p-)/rate_minus for u < p-, else
+                 -log((1-u)/(1-p-))/rate_plus: the two-sided exponential
+                 with mass p- below 0, drawn from one open uniform u
+                 (1 - u is exact for u = (k + 1/2) 2^-53)
 """
 import ctypes
 import os
@@ -101,6 +106,16 @@ def exponentials(seed, stream, n, threads=0, out=None):
     return out
 
 
+def two_sided_exponentials(seed, stream, n, rate_plus, rate_minus, p_minus, threads=0):
+    """Two-sided exponential samples (mass p_minus below 0), one uniform each."""
+    u = uniform53(seed, stream, n, threads)
+    neg = u < p_minus
+    v = np.empty(n, np.float64)
+    v[neg] = np.log(u[neg] / p_minus) / rate_minus
+    v[~neg] = -np.log((1.0 - u[~neg]) / (1.0 - p_minus)) / rate_plus
+    return v
+
+
 # Workload definitions (seeds and streams fixed here so every user agrees).
 def uniforms_2e20():
     """Plain FP64 quantile workload: 2^20 open uniforms, seed 0."""
@@ -125,6 +140,15 @@ def recycle_normals(n=1 << 26, threads=0):
 def recycle_exponentials(n=1 << 26, threads=0):
     """Exp(1) samples for the exponential -> normal map, seed 2 stream 1."""
     return exponentials(2, 1, n, threads)
+
+
+HYPERBOLIC_PARAMS = (1.0, 0.0, 1.0)   # (alpha, beta, delta) of the Section 8.1 illustration
+
+
+def recycle_two_sided(n, alpha, beta, p_minus, threads=0):
+    """Base samples for the exponential -> hyperbolic map: rates alpha -+ beta,
+    mass p_minus below 0, seed 2 stream 2."""
+    return two_sided_exponentials(2, 2, n, alpha - beta, alpha + beta, p_minus, threads)
 
 
 # Batched / serving request mix: per request r, three parameter uniforms from

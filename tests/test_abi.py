@@ -51,6 +51,10 @@ def test_null_context_rejected_without_device_work():
     assert b"context" in lib.qm_last_error()
     assert lib.qm_recycle_student_t(None, p, p, 10, qm.QM_F64, qm.QM_PLAIN, 4.0, None) == qm.QM_E_INVAL
     assert lib.qm_recycle_exp_to_normal(None, p, p, 10, qm.QM_F64, qm.QM_PLAIN, None) == qm.QM_E_INVAL
+    assert lib.qm_recycle_exp_to_hyperbolic(None, p, p, 10, qm.QM_F64, qm.QM_PLAIN, 1.0, 0.0, 1.0, 0.0,
+                                            None) == qm.QM_E_INVAL
+    lp = ctypes.c_double()
+    assert lib.qm_hyperbolic_masses(None, 1.0, 0.0, 1.0, ctypes.byref(lp), None) == qm.QM_E_INVAL
     assert lib.qm_init(0, 0, None) == qm.QM_E_INVAL
     lib.qm_shutdown(None)
 

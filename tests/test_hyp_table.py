@@ -1,0 +1,151 @@
+"""CPU checks of the exponential -> hyperbolic table builder (Section 8.1).
+
+The builder's solution of the left/right recycling ODEs, and its tables
+evaluated on the host exactly as the kernel does (cell from the exponent
+and leading mantissa bits of t = |v|/v0, Horner in d = |v| - centre, the
+large-v form from v_top on), are compared with the oracle, which solves the
+defining equation F(x) = F0(v) by quadrature and bisection.  Closed forms
+pin the centre slope (Section 8.1, with K_1 from scipy) and the masses."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_0901_0638_amd as qm
+
+PARAMS = [(1.0, 0.0, 1.0), (1.0, 0.5, 1.0), (2.0, -1.5, 0.3), (1.0, 0.9, 5.0), (1.0, 0.0, 0.001),
+          (50.0, 10.0, 0.1)]
+
+
+def table_eval(h, rr, rl, v):
+    """The kernel's evaluation of a table, in numpy FP64."""
+    v = np.asarray(v, np.float64)
+    out = np.empty_like(v)
+    for i, x in enumerate(v):
+        S, rows = (h.left, rl) if x < 0 else (h.right, rr)
+        a = abs(x)
+        if not a < S.v_top:
+            Q = a if not np.isfinite(a) else a + (S.far_c0 + (S.far_c1 + S.far_c2 / a) / a)
+        else:
+            t = a * S.inv_v0
+            if t < 1:
+                j = int(t * qm.HYP_SUB)
+                ct = (j + 0.5) / qm.HYP_SUB
+            else:
+                m, e = np.frexp(t)
+                k = int(e) - 1
+                sub = int((2 * m - 1) * qm.HYP_SUB)
+                j = qm.HYP_SUB * (1 + k) + sub
+                ct = np.ldexp(1 + (sub + 0.5) / qm.HYP_SUB, k)
+            d = a - ct * S.v0
+            R = rows[j][0]
+            for c in rows[j][1:]:
+                R = R * d + c
+            Q = a * R
+        out[i] = math.copysign(Q, x)
+    return out
+
+
+def probe_points(h, p, seed):
+    alpha, beta, _ = p
+    rng = np.random.default_rng(seed)
+    pts = [rng.exponential(1 / (alpha - beta), 200), -rng.exponential(1 / (alpha + beta), 200),
+           np.geomspace(1e-9, 1e7, 40), -np.geomspace(1e-9, 1e7, 40)]
+    for S, sgn in ((h.right, 1), (h.left, -1)):
+        # every cell boundary region of the first octaves, the LDS edge, v_top
+        edges = [S.v0 * 2.0 ** k * (1 + i / qm.HYP_SUB) for k in range(-1, 6) for i in range(qm.HYP_SUB)]
+        edges += [S.v_top * (1 - 1e-16), S.v_top, S.v_top * 1.5, S.v_top * 1e3]
+        pts.append(sgn * np.array(edges))
+        pts.append(sgn * np.nextafter(np.array(edges), 0))
+    return np.concatenate(pts)
+
+
+@pytest.fixture(scope="module", params=PARAMS, ids=lambda p: "a%g_b%g_d%g" % p)
+def built(request):
+    p = request.param
+    h, rr, rl = qm.debug_hyperbolic_table(*p)
+    v = probe_points(h, p, 7)
+    return p, h, rr, rl, v, oracle.hyperbolic_map(v, *p)
+
+
+def test_dense_solution_matches_oracle(built):
+    """The ODE solution (and the direct tail solve beyond the anchor) is the
+    correctly rounded map: within one ulp of the oracle's."""
+    p, h, rr, rl, v, ref = built
+    q = qm.debug_hyperbolic_dense(*p, v)
+    rel = np.abs(q - ref) / np.abs(ref)
+    assert rel.max() <= 2.3e-16, (p, rel.max(), v[rel.argmax()])
+
+
+def test_table_matches_oracle(built):
+    p, h, rr, rl, v, ref = built
+    got = table_eval(h, rr, rl, v)
+    rel = np.abs(got - ref) / np.abs(ref)
+    assert rel.max() <= 6e-16, (p, rel.max(), v[rel.argmax()])
+
+
+def test_header_layout(built):
+    p, h, rr, rl, v, ref = built
+    for S, rows, rate in ((h.right, rr, p[0] - p[1]), (h.left, rl, p[0] + p[1])):
+        assert S.ncell == qm.HYP_SUB * (S.noct + 1) and rows.shape == (S.ncell, qm.HYP_DEGREE + 1)
+        assert 0 < S.noct <= 40
+        assert S.v0 == 2.0 ** round(math.log2(S.v0)) and S.inv_v0 * S.v0 == 1.0
+        assert S.v_top == S.v0 * 2.0 ** S.noct
+        assert S.max_rel_err < 1.2e-16         # the rounding of R itself, about half an ulp
+        assert S.v_top >= 32 / rate            # the cells cover the bulk of the base
+
+
+def test_masses_match_oracle(built):
+    p, h, *_ = built
+    lp, lm, _ = oracle.hyperbolic_masses(*p)
+    assert abs(h.log_p_plus - lp) <= 2e-16 * max(1.0, abs(lp)) + 1e-16
+    assert abs(h.log_p_minus - lm) <= 2e-16 * max(1.0, abs(lm)) + 1e-16
+    assert abs(np.logaddexp(h.log_p_plus, h.log_p_minus)) < 4e-16
+
+
+def test_centre_slope_closed_form(built):
+    """Q'(0+) = 2 p+ (alpha - beta) (alpha delta / gamma) K_1(delta gamma) e^{alpha delta}
+    and Q'(0-) likewise with p- and alpha + beta (Section 8.1)."""
+    special = pytest.importorskip("scipy.special")
+    p, h, rr, rl, *_ = built
+    a, b, d = p
+    g = math.sqrt(a * a - b * b)
+    for S, rows, lpm, rate in ((h.right, rr, h.log_p_plus, a - b), (h.left, rl, h.log_p_minus, a + b)):
+        x = -S.v0 / (2 * qm.HYP_SUB)            # d at v = 0 in the first cell
+        R0 = rows[0][0]
+        for c in rows[0][1:]:
+            R0 = R0 * x + c
+        want = 2 * math.exp(lpm) * rate * (a * d / g) * special.k1e(d * g) * math.exp(a * d - d * g)
+        assert abs(R0 / want - 1) < 2e-14, (p, R0, want)
+
+
+def test_large_v_constant(built):
+    """Far out Q - v -> c0 = log(C / ((alpha - beta) p+)) / (alpha - beta), with the
+    normalising constant C = gamma / (2 alpha delta K_1(delta gamma))."""
+    special = pytest.importorskip("scipy.special")
+    p, h, *_ = built
+    a, b, d = p
+    g = math.sqrt(a * a - b * b)
+    log_c = math.log(g / (2 * a * d)) - math.log(special.k1e(d * g)) + d * g
+    for S, lpm, rate in ((h.right, h.log_p_plus, a - b), (h.left, h.log_p_minus, a + b)):
+        c0 = (log_c - math.log(rate) - lpm) / rate
+        assert abs(S.far_c0 - c0) <= 1e-13 * max(1.0, abs(c0)), (p, S.far_c0, c0)
+
+
+def test_mirror_and_symmetry():
+    """beta -> -beta swaps the sides (x -> -x of the target); beta = 0 makes them equal."""
+    h1, r1, l1 = qm.debug_hyperbolic_table(1.0, 0.5, 1.0)
+    h2, r2, l2 = qm.debug_hyperbolic_table(1.0, -0.5, 1.0)
+    assert np.array_equal(r1, l2) and np.array_equal(l1, r2)
+    assert h1.log_p_plus == h2.log_p_minus and h1.log_p_minus == h2.log_p_plus
+    h0, r0, l0 = qm.debug_hyperbolic_table(1.0, 0.0, 1.0)
+    assert np.array_equal(r0, l0) and h0.log_p_plus == h0.log_p_minus
+    assert abs(h0.log_p_plus - math.log(0.5)) < 1e-16
+
+
+def test_invalid_parameters_rejected():
+    for p in [(1.0, 1.0, 1.0), (1.0, -1.5, 1.0), (1.0, 0.0, 0.0), (1.0, 0.0, -1.0), (float("nan"), 0.0, 1.0),
+              (float("inf"), 0.0, 1.0), (0.0, 0.0, 1.0)]:
+        with pytest.raises(ValueError):
+            qm.debug_hyperbolic_table(*p)
