@@ -86,55 +86,68 @@ typedef struct {
 
 static ld E_of(const hside* h, ld s) { return -h->ad * coshl(s) + h->bd * sinhl(s) + h->dg; }
 
-/* e^{E(s) - shift} cosh s */
-static ld integrand(const hside* h, ld s, ld shift) { return expl(E_of(h, s) - shift) * coshl(s); }
-
-static ld gl_panel(const hside* h, ld a, ld b, ld shift)
+/* E(a + u) - E(a) = -2 sinh(u/2) (alpha delta sinh(a + u/2) - beta delta cosh(a + u/2)),
+   exact in u however large a is (a + u itself may round to a) */
+static ld dE(const hside* h, ld a, ld u)
 {
-    ld c = 0.5L * (a + b), r = 0.5L * (b - a), sum = 0;
-    for (int i = 0; i < GL_N; ++i) sum += gl_w[i] * integrand(h, c + r * gl_x[i], shift);
+    ld m = a + 0.5L * u;
+    return -2 * sinhl(0.5L * u) * (h->ad * sinhl(m) - h->bd * coshl(m));
+}
+
+/* The integrand at s = a + u: e^{E(s) - shift} cosh s, with E(a) - shift
+   given as ea (so that it is 0 where shift = E(a)) */
+static ld integrand(const hside* h, ld a, ld ea, ld u) { return expl(ea + dE(h, a, u)) * coshl(a + u); }
+
+static ld gl_panel(const hside* h, ld a, ld ea, ld u0, ld u1)
+{
+    ld c = 0.5L * (u0 + u1), r = 0.5L * (u1 - u0), sum = 0;
+    for (int i = 0; i < GL_N; ++i) sum += gl_w[i] * integrand(h, a, ea, c + r * gl_x[i]);
     return sum * r;
 }
 
 /* Halve a panel until its two halves agree with it to tol, or to the
-   rounding of the integrand itself: E(s) carries an absolute error of a few
+   rounding of the integrand itself: E carries an absolute error of a few
    ulps of |E|, a relative error of e^E, so no estimate is better than about
    |E| eps (the integrand is positive: the sums do not cancel). */
-static ld gl_adapt(const hside* h, ld a, ld b, ld shift, ld whole, ld tol, int depth)
+static ld gl_adapt(const hside* h, ld a, ld ea, ld u0, ld u1, ld whole, ld tol, int depth)
 {
-    ld m = 0.5L * (a + b);
-    ld left = gl_panel(h, a, m, shift), right = gl_panel(h, m, b, shift);
+    ld m = 0.5L * (u0 + u1);
+    ld left = gl_panel(h, a, ea, u0, m), right = gl_panel(h, a, ea, m, u1);
     ld diff = fabsl(left + right - whole);
-    ld noise = 64 * LDBL_EPSILON * (1 + fabsl(E_of(h, a)) + fabsl(E_of(h, b)));
+    ld noise = 64 * LDBL_EPSILON * (1 + fabsl(E_of(h, a + u0)) + fabsl(E_of(h, a + u1)));
     if (depth >= 30 || diff <= tol || diff <= noise * (left + right)) return left + right;
-    return gl_adapt(h, a, m, shift, left, 0.5L * tol, depth + 1) + gl_adapt(h, m, b, shift, right, 0.5L * tol, depth + 1);
+    return gl_adapt(h, a, ea, u0, m, left, 0.5L * tol, depth + 1) +
+           gl_adapt(h, a, ea, m, u1, right, 0.5L * tol, depth + 1);
 }
 
-/* int_a^b e^{E(s) - shift} cosh s ds, to 1e-21 relative, or to the absolute
-   tolerance floor when that is larger (a panel that is a negligible part of
-   a larger sum) */
-static ld integrate_tol(const hside* h, ld a, ld b, ld shift, ld floor_tol)
+/* int over s in [a + u0, a + u1] of e^{E(s) - shift} cosh s ds (ea = E(a) -
+   shift), to 1e-21 relative, or to the absolute tolerance floor when that is
+   larger (a panel that is a negligible part of a larger sum) */
+static ld integrate_tol(const hside* h, ld a, ld ea, ld u0, ld u1, ld floor_tol)
 {
-    if (!(b > a)) return 0;
-    ld whole = gl_panel(h, a, b, shift);
+    if (!(u1 > u0)) return 0;
+    ld whole = gl_panel(h, a, ea, u0, u1);
     ld tol = 1e-21L * fabsl(whole);
     if (tol < floor_tol) tol = floor_tol;
-    return gl_adapt(h, a, b, shift, whole, tol + 1e-4000L, 0);
+    return gl_adapt(h, a, ea, u0, u1, whole, tol + 1e-4000L, 0);
 }
 
-static ld integrate(const hside* h, ld a, ld b, ld shift) { return integrate_tol(h, a, b, shift, 0); }
+/* int_a^b e^{E(s) - shift} cosh s ds */
+static ld integrate(const hside* h, ld a, ld b, ld shift) { return integrate_tol(h, a, E_of(h, a) - shift, 0, b - a, 0); }
 
 /* int_a^inf e^{E(s) - shift} cosh s ds, by panels until they vanish.  Past
    the peak the integrand falls like e^{E'(a)(s - a)} at first (and faster
    after), so the panels are 1/|E'(a)| wide, at most 1: each holds a fixed
-   share of the decay, however far out a lies. */
+   share of the decay, however far out a lies.  The panels are placed by
+   their offset from a, which resolves widths far below the spacing of
+   numbers near a. */
 static ld integrate_to_inf(const hside* h, ld a, ld shift)
 {
     ld slope = h->ad * sinhl(a) - h->bd * coshl(a);     /* -E'(a) */
     ld w = (a > h->speak && slope > 1) ? 1 / slope : 1;
-    ld sum = 0;
+    ld ea = E_of(h, a) - shift, sum = 0;
     for (int k = 0; k < 100000; ++k) {
-        ld p = integrate_tol(h, a + k * w, a + (k + 1) * w, shift, 1e-22L * sum);
+        ld p = integrate_tol(h, a, ea, k * w, (k + 1) * w, 1e-22L * sum);
         sum += p;
         if (a + k * w > h->speak && p <= 1e-30L * sum) break;
     }
@@ -147,7 +160,7 @@ static ld log_upper(const hside* h, ld x)
     ld S = asinhl(x / h->delta);
     if (S > h->speak) {
         ld e = E_of(h, S);
-        return h->ks + e + logl(integrate_to_inf(h, S, e));
+        return h->ks + e + logl(integrate_to_inf(h, S, e));   /* e - shift is exactly 0 */
     }
     return h->ks + logl(integrate(h, S, h->speak, 0) + integrate_to_inf(h, h->speak, 0));
 }
