@@ -194,8 +194,8 @@ qm_status qm_init(int hip_device, uint64_t hbm_budget_bytes, qm_ctx** out)
         {&c->shape.hybrid[1], "QM_SHAPE_NQ64", 64, 4}, /* FP64 quantile */
         {&c->shape.student[0], "QM_SHAPE_T32", 3, 4},  /* Student t, FP32 outputs */
         {&c->shape.student[1], "QM_SHAPE_T64", 2, 4},  /* Student t, FP64 outputs */
-        {&c->shape.hyperbolic[0], "QM_SHAPE_H32", 2, 4}, /* exp -> hyperbolic, FP32 */
-        {&c->shape.hyperbolic[1], "QM_SHAPE_H64", 2, 4}, /* exp -> hyperbolic, FP64 */
+        {&c->shape.hyperbolic[0], "QM_SHAPE_H32", 8, 2}, /* exp -> hyperbolic, FP32 */
+        {&c->shape.hyperbolic[1], "QM_SHAPE_H64", 8, 4}, /* exp -> hyperbolic, FP64 */
     };
     long env_bpc = 0, env_unroll = 0;
     if (const char* ev = getenv("QM_BLOCKS_PER_CU")) env_bpc = strtol(ev, nullptr, 10);

@@ -4,17 +4,21 @@
  * x = mu + sign(v) Q_side(|v|), Q = a R(a), a = |v|, with R the per-cell
  * polynomial of the side (v >= 0: the right map; v < 0: the mirrored left
  * map) built on the host from the recycling ODE (qm_hyp_table.cpp).  Cells
- * are uniform in t = a / v0 on [0, 1) and eight per octave of t beyond, so
- * the cell index comes from the exponent and the leading mantissa bits of t
- * with no table search.  Each workgroup stages the cells with
- * a < v_lds (64 / rate and more: all but a fraction e^-64 of the base's
- * samples) of both sides in LDS, then streams 16-byte vectors.  Elements
- * beyond are entered by a wave vote: the side's further cells from global
- * memory, and from v_top on the large-v form a + c0 + c1/a + c2/a^2.
+ * are eight per octave of t = 1 + a/v0 (v0 shared by both sides), so the
+ * cell index is the exponent and top three mantissa bits of t, and the
+ * cell's centre is t with its lower bits replaced: no table search, no
+ * per-side selects but a row offset.  Each workgroup stages the cells that
+ * reach a = 64 / rate (all but a fraction e^-64 of the base's samples) of
+ * both sides in LDS, then streams 16-byte vectors; a lane evaluates all its
+ * elements' polynomials (independent chains) before one wave vote admits
+ * the rare far elements: the side's further cells from global memory, and
+ * from v_top on the large-v form a + c0 + c1/a + c2/a^2.
  */
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <stdlib.h>
+
+#include <algorithm>
 
 #include "qm_device.hpp"
 #include "qm_hyp_table.h"
@@ -26,21 +30,22 @@ typedef double d2 __attribute__((ext_vector_type(2)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 
 constexpr int HYP_ROW = HYP_DEGREE + 1;
+/* LDS row stride in doubles: rows of 12 doubles start 24 banks apart, so
+   rows 8 apart would share banks; one double of padding staggers them. */
+constexpr int HYP_LDS_STRIDE = HYP_ROW + 1;
+static_assert(HYP_SUB == 8, "the cell index takes the top 3 mantissa bits of t");
 
-struct HypSideParams {
-    double v0, inv_v0;
-    double v_lds, v_top;          /* a < v_lds: LDS cells; a >= v_top: large-v form */
-    double c0, c1, c2;
+/* The far path's parameters of one side. */
+struct HypSideFar {
+    double v_top, c0, c1, c2;
     const double* gcoef;          /* the side's rows in global memory */
-    int nlds, ncell;
-    int lds_base;                 /* first LDS row of the side */
-    int pad;
+    int ncell, pad;
 };
 
 struct HypParams {
-    HypSideParams r, l;           /* v >= 0, v < 0 */
-    double mu;
-    int lds_stride;               /* doubles per LDS row */
+    double v0, inv_v0, mu;        /* v0 is shared by both sides */
+    HypSideFar r, l;              /* v >= 0, v < 0 */
+    int nlds;                     /* cells per side in LDS, right side's first */
     int pad;
 };
 
@@ -52,20 +57,15 @@ struct HypArgs {
     HypParams P;
 };
 
-/* Cell j of t = a / v0 >= 0 (uniform on [0, 1), HYP_SUB per octave beyond)
-   and its centre in units of v0.  The centre, 2^k (1 + (i + 1/2)/HYP_SUB),
-   is exact, and so is a - centre for a in the cell's octave. */
-__device__ __forceinline__ int hyp_cell(double t, double* centre_t)
+/* Cell of t = 1 + a/v0 >= 1: the biased exponent and the top three mantissa
+   bits of t give j = 8 k + i for t in [2^k (1 + i/8), 2^k (1 + (i+1)/8));
+   the cell's centre in t, 2^k (1 + (i + 1/2)/8), is t with the lower
+   mantissa bits replaced by 1000...  NaN and inf give j >= 8192. */
+__device__ __forceinline__ int hyp_cell(double t, double* tc)
 {
-    const bool uni = t < 1.0;
-    const int ex = __builtin_amdgcn_frexp_exp(t);           /* t = m 2^ex, m in [0.5, 1) */
-    const double m2 = 2.0 * __builtin_amdgcn_frexp_mant(t);  /* [1, 2) */
-    const double f = uni ? t : m2 - 1.0;                    /* position in the octave, [0, 1) */
-    const int i = (int)(f * HYP_SUB);
-    const int k = uni ? 0 : ex - 1;
-    const double c = ((uni ? 0.0 : 1.0) + (i + 0.5) * (1.0 / HYP_SUB));
-    *centre_t = __builtin_amdgcn_ldexp(c, k);
-    return uni ? i : HYP_SUB * (1 + k) + i;
+    const uint32_t hi = (uint32_t)__double2hiint(t);
+    *tc = __hiloint2double((int)((hi & ~((1u << 17) - 1)) | (1u << 16)), 0);
+    return (int)(hi >> 17) - (1023 << 3);
 }
 
 __device__ __forceinline__ double hyp_poly(const double* __restrict__ c, double d)
@@ -76,54 +76,55 @@ __device__ __forceinline__ double hyp_poly(const double* __restrict__ c, double 
     return R;
 }
 
-/* a >= v_lds or NaN: global-memory cells up to v_top, then the large-v form. */
-static __device__ __noinline__ double hyp_far(double a, const HypSideParams& S)
+/* |Q(v)| from the LDS cells; *far for lanes beyond them (and NaN). */
+__device__ __forceinline__ double hyp_near(double v, const double* __restrict__ lds, const HypParams& P, bool* far)
 {
-    if (!(a < S.v_top)) {
-        if (!(a < __builtin_inf())) return a;                /* inf -> inf, NaN -> NaN */
-        return a + (S.c0 + (S.c1 + S.c2 / a) / a);
-    }
-    double ct;
-    int j = hyp_cell(a * S.inv_v0, &ct);
-    j = j < S.ncell - 1 ? j : S.ncell - 1;
-    j = j > 0 ? j : 0;
-    const double d = a - ct * S.v0;
-    return a * hyp_poly(S.gcoef + j * HYP_ROW, d);
+    const double a = __builtin_fabs(v);
+    const double t = __builtin_fma(a, P.inv_v0, 1.0);
+    double tc;
+    int j = hyp_cell(t, &tc);                    /* >= 0: t >= 1 */
+    const bool out = !((unsigned)j < (unsigned)P.nlds);
+    *far = out;
+    j = out ? P.nlds - 1 : j;                     /* far and NaN lanes stay in bounds */
+    const int row = j + (v < 0.0 ? P.nlds : 0);
+    const double d = __builtin_fma(-P.v0, tc - 1.0, a);   /* a - centre; tc - 1 is exact */
+    return a * hyp_poly(lds + row * HYP_LDS_STRIDE, d);
 }
 
-__device__ __forceinline__ double hyp_eval(double v, const double* __restrict__ lds, const HypParams& P)
+/* |Q(v)| beyond the LDS cells: the side's global-memory cells up to v_top,
+   then the large-v form; inf -> inf, NaN -> NaN.  The side's parameters
+   come as plain values selected per lane (a reference to a lane-dependent
+   side, or a struct passed by value, would put them in scratch memory). */
+static __device__ __noinline__ double hyp_far(double a, double v0, double inv_v0, double v_top, double c0, double c1,
+                                              double c2, const double* gcoef, int ncell)
+{
+    if (!(a < v_top)) {
+        if (!(a < __builtin_inf())) return a;
+        return a + (c0 + (c1 + c2 / a) / a);
+    }
+    double tc;
+    int j = hyp_cell(__builtin_fma(a, inv_v0, 1.0), &tc);
+    j = (unsigned)j < (unsigned)ncell ? j : ncell - 1;
+    return a * hyp_poly(gcoef + j * HYP_ROW, __builtin_fma(-v0, tc - 1.0, a));
+}
+
+__device__ __forceinline__ double hyp_far_of(double v, const HypParams& P)
 {
     const bool neg = v < 0.0;
-    const double a = __builtin_fabs(v);
-    const double v0 = neg ? P.l.v0 : P.r.v0;
-    const double inv_v0 = neg ? P.l.inv_v0 : P.r.inv_v0;
-    const double v_lds = neg ? P.l.v_lds : P.r.v_lds;
-    const int nlds = neg ? P.l.nlds : P.r.nlds;
-    const int base = neg ? P.l.lds_base : P.r.lds_base;
-    double ct;
-    int j = hyp_cell(a * inv_v0, &ct);
-    j = j < nlds - 1 ? j : nlds - 1;                         /* far and NaN lanes stay in bounds */
-    j = j > 0 ? j : 0;
-    const double d = a - ct * v0;
-    double Q = a * hyp_poly(lds + (base + j) * P.lds_stride, d);
-    const bool far = !(a < v_lds);
-    if (wave_any(far)) {
-        double qf = hyp_far(far ? a : 0.0, neg ? P.l : P.r);
-        Q = far ? qf : Q;
-    }
-    return P.mu + __builtin_copysign(Q, v);
+    return hyp_far(__builtin_fabs(v), P.v0, P.inv_v0, neg ? P.l.v_top : P.r.v_top, neg ? P.l.c0 : P.r.c0,
+                   neg ? P.l.c1 : P.r.c1, neg ? P.l.c2 : P.r.c2, neg ? P.l.gcoef : P.r.gcoef,
+                   neg ? P.l.ncell : P.r.ncell);
 }
 
-/* Both sides' LDS rows, row stride P.lds_stride. */
+/* Both sides' LDS rows: right side rows 0..nlds-1, left side after. */
 __device__ __forceinline__ void stage_hyp(double* lds, const HypParams& P)
 {
-    const int nr = P.r.nlds * HYP_ROW, nl = P.l.nlds * HYP_ROW;
-    for (int i = threadIdx.x; i < nr + nl; i += blockDim.x) {
-        const bool left = i >= nr;
-        const int e = left ? i - nr : i;
+    const int n = P.nlds * HYP_ROW;
+    for (int i = threadIdx.x; i < 2 * n; i += blockDim.x) {
+        const bool left = i >= n;
+        const int e = left ? i - n : i;
         const int row = e / HYP_ROW, col = e - row * HYP_ROW;
-        const double* src = left ? P.l.gcoef : P.r.gcoef;
-        lds[((left ? P.l.lds_base : P.r.lds_base) + row) * P.lds_stride + col] = src[e];
+        lds[((left ? P.nlds : 0) + row) * HYP_LDS_STRIDE + col] = (left ? P.l.gcoef : P.r.gcoef)[e];
     }
 }
 
@@ -131,11 +132,37 @@ template <typename T> struct hvec;
 template <> struct hvec<double> { typedef d2 type; static constexpr int n = 2; };
 template <> struct hvec<float> { typedef f4 type; static constexpr int n = 4; };
 
-/* FP32 in/out: the FP64 evaluation, rounded once. */
+/* x = mu + sign(v) |Q|, in FP64; FP32 outputs round it once. */
 template <typename T>
-__device__ __forceinline__ T hyp_op(T v, const double* lds, const HypParams& P)
+__device__ __forceinline__ T hyp_out(double q, T v, const HypParams& P)
 {
-    return (T)hyp_eval((double)v, lds, P);
+    return (T)(P.mu + __builtin_copysign(q, (double)v));
+}
+
+/* The K elements a lane holds: every element's cell polynomial first (K
+   independent chains), then one wave vote for the far fix-up. */
+template <typename T, int K>
+__device__ __forceinline__ void hyp_lane(const T (&v)[K], T (&y)[K], const double* lds, const HypParams& P)
+{
+    double q[K];
+    bool far[K];
+    bool anyfar = false;
+#pragma unroll
+    for (int e = 0; e < K; ++e) {
+        q[e] = hyp_near((double)v[e], lds, P, &far[e]);
+        anyfar |= far[e];
+    }
+    if (wave_any(anyfar)) {
+#pragma unroll
+        for (int e = 0; e < K; ++e) {
+            if (wave_any(far[e])) {
+                double qf = hyp_far_of(far[e] ? (double)v[e] : 0.0, P);
+                q[e] = far[e] ? qf : q[e];
+            }
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < K; ++e) y[e] = hyp_out<T>(q[e], v[e], P);
 }
 
 template <typename T, bool VECTOR, int UNROLL>
@@ -158,79 +185,74 @@ __global__ __launch_bounds__(256) void k_hyperbolic(HypArgs<T> a)
             V x[UNROLL];
 #pragma unroll
             for (int k = 0; k < UNROLL; ++k) x[k] = __builtin_nontemporal_load(vin + i + k * stride);
+            T v[UNROLL * NV], y[UNROLL * NV];
+#pragma unroll
+            for (int k = 0; k < UNROLL; ++k)
+#pragma unroll
+                for (int j = 0; j < NV; ++j) v[k * NV + j] = x[k][j];
+            hyp_lane<T, UNROLL * NV>(v, y, lds_hyp, P);
 #pragma unroll
             for (int k = 0; k < UNROLL; ++k) {
-                V y;
+                V o;
 #pragma unroll
-                for (int j = 0; j < NV; ++j) y[j] = hyp_op<T>(x[k][j], lds_hyp, P);
-                __builtin_nontemporal_store(y, vout + i + k * stride);
+                for (int j = 0; j < NV; ++j) o[j] = y[k * NV + j];
+                __builtin_nontemporal_store(o, vout + i + k * stride);
             }
         }
         for (; i < a.nvec; i += stride) {
             V x = __builtin_nontemporal_load(vin + i);
-            V y;
+            T v[NV], y[NV];
 #pragma unroll
-            for (int j = 0; j < NV; ++j) y[j] = hyp_op<T>(x[j], lds_hyp, P);
-            __builtin_nontemporal_store(y, vout + i);
+            for (int j = 0; j < NV; ++j) v[j] = x[j];
+            hyp_lane<T, NV>(v, y, lds_hyp, P);
+            V o;
+#pragma unroll
+            for (int j = 0; j < NV; ++j) o[j] = y[j];
+            __builtin_nontemporal_store(o, vout + i);
         }
         if (blockIdx.x == 0) {
             uint64_t extra = a.head + (a.n - a.tail_begin);
             for (uint64_t e = threadIdx.x; e < extra; e += blockDim.x) {
                 uint64_t idx = e < a.head ? e : a.tail_begin + (e - a.head);
-                a.out[idx] = hyp_op<T>(a.in[idx], lds_hyp, P);
+                T v[1] = {a.in[idx]}, y[1];
+                hyp_lane<T, 1>(v, y, lds_hyp, P);
+                a.out[idx] = y[0];
             }
         }
     } else {
-        for (uint64_t i = tid; i < a.n; i += stride) a.out[i] = hyp_op<T>(a.in[i], lds_hyp, P);
+        for (uint64_t i = tid; i < a.n; i += stride) {
+            T v[1] = {a.in[i]}, y[1];
+            hyp_lane<T, 1>(v, y, lds_hyp, P);
+            a.out[i] = y[0];
+        }
     }
-}
-
-/* LDS row stride: rows of 12 doubles start 24 banks apart; one double of
-   padding staggers rows that share a bank.  QM_HYP_LDS_STRIDE (12..20)
-   overrides it (tuning). */
-static int hyp_lds_stride()
-{
-    static const int s = [] {
-        const char* e = getenv("QM_HYP_LDS_STRIDE");
-        int v = e ? atoi(e) : HYP_ROW + 1;
-        return (v >= HYP_ROW && v <= 20) ? v : HYP_ROW + 1;
-    }();
-    return s;
 }
 
 constexpr size_t HYP_LDS_MAX = 48 * 1024;   /* bytes of LDS per workgroup for the cells */
 
 static bool side_valid(const HypSide& s, uint64_t ncoef)
 {
-    return s.noct >= 0 && s.noct <= HYP_MAX_OCT && s.ncell == HYP_SUB * (s.noct + 1) &&
+    return s.noct >= 1 && s.noct <= HYP_MAX_OCT && s.ncell == HYP_SUB * s.noct &&
            s.coef_offset + (uint64_t)s.ncell * HYP_ROW <= ncoef && s.v0 > 0 && s.v_top > 0;
 }
 
-/* Cells of a side kept in LDS: through the octave that reaches 64 / rate,
-   within the LDS budget `cap` rows. */
-static int lds_cells(const HypSide& s, double rate, int cap)
+/* Octaves of t = 1 + v/v0 that reach 64 / rate. */
+static int octaves_to(double v0, double rate)
 {
-    int noct = 0;
-    while (noct < s.noct && s.v0 * (double)(1ull << noct) < 64.0 / rate) ++noct;
-    int n = HYP_SUB * (noct + 1);
-    if (n > cap) n = cap - cap % HYP_SUB;
-    return n < HYP_SUB ? HYP_SUB : n;
+    int k = 1;
+    while (k < HYP_MAX_OCT && v0 * ((double)(1ull << k) - 1.0) < 64.0 / rate) ++k;
+    return k;
 }
 
-static void side_params(const HypSide& s, const double* d_block, int nlds, int base, HypSideParams* p)
+static void side_far(const HypSide& s, const double* d_block, HypSideFar* f)
 {
-    p->v0 = s.v0;
-    p->inv_v0 = s.inv_v0;
-    p->v_top = s.v_top;
-    p->v_lds = nlds >= s.ncell ? s.v_top : s.v0 * (double)(1ull << (nlds / HYP_SUB - 1));
-    p->c0 = s.far_c0;
-    p->c1 = s.far_c1;
-    p->c2 = s.far_c2;
-    p->gcoef = d_block + s.coef_offset;
-    p->nlds = nlds;
-    p->ncell = s.ncell;
-    p->lds_base = base;
-    p->pad = 0;
+    f->v_top = s.v_top;
+    f->c0 = s.far_c0;
+    f->c1 = s.far_c1;
+    f->c2 = s.far_c2;
+    f->gcoef = d_block + s.coef_offset;
+    f->ncell = s.ncell;
+    f->pad = 0;
 }
 
 template <typename T>
@@ -276,19 +298,24 @@ hipError_t launch_hyperbolic(int dtype, int mode, const void* in, void* out, uin
                              const HypTableHeader& h, uint64_t ncoef, double mu, hipStream_t s,
                              const LaunchShape& shape)
 {
-    if (!side_valid(h.right, ncoef) || !side_valid(h.left, ncoef)) return hipErrorInvalidValue;
+    if (!side_valid(h.right, ncoef) || !side_valid(h.left, ncoef) || h.right.v0 != h.left.v0 ||
+        h.right.inv_v0 != h.left.inv_v0)
+        return hipErrorInvalidValue;
     const double* d_block = reinterpret_cast<const double*>(reinterpret_cast<const char*>(d_table) + sizeof(HypTableHeader));
-    const int stride = hyp_lds_stride();
-    const int cap = (int)(HYP_LDS_MAX / (sizeof(double) * stride)) / 2;
+    /* LDS cells per side: through the octave reaching 64 / rate on either
+       side, within both sides' tables and the LDS budget */
+    int noct = std::max(octaves_to(h.right.v0, h.alpha - h.beta), octaves_to(h.right.v0, h.alpha + h.beta));
+    noct = std::min(noct, std::min(h.right.noct, h.left.noct));
+    noct = std::min(noct, (int)(HYP_LDS_MAX / (2 * HYP_LDS_STRIDE * sizeof(double) * HYP_SUB)));
     HypParams P;
-    const int nr = lds_cells(h.right, h.alpha - h.beta, cap);
-    const int nl = lds_cells(h.left, h.alpha + h.beta, cap);
-    side_params(h.right, d_block, nr, 0, &P.r);
-    side_params(h.left, d_block, nl, nr, &P.l);
+    P.v0 = h.right.v0;
+    P.inv_v0 = h.right.inv_v0;
     P.mu = mu;
-    P.lds_stride = stride;
+    side_far(h.right, d_block, &P.r);
+    side_far(h.left, d_block, &P.l);
+    P.nlds = HYP_SUB * noct;
     P.pad = 0;
-    const size_t lds = (size_t)(nr + nl) * stride * sizeof(double);
+    const size_t lds = (size_t)2 * P.nlds * HYP_LDS_STRIDE * sizeof(double);
     if (dtype == QM_F64 && mode == QM_PLAIN) return launch_h<double>(in, out, n, P, lds, s, shape.hyperbolic[1]);
     if (dtype == QM_F32 && mode == QM_F32_REFINE) return launch_h<float>(in, out, n, P, lds, s, shape.hyperbolic[0]);
     return hipErrorInvalidValue;

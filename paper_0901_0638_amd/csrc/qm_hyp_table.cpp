@@ -32,9 +32,10 @@
  * there (the decaying mode of the backward direction limits them), which
  * would make the far range, out to where the large-v form below holds,
  * cost millions of steps.  The table holds R(v) = Q(v)/v in
- * cells of t = v / v0: eight uniform cells on [0, 1), then eight per octave
- * of t, so that the relative width of a cell is the same at every scale
- * (Q is nearly v + const far out, and curved on the scale delta near 0).
+ * cells of t = 1 + v / v0, eight per octave of t: uniform cells on
+ * [0, v0), then cells whose relative width tends to 1/8 (Q is nearly
+ * v + const far out, and curved on the scale delta near 0).  Both sides
+ * share v0, a power of 2.
  * Each cell holds the degree-11 Chebyshev interpolant of R as monomials in
  * d = v - centre, checked against the solution.  Beyond the last
  * octave, Q = v + c0 + c1/v + c2/v^2 (the expansion of the tail condition
@@ -42,6 +43,7 @@
  */
 #include <quadmath.h>
 
+#include <climits>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -538,70 +540,86 @@ fq fit_cell(const SideSolution& ss, fq lo, fq hi, double* row, fq* rounded)
     return worst;
 }
 
-/*
- * Cells of one side.  The octave cells [2^e (1 + i/S), 2^e (1 + (i+1)/S))
- * do not depend on v0, so they are fitted once, from the top octave down;
- * v0 = 2^e is the largest power of 2 whose uniform cells on [0, v0) meet
- * the tolerance.  Returns false if none does.
- */
-bool fit_side(const SideSolution& ss, std::vector<double>& coef, HypSide* hs, char* err, int errlen)
+/* Bounds in v of cell j = HYP_SUB k + i: t = 1 + v/v0 in
+   [2^k (1 + i/S), 2^k (1 + (i+1)/S)). */
+void cell_bounds(fq v0, int j, fq* lo, fq* hi)
 {
-    const fq tol = 2e-17Q;
-    fq v_top;
-    if (!far_start(ss, tol / 4, &v_top)) {
-        snprintf(err, errlen, "large-v form not accurate at 2^30 / (alpha - beta)");
-        return false;
-    }
-    const int top_exp = (int)lrintq(log2q(v_top));
+    const int k = j / HYP_SUB, i = j % HYP_SUB;
+    *lo = v0 * (ldexpq(1 + (fq)i / HYP_SUB, k) - 1);
+    *hi = v0 * (ldexpq(1 + (fq)(i + 1) / HYP_SUB, k) - 1);
+}
+
+/* Fit cells [j0, j1) of a side for v0 into rows (HYP_DEGREE + 1 doubles per
+   cell, cell j0 first).  Returns false, with the failing cell in *bad, if
+   one misses tol; *worst gets the largest error of the rounded rows. */
+bool fit_cells(const SideSolution& ss, fq v0, int j0, int j1, fq tol, double* rows, fq* worst, int* bad)
+{
     const int W = HYP_DEGREE + 1;
-    std::vector<double> oct;    /* octave rows, top octave first */
-    fq worst = 0;   /* of the rounded rows */
-    for (int e = top_exp; e >= top_exp - HYP_MAX_OCT; --e) {
-        /* try v0 = 2^e: uniform cells on [0, 2^e) */
-        const fq v0 = ldexpq(1, e);
-        std::vector<double> uni((size_t)HYP_SUB * W);
-        fq wu = 0, wu_r = 0;
-        for (int j = 0; j < HYP_SUB && wu <= tol; ++j) {
-            fq rj, ej = fit_cell(ss, v0 * j / HYP_SUB, v0 * (j + 1) / HYP_SUB, &uni[(size_t)j * W], &rj);
-            if (ej > wu) wu = ej;
-            if (rj > wu_r) wu_r = rj;
+    for (int j = j0; j < j1; ++j) {
+        fq lo, hi, r;
+        cell_bounds(v0, j, &lo, &hi);
+        fq e = fit_cell(ss, lo, hi, rows + (size_t)(j - j0) * W, &r);
+        if (r > *worst) *worst = r;
+        if (e > tol) {
+            *bad = j;
+            return false;
         }
-        if (wu <= tol) {
-            const int noct = top_exp - e;
-            hs->v0 = (double)v0;
-            hs->inv_v0 = (double)(1 / v0);
-            hs->v_top = (double)v_top;
-            hs->far_c0 = (double)ss.c0;
-            hs->far_c1 = (double)ss.c1;
-            hs->far_c2 = (double)ss.c2;
-            hs->max_rel_err = (double)(wu_r > worst ? wu_r : worst);
-            hs->noct = noct;
-            hs->ncell = HYP_SUB * (noct + 1);
-            hs->coef_offset = coef.size();
-            coef.insert(coef.end(), uni.begin(), uni.end());
-            /* octaves in increasing order: octave k covers [v0 2^k, v0 2^(k+1)) */
-            for (int k = 0; k < noct; ++k) {
-                size_t at = (size_t)(noct - 1 - k) * HYP_SUB * W;
-                coef.insert(coef.end(), oct.begin() + at, oct.begin() + at + (size_t)HYP_SUB * W);
-            }
-            return true;
-        }
-        /* otherwise the octave [2^(e-1), 2^e) joins the table */
-        const fq base = ldexpq(1, e - 1);
-        std::vector<double> rows((size_t)HYP_SUB * W);
-        for (int i = 0; i < HYP_SUB; ++i) {
-            fq ri, ei = fit_cell(ss, base * (1 + (fq)i / HYP_SUB), base * (1 + (fq)(i + 1) / HYP_SUB),
-                                 &rows[(size_t)i * W], &ri);
-            if (ei > tol) {
-                snprintf(err, errlen, "cell near v=%g misses the accuracy target (%.2e)", (double)base, (double)ei);
-                return false;
-            }
-            if (ri > worst) worst = ri;
-        }
-        oct.insert(oct.end(), rows.begin(), rows.end());
     }
-    snprintf(err, errlen, "more than %d octaves needed", HYP_MAX_OCT);
-    return false;
+    return true;
+}
+
+const fq HYP_TOL = 2e-17Q;
+
+/*
+ * Cells of one side for v0 = 2^lv, lv <= max_lv: the largest lv whose
+ * cells all meet the tolerance (the first octave of t, uniform cells on
+ * [0, v0), and the next two decide it; the rest are then fitted and
+ * checked).  The cells reach v_top = v0 (2^noct - 1), beyond the first
+ * power of 2 from which on the large-v form holds.  Returns lv, or
+ * INT_MIN with a message if none fits.
+ */
+int fit_side(const SideSolution& ss, int max_lv, std::vector<double>* rows_out, HypSide* hs, char* err, int errlen)
+{
+    fq P;
+    if (!far_start(ss, HYP_TOL / 4, &P)) {
+        snprintf(err, errlen, "large-v form not accurate at 2^30 / (alpha - beta)");
+        return INT_MIN;
+    }
+    const int W = HYP_DEGREE + 1;
+    int lv = (int)lrintq(log2q(P));
+    if (lv > 3) lv = 3;
+    if (lv > max_lv) lv = max_lv;
+    for (; lv >= -60; --lv) {
+        const fq v0 = ldexpq(1, lv);
+        int noct = 1;
+        while (v0 * (ldexpq(1, noct) - 1) < P) ++noct;
+        if (noct > HYP_MAX_OCT) break;
+        const int ncell = HYP_SUB * noct;
+        std::vector<double> rows((size_t)ncell * W);
+        fq worst = 0;
+        int bad = -1;
+        const int head = ncell < 3 * HYP_SUB ? ncell : 3 * HYP_SUB;
+        if (!fit_cells(ss, v0, 0, head, HYP_TOL, rows.data(), &worst, &bad)) continue;
+        if (!fit_cells(ss, v0, head, ncell, HYP_TOL, rows.data() + (size_t)head * W, &worst, &bad)) {
+            fq lo, hi;
+            cell_bounds(v0, bad, &lo, &hi);
+            snprintf(err, errlen, "cell near v=%g misses the accuracy target", (double)lo);
+            return INT_MIN;
+        }
+        hs->v0 = (double)v0;
+        hs->inv_v0 = (double)(1 / v0);
+        hs->v_top = (double)(v0 * (ldexpq(1, noct) - 1));
+        hs->far_c0 = (double)ss.c0;
+        hs->far_c1 = (double)ss.c1;
+        hs->far_c2 = (double)ss.c2;
+        hs->max_rel_err = (double)worst;
+        hs->noct = noct;
+        hs->ncell = ncell;
+        *rows_out = std::move(rows);
+        return lv;
+    }
+    snprintf(err, errlen, "no cell width met the accuracy target within %d octaves", HYP_MAX_OCT);
+    return INT_MIN;
 }
 
 bool check_params(double alpha, double beta, double delta)
@@ -624,14 +642,27 @@ int build_hyperbolic_table(double alpha, double beta, double delta, HostHypTable
     const Side left = make_side(alpha, -(fq)beta, delta);
     H.log_p_plus = (double)right.log_p;
     H.log_p_minus = (double)left.log_p;
-    std::vector<double> coef;
     SideSolution rs, ls;
-    if (!solve_side(right, &rs, err, errlen) || !fit_side(rs, coef, &H.right, err, errlen)) return -1;
-    if (!solve_side(left, &ls, err, errlen) || !fit_side(ls, coef, &H.left, err, errlen)) return -1;
-    out->coef = (double*)malloc(coef.size() * sizeof(double));
+    if (!solve_side(right, &rs, err, errlen) || !solve_side(left, &ls, err, errlen)) return -1;
+    /* both sides share v0 (one cell computation for every lane): the
+       smaller of the two sides' own choices */
+    std::vector<double> rr, rl;
+    int lr = fit_side(rs, 3, &rr, &H.right, err, errlen);
+    if (lr == INT_MIN) return -1;
+    int ll = fit_side(ls, lr, &rl, &H.left, err, errlen);
+    for (int it = 0; it < 8 && ll != INT_MIN && ll != lr; ++it) {
+        lr = fit_side(rs, ll, &rr, &H.right, err, errlen);
+        if (lr == INT_MIN) return -1;
+        if (lr != ll) ll = fit_side(ls, lr, &rl, &H.left, err, errlen);
+    }
+    if (ll == INT_MIN || ll != lr) return ll == INT_MIN ? -1 : fail(err, errlen, "no common cell width");
+    H.right.coef_offset = 0;
+    H.left.coef_offset = rr.size();
+    out->ncoef = rr.size() + rl.size();
+    out->coef = (double*)malloc(out->ncoef * sizeof(double));
     if (!out->coef) return fail(err, errlen, "out of memory");
-    memcpy(out->coef, coef.data(), coef.size() * sizeof(double));
-    out->ncoef = coef.size();
+    memcpy(out->coef, rr.data(), rr.size() * sizeof(double));
+    memcpy(out->coef + rr.size(), rl.data(), rl.size() * sizeof(double));
     return 0;
 }
 

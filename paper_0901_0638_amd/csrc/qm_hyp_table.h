@@ -14,11 +14,13 @@ constexpr int HYP_MAX_OCT = 40;     /* octaves per side at most */
 /*
  * One side of the map (v >= 0 with beta, or the mirrored v < 0 side with
  * -beta): Q(v) = v R(v) for 0 <= v < v_top, R in cells of the variable
- * t = v / v0 (v0 a power of 2): HYP_SUB uniform cells on [0, 1), then
- * HYP_SUB equal cells in each octave [2^k, 2^(k+1)), k < noct.  Cell j
- * holds R = sum_k c_{j,k} d^k, d = v - centre_j, highest power first,
- * HYP_DEGREE + 1 doubles per row, starting coef_offset doubles into the
- * table's coefficient block.  From v_top (= v0 2^noct) on:
+ * t = 1 + v / v0 (v0 a power of 2, the same for both sides): HYP_SUB equal
+ * cells in each octave [2^k, 2^(k+1)) of t, k < noct, so cell
+ * j = HYP_SUB k + i is read off the exponent and leading mantissa bits of t.
+ * Cell j holds R = sum_k c_{j,k} d^k, d = v - centre_j, centre_j at
+ * t = 2^k (1 + (i + 1/2)/HYP_SUB), highest power first, HYP_DEGREE + 1
+ * doubles per row, starting coef_offset doubles into the table's
+ * coefficient block.  From v_top = v0 (2^noct - 1) on:
  * Q = v + far_c0 + (far_c1 + far_c2 / v) / v, the large-v expansion of the
  * tail condition (Section 8.1: both H and the base have constant rates far
  * out, so Q - v tends to a constant).
@@ -28,7 +30,7 @@ struct HypSide {
     double far_c0, far_c1, far_c2;
     double max_rel_err;      /* builder's check of the rounded coefficients */
     int32_t noct;
-    int32_t ncell;           /* HYP_SUB (noct + 1) */
+    int32_t ncell;           /* HYP_SUB noct */
     uint64_t coef_offset;
 };
 

@@ -2,8 +2,8 @@
 
 The builder's solution of the left/right recycling ODEs, and its tables
 evaluated on the host exactly as the kernel does (cell from the exponent
-and leading mantissa bits of t = |v|/v0, Horner in d = |v| - centre, the
-large-v form from v_top on), are compared with the oracle, which solves the
+and leading mantissa bits of t = 1 + |v|/v0, Horner in d = |v| - centre,
+the large-v form from v_top on), are compared with the oracle, which solves the
 defining equation F(x) = F0(v) by quadrature and bisection.  Closed forms
 pin the centre slope (Section 8.1, with K_1 from scipy) and the masses."""
 import math
@@ -19,7 +19,9 @@ PARAMS = [(1.0, 0.0, 1.0), (1.0, 0.5, 1.0), (2.0, -1.5, 0.3), (1.0, 0.9, 5.0), (
 
 
 def table_eval(h, rr, rl, v):
-    """The kernel's evaluation of a table, in numpy FP64."""
+    """The kernel's evaluation of a table, in numpy FP64: t = 1 + |v|/v0 by
+    one fused multiply-add, the cell from the exponent and top three
+    mantissa bits of t, its centre from t with the lower bits replaced."""
     v = np.asarray(v, np.float64)
     out = np.empty_like(v)
     for i, x in enumerate(v):
@@ -28,17 +30,12 @@ def table_eval(h, rr, rl, v):
         if not a < S.v_top:
             Q = a if not np.isfinite(a) else a + (S.far_c0 + (S.far_c1 + S.far_c2 / a) / a)
         else:
-            t = a * S.inv_v0
-            if t < 1:
-                j = int(t * qm.HYP_SUB)
-                ct = (j + 0.5) / qm.HYP_SUB
-            else:
-                m, e = np.frexp(t)
-                k = int(e) - 1
-                sub = int((2 * m - 1) * qm.HYP_SUB)
-                j = qm.HYP_SUB * (1 + k) + sub
-                ct = np.ldexp(1 + (sub + 0.5) / qm.HYP_SUB, k)
-            d = a - ct * S.v0
+            t = fma(a, S.inv_v0, 1.0)
+            bits = np.float64(t).view(np.uint64)
+            hi = int(bits >> np.uint64(32))
+            j = (hi >> 17) - (1023 << 3)
+            tc = np.uint64(((hi & ~((1 << 17) - 1)) | (1 << 16)) << 32).view(np.float64)
+            d = fma(-S.v0, float(tc) - 1.0, a)
             R = rows[j][0]
             for c in rows[j][1:]:
                 R = R * d + c
@@ -47,17 +44,25 @@ def table_eval(h, rr, rl, v):
     return out
 
 
+def fma(x, y, z):
+    """x y + z rounded once (exact rational arithmetic)."""
+    from fractions import Fraction
+    return float(Fraction(x) * Fraction(y) + Fraction(z))
+
+
 def probe_points(h, p, seed):
     alpha, beta, _ = p
     rng = np.random.default_rng(seed)
     pts = [rng.exponential(1 / (alpha - beta), 200), -rng.exponential(1 / (alpha + beta), 200),
            np.geomspace(1e-9, 1e7, 40), -np.geomspace(1e-9, 1e7, 40)]
     for S, sgn in ((h.right, 1), (h.left, -1)):
-        # every cell boundary region of the first octaves, the LDS edge, v_top
-        edges = [S.v0 * 2.0 ** k * (1 + i / qm.HYP_SUB) for k in range(-1, 6) for i in range(qm.HYP_SUB)]
+        # every cell boundary of the first octaves of t = 1 + v/v0, v_top
+        edges = [S.v0 * (2.0 ** k * (1 + i / qm.HYP_SUB) - 1) for k in range(0, 7) for i in range(qm.HYP_SUB)]
         edges += [S.v_top * (1 - 1e-16), S.v_top, S.v_top * 1.5, S.v_top * 1e3]
-        pts.append(sgn * np.array(edges))
-        pts.append(sgn * np.nextafter(np.array(edges), 0))
+        edges = np.array(edges)
+        edges = edges[edges > 0]
+        pts.append(sgn * edges)
+        pts.append(sgn * np.nextafter(edges, 0))
     return np.concatenate(pts)
 
 
@@ -88,10 +93,11 @@ def test_table_matches_oracle(built):
 def test_header_layout(built):
     p, h, rr, rl, v, ref = built
     for S, rows, rate in ((h.right, rr, p[0] - p[1]), (h.left, rl, p[0] + p[1])):
-        assert S.ncell == qm.HYP_SUB * (S.noct + 1) and rows.shape == (S.ncell, qm.HYP_DEGREE + 1)
+        assert S.ncell == qm.HYP_SUB * S.noct and rows.shape == (S.ncell, qm.HYP_DEGREE + 1)
         assert 0 < S.noct <= 40
         assert S.v0 == 2.0 ** round(math.log2(S.v0)) and S.inv_v0 * S.v0 == 1.0
-        assert S.v_top == S.v0 * 2.0 ** S.noct
+        assert S.v0 == h.right.v0                  # one v0 for both sides
+        assert S.v_top == S.v0 * (2.0 ** S.noct - 1)
         assert S.max_rel_err < 1.2e-16         # the rounding of R itself, about half an ulp
         assert S.v_top >= 32 / rate            # the cells cover the bulk of the base
 
@@ -112,7 +118,7 @@ def test_centre_slope_closed_form(built):
     a, b, d = p
     g = math.sqrt(a * a - b * b)
     for S, rows, lpm, rate in ((h.right, rr, h.log_p_plus, a - b), (h.left, rl, h.log_p_minus, a + b)):
-        x = -S.v0 / (2 * qm.HYP_SUB)            # d at v = 0 in the first cell
+        x = -S.v0 / (2 * qm.HYP_SUB)            # d at v = 0 in the first cell (centre v0/16)
         R0 = rows[0][0]
         for c in rows[0][1:]:
             R0 = R0 * x + c
