@@ -46,10 +46,11 @@ int qm_debug_hyperbolic_dense(double alpha, double beta, double delta, const dou
 /*
  * Build the hyperbolic table on the host.  header_out (may be NULL)
  * receives the header (struct qm::HypTableHeader of csrc/qm_hyp_table.h,
- * 184 bytes: parameters, the two sides' masses, and for each side the cell
- * layout, large-v constants and the builder's check of its rounded rows);
- * coef_out (may be NULL) receives the rows of both sides, at their
- * coef_offset, if coef_cap doubles are enough.  Returns the number of
+ * 360 bytes: parameters, the two sides' masses, and for each side and each
+ * cell set -- FP64 outputs, FP32 outputs -- the cell layout, large-v
+ * constants and the builder's check of its rounded rows); coef_out (may be
+ * NULL) receives the rows of all four, at their coef_offset, if coef_cap
+ * doubles are enough.  Returns the number of
  * doubles, or -1 if the build failed.
  */
 int qm_debug_hyperbolic_table(double alpha, double beta, double delta, void* header_out, double* coef_out,

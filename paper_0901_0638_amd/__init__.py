@@ -216,17 +216,18 @@ class HypSide(ctypes.Structure):
     _fields_ = [("v0", ctypes.c_double), ("inv_v0", ctypes.c_double), ("v_top", ctypes.c_double),
                 ("far_c0", ctypes.c_double), ("far_c1", ctypes.c_double), ("far_c2", ctypes.c_double),
                 ("max_rel_err", ctypes.c_double), ("noct", ctypes.c_int32), ("ncell", ctypes.c_int32),
-                ("coef_offset", ctypes.c_uint64)]
+                ("degree", ctypes.c_int32), ("reserved", ctypes.c_int32), ("coef_offset", ctypes.c_uint64)]
 
 
 class HypTableHeader(ctypes.Structure):
     """Layout of qm::HypTableHeader (csrc/qm_hyp_table.h)."""
     _fields_ = [("alpha", ctypes.c_double), ("beta", ctypes.c_double), ("delta", ctypes.c_double),
                 ("log_p_plus", ctypes.c_double), ("log_p_minus", ctypes.c_double),
-                ("right", HypSide), ("left", HypSide)]
+                ("right", HypSide), ("left", HypSide), ("right32", HypSide), ("left32", HypSide)]
 
 
-HYP_DEGREE = 11
+HYP_DEGREE = 11       # FP64-output cells
+HYP_DEGREE_F32 = 7    # FP32-output cells
 HYP_SUB = 8
 
 
@@ -243,8 +244,11 @@ def debug_hyperbolic_dense(alpha, beta, delta, v):
     return q
 
 
-def debug_hyperbolic_table(alpha, beta, delta):
-    """(header, right rows[ncell, HYP_DEGREE+1], left rows) of the host-built table."""
+def debug_hyperbolic_table(alpha, beta, delta, which="f64"):
+    """(header, right rows[ncell, degree+1], left rows) of the host-built table;
+    `which` selects the cells for FP64 ("f64") or FP32 ("f32") outputs.  The
+    header's `right`/`left` fields describe the FP64 cells, `right32`/`left32`
+    the FP32 ones."""
     import numpy as np
     h = HypTableHeader()
     lib = load()
@@ -254,6 +258,7 @@ def debug_hyperbolic_table(alpha, beta, delta):
         raise ValueError("table build failed for %r" % ((alpha, beta, delta),))
     block = np.empty(n, np.float64)
     lib.qm_debug_hyperbolic_table(float(alpha), float(beta), float(delta), None, block.ctypes.data_as(dp), n)
-    W = HYP_DEGREE + 1
-    rows = [block[s.coef_offset:s.coef_offset + s.ncell * W].reshape(s.ncell, W) for s in (h.right, h.left)]
+    sides = (h.right, h.left) if which == "f64" else (h.right32, h.left32)
+    rows = [block[s.coef_offset:s.coef_offset + s.ncell * (s.degree + 1)].reshape(s.ncell, s.degree + 1)
+            for s in sides]
     return h, rows[0], rows[1]

@@ -29,10 +29,13 @@ namespace qm {
 typedef double d2 __attribute__((ext_vector_type(2)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 
-constexpr int HYP_ROW = HYP_DEGREE + 1;
-/* LDS row stride in doubles: rows of 12 doubles start 24 banks apart, so
-   rows 8 apart would share banks; one double of padding staggers them. */
-constexpr int HYP_LDS_STRIDE = HYP_ROW + 1;
+/* Rows of DEG + 1 doubles; in LDS one double of padding staggers the rows
+   over the banks (rows of 12 or 8 doubles would otherwise start on the
+   same few banks). */
+template <int DEG> struct HypRow {
+    static constexpr int n = DEG + 1;
+    static constexpr int lds = DEG + 2;
+};
 static_assert(HYP_SUB == 8, "the cell index takes the top 3 mantissa bits of t");
 
 /* The far path's parameters of one side. */
@@ -68,15 +71,17 @@ __device__ __forceinline__ int hyp_cell(double t, double* tc)
     return (int)(hi >> 17) - (1023 << 3);
 }
 
+template <int DEG>
 __device__ __forceinline__ double hyp_poly(const double* __restrict__ c, double d)
 {
     double R = c[0];
 #pragma unroll
-    for (int k = 1; k <= HYP_DEGREE; ++k) R = __builtin_fma(R, d, c[k]);
+    for (int k = 1; k <= DEG; ++k) R = __builtin_fma(R, d, c[k]);
     return R;
 }
 
 /* |Q(v)| from the LDS cells; *far for lanes beyond them (and NaN). */
+template <int DEG>
 __device__ __forceinline__ double hyp_near(double v, const double* __restrict__ lds, const HypParams& P, bool* far)
 {
     const double a = __builtin_fabs(v);
@@ -88,13 +93,14 @@ __device__ __forceinline__ double hyp_near(double v, const double* __restrict__ 
     j = out ? P.nlds - 1 : j;                     /* far and NaN lanes stay in bounds */
     const int row = j + (v < 0.0 ? P.nlds : 0);
     const double d = __builtin_fma(-P.v0, tc - 1.0, a);   /* a - centre; tc - 1 is exact */
-    return a * hyp_poly(lds + row * HYP_LDS_STRIDE, d);
+    return a * hyp_poly<DEG>(lds + row * HypRow<DEG>::lds, d);
 }
 
 /* |Q(v)| beyond the LDS cells: the side's global-memory cells up to v_top,
    then the large-v form; inf -> inf, NaN -> NaN.  The side's parameters
    come as plain values selected per lane (a reference to a lane-dependent
    side, or a struct passed by value, would put them in scratch memory). */
+template <int DEG>
 static __device__ __noinline__ double hyp_far(double a, double v0, double inv_v0, double v_top, double c0, double c1,
                                               double c2, const double* gcoef, int ncell)
 {
@@ -105,26 +111,29 @@ static __device__ __noinline__ double hyp_far(double a, double v0, double inv_v0
     double tc;
     int j = hyp_cell(__builtin_fma(a, inv_v0, 1.0), &tc);
     j = (unsigned)j < (unsigned)ncell ? j : ncell - 1;
-    return a * hyp_poly(gcoef + j * HYP_ROW, __builtin_fma(-v0, tc - 1.0, a));
+    return a * hyp_poly<DEG>(gcoef + j * HypRow<DEG>::n, __builtin_fma(-v0, tc - 1.0, a));
 }
 
+template <int DEG>
 __device__ __forceinline__ double hyp_far_of(double v, const HypParams& P)
 {
     const bool neg = v < 0.0;
-    return hyp_far(__builtin_fabs(v), P.v0, P.inv_v0, neg ? P.l.v_top : P.r.v_top, neg ? P.l.c0 : P.r.c0,
+    return hyp_far<DEG>(__builtin_fabs(v), P.v0, P.inv_v0, neg ? P.l.v_top : P.r.v_top, neg ? P.l.c0 : P.r.c0,
                    neg ? P.l.c1 : P.r.c1, neg ? P.l.c2 : P.r.c2, neg ? P.l.gcoef : P.r.gcoef,
                    neg ? P.l.ncell : P.r.ncell);
 }
 
 /* Both sides' LDS rows: right side rows 0..nlds-1, left side after. */
+template <int DEG>
 __device__ __forceinline__ void stage_hyp(double* lds, const HypParams& P)
 {
-    const int n = P.nlds * HYP_ROW;
+    constexpr int W = HypRow<DEG>::n;
+    const int n = P.nlds * W;
     for (int i = threadIdx.x; i < 2 * n; i += blockDim.x) {
         const bool left = i >= n;
         const int e = left ? i - n : i;
-        const int row = e / HYP_ROW, col = e - row * HYP_ROW;
-        lds[((left ? P.nlds : 0) + row) * HYP_LDS_STRIDE + col] = (left ? P.l.gcoef : P.r.gcoef)[e];
+        const int row = e / W, col = e - row * W;
+        lds[((left ? P.nlds : 0) + row) * HypRow<DEG>::lds + col] = (left ? P.l.gcoef : P.r.gcoef)[e];
     }
 }
 
@@ -141,7 +150,7 @@ __device__ __forceinline__ T hyp_out(double q, T v, const HypParams& P)
 
 /* The K elements a lane holds: every element's cell polynomial first (K
    independent chains), then one wave vote for the far fix-up. */
-template <typename T, int K>
+template <typename T, int K, int DEG>
 __device__ __forceinline__ void hyp_lane(const T (&v)[K], T (&y)[K], const double* lds, const HypParams& P)
 {
     double q[K];
@@ -149,14 +158,14 @@ __device__ __forceinline__ void hyp_lane(const T (&v)[K], T (&y)[K], const doubl
     bool anyfar = false;
 #pragma unroll
     for (int e = 0; e < K; ++e) {
-        q[e] = hyp_near((double)v[e], lds, P, &far[e]);
+        q[e] = hyp_near<DEG>((double)v[e], lds, P, &far[e]);
         anyfar |= far[e];
     }
     if (wave_any(anyfar)) {
 #pragma unroll
         for (int e = 0; e < K; ++e) {
             if (wave_any(far[e])) {
-                double qf = hyp_far_of(far[e] ? (double)v[e] : 0.0, P);
+                double qf = hyp_far_of<DEG>(far[e] ? (double)v[e] : 0.0, P);
                 q[e] = far[e] ? qf : q[e];
             }
         }
@@ -165,12 +174,12 @@ __device__ __forceinline__ void hyp_lane(const T (&v)[K], T (&y)[K], const doubl
     for (int e = 0; e < K; ++e) y[e] = hyp_out<T>(q[e], v[e], P);
 }
 
-template <typename T, bool VECTOR, int UNROLL>
+template <typename T, bool VECTOR, int UNROLL, int DEG>
 __global__ __launch_bounds__(256) void k_hyperbolic(HypArgs<T> a)
 {
     extern __shared__ double lds_hyp[];
     const HypParams P = a.P;
-    stage_hyp(lds_hyp, P);
+    stage_hyp<DEG>(lds_hyp, P);
     __syncthreads();
 
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
@@ -190,7 +199,7 @@ __global__ __launch_bounds__(256) void k_hyperbolic(HypArgs<T> a)
             for (int k = 0; k < UNROLL; ++k)
 #pragma unroll
                 for (int j = 0; j < NV; ++j) v[k * NV + j] = x[k][j];
-            hyp_lane<T, UNROLL * NV>(v, y, lds_hyp, P);
+            hyp_lane<T, UNROLL * NV, DEG>(v, y, lds_hyp, P);
 #pragma unroll
             for (int k = 0; k < UNROLL; ++k) {
                 V o;
@@ -204,7 +213,7 @@ __global__ __launch_bounds__(256) void k_hyperbolic(HypArgs<T> a)
             T v[NV], y[NV];
 #pragma unroll
             for (int j = 0; j < NV; ++j) v[j] = x[j];
-            hyp_lane<T, NV>(v, y, lds_hyp, P);
+            hyp_lane<T, NV, DEG>(v, y, lds_hyp, P);
             V o;
 #pragma unroll
             for (int j = 0; j < NV; ++j) o[j] = y[j];
@@ -215,14 +224,14 @@ __global__ __launch_bounds__(256) void k_hyperbolic(HypArgs<T> a)
             for (uint64_t e = threadIdx.x; e < extra; e += blockDim.x) {
                 uint64_t idx = e < a.head ? e : a.tail_begin + (e - a.head);
                 T v[1] = {a.in[idx]}, y[1];
-                hyp_lane<T, 1>(v, y, lds_hyp, P);
+                hyp_lane<T, 1, DEG>(v, y, lds_hyp, P);
                 a.out[idx] = y[0];
             }
         }
     } else {
         for (uint64_t i = tid; i < a.n; i += stride) {
             T v[1] = {a.in[i]}, y[1];
-            hyp_lane<T, 1>(v, y, lds_hyp, P);
+            hyp_lane<T, 1, DEG>(v, y, lds_hyp, P);
             a.out[i] = y[0];
         }
     }
@@ -230,10 +239,10 @@ __global__ __launch_bounds__(256) void k_hyperbolic(HypArgs<T> a)
 
 constexpr size_t HYP_LDS_MAX = 48 * 1024;   /* bytes of LDS per workgroup for the cells */
 
-static bool side_valid(const HypSide& s, uint64_t ncoef)
+static bool side_valid(const HypSide& s, int degree, uint64_t ncoef)
 {
-    return s.noct >= 1 && s.noct <= HYP_MAX_OCT && s.ncell == HYP_SUB * s.noct &&
-           s.coef_offset + (uint64_t)s.ncell * HYP_ROW <= ncoef && s.v0 > 0 && s.v_top > 0;
+    return s.degree == degree && s.noct >= 1 && s.noct <= HYP_MAX_OCT && s.ncell == HYP_SUB * s.noct &&
+           s.coef_offset + (uint64_t)s.ncell * (degree + 1) <= ncoef && s.v0 > 0 && s.v_top > 0;
 }
 
 /* Octaves of t = 1 + v/v0 that reach 64 / rate. */
@@ -255,10 +264,27 @@ static void side_far(const HypSide& s, const double* d_block, HypSideFar* f)
     f->pad = 0;
 }
 
-template <typename T>
-static hipError_t launch_h(const void* in, void* out, uint64_t n, const HypParams& P, size_t lds, hipStream_t s,
+template <typename T, int DEG>
+static hipError_t launch_h(const void* in, void* out, uint64_t n, const HypTableHeader& h, const HypSide& R,
+                           const HypSide& L, uint64_t ncoef, const double* d_block, double mu, hipStream_t s,
                            const KernelShape& shape)
 {
+    if (!side_valid(R, DEG, ncoef) || !side_valid(L, DEG, ncoef) || R.v0 != L.v0 || R.inv_v0 != L.inv_v0)
+        return hipErrorInvalidValue;
+    /* LDS cells per side: through the octave reaching 64 / rate on either
+       side, within both sides' cells and the LDS budget */
+    int noct = std::max(octaves_to(R.v0, h.alpha - h.beta), octaves_to(R.v0, h.alpha + h.beta));
+    noct = std::min(noct, std::min(R.noct, L.noct));
+    noct = std::min(noct, (int)(HYP_LDS_MAX / (2 * HypRow<DEG>::lds * sizeof(double) * HYP_SUB)));
+    HypParams P;
+    P.v0 = R.v0;
+    P.inv_v0 = R.inv_v0;
+    P.mu = mu;
+    side_far(R, d_block, &P.r);
+    side_far(L, d_block, &P.l);
+    P.nlds = HYP_SUB * noct;
+    P.pad = 0;
+    const size_t lds = (size_t)2 * P.nlds * HypRow<DEG>::lds * sizeof(double);
     HypArgs<T> a;
     a.in = static_cast<const T*>(in);
     a.out = static_cast<T*>(out);
@@ -277,11 +303,11 @@ static hipError_t launch_h(const void* in, void* out, uint64_t n, const HypParam
         if (blocks > shape.max_blocks) blocks = shape.max_blocks;
         if (blocks < 1) blocks = 1;
         if (shape.unroll == 4)
-            hipLaunchKernelGGL((k_hyperbolic<T, true, 4>), dim3((unsigned)blocks), dim3(256), lds, s, a);
+            hipLaunchKernelGGL((k_hyperbolic<T, true, 4, DEG>), dim3((unsigned)blocks), dim3(256), lds, s, a);
         else if (shape.unroll == 1)
-            hipLaunchKernelGGL((k_hyperbolic<T, true, 1>), dim3((unsigned)blocks), dim3(256), lds, s, a);
+            hipLaunchKernelGGL((k_hyperbolic<T, true, 1, DEG>), dim3((unsigned)blocks), dim3(256), lds, s, a);
         else
-            hipLaunchKernelGGL((k_hyperbolic<T, true, 2>), dim3((unsigned)blocks), dim3(256), lds, s, a);
+            hipLaunchKernelGGL((k_hyperbolic<T, true, 2, DEG>), dim3((unsigned)blocks), dim3(256), lds, s, a);
     } else {
         a.head = 0;
         a.nvec = n;
@@ -289,7 +315,7 @@ static hipError_t launch_h(const void* in, void* out, uint64_t n, const HypParam
         uint64_t blocks = (n + 255) / 256;
         if (blocks > shape.max_blocks) blocks = shape.max_blocks;
         if (blocks < 1) blocks = 1;
-        hipLaunchKernelGGL((k_hyperbolic<T, false, 1>), dim3((unsigned)blocks), dim3(256), lds, s, a);
+        hipLaunchKernelGGL((k_hyperbolic<T, false, 1, DEG>), dim3((unsigned)blocks), dim3(256), lds, s, a);
     }
     return hipGetLastError();
 }
@@ -298,26 +324,12 @@ hipError_t launch_hyperbolic(int dtype, int mode, const void* in, void* out, uin
                              const HypTableHeader& h, uint64_t ncoef, double mu, hipStream_t s,
                              const LaunchShape& shape)
 {
-    if (!side_valid(h.right, ncoef) || !side_valid(h.left, ncoef) || h.right.v0 != h.left.v0 ||
-        h.right.inv_v0 != h.left.inv_v0)
-        return hipErrorInvalidValue;
     const double* d_block = reinterpret_cast<const double*>(reinterpret_cast<const char*>(d_table) + sizeof(HypTableHeader));
-    /* LDS cells per side: through the octave reaching 64 / rate on either
-       side, within both sides' tables and the LDS budget */
-    int noct = std::max(octaves_to(h.right.v0, h.alpha - h.beta), octaves_to(h.right.v0, h.alpha + h.beta));
-    noct = std::min(noct, std::min(h.right.noct, h.left.noct));
-    noct = std::min(noct, (int)(HYP_LDS_MAX / (2 * HYP_LDS_STRIDE * sizeof(double) * HYP_SUB)));
-    HypParams P;
-    P.v0 = h.right.v0;
-    P.inv_v0 = h.right.inv_v0;
-    P.mu = mu;
-    side_far(h.right, d_block, &P.r);
-    side_far(h.left, d_block, &P.l);
-    P.nlds = HYP_SUB * noct;
-    P.pad = 0;
-    const size_t lds = (size_t)2 * P.nlds * HYP_LDS_STRIDE * sizeof(double);
-    if (dtype == QM_F64 && mode == QM_PLAIN) return launch_h<double>(in, out, n, P, lds, s, shape.hyperbolic[1]);
-    if (dtype == QM_F32 && mode == QM_F32_REFINE) return launch_h<float>(in, out, n, P, lds, s, shape.hyperbolic[0]);
+    if (dtype == QM_F64 && mode == QM_PLAIN)
+        return launch_h<double, HYP_DEGREE>(in, out, n, h, h.right, h.left, ncoef, d_block, mu, s, shape.hyperbolic[1]);
+    if (dtype == QM_F32 && mode == QM_F32_REFINE)
+        return launch_h<float, HYP_DEGREE_F32>(in, out, n, h, h.right32, h.left32, ncoef, d_block, mu, s,
+                                               shape.hyperbolic[0]);
     return hipErrorInvalidValue;
 }
 

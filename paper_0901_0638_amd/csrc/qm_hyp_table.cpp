@@ -508,30 +508,30 @@ bool far_start(const SideSolution& ss, fq tol, fq* P)
 }
 
 /*
- * Fit R = Q/v on [lo, hi] (degree HYP_DEGREE, Chebyshev points), rounded to
+ * Fit R = Q/v on [lo, hi] (degree deg, Chebyshev points), rounded to
  * double, highest power first.  Returns the largest relative error of the
- * interpolant at 2 HYP_DEGREE + 1 points against the solution; *rounded
- * gets that of the double row (which includes the rounding of R itself).
+ * interpolant at 2 deg + 1 points against the solution; *rounded gets that
+ * of the double row (which includes the rounding of R itself).
  */
-fq fit_cell(const SideSolution& ss, fq lo, fq hi, double* row, fq* rounded)
+fq fit_cell(const SideSolution& ss, int deg, fq lo, fq hi, double* row, fq* rounded)
 {
     fq c = (lo + hi) / 2, hw = (hi - lo) / 2;
     fq fv[64], mono[64];
-    for (int i = 0; i <= HYP_DEGREE; ++i) {
-        fq v = c + hw * cosq(M_PIq * (i + 0.5Q) / (HYP_DEGREE + 1));
+    for (int i = 0; i <= deg; ++i) {
+        fq v = c + hw * cosq(M_PIq * (i + 0.5Q) / (deg + 1));
         fv[i] = ss.eval(v) / v;
     }
-    cheb_to_monomial(fv, HYP_DEGREE, hw, mono);
-    for (int k = 0; k <= HYP_DEGREE; ++k) row[HYP_DEGREE - k] = (double)mono[k];
+    cheb_to_monomial(fv, deg, hw, mono);
+    for (int k = 0; k <= deg; ++k) row[deg - k] = (double)mono[k];
     fq worst = 0, worst_r = 0;
-    const int NT = 2 * HYP_DEGREE;
+    const int NT = 2 * deg;
     for (int t = 0; t <= NT; ++t) {
         fq d = -hw + 2 * hw * t / NT;
         fq v = c + d;
         fq ref = v > 0 ? ss.eval(v) / v : ss.slope0;
         fq pe = 0, pr = 0;
-        for (int k = HYP_DEGREE; k >= 0; --k) pe = pe * d + mono[k];
-        for (int k = 0; k <= HYP_DEGREE; ++k) pr = pr * d + (fq)row[k];
+        for (int k = deg; k >= 0; --k) pe = pe * d + mono[k];
+        for (int k = 0; k <= deg; ++k) pr = pr * d + (fq)row[k];
         fq et = fabsq(pe / ref - 1), er = fabsq(pr / ref - 1);
         if (et > worst) worst = et;
         if (er > worst_r) worst_r = er;
@@ -549,18 +549,24 @@ void cell_bounds(fq v0, int j, fq* lo, fq* hi)
     *hi = v0 * (ldexpq(1 + (fq)(i + 1) / HYP_SUB, k) - 1);
 }
 
-/* Fit cells [j0, j1) of a side for v0 into rows (HYP_DEGREE + 1 doubles per
-   cell, cell j0 first).  Returns false, with the failing cell in *bad, if
-   one misses tol; *worst gets the largest error of the rounded rows. */
-bool fit_cells(const SideSolution& ss, fq v0, int j0, int j1, fq tol, double* rows, fq* worst, int* bad)
+/* One cell set: its degree and the truncation tolerance its cells meet. */
+struct CellSpec {
+    int deg;
+    fq tol;
+};
+
+/* Fit cells [j0, j1) of a side for v0 into rows (deg + 1 doubles per cell,
+   cell j0 first).  Returns false, with the failing cell in *bad, if one
+   misses tol; *worst gets the largest error of the rounded rows. */
+bool fit_cells(const SideSolution& ss, const CellSpec& cs, fq v0, int j0, int j1, double* rows, fq* worst, int* bad)
 {
-    const int W = HYP_DEGREE + 1;
+    const int W = cs.deg + 1;
     for (int j = j0; j < j1; ++j) {
         fq lo, hi, r;
         cell_bounds(v0, j, &lo, &hi);
-        fq e = fit_cell(ss, lo, hi, rows + (size_t)(j - j0) * W, &r);
+        fq e = fit_cell(ss, cs.deg, lo, hi, rows + (size_t)(j - j0) * W, &r);
         if (r > *worst) *worst = r;
-        if (e > tol) {
+        if (e > cs.tol) {
             *bad = j;
             return false;
         }
@@ -568,24 +574,23 @@ bool fit_cells(const SideSolution& ss, fq v0, int j0, int j1, fq tol, double* ro
     return true;
 }
 
-const fq HYP_TOL = 2e-17Q;
-
 /*
  * Cells of one side for v0 = 2^lv, lv <= max_lv: the largest lv whose
  * cells all meet the tolerance (the first octave of t, uniform cells on
  * [0, v0), and the next two decide it; the rest are then fitted and
  * checked).  The cells reach v_top = v0 (2^noct - 1), beyond the first
- * power of 2 from which on the large-v form holds.  Returns lv, or
- * INT_MIN with a message if none fits.
+ * power of 2 from which on the large-v form holds to a quarter of the
+ * tolerance.  Returns lv, or INT_MIN with a message if none fits.
  */
-int fit_side(const SideSolution& ss, int max_lv, std::vector<double>* rows_out, HypSide* hs, char* err, int errlen)
+int fit_side(const SideSolution& ss, const CellSpec& cs, int max_lv, std::vector<double>* rows_out, HypSide* hs,
+             char* err, int errlen)
 {
     fq P;
-    if (!far_start(ss, HYP_TOL / 4, &P)) {
+    if (!far_start(ss, cs.tol / 4, &P)) {
         snprintf(err, errlen, "large-v form not accurate at 2^30 / (alpha - beta)");
         return INT_MIN;
     }
-    const int W = HYP_DEGREE + 1;
+    const int W = cs.deg + 1;
     int lv = (int)lrintq(log2q(P));
     if (lv > 3) lv = 3;
     if (lv > max_lv) lv = max_lv;
@@ -599,8 +604,8 @@ int fit_side(const SideSolution& ss, int max_lv, std::vector<double>* rows_out, 
         fq worst = 0;
         int bad = -1;
         const int head = ncell < 3 * HYP_SUB ? ncell : 3 * HYP_SUB;
-        if (!fit_cells(ss, v0, 0, head, HYP_TOL, rows.data(), &worst, &bad)) continue;
-        if (!fit_cells(ss, v0, head, ncell, HYP_TOL, rows.data() + (size_t)head * W, &worst, &bad)) {
+        if (!fit_cells(ss, cs, v0, 0, head, rows.data(), &worst, &bad)) continue;
+        if (!fit_cells(ss, cs, v0, head, ncell, rows.data() + (size_t)head * W, &worst, &bad)) {
             fq lo, hi;
             cell_bounds(v0, bad, &lo, &hi);
             snprintf(err, errlen, "cell near v=%g misses the accuracy target", (double)lo);
@@ -615,11 +620,39 @@ int fit_side(const SideSolution& ss, int max_lv, std::vector<double>* rows_out, 
         hs->max_rel_err = (double)worst;
         hs->noct = noct;
         hs->ncell = ncell;
+        hs->degree = cs.deg;
+        hs->reserved = 0;
         *rows_out = std::move(rows);
         return lv;
     }
     snprintf(err, errlen, "no cell width met the accuracy target within %d octaves", HYP_MAX_OCT);
     return INT_MIN;
+}
+
+/* Both sides' cells of one set, with one v0: the smaller of the two sides'
+   own choices.  Appends the right side's rows, then the left side's. */
+bool fit_set(const SideSolution& rs, const SideSolution& ls, const CellSpec& cs, HypSide* right, HypSide* left,
+             std::vector<double>& coef, char* err, int errlen)
+{
+    std::vector<double> rr, rl;
+    int lr = fit_side(rs, cs, 3, &rr, right, err, errlen);
+    if (lr == INT_MIN) return false;
+    int ll = fit_side(ls, cs, lr, &rl, left, err, errlen);
+    for (int it = 0; it < 8 && ll != INT_MIN && ll != lr; ++it) {
+        lr = fit_side(rs, cs, ll, &rr, right, err, errlen);
+        if (lr == INT_MIN) return false;
+        if (lr != ll) ll = fit_side(ls, cs, lr, &rl, left, err, errlen);
+    }
+    if (ll == INT_MIN) return false;
+    if (ll != lr) {
+        snprintf(err, errlen, "no common cell width");
+        return false;
+    }
+    right->coef_offset = coef.size();
+    coef.insert(coef.end(), rr.begin(), rr.end());
+    left->coef_offset = coef.size();
+    coef.insert(coef.end(), rl.begin(), rl.end());
+    return true;
 }
 
 bool check_params(double alpha, double beta, double delta)
@@ -644,25 +677,13 @@ int build_hyperbolic_table(double alpha, double beta, double delta, HostHypTable
     H.log_p_minus = (double)left.log_p;
     SideSolution rs, ls;
     if (!solve_side(right, &rs, err, errlen) || !solve_side(left, &ls, err, errlen)) return -1;
-    /* both sides share v0 (one cell computation for every lane): the
-       smaller of the two sides' own choices */
-    std::vector<double> rr, rl;
-    int lr = fit_side(rs, 3, &rr, &H.right, err, errlen);
-    if (lr == INT_MIN) return -1;
-    int ll = fit_side(ls, lr, &rl, &H.left, err, errlen);
-    for (int it = 0; it < 8 && ll != INT_MIN && ll != lr; ++it) {
-        lr = fit_side(rs, ll, &rr, &H.right, err, errlen);
-        if (lr == INT_MIN) return -1;
-        if (lr != ll) ll = fit_side(ls, lr, &rl, &H.left, err, errlen);
-    }
-    if (ll == INT_MIN || ll != lr) return ll == INT_MIN ? -1 : fail(err, errlen, "no common cell width");
-    H.right.coef_offset = 0;
-    H.left.coef_offset = rr.size();
-    out->ncoef = rr.size() + rl.size();
+    std::vector<double> coef;
+    if (!fit_set(rs, ls, CellSpec{HYP_DEGREE, 2e-17Q}, &H.right, &H.left, coef, err, errlen)) return -1;
+    if (!fit_set(rs, ls, CellSpec{HYP_DEGREE_F32, 1e-10Q}, &H.right32, &H.left32, coef, err, errlen)) return -1;
+    out->ncoef = coef.size();
     out->coef = (double*)malloc(out->ncoef * sizeof(double));
     if (!out->coef) return fail(err, errlen, "out of memory");
-    memcpy(out->coef, rr.data(), rr.size() * sizeof(double));
-    memcpy(out->coef + rr.size(), rl.data(), rl.size() * sizeof(double));
+    memcpy(out->coef, coef.data(), out->ncoef * sizeof(double));
     return 0;
 }
 

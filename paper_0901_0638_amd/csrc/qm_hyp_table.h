@@ -7,7 +7,8 @@
 
 namespace qm {
 
-constexpr int HYP_DEGREE = 11;      /* polynomial degree per cell */
+constexpr int HYP_DEGREE = 11;      /* polynomial degree per cell, FP64 outputs */
+constexpr int HYP_DEGREE_F32 = 7;   /* FP32 outputs (cells to 1e-10, evaluated in FP64) */
 constexpr int HYP_SUB = 8;          /* cells per octave (a power of 2) */
 constexpr int HYP_MAX_OCT = 40;     /* octaves per side at most */
 
@@ -18,7 +19,7 @@ constexpr int HYP_MAX_OCT = 40;     /* octaves per side at most */
  * cells in each octave [2^k, 2^(k+1)) of t, k < noct, so cell
  * j = HYP_SUB k + i is read off the exponent and leading mantissa bits of t.
  * Cell j holds R = sum_k c_{j,k} d^k, d = v - centre_j, centre_j at
- * t = 2^k (1 + (i + 1/2)/HYP_SUB), highest power first, HYP_DEGREE + 1
+ * t = 2^k (1 + (i + 1/2)/HYP_SUB), highest power first, degree + 1
  * doubles per row, starting coef_offset doubles into the table's
  * coefficient block.  From v_top = v0 (2^noct - 1) on:
  * Q = v + far_c0 + (far_c1 + far_c2 / v) / v, the large-v expansion of the
@@ -31,15 +32,20 @@ struct HypSide {
     double max_rel_err;      /* builder's check of the rounded coefficients */
     int32_t noct;
     int32_t ncell;           /* HYP_SUB noct */
+    int32_t degree;          /* rows of degree + 1 doubles */
+    int32_t reserved;
     uint64_t coef_offset;
 };
 
 struct HypTableHeader {
     double alpha, beta, delta;
     double log_p_plus, log_p_minus;   /* target masses on x > 0 and x < 0 */
-    HypSide right;                    /* v >= 0 */
+    HypSide right;                    /* v >= 0, FP64 outputs (degree HYP_DEGREE, to 2e-17) */
     HypSide left;                     /* v < 0, as -Q(-v) of the mirrored side */
+    HypSide right32, left32;          /* FP32 outputs (degree HYP_DEGREE_F32, to 1e-10) */
 };
+
+static_assert(sizeof(HypTableHeader) == 360, "the header layout is part of qm_debug.h");
 
 struct HostHypTable {
     HypTableHeader hdr;

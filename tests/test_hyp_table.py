@@ -6,6 +6,7 @@ and leading mantissa bits of t = 1 + |v|/v0, Horner in d = |v| - centre,
 the large-v form from v_top on), are compared with the oracle, which solves the
 defining equation F(x) = F0(v) by quadrature and bisection.  Closed forms
 pin the centre slope (Section 8.1, with K_1 from scipy) and the masses."""
+import ctypes
 import math
 
 import numpy as np
@@ -18,14 +19,15 @@ PARAMS = [(1.0, 0.0, 1.0), (1.0, 0.5, 1.0), (2.0, -1.5, 0.3), (1.0, 0.9, 5.0), (
           (50.0, 10.0, 0.1)]
 
 
-def table_eval(h, rr, rl, v):
+def table_eval(h, rr, rl, v, which="f64"):
     """The kernel's evaluation of a table, in numpy FP64: t = 1 + |v|/v0 by
     one fused multiply-add, the cell from the exponent and top three
     mantissa bits of t, its centre from t with the lower bits replaced."""
     v = np.asarray(v, np.float64)
     out = np.empty_like(v)
+    right, left = (h.right, h.left) if which == "f64" else (h.right32, h.left32)
     for i, x in enumerate(v):
-        S, rows = (h.left, rl) if x < 0 else (h.right, rr)
+        S, rows = (left, rl) if x < 0 else (right, rr)
         a = abs(x)
         if not a < S.v_top:
             Q = a if not np.isfinite(a) else a + (S.far_c0 + (S.far_c1 + S.far_c2 / a) / a)
@@ -90,16 +92,33 @@ def test_table_matches_oracle(built):
     assert rel.max() <= 6e-16, (p, rel.max(), v[rel.argmax()])
 
 
+def test_fp32_cells_match_oracle(built):
+    """The cells for FP32 outputs (degree 7, truncation 1e-10) evaluated in FP64."""
+    p, h, _, _, v, ref = built
+    _, r32, l32 = qm.debug_hyperbolic_table(*p, which="f32")
+    got = table_eval(h, r32, l32, v, "f32")
+    rel = np.abs(got - ref) / np.abs(ref)
+    assert rel.max() <= 1.2e-10, (p, rel.max(), v[rel.argmax()])
+
+
 def test_header_layout(built):
     p, h, rr, rl, v, ref = built
-    for S, rows, rate in ((h.right, rr, p[0] - p[1]), (h.left, rl, p[0] + p[1])):
-        assert S.ncell == qm.HYP_SUB * S.noct and rows.shape == (S.ncell, qm.HYP_DEGREE + 1)
+    assert ctypes.sizeof(qm.HypTableHeader) == 360
+    _, r32, l32 = qm.debug_hyperbolic_table(*p, which="f32")
+    for S, rows, rate, deg, bound, S0 in ((h.right, rr, p[0] - p[1], qm.HYP_DEGREE, 1.2e-16, h.right),
+                                         (h.left, rl, p[0] + p[1], qm.HYP_DEGREE, 1.2e-16, h.right),
+                                         (h.right32, r32, p[0] - p[1], qm.HYP_DEGREE_F32, 1e-10, h.right32),
+                                         (h.left32, l32, p[0] + p[1], qm.HYP_DEGREE_F32, 1e-10, h.right32)):
+        assert S.degree == deg
+        assert S.ncell == qm.HYP_SUB * S.noct and rows.shape == (S.ncell, deg + 1)
         assert 0 < S.noct <= 40
         assert S.v0 == 2.0 ** round(math.log2(S.v0)) and S.inv_v0 * S.v0 == 1.0
-        assert S.v0 == h.right.v0                  # one v0 for both sides
+        assert S.v0 == S0.v0                      # one v0 for both sides of a cell set
         assert S.v_top == S.v0 * (2.0 ** S.noct - 1)
-        assert S.max_rel_err < 1.2e-16         # the rounding of R itself, about half an ulp
-        assert S.v_top >= 32 / rate            # the cells cover the bulk of the base
+        assert S.max_rel_err < bound              # FP64: the rounding of R itself, about half an ulp
+        # the cells cover the bulk of the base (the FP32 set's large-v form can
+        # take over earlier: it needs only 2.5e-11)
+        assert S.v_top >= (32 if deg == qm.HYP_DEGREE else 16) / rate
 
 
 def test_masses_match_oracle(built):
