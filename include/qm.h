@@ -76,7 +76,7 @@ enum qm_dtype { QM_F32 = 0, QM_F64 = 1 };
 enum qm_mode { QM_PLAIN = 0, QM_F32_REFINE = 1, QM_PAPER = 2 };
 
 /* QM_UNIFORM (the uniforms themselves) is accepted by qm_generate only. */
-enum qm_kind { QM_NORMAL_QUANTILE = 0, QM_STUDENT_T = 1, QM_EXP_TO_NORMAL = 2, QM_UNIFORM = 3 };
+enum qm_kind { QM_NORMAL_QUANTILE = 0, QM_STUDENT_T = 1, QM_EXP_TO_NORMAL = 2, QM_UNIFORM = 3, QM_EXP_TO_HYPERBOLIC = 4 };
 
 typedef struct qm_ctx qm_ctx;
 
@@ -215,17 +215,21 @@ typedef struct {
     void* d_out;        /* device output, n elements of dtype */
     uint64_t n;
     uint64_t user_tag;  /* opaque to the library */
+    double alpha, beta, delta, mu;  /* QM_EXP_TO_HYPERBOLIC only: the target's parameters */
 } qm_request;
 
 /*
- * Run `count` requests (host array) of mixed kinds, dtypes, modes and nu as
- * one persistent launch on hip_stream: workgroups claim fixed-size chunks
+ * Run `count` requests (host array) of mixed kinds (every kind but
+ * QM_UNIFORM), dtypes, modes, nu and hyperbolic parameters as one
+ * persistent launch on hip_stream: workgroups claim fixed-size chunks
  * from a device counter; each chunk belongs to one request and is evaluated
  * by the same device code as the single-request call with that kind, dtype
  * and mode, so each output is bitwise identical to the single call's.
  * Validation covers every request before anything is launched; the first
- * invalid one decides the status.  The call returns after enqueueing; the
- * descriptor upload is ordered on hip_stream.
+ * invalid one decides the status.  Student t and hyperbolic tables not yet
+ * in the context are built by this call, on the host, before the launch.
+ * The call returns after enqueueing; the descriptor upload is ordered on
+ * hip_stream.
  */
 qm_status qm_run_batch(qm_ctx* ctx, const qm_request* reqs, uint64_t count, void* hip_stream);
 

@@ -16,6 +16,7 @@ import ctypes
 from ._lib import (  # noqa: F401
     QM_E_CLOSED, QM_E_DTYPE, QM_E_HIP, QM_E_INVAL, QM_E_NOMEM, QM_E_TICKET, QM_EXP_TO_NORMAL, QM_F32,
     QM_F32_REFINE, QM_F64, QM_NORMAL_QUANTILE, QM_OK, QM_PAPER, QM_PENDING, QM_PLAIN, QM_STUDENT_T, QM_UNIFORM, QMError,
+    QM_EXP_TO_HYPERBOLIC,
     check, load, qm_request,
 )
 
@@ -132,12 +133,14 @@ def qm_hyperbolic_masses(ctx, alpha, beta, delta):
     return lp.value, lm.value
 
 
-def make_request(kind, inp, out, mode=None, nu=0.0, user_tag=0):
-    """qm_request for qm_run_batch / qm_submit from a pair of device tensors."""
+def make_request(kind, inp, out, mode=None, nu=0.0, user_tag=0, hyperbolic=(0.0, 0.0, 0.0), mu=0.0):
+    """qm_request for qm_run_batch / qm_submit from a pair of device tensors
+    (`hyperbolic` = (alpha, beta, delta) and `mu` for QM_EXP_TO_HYPERBOLIC)."""
     pi, po, n, dt = _io(inp, out)
     if mode is None:
         mode = QM_PLAIN if dt == QM_F64 else QM_F32_REFINE
-    return qm_request(kind, dt, mode, 0, float(nu), pi.value, po.value, n, user_tag)
+    a, b, d = (float(x) for x in hyperbolic)
+    return qm_request(kind, dt, mode, 0, float(nu), pi.value, po.value, n, user_tag, a, b, d, float(mu))
 
 
 def qm_run_batch(ctx, reqs, stream=None, device_tensor=None):

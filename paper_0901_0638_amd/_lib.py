@@ -31,6 +31,7 @@ QM_NORMAL_QUANTILE = 0
 QM_STUDENT_T = 1
 QM_EXP_TO_NORMAL = 2
 QM_UNIFORM = 3
+QM_EXP_TO_HYPERBOLIC = 4
 
 
 class qm_request(ctypes.Structure):
@@ -44,6 +45,10 @@ class qm_request(ctypes.Structure):
         ("d_out", ctypes.c_void_p),
         ("n", ctypes.c_uint64),
         ("user_tag", ctypes.c_uint64),
+        ("alpha", ctypes.c_double),
+        ("beta", ctypes.c_double),
+        ("delta", ctypes.c_double),
+        ("mu", ctypes.c_double),
     ]
 
 

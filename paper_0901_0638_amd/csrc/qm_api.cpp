@@ -40,6 +40,11 @@ qm_status hip_fail(hipError_t e, const char* what)
 
 size_t dtype_size(int dtype) { return dtype == QM_F64 ? 8 : 4; }
 
+bool hyp_params_ok(double alpha, double beta, double delta)
+{
+    return std::isfinite(alpha) && std::isfinite(beta) && std::isfinite(delta) && delta > 0 && alpha > std::fabs(beta);
+}
+
 }  // namespace
 
 namespace qm {
@@ -66,6 +71,14 @@ qm_status check_request(const qm_request& r, int* dtype_size_out)
             return fail(QM_E_DTYPE, "Student t: F64 QM_PLAIN or F32 QM_F32_REFINE");
         if (std::isnan(r.nu) || !(r.nu >= 0.5))
             return fail(QM_E_INVAL, "nu must be >= 0.5 or +inf (got %g)", r.nu);
+        break;
+    case QM_EXP_TO_HYPERBOLIC:
+        if (!(r.dtype == QM_F64 && r.mode == QM_PLAIN) && !(r.dtype == QM_F32 && r.mode == QM_F32_REFINE))
+            return fail(QM_E_DTYPE, "exp->hyperbolic: F64 QM_PLAIN or F32 QM_F32_REFINE");
+        if (!hyp_params_ok(r.alpha, r.beta, r.delta))
+            return fail(QM_E_INVAL, "need |beta| < alpha, delta > 0, all finite (got %g, %g, %g)", r.alpha, r.beta,
+                        r.delta);
+        if (!std::isfinite(r.mu)) return fail(QM_E_INVAL, "mu must be finite");
         break;
     default:
         return fail(QM_E_INVAL, "unknown kind %u", r.kind);
@@ -155,6 +168,12 @@ qm_status run_single(qm_ctx* ctx, const qm_request& r, hipStream_t s)
         qm_status st = get_table(ctx, r.nu, &t);
         if (st != QM_OK) return st;
         e = launch_student(r.dtype, r.mode, r.d_in, r.d_out, r.n, t->d_table, t->hdr, s, ctx->shape);
+    } else if (r.kind == QM_EXP_TO_HYPERBOLIC) {
+        const DeviceHypTable* t = nullptr;
+        qm_status st = get_hyp_table(ctx, r.alpha, r.beta, r.delta, &t);
+        if (st != QM_OK) return st;
+        e = launch_hyperbolic(r.dtype, r.mode, r.d_in, r.d_out, r.n, t->d_table, t->hdr, t->ncoef, r.mu, s,
+                              ctx->shape);
     } else {
         e = launch_elementwise(r.kind, r.dtype, r.mode, r.d_in, r.d_out, r.n, s, ctx->shape);
     }
@@ -267,39 +286,33 @@ qm_status qm_recycle_exp_to_normal(qm_ctx* ctx, const void* d_x, void* d_z, uint
     return single(ctx, QM_EXP_TO_NORMAL, d_x, d_z, n, dtype, mode, 0.0, s);
 }
 
-static bool hyp_params_ok(double alpha, double beta, double delta)
-{
-    return std::isfinite(alpha) && std::isfinite(beta) && std::isfinite(delta) && delta > 0 && alpha > std::fabs(beta);
-}
-
 qm_status qm_recycle_exp_to_hyperbolic(qm_ctx* ctx, const void* d_v, void* d_x, uint64_t n, int dtype, int mode,
                                        double alpha, double beta, double delta, double mu, void* s)
 {
     if (!ctx) return fail(QM_E_INVAL, "context is NULL");
     if (dtype != QM_F32 && dtype != QM_F64) return fail(QM_E_INVAL, "unknown dtype %d", dtype);
     if (mode != QM_PLAIN && mode != QM_F32_REFINE && mode != QM_PAPER) return fail(QM_E_INVAL, "unknown mode %d", mode);
-    if (!(dtype == QM_F64 && mode == QM_PLAIN) && !(dtype == QM_F32 && mode == QM_F32_REFINE))
-        return fail(QM_E_DTYPE, "exp->hyperbolic: F64 QM_PLAIN or F32 QM_F32_REFINE");
-    if (!hyp_params_ok(alpha, beta, delta))
-        return fail(QM_E_INVAL, "need |beta| < alpha, delta > 0, all finite (got %g, %g, %g)", alpha, beta, delta);
-    if (!std::isfinite(mu)) return fail(QM_E_INVAL, "mu must be finite");
-    const size_t es = dtype_size(dtype);
-    if (n > 0) {
-        if (!d_v || !d_x) return fail(QM_E_INVAL, "NULL buffer with n > 0");
-        uintptr_t a = (uintptr_t)d_v, b = (uintptr_t)d_x;
-        if (a % es || b % es) return fail(QM_E_INVAL, "buffers must be aligned to the element size");
-        if (n > (UINT64_MAX / 2) / es) return fail(QM_E_INVAL, "n too large");
-        uint64_t bytes = n * es;
-        if (a != b && a < b + bytes && b < a + bytes) return fail(QM_E_INVAL, "input and output partially overlap");
-    }
+    qm_request r{};
+    r.kind = QM_EXP_TO_HYPERBOLIC;
+    r.dtype = (uint32_t)dtype;
+    r.mode = (uint32_t)mode;
+    r.d_in = d_v;
+    r.d_out = d_x;
+    r.n = n;
+    r.alpha = alpha;
+    r.beta = beta;
+    r.delta = delta;
+    r.mu = mu;
+    qm_status st = qm::check_request(r, nullptr);
+    if (st != QM_OK) return st;
     hipError_t e = hipSetDevice(ctx->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    /* the table is built (and cached) even for n = 0, so that a call can
+       prepare it ahead of time */
     const DeviceHypTable* t = nullptr;
-    qm_status st = qm::get_hyp_table(ctx, alpha, beta, delta, &t);
-    if (st != QM_OK || n == 0) return st;
-    e = qm::launch_hyperbolic(dtype, mode, d_v, d_x, n, t->d_table, t->hdr, t->ncoef, mu, (hipStream_t)s, ctx->shape);
-    if (e != hipSuccess) return hip_fail(e, "kernel launch");
-    return QM_OK;
+    st = qm::get_hyp_table(ctx, alpha, beta, delta, &t);
+    if (st != QM_OK) return st;
+    return qm::run_single(ctx, r, (hipStream_t)s);
 }
 
 qm_status qm_hyperbolic_masses(qm_ctx* ctx, double alpha, double beta, double delta, double* log_p_plus,

@@ -4,6 +4,7 @@
 #pragma once
 #include <stdint.h>
 
+#include "qm_hyp_device.hpp"
 #include "qm_internal.h"
 #include "qm_student_device.hpp"
 
@@ -17,13 +18,13 @@ namespace qm {
 constexpr uint64_t QM_CHUNK_MIN = 2048;
 constexpr uint64_t QM_CHUNK_MAX = 32768;
 
-/* Dynamic LDS (the largest Student t table of the batch) the batch kernel
+/* Dynamic LDS (the largest Student t or hyperbolic table of the batch) the batch kernel
    may ask for: 64 KB less its static 8 KB gather list and claim slot. */
 constexpr size_t QM_BATCH_DYNAMIC_LDS_MAX = 65536 - 8192 - 256;
 
 enum BatchOp : uint32_t {
     BOP_NQ64_PLAIN = 0, BOP_NQ64_PAPER, BOP_NQ32_REFINE, BOP_NQ32_PAPER, BOP_NQ32_PLAIN,
-    BOP_E64_PLAIN, BOP_E64_PAPER, BOP_E32_REFINE, BOP_T64, BOP_T32,
+    BOP_E64_PLAIN, BOP_E64_PAPER, BOP_E32_REFINE, BOP_T64, BOP_T32, BOP_H64, BOP_H32,
 };
 
 /* Device block: header, then nreq BatchReq. */
@@ -43,7 +44,10 @@ struct BatchReq {
     uint64_t n;
     uint64_t chunk_base;    /* global index of the request's first chunk */
     const double* coef;     /* Student t: device cell rows of the request's dtype */
-    StudentParams P;        /* Student t: table parameters */
+    union {
+        StudentParams P;    /* Student t: table parameters */
+        HypParams H;        /* exp -> hyperbolic: table parameters (cells of the request's dtype) */
+    };
 };
 
 StudentParams make_params(const TTableHeader& h, const TCells& c, const double* d_rows);

@@ -9,8 +9,8 @@
  * per-element functions as the single-request kernels, so every output is
  * bitwise identical to the single call's.  A chunk belongs to one request,
  * so the kind switch and the wave votes inside the maps are uniform across
- * the workgroup.  A Student t chunk stages its table in LDS unless the
- * workgroup's previous chunk already did.  The loop ends when the counter
+ * the workgroup.  A Student t or hyperbolic chunk stages its table in LDS
+ * unless the workgroup's previous chunk already did.  The loop ends when the counter
  * passes the last chunk, which every workgroup reaches without waiting on
  * any other.
  */
@@ -20,6 +20,7 @@
 #include "qm_batch.h"
 #include "qm_device.hpp"
 #include "qm_hybrid.hpp"
+#include "qm_hyp_device.hpp"
 #include "qm_student_device.hpp"
 
 namespace qm {
@@ -161,6 +162,25 @@ static __device__ __noinline__ void chunk_t32(const void* in, void* out, uint64_
                      [&](float z) { return (float)student_eval<T_DEGREE_F32>((double)z, lds_tab, P); });
 }
 
+/* Exponential -> hyperbolic from the cells in LDS: mu + sign(v) |Q(v)|, as
+   the map kernel forms it. */
+static __device__ __noinline__ void chunk_h64(const void* in, void* out, uint64_t begin, uint64_t end,
+                                              const HypParams H)
+{
+    chunk_map<double>((const double*)in, (double*)out, begin, end, [&](double v) {
+        return H.mu + __builtin_copysign(hyp_abs_q<HYP_DEGREE>(v, lds_tab, H), v);
+    });
+}
+
+static __device__ __noinline__ void chunk_h32(const void* in, void* out, uint64_t begin, uint64_t end,
+                                              const HypParams H)
+{
+    chunk_map<float>((const float*)in, (float*)out, begin, end, [&](float v) {
+        const double vd = (double)v;
+        return (float)(H.mu + __builtin_copysign(hyp_abs_q<HYP_DEGREE_F32>(vd, lds_tab, H), vd));
+    });
+}
+
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_batch(BatchHeader* hdr, const BatchReq* __restrict__ reqs)
 {
     __shared__ uint64_t s_chunk;
@@ -211,6 +231,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
                 else chunk_t64<T_DEGREE_LOW>(R.in, R.out, begin, end, R.P);
             }
             else chunk_t32(R.in, R.out, begin, end, R.P);
+            break;
+        }
+        case BOP_H64:
+        case BOP_H32: {
+            if (loaded != R.H.r.gcoef) {
+                __syncthreads();
+                if (R.op == BOP_H64) stage_hyp<HYP_DEGREE>(lds_tab, R.H);
+                else stage_hyp<HYP_DEGREE_F32>(lds_tab, R.H);
+                __syncthreads();
+                loaded = R.H.r.gcoef;
+            }
+            if (R.op == BOP_H64) chunk_h64(R.in, R.out, begin, end, R.H);
+            else chunk_h32(R.in, R.out, begin, end, R.H);
             break;
         }
         default:

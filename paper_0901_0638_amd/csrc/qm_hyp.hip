@@ -20,37 +20,13 @@
 
 #include <algorithm>
 
-#include "qm_device.hpp"
-#include "qm_hyp_table.h"
+#include "qm_hyp_device.hpp"
 #include "qm_internal.h"
 
 namespace qm {
 
 typedef double d2 __attribute__((ext_vector_type(2)));
 typedef float f4 __attribute__((ext_vector_type(4)));
-
-/* Rows of DEG + 1 doubles; in LDS one double of padding staggers the rows
-   over the banks (rows of 12 or 8 doubles would otherwise start on the
-   same few banks). */
-template <int DEG> struct HypRow {
-    static constexpr int n = DEG + 1;
-    static constexpr int lds = DEG + 2;
-};
-static_assert(HYP_SUB == 8, "the cell index takes the top 3 mantissa bits of t");
-
-/* The far path's parameters of one side. */
-struct HypSideFar {
-    double v_top, c0, c1, c2;
-    const double* gcoef;          /* the side's rows in global memory */
-    int ncell, pad;
-};
-
-struct HypParams {
-    double v0, inv_v0, mu;        /* v0 is shared by both sides */
-    HypSideFar r, l;              /* v >= 0, v < 0 */
-    int nlds;                     /* cells per side in LDS, right side's first */
-    int pad;
-};
 
 template <typename T>
 struct HypArgs {
@@ -59,83 +35,6 @@ struct HypArgs {
     uint64_t head, nvec, tail_begin, n;
     HypParams P;
 };
-
-/* Cell of t = 1 + a/v0 >= 1: the biased exponent and the top three mantissa
-   bits of t give j = 8 k + i for t in [2^k (1 + i/8), 2^k (1 + (i+1)/8));
-   the cell's centre in t, 2^k (1 + (i + 1/2)/8), is t with the lower
-   mantissa bits replaced by 1000...  NaN and inf give j >= 8192. */
-__device__ __forceinline__ int hyp_cell(double t, double* tc)
-{
-    const uint32_t hi = (uint32_t)__double2hiint(t);
-    *tc = __hiloint2double((int)((hi & ~((1u << 17) - 1)) | (1u << 16)), 0);
-    return (int)(hi >> 17) - (1023 << 3);
-}
-
-template <int DEG>
-__device__ __forceinline__ double hyp_poly(const double* __restrict__ c, double d)
-{
-    double R = c[0];
-#pragma unroll
-    for (int k = 1; k <= DEG; ++k) R = __builtin_fma(R, d, c[k]);
-    return R;
-}
-
-/* |Q(v)| from the LDS cells; *far for lanes beyond them (and NaN). */
-template <int DEG>
-__device__ __forceinline__ double hyp_near(double v, const double* __restrict__ lds, const HypParams& P, bool* far)
-{
-    const double a = __builtin_fabs(v);
-    const double t = __builtin_fma(a, P.inv_v0, 1.0);
-    double tc;
-    int j = hyp_cell(t, &tc);                    /* >= 0: t >= 1 */
-    const bool out = !((unsigned)j < (unsigned)P.nlds);
-    *far = out;
-    j = out ? P.nlds - 1 : j;                     /* far and NaN lanes stay in bounds */
-    const int row = j + (v < 0.0 ? P.nlds : 0);
-    const double d = __builtin_fma(-P.v0, tc - 1.0, a);   /* a - centre; tc - 1 is exact */
-    return a * hyp_poly<DEG>(lds + row * HypRow<DEG>::lds, d);
-}
-
-/* |Q(v)| beyond the LDS cells: the side's global-memory cells up to v_top,
-   then the large-v form; inf -> inf, NaN -> NaN.  The side's parameters
-   come as plain values selected per lane (a reference to a lane-dependent
-   side, or a struct passed by value, would put them in scratch memory). */
-template <int DEG>
-static __device__ __noinline__ double hyp_far(double a, double v0, double inv_v0, double v_top, double c0, double c1,
-                                              double c2, const double* gcoef, int ncell)
-{
-    if (!(a < v_top)) {
-        if (!(a < __builtin_inf())) return a;
-        return a + (c0 + (c1 + c2 / a) / a);
-    }
-    double tc;
-    int j = hyp_cell(__builtin_fma(a, inv_v0, 1.0), &tc);
-    j = (unsigned)j < (unsigned)ncell ? j : ncell - 1;
-    return a * hyp_poly<DEG>(gcoef + j * HypRow<DEG>::n, __builtin_fma(-v0, tc - 1.0, a));
-}
-
-template <int DEG>
-__device__ __forceinline__ double hyp_far_of(double v, const HypParams& P)
-{
-    const bool neg = v < 0.0;
-    return hyp_far<DEG>(__builtin_fabs(v), P.v0, P.inv_v0, neg ? P.l.v_top : P.r.v_top, neg ? P.l.c0 : P.r.c0,
-                   neg ? P.l.c1 : P.r.c1, neg ? P.l.c2 : P.r.c2, neg ? P.l.gcoef : P.r.gcoef,
-                   neg ? P.l.ncell : P.r.ncell);
-}
-
-/* Both sides' LDS rows: right side rows 0..nlds-1, left side after. */
-template <int DEG>
-__device__ __forceinline__ void stage_hyp(double* lds, const HypParams& P)
-{
-    constexpr int W = HypRow<DEG>::n;
-    const int n = P.nlds * W;
-    for (int i = threadIdx.x; i < 2 * n; i += blockDim.x) {
-        const bool left = i >= n;
-        const int e = left ? i - n : i;
-        const int row = e / W, col = e - row * W;
-        lds[((left ? P.nlds : 0) + row) * HypRow<DEG>::lds + col] = (left ? P.l.gcoef : P.r.gcoef)[e];
-    }
-}
 
 template <typename T> struct hvec;
 template <> struct hvec<double> { typedef d2 type; static constexpr int n = 2; };
@@ -264,27 +163,36 @@ static void side_far(const HypSide& s, const double* d_block, HypSideFar* f)
     f->pad = 0;
 }
 
-template <typename T, int DEG>
-static hipError_t launch_h(const void* in, void* out, uint64_t n, const HypTableHeader& h, const HypSide& R,
-                           const HypSide& L, uint64_t ncoef, const double* d_block, double mu, hipStream_t s,
-                           const KernelShape& shape)
+bool make_hyp_params(const HypTableHeader& h, bool f32, const HypTableHeader* d_table, uint64_t ncoef, double mu,
+                     HypParams* P, size_t* lds_bytes)
 {
-    if (!side_valid(R, DEG, ncoef) || !side_valid(L, DEG, ncoef) || R.v0 != L.v0 || R.inv_v0 != L.inv_v0)
-        return hipErrorInvalidValue;
+    const HypSide& R = f32 ? h.right32 : h.right;
+    const HypSide& L = f32 ? h.left32 : h.left;
+    const int deg = f32 ? HYP_DEGREE_F32 : HYP_DEGREE;
+    if (!side_valid(R, deg, ncoef) || !side_valid(L, deg, ncoef) || R.v0 != L.v0 || R.inv_v0 != L.inv_v0)
+        return false;
+    const double* d_block = reinterpret_cast<const double*>(reinterpret_cast<const char*>(d_table) + sizeof(HypTableHeader));
+    const int stride = deg + 2;   /* HypRow<deg>::lds */
     /* LDS cells per side: through the octave reaching 64 / rate on either
        side, within both sides' cells and the LDS budget */
     int noct = std::max(octaves_to(R.v0, h.alpha - h.beta), octaves_to(R.v0, h.alpha + h.beta));
     noct = std::min(noct, std::min(R.noct, L.noct));
-    noct = std::min(noct, (int)(HYP_LDS_MAX / (2 * HypRow<DEG>::lds * sizeof(double) * HYP_SUB)));
-    HypParams P;
-    P.v0 = R.v0;
-    P.inv_v0 = R.inv_v0;
-    P.mu = mu;
-    side_far(R, d_block, &P.r);
-    side_far(L, d_block, &P.l);
-    P.nlds = HYP_SUB * noct;
-    P.pad = 0;
-    const size_t lds = (size_t)2 * P.nlds * HypRow<DEG>::lds * sizeof(double);
+    noct = std::min(noct, (int)(HYP_LDS_MAX / (2 * stride * sizeof(double) * HYP_SUB)));
+    P->v0 = R.v0;
+    P->inv_v0 = R.inv_v0;
+    P->mu = mu;
+    side_far(R, d_block, &P->r);
+    side_far(L, d_block, &P->l);
+    P->nlds = HYP_SUB * noct;
+    P->pad = 0;
+    *lds_bytes = (size_t)2 * P->nlds * stride * sizeof(double);
+    return true;
+}
+
+template <typename T, int DEG>
+static hipError_t launch_h(const void* in, void* out, uint64_t n, const HypParams& P, size_t lds, hipStream_t s,
+                           const KernelShape& shape)
+{
     HypArgs<T> a;
     a.in = static_cast<const T*>(in);
     a.out = static_cast<T*>(out);
@@ -324,13 +232,13 @@ hipError_t launch_hyperbolic(int dtype, int mode, const void* in, void* out, uin
                              const HypTableHeader& h, uint64_t ncoef, double mu, hipStream_t s,
                              const LaunchShape& shape)
 {
-    const double* d_block = reinterpret_cast<const double*>(reinterpret_cast<const char*>(d_table) + sizeof(HypTableHeader));
-    if (dtype == QM_F64 && mode == QM_PLAIN)
-        return launch_h<double, HYP_DEGREE>(in, out, n, h, h.right, h.left, ncoef, d_block, mu, s, shape.hyperbolic[1]);
-    if (dtype == QM_F32 && mode == QM_F32_REFINE)
-        return launch_h<float, HYP_DEGREE_F32>(in, out, n, h, h.right32, h.left32, ncoef, d_block, mu, s,
-                                               shape.hyperbolic[0]);
-    return hipErrorInvalidValue;
+    const bool f32 = dtype == QM_F32 && mode == QM_F32_REFINE;
+    if (!f32 && !(dtype == QM_F64 && mode == QM_PLAIN)) return hipErrorInvalidValue;
+    HypParams P;
+    size_t lds = 0;
+    if (!make_hyp_params(h, f32, d_table, ncoef, mu, &P, &lds)) return hipErrorInvalidValue;
+    if (f32) return launch_h<float, HYP_DEGREE_F32>(in, out, n, P, lds, s, shape.hyperbolic[0]);
+    return launch_h<double, HYP_DEGREE>(in, out, n, P, lds, s, shape.hyperbolic[1]);
 }
 
 }  // namespace qm

@@ -1,0 +1,135 @@
+/*
+ * qm_hyp_device.hpp -- device evaluation of the exponential -> hyperbolic
+ * tables (Section 8.1; layout in qm_hyp_table.h), shared by the map kernel
+ * (qm_hyp.hip) and the batch kernel (qm_batch.hip).
+ */
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "qm_device.hpp"
+#include "qm_hyp_table.h"
+
+namespace qm {
+
+/* Rows of DEG + 1 doubles; in LDS one double of padding staggers the rows
+   over the banks (rows of 12 or 8 doubles would otherwise start on the
+   same few banks). */
+template <int DEG> struct HypRow {
+    static constexpr int n = DEG + 1;
+    static constexpr int lds = DEG + 2;
+};
+static_assert(HYP_SUB == 8, "the cell index takes the top 3 mantissa bits of t");
+
+/* The far path's parameters of one side. */
+struct HypSideFar {
+    double v_top, c0, c1, c2;
+    const double* gcoef;          /* the side's rows in global memory */
+    int ncell, pad;
+};
+
+struct HypParams {
+    double v0, inv_v0, mu;        /* v0 is shared by both sides */
+    HypSideFar r, l;              /* v >= 0, v < 0 */
+    int nlds;                     /* cells per side in LDS, right side's first */
+    int pad;
+};
+
+
+/* Cell of t = 1 + a/v0 >= 1: the biased exponent and the top three mantissa
+   bits of t give j = 8 k + i for t in [2^k (1 + i/8), 2^k (1 + (i+1)/8));
+   the cell's centre in t, 2^k (1 + (i + 1/2)/8), is t with the lower
+   mantissa bits replaced by 1000...  NaN and inf give j >= 8192. */
+__device__ __forceinline__ int hyp_cell(double t, double* tc)
+{
+    const uint32_t hi = (uint32_t)__double2hiint(t);
+    *tc = __hiloint2double((int)((hi & ~((1u << 17) - 1)) | (1u << 16)), 0);
+    return (int)(hi >> 17) - (1023 << 3);
+}
+
+template <int DEG>
+__device__ __forceinline__ double hyp_poly(const double* __restrict__ c, double d)
+{
+    double R = c[0];
+#pragma unroll
+    for (int k = 1; k <= DEG; ++k) R = __builtin_fma(R, d, c[k]);
+    return R;
+}
+
+/* |Q(v)| from the LDS cells; *far for lanes beyond them (and NaN). */
+template <int DEG>
+__device__ __forceinline__ double hyp_near(double v, const double* __restrict__ lds, const HypParams& P, bool* far)
+{
+    const double a = __builtin_fabs(v);
+    const double t = __builtin_fma(a, P.inv_v0, 1.0);
+    double tc;
+    int j = hyp_cell(t, &tc);                    /* >= 0: t >= 1 */
+    const bool out = !((unsigned)j < (unsigned)P.nlds);
+    *far = out;
+    j = out ? P.nlds - 1 : j;                     /* far and NaN lanes stay in bounds */
+    const int row = j + (v < 0.0 ? P.nlds : 0);
+    const double d = __builtin_fma(-P.v0, tc - 1.0, a);   /* a - centre; tc - 1 is exact */
+    return a * hyp_poly<DEG>(lds + row * HypRow<DEG>::lds, d);
+}
+
+/* |Q(v)| beyond the LDS cells: the side's global-memory cells up to v_top,
+   then the large-v form; inf -> inf, NaN -> NaN.  The side's parameters
+   come as plain values selected per lane (a reference to a lane-dependent
+   side, or a struct passed by value, would put them in scratch memory). */
+template <int DEG>
+static __device__ __noinline__ double hyp_far(double a, double v0, double inv_v0, double v_top, double c0, double c1,
+                                              double c2, const double* gcoef, int ncell)
+{
+    if (!(a < v_top)) {
+        if (!(a < __builtin_inf())) return a;
+        return a + (c0 + (c1 + c2 / a) / a);
+    }
+    double tc;
+    int j = hyp_cell(__builtin_fma(a, inv_v0, 1.0), &tc);
+    j = (unsigned)j < (unsigned)ncell ? j : ncell - 1;
+    return a * hyp_poly<DEG>(gcoef + j * HypRow<DEG>::n, __builtin_fma(-v0, tc - 1.0, a));
+}
+
+template <int DEG>
+__device__ __forceinline__ double hyp_far_of(double v, const HypParams& P)
+{
+    const bool neg = v < 0.0;
+    return hyp_far<DEG>(__builtin_fabs(v), P.v0, P.inv_v0, neg ? P.l.v_top : P.r.v_top, neg ? P.l.c0 : P.r.c0,
+                   neg ? P.l.c1 : P.r.c1, neg ? P.l.c2 : P.r.c2, neg ? P.l.gcoef : P.r.gcoef,
+                   neg ? P.l.ncell : P.r.ncell);
+}
+
+/* Both sides' LDS rows: right side rows 0..nlds-1, left side after. */
+template <int DEG>
+__device__ __forceinline__ void stage_hyp(double* lds, const HypParams& P)
+{
+    constexpr int W = HypRow<DEG>::n;
+    const int n = P.nlds * W;
+    for (int i = threadIdx.x; i < 2 * n; i += blockDim.x) {
+        const bool left = i >= n;
+        const int e = left ? i - n : i;
+        const int row = e / W, col = e - row * W;
+        lds[((left ? P.nlds : 0) + row) * HypRow<DEG>::lds + col] = (left ? P.l.gcoef : P.r.gcoef)[e];
+    }
+}
+
+/* |Q(v)| of one element, with its own wave vote for the far path. */
+template <int DEG>
+__device__ __forceinline__ double hyp_abs_q(double v, const double* __restrict__ lds, const HypParams& P)
+{
+    bool far;
+    double q = hyp_near<DEG>(v, lds, P, &far);
+    if (wave_any(far)) {
+        double qf = hyp_far_of<DEG>(far ? v : 0.0, P);
+        q = far ? qf : q;
+    }
+    return q;
+}
+
+/* Kernel parameters of a table's cell set for FP64 (f32 = false) or FP32
+   outputs (qm_hyp.hip): false if the header is not a valid table of ncoef
+   doubles.  *lds_bytes gets the LDS the staged cells take. */
+bool make_hyp_params(const HypTableHeader& h, bool f32, const HypTableHeader* d_table, uint64_t ncoef, double mu,
+                     HypParams* P, size_t* lds_bytes);
+
+}  // namespace qm

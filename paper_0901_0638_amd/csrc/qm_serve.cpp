@@ -150,6 +150,8 @@ static uint32_t batch_op(const qm_request& r)
     case QM_EXP_TO_NORMAL:
         if (r.dtype == QM_F64) return r.mode == QM_PAPER ? BOP_E64_PAPER : BOP_E64_PLAIN;
         return BOP_E32_REFINE;
+    case QM_EXP_TO_HYPERBOLIC:
+        return r.dtype == QM_F64 ? BOP_H64 : BOP_H32;
     default:
         return r.dtype == QM_F64 ? BOP_T64 : BOP_T32;
     }
@@ -210,10 +212,18 @@ qm_status enqueue_batch(qm_ctx* ctx, const qm_request* reqs, uint64_t count, hip
             b.coef = table_block(t->d_table) + c.coef_offset;
             b.P = make_params(t->hdr, c, b.coef);
             if (!t->hdr.identity) lds = std::max(lds, (size_t)c.nlds * b.P.lds_stride * sizeof(double));
+        } else if (r.kind == QM_EXP_TO_HYPERBOLIC) {
+            const DeviceHypTable* t = nullptr;
+            qm_status st = get_hyp_table(ctx, r.alpha, r.beta, r.delta, &t);
+            if (st != QM_OK) return st;
+            size_t l = 0;
+            if (!make_hyp_params(t->hdr, r.dtype == QM_F32, t->d_table, t->ncoef, r.mu, &b.H, &l))
+                return set_error(QM_E_INVAL, "invalid hyperbolic table");
+            lds = std::max(lds, l);
         }
         d.push_back(b);
     }
-    if (lds > QM_BATCH_DYNAMIC_LDS_MAX) return set_error(QM_E_INVAL, "Student t table larger than the LDS a launch may use");
+    if (lds > QM_BATCH_DYNAMIC_LDS_MAX) return set_error(QM_E_INVAL, "table larger than the LDS a launch may use");
     if (d.empty()) {
         if (done && hipEventRecord(done, s) != hipSuccess) return set_error(QM_E_HIP, "hipEventRecord failed");
         return QM_OK;

@@ -7,6 +7,7 @@
 #include "qm_internal.h"
 
 struct DeviceTable;
+struct DeviceHypTable;
 
 namespace qm {
 
@@ -18,6 +19,8 @@ qm_status check_request(const qm_request& r, int* dtype_size_out);
 qm_status run_single(qm_ctx* ctx, const qm_request& r, hipStream_t s);
 /* Per-nu table of a context (built on first use). */
 qm_status get_table(qm_ctx* ctx, double nu, const DeviceTable** out);
+/* Per-(alpha, beta, delta) hyperbolic table of a context (built on first use). */
+qm_status get_hyp_table(qm_ctx* ctx, double alpha, double beta, double delta, const DeviceHypTable** out);
 const TTableHeader* device_table_ptr(const DeviceTable* t);
 const TTableHeader& device_table_hdr(const DeviceTable* t);
 const LaunchShape& ctx_shape(const qm_ctx* ctx);

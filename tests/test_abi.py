@@ -37,6 +37,15 @@ def test_library_exports_every_symbol():
         assert hasattr(lib, name), name
 
 
+def test_request_layout():
+    """qm_request as include/qm.h declares it: 88 bytes, the hyperbolic
+    parameters after user_tag."""
+    r = _lib.qm_request
+    assert ctypes.sizeof(r) == 88
+    assert r.user_tag.offset == 48 and r.alpha.offset == 56 and r.mu.offset == 80
+    assert qm.QM_EXP_TO_HYPERBOLIC == 4
+
+
 def test_status_strings():
     lib = _lib.load()
     for s, name in [(0, b"QM_OK"), (1, b"QM_PENDING"), (-1, b"QM_E_INVAL"), (-2, b"QM_E_DTYPE"),

@@ -226,3 +226,79 @@ def test_batch_full_size_mix_sampled(ctx):
         assert_close(got, oracle_of(r, x), rtol, str(r))
     del ins, outs
     torch.cuda.empty_cache()
+
+
+HYP_PARAMS = [(1.0, 0.0, 1.0), (1.0, 0.5, 1.0), (2.0, -1.5, 0.3)]
+
+
+def hyperbolic_requests(seed):
+    """Exponential -> hyperbolic requests of both dtypes, three parameter
+    sets (two locations) and ragged sizes, with a quantile and a Student t
+    request between them."""
+    reqs, cases = [], []
+    for i, p in enumerate(HYP_PARAMS):
+        for dtype in (np.float64, np.float32):
+            for n in (1, 3001 + 17 * i, 40000 + 3 * i):
+                lp, lm, _ = oracle.hyperbolic_masses(*p)
+                x = qi.two_sided_exponentials(seed + i, 3, n, p[0] - p[1], p[0] + p[1], np.exp(lm)).astype(dtype)
+                d = torch.from_numpy(x).cuda()
+                o = torch.full_like(d, float("nan"))
+                mu = 0.0 if n != 1 else 0.75
+                reqs.append(qm.make_request(qm.QM_EXP_TO_HYPERBOLIC, d, o, hyperbolic=p, mu=mu))
+                cases.append((p, mu, d, o))
+    u = torch.from_numpy(qi.uniform53(seed, 9, 20000)).cuda()
+    w = torch.full_like(u, float("nan"))
+    z = torch.from_numpy(qi.normals(seed, 8, 20000)).cuda()
+    t = torch.full_like(z, float("nan"))
+    reqs.insert(2, qm.make_request(qm.QM_NORMAL_QUANTILE, u, w))
+    reqs.insert(5, qm.make_request(qm.QM_STUDENT_T, z, t, nu=4.0))
+    return reqs, cases, (u, w, z, t)
+
+
+def check_hyperbolic_cases(ctx, cases, others):
+    rng = np.random.default_rng(5)
+    for p, mu, d, o in cases:
+        ref = torch.empty_like(d)
+        qm.qm_recycle_exp_to_hyperbolic(ctx, d, ref, *p, mu=mu)
+        torch.cuda.synchronize()
+        a, b = o.cpu().numpy(), ref.cpu().numpy()
+        assert np.array_equal(a.view(np.uint8), b.view(np.uint8)), ("not bitwise equal", p, mu, a.size, a.dtype)
+        if mu == 0.0:
+            idx = np.unique(rng.integers(0, a.size, 64))
+            x = d.cpu().numpy()[idx].astype(np.float64)
+            rtol = RTOL_F32 if a.dtype == np.float32 else RTOL_F64
+            assert_close(a[idx], oracle.hyperbolic_map(x, *p), rtol, str(p))
+    u, w, z, t = others
+    assert torch.equal(w, single(ctx, qm.QM_NORMAL_QUANTILE, qm.QM_PLAIN, 0.0, u))
+    assert torch.equal(t, single(ctx, qm.QM_STUDENT_T, qm.QM_PLAIN, 4.0, z))
+
+
+def test_batch_hyperbolic_bitwise_equal_to_single(ctx):
+    reqs, cases, others = hyperbolic_requests(60)
+    qm.qm_run_batch(ctx, reqs, device_tensor=others[0])
+    torch.cuda.synchronize()
+    check_hyperbolic_cases(ctx, cases, others)
+
+
+def test_serving_hyperbolic(ctx):
+    reqs, cases, others = hyperbolic_requests(70)
+    tickets = [qm.qm_submit(ctx, r) for r in reqs]
+    deadline = time.time() + 60
+    pending = set(tickets)
+    while pending and time.time() < deadline:
+        pending = {t for t in pending if qm.qm_poll(ctx, t) == qm.QM_PENDING}
+        time.sleep(0.001)
+    assert not pending, "requests did not complete"
+    check_hyperbolic_cases(ctx, cases, others)
+
+
+def test_batch_hyperbolic_validation(ctx):
+    d = torch.zeros(16, dtype=torch.float64, device="cuda")
+    good = qm.make_request(qm.QM_EXP_TO_HYPERBOLIC, d, d, hyperbolic=(1.0, 0.0, 1.0))
+    for bad in [qm.make_request(qm.QM_EXP_TO_HYPERBOLIC, d, d, hyperbolic=(1.0, 1.0, 1.0)),
+                qm.make_request(qm.QM_EXP_TO_HYPERBOLIC, d, d, hyperbolic=(1.0, 0.0, 1.0), mu=float("nan")),
+                qm.make_request(qm.QM_EXP_TO_HYPERBOLIC, d, d, mode=qm.QM_PAPER, hyperbolic=(1.0, 0.0, 1.0))]:
+        with pytest.raises(qm.QMError):
+            qm.qm_run_batch(ctx, [good, bad], device_tensor=d)
+        with pytest.raises(qm.QMError):
+            qm.qm_submit(ctx, bad)
