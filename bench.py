@@ -72,7 +72,10 @@ def percentile(xs, p):
 
 
 def timed_launches(torch, stream, fn, reps):
-    """Per-launch durations (ms) with HIP events on the launch stream."""
+    """Per-launch durations (ms) with HIP events on the launch stream, after
+    one untimed call (the first launch of a kernel also loads its code)."""
+    fn()
+    torch.cuda.synchronize()
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
     for a, b in ev:
         a.record(stream)
