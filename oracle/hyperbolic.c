@@ -84,14 +84,23 @@ typedef struct {
     ld delta;
 } hside;
 
-static ld E_of(const hside* h, ld s) { return -h->ad * coshl(s) + h->bd * sinhl(s) + h->dg; }
+/* E(s) = -alpha delta cosh s + beta delta sinh s + delta gamma, formed as
+   -2 delta gamma sinh^2((s - s_peak)/2) (alpha = gamma cosh s_peak,
+   beta = gamma sinh s_peak): the same number without the cancellation of
+   the first form when beta is close to alpha */
+static ld E_of(const hside* h, ld s)
+{
+    ld q = sinhl(0.5L * (s - h->speak));
+    return -2 * h->dg * q * q;
+}
 
-/* E(a + u) - E(a) = -2 sinh(u/2) (alpha delta sinh(a + u/2) - beta delta cosh(a + u/2)),
-   exact in u however large a is (a + u itself may round to a) */
+/* E(a + u) - E(a) = -2 sinh(u/2) (alpha delta sinh(a + u/2) - beta delta cosh(a + u/2))
+   = -2 delta gamma sinh(u/2) sinh(a + u/2 - s_peak), exact in u however large
+   a is (a + u itself may round to a) */
 static ld dE(const hside* h, ld a, ld u)
 {
     ld m = a + 0.5L * u;
-    return -2 * sinhl(0.5L * u) * (h->ad * sinhl(m) - h->bd * coshl(m));
+    return -2 * sinhl(0.5L * u) * h->dg * sinhl(m - h->speak);   /* alpha sinh m - beta cosh m = gamma sinh(m - s_peak) */
 }
 
 /* The integrand at s = a + u: e^{E(s) - shift} cosh s, with E(a) - shift
@@ -143,7 +152,7 @@ static ld integrate(const hside* h, ld a, ld b, ld shift) { return integrate_tol
    numbers near a. */
 static ld integrate_to_inf(const hside* h, ld a, ld shift)
 {
-    ld slope = h->ad * sinhl(a) - h->bd * coshl(a);     /* -E'(a) */
+    ld slope = h->dg * sinhl(a - h->speak);     /* -E'(a) */
     ld w = (a > h->speak && slope > 1) ? 1 / slope : 1;
     ld ea = E_of(h, a) - shift, sum = 0;
     for (int k = 0; k < 100000; ++k) {
