@@ -97,8 +97,15 @@ struct Side {
     fq log_c;               /* log C */
     fq log_p;               /* log of this side's mass */
 
-    /* E(s) = -alpha delta cosh s + beta delta sinh s + delta gamma <= 0 */
-    fq E(fq s) const { return -ad * coshq(s) + bd * sinhq(s) + dg; }
+    /* E(s) = -alpha delta cosh s + beta delta sinh s + delta gamma
+            = -delta gamma (cosh(s - s_peak) - 1) = -2 delta gamma sinh^2((s - s_peak)/2) <= 0
+       (alpha = gamma cosh s_peak, beta = gamma sinh s_peak): no cancellation,
+       however close beta is to alpha */
+    fq E(fq s) const
+    {
+        fq h = sinhq((s - speak) / 2);
+        return -2 * dg * h * h;
+    }
 
     fq panel(fq a, fq b, fq shift) const
     {
@@ -134,7 +141,7 @@ struct Side {
     /* int_a^inf, by panels 1/|E'(a)| wide past the peak (the decay length) */
     fq integral_to_inf(fq a, fq shift) const
     {
-        fq slope = ad * sinhq(a) - bd * coshq(a);
+        fq slope = dg * sinhq(a - speak);    /* -E'(a) */
         fq w = (a > speak && slope > 1) ? 1 / slope : 1;
         fq sum = 0;
         for (int k = 0; k < 100000; ++k) {
@@ -159,7 +166,13 @@ struct Side {
         return log_scale() + logq(integral(S, speak, 0) + integral_to_inf(speak, 0));
     }
 
-    fq log_f(fq x) const { return log_c - alpha * sqrtq(delta * delta + x * x) + beta * x; }
+    /* log f(x) = log C - (alpha sqrt(delta^2 + x^2) - beta x); for x >= 0 the
+       bracket is r x + alpha delta^2 / (sqrt(delta^2 + x^2) + x), r = alpha - beta */
+    fq log_f(fq x) const
+    {
+        fq rt = sqrtq(delta * delta + x * x);
+        return log_c - (x >= 0 ? rate * x + alpha * delta * delta / (rt + x) : alpha * rt - beta * x);
+    }
 };
 
 /* K_1(z) = int_0^inf e^{-z cosh t} cosh t dt, scaled by e^{z} (DLMF 10.32.8) */
@@ -482,7 +495,7 @@ bool solve_side(const Side& sd, SideSolution* ss, char* err, int errlen)
     fq qf = horner(f.a, f.h), qb = horner(b.a, b.h);
     fq df = horner_d(f.a, f.h), db = horner_d(b.a, b.h);
     fq mis = fabsq(qf / qb - 1) + fabsq(df / db - 1);
-    if (!(mis < 1e-22Q)) {
+    if (!(mis < 1e-19Q)) {   /* two orders below the cells' 2e-17 */
         snprintf(err, errlen, "legs disagree at v=%g by %.3e", (double)ss->v_match, (double)mis);
         return false;
     }
@@ -703,7 +716,10 @@ extern "C" int qm_debug_hyperbolic_table(double alpha, double beta, double delta
 {
     qm::HostHypTable t;
     char err[256];
-    if (qm::build_hyperbolic_table(alpha, beta, delta, &t, err, sizeof err) != 0) return -1;
+    if (qm::build_hyperbolic_table(alpha, beta, delta, &t, err, sizeof err) != 0) {
+        fprintf(stderr, "qm_debug_hyperbolic_table: %s\n", err);
+        return -1;
+    }
     int need = (int)t.ncoef;
     if (header_out) memcpy(header_out, &t.hdr, sizeof t.hdr);
     if (coef_out && coef_cap >= need && need > 0) memcpy(coef_out, t.coef, sizeof(double) * need);

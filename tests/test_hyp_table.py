@@ -174,3 +174,17 @@ def test_invalid_parameters_rejected():
               (float("inf"), 0.0, 1.0), (0.0, 0.0, 1.0)]:
         with pytest.raises(ValueError):
             qm.debug_hyperbolic_table(*p)
+
+
+@pytest.mark.parametrize("p", [(1.0, 0.999999, 1.0), (1.0, -0.999999, 1.0), (1.0, 0.0, 1e-6), (1e-6, 0.0, 1.0),
+                               (1000.0, 0.0, 0.001)], ids=lambda p: "a%g_b%g_d%g" % p)
+def test_extreme_parameters(p):
+    """Near-degenerate skew (|beta| -> alpha), a near-Laplace and a near-flat
+    target: the builder finishes (the peak's exponent is formed without
+    cancellation) and its table matches the oracle."""
+    h, rr, rl = qm.debug_hyperbolic_table(*p)
+    rng = np.random.default_rng(3)
+    v = np.concatenate([rng.exponential(1 / (p[0] - p[1]), 30), -rng.exponential(1 / (p[0] + p[1]), 30)])
+    ref = oracle.hyperbolic_map(v, *p)
+    rel = np.abs(table_eval(h, rr, rl, v) - ref) / np.abs(ref)
+    assert rel.max() <= 6e-16, (p, rel.max())
