@@ -235,7 +235,9 @@ qm_status qm_run_batch(qm_ctx* ctx, const qm_request* reqs, uint64_t count, void
 
 /*
  * Serving loop.  qm_submit validates and enqueues one request and returns a
- * ticket immediately.  A scheduler thread admits queued requests in
+ * ticket; it returns at once unless the request needs a Student t or
+ * hyperbolic table the context does not hold yet, which it first builds in
+ * the calling thread (so the scheduler never waits for a build).  A scheduler thread admits queued requests in
  * arrival order while the bytes (in + out) of requests in flight stay within
  * the context's HBM budget, and launches everything admitted since its
  * previous launch as one batch; batches run on several streams, so requests

@@ -96,12 +96,16 @@ qm_status check_request(const qm_request& r, int* dtype_size_out)
     return QM_OK;
 }
 
-/* Look up (or build and upload) the table for nu. */
+/* Look up (or build and upload) the table for nu.  The build runs outside
+   the table lock, so lookups of other tables (the serving loop's) never
+   wait for it; if two threads build the same table, the first insert wins. */
 qm_status get_table(qm_ctx* ctx, double nu, const DeviceTable** out)
 {
-    std::lock_guard<std::mutex> lk(ctx->table_mu);
-    auto it = ctx->tables.find(nu);
-    if (it != ctx->tables.end()) { *out = &it->second; return QM_OK; }
+    {
+        std::lock_guard<std::mutex> lk(ctx->table_mu);
+        auto it = ctx->tables.find(nu);
+        if (it != ctx->tables.end()) { *out = &it->second; return QM_OK; }
+    }
     HostTTable ht{};
     char err[256] = {0};
     if (build_student_table(nu, &ht, err, sizeof err) != 0)
@@ -119,18 +123,23 @@ qm_status get_table(qm_ctx* ctx, double nu, const DeviceTable** out)
     dt.hdr = ht.hdr;
     dt.d_table = (TTableHeader*)d;
     free_student_table(&ht);
+    std::lock_guard<std::mutex> lk(ctx->table_mu);
     auto res = ctx->tables.emplace(nu, dt);
+    if (!res.second) (void)hipFree(d);   /* another thread's copy is already in use */
     *out = &res.first->second;
     return QM_OK;
 }
 
-/* Look up (or build and upload) the hyperbolic table for (alpha, beta, delta). */
+/* Look up (or build and upload) the hyperbolic table for (alpha, beta,
+   delta), built outside the lock like get_table's. */
 qm_status get_hyp_table(qm_ctx* ctx, double alpha, double beta, double delta, const DeviceHypTable** out)
 {
-    std::lock_guard<std::mutex> lk(ctx->table_mu);
     auto key = std::make_tuple(alpha, beta, delta);
-    auto it = ctx->hyp_tables.find(key);
-    if (it != ctx->hyp_tables.end()) { *out = &it->second; return QM_OK; }
+    {
+        std::lock_guard<std::mutex> lk(ctx->table_mu);
+        auto it = ctx->hyp_tables.find(key);
+        if (it != ctx->hyp_tables.end()) { *out = &it->second; return QM_OK; }
+    }
     HostHypTable ht{};
     char err[256] = {0};
     if (build_hyperbolic_table(alpha, beta, delta, &ht, err, sizeof err) != 0)
@@ -148,7 +157,9 @@ qm_status get_hyp_table(qm_ctx* ctx, double alpha, double beta, double delta, co
     dt.d_table = (HypTableHeader*)d;
     dt.ncoef = ht.ncoef;
     free_hyperbolic_table(&ht);
+    std::lock_guard<std::mutex> lk(ctx->table_mu);
     auto res = ctx->hyp_tables.emplace(key, dt);
+    if (!res.second) (void)hipFree(d);
     *out = &res.first->second;
     return QM_OK;
 }

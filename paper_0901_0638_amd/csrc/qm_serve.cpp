@@ -451,6 +451,20 @@ qm_status qm_submit(qm_ctx* ctx, const qm_request* req, uint64_t* ticket)
     if (st != QM_OK) return st;
     uint64_t bytes = 2 * req->n * (uint64_t)es;
     if (bytes > ctx->budget) return qm::set_error(QM_E_INVAL, "request larger than the HBM budget");
+    /* a table the request needs is built here, in the caller's thread, so
+       that the scheduler never stalls on a build and a failed build is this
+       request's error alone */
+    if (req->kind == QM_STUDENT_T || req->kind == QM_EXP_TO_HYPERBOLIC) {
+        if (hipSetDevice(ctx->device) != hipSuccess) return qm::set_error(QM_E_HIP, "hipSetDevice failed");
+        if (req->kind == QM_STUDENT_T) {
+            const DeviceTable* t = nullptr;
+            st = qm::get_table(ctx, req->nu, &t);
+        } else {
+            const DeviceHypTable* t = nullptr;
+            st = qm::get_hyp_table(ctx, req->alpha, req->beta, req->delta, &t);
+        }
+        if (st != QM_OK) return st;
+    }
     st = QM_OK;
     qm::Server* S = qm::server_of(ctx, &st);
     if (!S) return st;
