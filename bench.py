@@ -37,28 +37,33 @@ HBM_PEAK_GBS = 8000.0
 T_NUS = (1, 2, 3, 4, 5, 10, 30)
 
 
-def kernel_source_hash():
+QUANTILE_SOURCES = ("qm_kernels.hip", "qm_hybrid.hpp", "qm_device.hpp", "qm_coeffs.h", "qm_paper_coeffs.h")
+HYPERBOLIC_SOURCES = ("qm_hyp.hip", "qm_hyp_device.hpp", "qm_hyp_table.h", "qm_device.hpp")
+
+
+def kernel_source_hash(files=QUANTILE_SOURCES):
     import hashlib
     h = hashlib.sha256()
-    for f in ("qm_kernels.hip", "qm_hybrid.hpp", "qm_device.hpp", "qm_coeffs.h", "qm_paper_coeffs.h"):
+    for f in files:
         with open(os.path.join(ROOT, "paper_0901_0638_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def counted_traffic():
-    """HBM bytes per launch of the FP64 quantile kernel from the committed
-    rocprofv3 FETCH_SIZE/WRITE_SIZE summary, or None if the kernel sources
-    changed since those counters were taken."""
+def counted_traffic(profile="quantile_mixture_2e28_hbm_counters.md", kernel="k_hybrid<double>",
+                    files=QUANTILE_SOURCES):
+    """HBM bytes per launch of a kernel from its committed rocprofv3
+    FETCH_SIZE/WRITE_SIZE summary, or None if the kernel sources changed
+    since those counters were taken."""
     import re
-    path = os.path.join(ROOT, "profiles", "quantile_mixture_2e28_hbm_counters.md")
+    path = os.path.join(ROOT, "profiles", profile)
     try:
         text = open(path).read()
     except OSError:
         return None
     m = re.search(r"Kernel source hash: `([0-9a-f]+)`", text)
-    t = re.search(r"traffic_bytes_per_launch k_hybrid<double>: ([0-9]+)", text)
-    if not m or not t or m.group(1) != kernel_source_hash():
+    t = re.search(r"traffic_bytes_per_launch %s: ([0-9]+)" % re.escape(kernel), text)
+    if not m or not t or m.group(1) != kernel_source_hash(files):
         return None
     return int(t.group(1))
 
@@ -420,18 +425,96 @@ def run_serve(args, torch, qm, qi):
 
 
 # ---------------------------------------------------------------------------
+def run_hyperbolic(args, torch, qm, qi):
+    """Exponential -> hyperbolic (Section 8.1): 2^26 base samples of the
+    Section 8.1 illustration (alpha = delta = 1, beta = 0), FP64 then FP32
+    in/out per step, inputs resident in HBM."""
+    hp = qi.HYPERBOLIC_PARAMS
+    n = 1 << 26
+    t0 = time.time()
+    ctx = qm.Context(0)
+    tb = time.perf_counter()
+    lp, lm = qm.qm_hyperbolic_masses(ctx, *hp)       # builds and caches the table
+    tb = time.perf_counter() - tb
+    v64 = torch.from_numpy(qi.recycle_two_sided(n, hp[0], hp[1], math.exp(lm))).cuda()
+    v32 = v64.float()
+    x64 = torch.empty_like(v64)
+    x32 = torch.empty_like(v32)
+    torch.cuda.synchronize()
+    print("hyperbolic inputs ready in %.1f s (table %.2f s)" % (time.time() - t0, tb), file=sys.stderr, flush=True)
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        qm.qm_recycle_exp_to_hyperbolic(ctx, v64, x64, *hp)
+        qm.qm_recycle_exp_to_hyperbolic(ctx, v32, x32, *hp)
+    torch.cuda.synchronize()
+    if args.copy_calibration:
+        x64.copy_(v64)      # a plain copy of 2^26 doubles (512 MiB read + written), for counter scaling
+        torch.cuda.synchronize()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    t_start = time.perf_counter()
+    for k in range(args.steps):
+        ev[k][0].record(stream)
+        qm.qm_recycle_exp_to_hyperbolic(ctx, v64, x64, *hp)
+        ev[k][1].record(stream)
+        qm.qm_recycle_exp_to_hyperbolic(ctx, v32, x32, *hp)
+        ev[k][2].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    d64 = [e[0].elapsed_time(e[1]) for e in ev]
+    d32 = [e[1].elapsed_time(e[2]) for e in ev]
+    avg64, avg32 = sum(d64) / len(d64), sum(d32) / len(d32)
+    achieved = 16.0 * n / (avg64 * 1e-3) / 1e9
+    result = {
+        "metric": "Gsamples/s exponential->hyperbolic recycling (FP64 + FP32 in/out)",
+        "value": round(2.0 * n * args.steps / wall / 1e9, 3),
+        "unit": "Gsamples/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(wall * 1e3 / args.steps, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64+f32", "data": "synthetic",
+        "config": {"workload": "exp->hyperbolic, 2^26 two-sided exponential base samples of (alpha, beta, delta) = "
+                               "(1, 0, 1), seed 2 stream 2; FP64 then FP32 in/out",
+                   "n_per_pass": n, "passes_per_step": 2, "table_build_s": round(tb, 3)},
+        "fp64": {"gsamples_s": round(n / (avg64 * 1e-3) / 1e9, 2), "p50_ms": percentile(d64, 50),
+                 "p99_ms": percentile(d64, 99), "max_rel_err_bound": 2e-15},
+        "fp32": {"gsamples_s": round(n / (avg32 * 1e-3) / 1e9, 2), "p50_ms": percentile(d32, 50),
+                 "p99_ms": percentile(d32, 99), "gbs": round(8.0 * n / (avg32 * 1e-3) / 1e9, 1),
+                 "max_rel_err_bound": 2e-7},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": counted_traffic("hyperbolic_exp_2e26_hbm_counters.md", "k_hyperbolic<double>",
+                                                HYPERBOLIC_SOURCES),
+                     "kernel": "qm::k_hyperbolic<double, true, 4, 11> (8 workgroups/CU x 4 vectors)",
+                     "algorithmic_bytes_per_launch": 16.0 * n, "avg_launch_ms": round(avg64, 4)},
+    }
+    del v32, x32, x64
+    if not args.no_cpu:
+        import oracle
+        mm = 1 << 13
+        vs = v64[:mm].cpu().numpy()
+        threads = oracle.threads_used(0)
+        c0 = time.perf_counter()
+        oracle.hyperbolic_map(vs, *hp, threads=threads)
+        cdt = time.perf_counter() - c0
+        result["cpu_baseline"] = {"value": round(mm / cdt / 1e9, 9), "unit": "Gsamples/s", "cores": threads,
+                                  "kind": "oracle",
+                                  "sample": "first %d base samples, FP64 map, %.1f s wall on %d threads (%s)"
+                                            % (mm, cdt, threads, cpu_model())}
+    ctx.close()
+    return result
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=["quantile", "batch", "serve"], default="quantile")
+    ap.add_argument("--workload", choices=["quantile", "batch", "serve", "hyperbolic"], default="quantile")
     ap.add_argument("--n", type=int, default=1 << 28, help="samples per pass (quantile workload)")
     ap.add_argument("--cpu-sample", type=int, default=1 << 28, help="oracle sample size (elements)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the secondary maps")
     ap.add_argument("--copy-calibration", action="store_true",
-                    help="also run a plain device copy of the FP64 input (for HBM counter scaling)")
+                    help="also run a plain device copy of the FP64 input (for HBM counter scaling; "
+                         "quantile and hyperbolic workloads)")
     ap.add_argument("--batch-count", type=int, default=4096)
     ap.add_argument("--serve-count", type=int, default=2000)
     ap.add_argument("--rates", type=float, nargs="+", default=[1000, 2000, 5000, 10000, 20000, 50000, 100000, 0],
@@ -451,6 +534,8 @@ def main():
         result = run_batch(args, torch, qm, qi)
     elif args.workload == "serve":
         result = run_serve(args, torch, qm, qi)
+    elif args.workload == "hyperbolic":
+        result = run_hyperbolic(args, torch, qm, qi)
     else:
         result = run_quantile(args, torch, qm, qi)
     print(json.dumps(result), flush=True)
