@@ -268,10 +268,13 @@ fq step_size(const fq* a, fq hmax)
     return h;
 }
 
-void integrate(const Side& sd, fq v, fq Q, fq dQ, fq v1, std::vector<Node>& out)
+/* Taylor steps from (v, Q, Q') to v1; false if they do not get there
+   within the step budget (the tested parameters need at most a few
+   hundred). */
+bool integrate(const Side& sd, fq v, fq Q, fq dQ, fq v1, std::vector<Node>& out)
 {
-    fq dir = v1 > v ? 1 : -1;
-    for (int guard = 0; guard < 1000000; ++guard) {
+    const fq dir = v1 > v ? 1 : -1;
+    for (int guard = 0; guard < 20000; ++guard) {
         Node n;
         n.v0 = v;
         n.a[0] = Q;
@@ -286,8 +289,9 @@ void integrate(const Side& sd, fq v, fq Q, fq dQ, fq v1, std::vector<Node>& out)
         Q = horner(n.a, n.h);
         dQ = horner_d(n.a, n.h);
         v += n.h;
-        if (last) break;
+        if (last) return true;
     }
+    return false;
 }
 
 /*
@@ -486,10 +490,13 @@ bool solve_side(const Side& sd, SideSolution* ss, char* err, int errlen)
     }
     ss->v_a = va;
     ss->v_match = 20 / r;
-    integrate(sd, 0, 0, ss->slope0, ss->v_match, ss->fwd);
     const fq Qa = solve_far(sd, va, ss->far(va));
     const fq dQa = expq(sd.log_p - r * va + logq(r) - sd.log_f(Qa));
-    integrate(sd, va, Qa, dQa, ss->v_match, ss->bwd);
+    if (!integrate(sd, 0, 0, ss->slope0, ss->v_match, ss->fwd) ||
+        !integrate(sd, va, Qa, dQa, ss->v_match, ss->bwd)) {
+        snprintf(err, errlen, "the ODE integration exceeded its step budget");
+        return false;
+    }
     const Node& f = ss->fwd.back();
     const Node& b = ss->bwd.back();
     fq qf = horner(f.a, f.h), qb = horner(b.a, b.h);
