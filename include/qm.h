@@ -15,6 +15,9 @@
  *                             -> hyperbolic target        (Section 8.1)
  *   qm_generate               the uniforms of a counter-based stream, or w
  *                             of them, drawn and mapped in one pass
+ *   qm_generate_student_t, qm_generate_hyperbolic
+ *                             Student t / hyperbolic samples drawn the same
+ *                             way, through the recycling maps
  *   qm_run_batch              many such requests in one persistent launch
  *   qm_submit / qm_poll       continuous-batching serving loop
  *
@@ -203,6 +206,35 @@ qm_status qm_hyperbolic_masses(qm_ctx* ctx, double alpha, double beta, double de
  */
 qm_status qm_generate(qm_ctx* ctx, uint64_t seed, uint64_t stream, uint64_t first, void* d_out, uint64_t n,
                       int kind, int dtype, int mode, void* hip_stream);
+
+/*
+ * Fused generation of Student t samples: element e of the stream is
+ * t = F_nu^{-1}(Phi(z)) of the normal z that qm_generate (kind
+ * QM_NORMAL_QUANTILE, same dtype and mode) writes for element e, computed
+ * in registers by the same device code as qm_generate followed by
+ * qm_recycle_student_t, and bitwise equal to that two-call chain.  Only t
+ * is written.  nu as for qm_recycle_student_t (+inf gives the normals).
+ * dtype/mode: F64 PLAIN; F32 F32_REFINE.  Other arguments and errors as for
+ * qm_generate, and QM_E_INVAL for an invalid nu.
+ */
+qm_status qm_generate_student_t(qm_ctx* ctx, uint64_t seed, uint64_t stream, uint64_t first, void* d_out, uint64_t n,
+                                int dtype, int mode, double nu, void* hip_stream);
+
+/*
+ * Fused generation of hyperbolic samples (Section 8.1): element e's open
+ * uniform u (as qm_generate kind QM_UNIFORM writes it, widened to FP64 for
+ * F32) becomes a sample of the two-sided exponential base,
+ *   v = log(u / p-) * (1 / (alpha + beta))        for u < p-,
+ *   v = -log((1 - u) / p+) * (1 / (alpha - beta))  otherwise,
+ * with p- = exp(log p-), p+ = exp(log p+) of qm_hyperbolic_masses and the
+ * reciprocals each rounded once (all in FP64), and then
+ * x = mu + Q(v) as qm_recycle_exp_to_hyperbolic maps it.  Only x is written.
+ * dtype/mode: F64 PLAIN; F32 F32_REFINE.  Other arguments and errors as for
+ * qm_generate and qm_recycle_exp_to_hyperbolic.
+ */
+qm_status qm_generate_hyperbolic(qm_ctx* ctx, uint64_t seed, uint64_t stream, uint64_t first, void* d_out, uint64_t n,
+                                 int dtype, int mode, double alpha, double beta, double delta, double mu,
+                                 void* hip_stream);
 
 /* One request of a batch or of the serving loop. */
 typedef struct {

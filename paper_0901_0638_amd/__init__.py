@@ -100,6 +100,25 @@ def qm_generate(ctx, seed, stream_id, first, out, kind=QM_NORMAL_QUANTILE, mode=
                              out.numel(), int(kind), dt, int(mode), _stream(stream, out)))
 
 
+def qm_generate_student_t(ctx, seed, stream_id, first, out, nu, mode=None, stream=None):
+    """Student t samples of a Philox stream: the t map of qm_generate's normals, fused."""
+    dt = _dtype_of(out)
+    if mode is None:
+        mode = QM_PLAIN if dt == QM_F64 else QM_F32_REFINE
+    check(load().qm_generate_student_t(ctx.handle, int(seed), int(stream_id), int(first), ctypes.c_void_p(out.data_ptr()),
+                                       out.numel(), dt, int(mode), float(nu), _stream(stream, out)))
+
+
+def qm_generate_hyperbolic(ctx, seed, stream_id, first, out, alpha, beta, delta, mu=0.0, mode=None, stream=None):
+    """Hyperbolic samples of a Philox stream: each uniform's two-sided exponential base sample, mapped, fused."""
+    dt = _dtype_of(out)
+    if mode is None:
+        mode = QM_PLAIN if dt == QM_F64 else QM_F32_REFINE
+    check(load().qm_generate_hyperbolic(ctx.handle, int(seed), int(stream_id), int(first),
+                                        ctypes.c_void_p(out.data_ptr()), out.numel(), dt, int(mode), float(alpha),
+                                        float(beta), float(delta), float(mu), _stream(stream, out)))
+
+
 def qm_recycle_student_t(ctx, z, t, nu, mode=None, stream=None):
     """t = F_nu^{-1}(Phi(z)) (FP64 PLAIN or FP32 F32_REFINE)."""
     pi, po, n, dt = _io(z, t)

@@ -368,6 +368,56 @@ qm_status qm_generate(qm_ctx* ctx, uint64_t seed, uint64_t stream, uint64_t firs
     return QM_OK;
 }
 
+/* The checks qm_generate makes of its stream arguments and output. */
+static qm_status check_generate(qm_ctx* ctx, uint64_t seed, uint64_t stream, uint64_t first, void* d_out, uint64_t n,
+                                int dtype, int mode)
+{
+    if (!ctx) return fail(QM_E_INVAL, "context is NULL");
+    if (seed > 0xFFFFFFFFull || stream > 0xFFFFFFFFull) return fail(QM_E_INVAL, "seed and stream must be < 2^32");
+    if (dtype != QM_F32 && dtype != QM_F64) return fail(QM_E_INVAL, "unknown dtype %d", dtype);
+    if (mode != QM_PLAIN && mode != QM_F32_REFINE && mode != QM_PAPER) return fail(QM_E_INVAL, "unknown mode %d", mode);
+    if (!(dtype == QM_F64 && mode == QM_PLAIN) && !(dtype == QM_F32 && mode == QM_F32_REFINE))
+        return fail(QM_E_DTYPE, "F64 QM_PLAIN or F32 QM_F32_REFINE");
+    if (first > (1ull << 63) || n > (1ull << 63) - first) return fail(QM_E_INVAL, "first + n beyond 2^63");
+    if (n > 0 && !d_out) return fail(QM_E_INVAL, "NULL output with n > 0");
+    if ((uintptr_t)d_out % dtype_size(dtype)) return fail(QM_E_INVAL, "output must be aligned to the element size");
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    return QM_OK;
+}
+
+qm_status qm_generate_student_t(qm_ctx* ctx, uint64_t seed, uint64_t stream, uint64_t first, void* d_out, uint64_t n,
+                                int dtype, int mode, double nu, void* hs)
+{
+    qm_status st = check_generate(ctx, seed, stream, first, d_out, n, dtype, mode);
+    if (st != QM_OK) return st;
+    if (std::isnan(nu) || !(nu >= 0.5)) return fail(QM_E_INVAL, "nu must be >= 0.5 or +inf (got %g)", nu);
+    const DeviceTable* t = nullptr;
+    st = qm::get_table(ctx, nu, &t);
+    if (st != QM_OK || n == 0) return st;
+    hipError_t e = qm::launch_generate_student(dtype, mode, (uint32_t)seed, (uint32_t)stream, first, d_out, n,
+                                               t->d_table, t->hdr, (hipStream_t)hs, ctx->shape);
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    return QM_OK;
+}
+
+qm_status qm_generate_hyperbolic(qm_ctx* ctx, uint64_t seed, uint64_t stream, uint64_t first, void* d_out, uint64_t n,
+                                 int dtype, int mode, double alpha, double beta, double delta, double mu, void* hs)
+{
+    qm_status st = check_generate(ctx, seed, stream, first, d_out, n, dtype, mode);
+    if (st != QM_OK) return st;
+    if (!hyp_params_ok(alpha, beta, delta))
+        return fail(QM_E_INVAL, "need |beta| < alpha, delta > 0, all finite (got %g, %g, %g)", alpha, beta, delta);
+    if (!std::isfinite(mu)) return fail(QM_E_INVAL, "mu must be finite");
+    const DeviceHypTable* t = nullptr;
+    st = qm::get_hyp_table(ctx, alpha, beta, delta, &t);
+    if (st != QM_OK || n == 0) return st;
+    hipError_t e = qm::launch_generate_hyperbolic(dtype, mode, (uint32_t)seed, (uint32_t)stream, first, d_out, n,
+                                                  t->d_table, t->hdr, t->ncoef, mu, (hipStream_t)hs, ctx->shape);
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    return QM_OK;
+}
+
 const char* qm_status_string(qm_status s)
 {
     switch (s) {

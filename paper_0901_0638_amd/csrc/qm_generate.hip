@@ -18,11 +18,14 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <cmath>
 #include <type_traits>
 
 #include "qm_hybrid.hpp"
+#include "qm_hyp_device.hpp"
 #include "qm_internal.h"
 #include "qm_philox.hpp"
+#include "qm_student_device.hpp"
 
 namespace qm {
 
@@ -180,6 +183,314 @@ hipError_t launch_generate(int kind, int dtype, int mode, uint32_t seed, uint32_
         if (kind == QM_NORMAL_QUANTILE && mode == QM_PLAIN) return launch_gen<float, OpNQ32Plain, false>(a, s, shape);
     }
     return hipErrorInvalidValue;
+}
+
+StudentParams make_params(const TTableHeader& h, const TCells& c, const double* d_rows);
+
+/* The base's constants as the fused hyperbolic kernel takes them: p- and p+
+   as exp of the table's log masses, the reciprocal rates 1/(alpha + beta)
+   and 1/(alpha - beta), each one rounding. */
+static void hyp_base_constants(const HypTableHeader& h, double* p_minus, double* p_plus, double* inv_minus,
+                               double* inv_plus)
+{
+    *p_minus = std::exp(h.log_p_minus);
+    *p_plus = std::exp(h.log_p_plus);
+    *inv_minus = 1.0 / (h.alpha + h.beta);
+    *inv_plus = 1.0 / (h.alpha - h.beta);
+}
+
+/* Fused uniform -> normal -> Student t.  The quantile stage is the one of
+   k_generate (H, gathered per wave with GATHER); each normal then goes
+   through student_eval from the LDS table, as in k_student. */
+template <typename T, int UNROLL, class H, bool GATHER, bool VECTOR, int DEG>
+__global__ __launch_bounds__(256) void k_generate_t(GenArgs<T> a, const double* __restrict__ coef, StudentParams P)
+{
+    extern __shared__ double lds_gt[];
+    stage_table(lds_gt, coef, P);
+    __syncthreads();
+    typedef typename vec16<T>::type V;
+    constexpr int NV = vec16<T>::n;
+    constexpr int K = NV * UNROLL;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    auto tmap = [&](T z) { return (T)student_eval<DEG>((double)z, lds_gt, P); };
+    if (VECTOR) {
+        const uint32_t lane = __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+        __shared__ T outer_buf[GATHER ? 4 : 1][GATHER ? 64 * K : 1];
+        T* buf = outer_buf[GATHER ? (threadIdx.x >> 6) : 0];
+        V* vout = reinterpret_cast<V*>(a.out + a.head);
+        const uint64_t block0 = (a.first + a.head) / NV;
+        const uint64_t wave_first = tid - lane;
+        for (uint64_t i0 = wave_first; i0 < a.nvec; i0 += UNROLL * stride) {
+            const uint64_t i = i0 + lane;
+            T u[K], w[K];
+#pragma unroll
+            for (int k = 0; k < UNROLL; ++k) {
+                T b[NV];
+                block_uniforms(block0 + i + k * stride, a.k0, a.k1, b);
+#pragma unroll
+                for (int j = 0; j < NV; ++j) u[NV * k + j] = b[j];
+            }
+            if constexpr (GATHER) {
+                hybrid_eval<T, K, H>(u, w, buf, lane);
+            } else {
+                H op;
+#pragma unroll
+                for (int k = 0; k < K; ++k) w[k] = op(u[k]);
+            }
+#pragma unroll
+            for (int k = 0; k < K; ++k) w[k] = tmap(w[k]);
+#pragma unroll
+            for (int k = 0; k < UNROLL; ++k) {
+                uint64_t idx = i + k * stride;
+                V y;
+#pragma unroll
+                for (int j = 0; j < NV; ++j) y[j] = w[NV * k + j];
+                if (idx < a.nvec) __builtin_nontemporal_store(y, vout + idx);
+            }
+        }
+        if (blockIdx.x == 0) {
+            uint64_t extra = a.head + (a.n - a.tail_begin);
+            for (uint64_t e = threadIdx.x; e < extra; e += blockDim.x) {
+                uint64_t idx = e < a.head ? e : a.tail_begin + (e - a.head);
+                T u = stream_uniform<T>(a.first + idx, a.k0, a.k1);
+                T z;
+                if constexpr (GATHER) z = H::whole(u);
+                else z = H()(u);
+                a.out[idx] = tmap(z);
+            }
+        }
+    } else {
+        for (uint64_t i = tid; i < a.n; i += stride) {
+            T u = stream_uniform<T>(a.first + i, a.k0, a.k1);
+            T z;
+            if constexpr (GATHER) z = H::whole(u);
+            else z = H()(u);
+            a.out[i] = tmap(z);
+        }
+    }
+}
+
+/* The two-sided exponential base sample of an open uniform (Section 8.1),
+   in FP64: one logarithm of the side's ratio. */
+struct HypBase {
+    double p_minus, p_plus, inv_rate_minus, inv_rate_plus;
+    __device__ __forceinline__ double operator()(double u) const
+    {
+        const bool neg = u < p_minus;
+        const double ratio = neg ? u / p_minus : (1.0 - u) / p_plus;
+        return ::log(ratio) * (neg ? inv_rate_minus : -inv_rate_plus);
+    }
+};
+
+/* Fused uniform -> base sample -> hyperbolic: all K elements of a lane
+   through the LDS cells, then one wave vote for the far ones (as
+   k_hyperbolic). */
+template <typename T, int UNROLL, bool VECTOR, int DEG>
+__global__ __launch_bounds__(256) void k_generate_h(GenArgs<T> a, HypParams P, HypBase B)
+{
+    extern __shared__ double lds_gh[];
+    stage_hyp<DEG>(lds_gh, P);
+    __syncthreads();
+    typedef typename vec16<T>::type V;
+    constexpr int NV = vec16<T>::n;
+    constexpr int K = NV * UNROLL;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    auto one = [&](T u) {
+        const double v = B((double)u);
+        return (T)(P.mu + __builtin_copysign(hyp_abs_q<DEG>(v, lds_gh, P), v));
+    };
+    if (VECTOR) {
+        V* vout = reinterpret_cast<V*>(a.out + a.head);
+        const uint64_t block0 = (a.first + a.head) / NV;
+        uint64_t i = tid;
+        for (; i < a.nvec; i += UNROLL * stride) {
+            double v[K], q[K];
+            bool far[K];
+            bool anyfar = false;
+#pragma unroll
+            for (int k = 0; k < UNROLL; ++k) {
+                T b[NV];
+                /* blocks past the end are drawn but never stored */
+                block_uniforms(block0 + i + k * stride, a.k0, a.k1, b);
+#pragma unroll
+                for (int j = 0; j < NV; ++j) v[NV * k + j] = B((double)b[j]);
+            }
+#pragma unroll
+            for (int e = 0; e < K; ++e) {
+                q[e] = hyp_near<DEG>(v[e], lds_gh, P, &far[e]);
+                anyfar |= far[e];
+            }
+            if (wave_any(anyfar)) {
+#pragma unroll
+                for (int e = 0; e < K; ++e) {
+                    if (wave_any(far[e])) {
+                        double qf = hyp_far_of<DEG>(far[e] ? v[e] : 0.0, P);
+                        q[e] = far[e] ? qf : q[e];
+                    }
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < UNROLL; ++k) {
+                uint64_t idx = i + k * stride;
+                V y;
+#pragma unroll
+                for (int j = 0; j < NV; ++j) y[j] = (T)(P.mu + __builtin_copysign(q[NV * k + j], v[NV * k + j]));
+                if (idx < a.nvec) __builtin_nontemporal_store(y, vout + idx);
+            }
+        }
+        if (blockIdx.x == 0) {
+            uint64_t extra = a.head + (a.n - a.tail_begin);
+            for (uint64_t e = threadIdx.x; e < extra; e += blockDim.x) {
+                uint64_t idx = e < a.head ? e : a.tail_begin + (e - a.head);
+                a.out[idx] = one(stream_uniform<T>(a.first + idx, a.k0, a.k1));
+            }
+        }
+    } else {
+        for (uint64_t i = tid; i < a.n; i += stride) a.out[i] = one(stream_uniform<T>(a.first + i, a.k0, a.k1));
+    }
+}
+
+/* Vector geometry of a generate launch (head, whole blocks, tail) and its
+   grid; false if the output takes the element-by-element path. */
+template <typename T>
+static bool gen_geometry(GenArgs<T>& a, const KernelShape& shape, uint64_t* blocks)
+{
+    constexpr int NV = vec16<T>::n;
+    a.head = (NV - a.first % NV) % NV;
+    bool vector = a.head <= a.n && (a.n - a.head) >= (uint64_t)NV &&
+                  (reinterpret_cast<uintptr_t>(a.out + a.head) % 16) == 0;
+    uint64_t b;
+    if (vector) {
+        a.nvec = (a.n - a.head) / NV;
+        a.tail_begin = a.head + a.nvec * NV;
+        uint64_t per_block = 256ull * shape.unroll;
+        b = (a.nvec + per_block - 1) / per_block;
+    } else {
+        a.head = 0;
+        a.nvec = 0;
+        a.tail_begin = a.n;
+        b = (a.n + 255) / 256;
+    }
+    if (b > shape.max_blocks) b = shape.max_blocks;
+    *blocks = b < 1 ? 1 : b;
+    return vector;
+}
+
+template <typename T, class H, bool GATHER, int DEG>
+static hipError_t launch_gen_t(GenArgs<T> a, const double* coef, const StudentParams& P, size_t lds, hipStream_t s,
+                               const KernelShape& shape)
+{
+    uint64_t blocks;
+    if (gen_geometry(a, shape, &blocks)) {
+        if (shape.unroll == 4)
+            hipLaunchKernelGGL((k_generate_t<T, 4, H, GATHER, true, DEG>), dim3((unsigned)blocks), dim3(256), lds, s, a, coef, P);
+        else if (shape.unroll == 1)
+            hipLaunchKernelGGL((k_generate_t<T, 1, H, GATHER, true, DEG>), dim3((unsigned)blocks), dim3(256), lds, s, a, coef, P);
+        else
+            hipLaunchKernelGGL((k_generate_t<T, 2, H, GATHER, true, DEG>), dim3((unsigned)blocks), dim3(256), lds, s, a, coef, P);
+    } else {
+        hipLaunchKernelGGL((k_generate_t<T, 1, H, GATHER, false, DEG>), dim3((unsigned)blocks), dim3(256), lds, s, a, coef, P);
+    }
+    return hipGetLastError();
+}
+
+/* LDS the gather buffer of a generate kernel takes (4 waves x 64 lanes x K) */
+template <typename T>
+static size_t gather_bytes(int unroll)
+{
+    return (size_t)4 * 64 * vec16<T>::n * unroll * sizeof(T);
+}
+
+constexpr size_t GEN_LDS_MAX = 65536;   /* static + dynamic LDS of a generate workgroup */
+
+hipError_t launch_generate_student(int dtype, int mode, uint32_t seed, uint32_t stream, uint64_t first, void* out,
+                                   uint64_t n, const TTableHeader* d_table, const TTableHeader& h, hipStream_t s,
+                                   const LaunchShape& shape)
+{
+    if (h.identity) return launch_generate(QM_NORMAL_QUANTILE, dtype, mode, seed, stream, first, out, n, s, shape);
+    const bool f64 = dtype == QM_F64 && mode == QM_PLAIN;
+    if (!f64 && !(dtype == QM_F32 && mode == QM_F32_REFINE)) return hipErrorInvalidValue;
+    const TCells& c = f64 ? h.f64 : h.f32;
+    const double* coef = table_block(d_table) + c.coef_offset;
+    const StudentParams P = make_params(h, c, coef);
+    const size_t lds = (size_t)c.nlds * P.lds_stride * sizeof(double);
+    const KernelShape ks = shape.hybrid[f64];
+    /* the quantile stage gathers per wave when its buffer fits beside the
+       table (bitwise the same results either way) */
+    const bool gather = shape.compact &&
+                        lds + (f64 ? gather_bytes<double>(ks.unroll) : gather_bytes<float>(ks.unroll)) <= GEN_LDS_MAX;
+    if (lds > GEN_LDS_MAX) return hipErrorInvalidValue;
+    if (f64) {
+        GenArgs<double> a{};
+        a.out = static_cast<double*>(out);
+        a.k0 = seed;
+        a.k1 = stream;
+        a.first = first;
+        a.n = n;
+        if (c.degree == T_DEGREE_LOW) {
+            if (gather) return launch_gen_t<double, HybridNQ64, true, T_DEGREE_LOW>(a, coef, P, lds, s, ks);
+            return launch_gen_t<double, OpNQ64Plain, false, T_DEGREE_LOW>(a, coef, P, lds, s, ks);
+        }
+        if (gather) return launch_gen_t<double, HybridNQ64, true, T_DEGREE_HIGH>(a, coef, P, lds, s, ks);
+        return launch_gen_t<double, OpNQ64Plain, false, T_DEGREE_HIGH>(a, coef, P, lds, s, ks);
+    }
+    GenArgs<float> a{};
+    a.out = static_cast<float*>(out);
+    a.k0 = seed;
+    a.k1 = stream;
+    a.first = first;
+    a.n = n;
+    if (gather) return launch_gen_t<float, HybridNQ32, true, T_DEGREE_F32>(a, coef, P, lds, s, ks);
+    return launch_gen_t<float, OpNQ32Refine, false, T_DEGREE_F32>(a, coef, P, lds, s, ks);
+}
+
+template <typename T, int DEG>
+static hipError_t launch_gen_h(GenArgs<T> a, const HypParams& P, const HypBase& B, size_t lds, hipStream_t s,
+                               const KernelShape& shape)
+{
+    uint64_t blocks;
+    if (gen_geometry(a, shape, &blocks)) {
+        if (shape.unroll == 4)
+            hipLaunchKernelGGL((k_generate_h<T, 4, true, DEG>), dim3((unsigned)blocks), dim3(256), lds, s, a, P, B);
+        else if (shape.unroll == 1)
+            hipLaunchKernelGGL((k_generate_h<T, 1, true, DEG>), dim3((unsigned)blocks), dim3(256), lds, s, a, P, B);
+        else
+            hipLaunchKernelGGL((k_generate_h<T, 2, true, DEG>), dim3((unsigned)blocks), dim3(256), lds, s, a, P, B);
+    } else {
+        hipLaunchKernelGGL((k_generate_h<T, 1, false, DEG>), dim3((unsigned)blocks), dim3(256), lds, s, a, P, B);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_generate_hyperbolic(int dtype, int mode, uint32_t seed, uint32_t stream, uint64_t first, void* out,
+                                      uint64_t n, const HypTableHeader* d_table, const HypTableHeader& h,
+                                      uint64_t ncoef, double mu, hipStream_t s, const LaunchShape& shape)
+{
+    const bool f32 = dtype == QM_F32 && mode == QM_F32_REFINE;
+    if (!f32 && !(dtype == QM_F64 && mode == QM_PLAIN)) return hipErrorInvalidValue;
+    HypParams P;
+    size_t lds = 0;
+    if (!make_hyp_params(h, f32, d_table, ncoef, mu, &P, &lds)) return hipErrorInvalidValue;
+    HypBase B;
+    hyp_base_constants(h, &B.p_minus, &B.p_plus, &B.inv_rate_minus, &B.inv_rate_plus);
+    if (f32) {
+        GenArgs<float> a{};
+        a.out = static_cast<float*>(out);
+        a.k0 = seed;
+        a.k1 = stream;
+        a.first = first;
+        a.n = n;
+        return launch_gen_h<float, HYP_DEGREE_F32>(a, P, B, lds, s, shape.hyperbolic[0]);
+    }
+    GenArgs<double> a{};
+    a.out = static_cast<double*>(out);
+    a.k0 = seed;
+    a.k1 = stream;
+    a.first = first;
+    a.n = n;
+    return launch_gen_h<double, HYP_DEGREE>(a, P, B, lds, s, shape.hyperbolic[1]);
 }
 
 }  // namespace qm

@@ -40,6 +40,16 @@ hipError_t launch_elementwise(int kind, int dtype, int mode, const void* in, voi
 hipError_t launch_generate(int kind, int dtype, int mode, uint32_t seed, uint32_t stream, uint64_t first,
                            void* out, uint64_t n, hipStream_t s, const LaunchShape& shape);
 
+/* Fused generation chains (qm_generate.hip): the Student t of the normal
+   quantile of each uniform, and the hyperbolic map of each uniform's
+   two-sided exponential base sample. */
+hipError_t launch_generate_student(int dtype, int mode, uint32_t seed, uint32_t stream, uint64_t first, void* out,
+                                   uint64_t n, const TTableHeader* d_table, const TTableHeader& h, hipStream_t s,
+                                   const LaunchShape& shape);
+hipError_t launch_generate_hyperbolic(int dtype, int mode, uint32_t seed, uint32_t stream, uint64_t first, void* out,
+                                      uint64_t n, const HypTableHeader* d_table, const HypTableHeader& h,
+                                      uint64_t ncoef, double mu, hipStream_t s, const LaunchShape& shape);
+
 /* The coefficient block that follows a device table's header. */
 inline const double* table_block(const TTableHeader* d_table)
 {
