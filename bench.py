@@ -228,6 +228,17 @@ def run_quantile(args, torch, qm, qi):
             fused[name] = {"gsamples_s": round(n / (avg * 1e-3) / 1e9, 2),
                            "gbs": round(buf.element_size() * n / (avg * 1e-3) / 1e9, 1),
                            "p50_ms": percentile(ds, 50), "p99_ms": percentile(ds, 99)}
+        # fused chains: Philox -> normal -> Student t (nu = 4), Philox -> base -> hyperbolic (1, 0, 1)
+        for name, buf, fn in (
+                ("student_t_f64_nu4", g64, lambda: qm.qm_generate_student_t(ctx, 1, 0, 0, g64, 4.0)),
+                ("student_t_f32_nu4", g32, lambda: qm.qm_generate_student_t(ctx, 1, 0, 0, g32, 4.0)),
+                ("hyperbolic_f64", g64, lambda: qm.qm_generate_hyperbolic(ctx, 1, 0, 0, g64, *qi.HYPERBOLIC_PARAMS)),
+                ("hyperbolic_f32", g32, lambda: qm.qm_generate_hyperbolic(ctx, 1, 0, 0, g32, *qi.HYPERBOLIC_PARAMS))):
+            ds = timed_launches(torch, stream, fn, 10)
+            avg = sum(ds) / len(ds)
+            fused[name] = {"gsamples_s": round(n / (avg * 1e-3) / 1e9, 2),
+                           "gbs": round(buf.element_size() * n / (avg * 1e-3) / 1e9, 1),
+                           "p50_ms": percentile(ds, 50), "p99_ms": percentile(ds, 99)}
         extra["generate_fused"] = fused
         del g64, g32
         result["extra"] = extra
