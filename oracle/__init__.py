@@ -17,6 +17,9 @@ precision, see oracle.c):
                           target (Section 8.1; hyperbolic.c)
   hyperbolic_masses(...)  (log p+, log p-, log C) of the hyperbolic target
   hyperbolic_log_tail(x, ...)  log(1 - F(x)) for x >= 0, log F(x) for x < 0
+  vg_map(v, lam, alpha, beta)  F^{-1}(F0(v)), the same base -> variance-gamma
+                          target with integer lambda (Section 8.2; vg.c)
+  vg_masses(...), vg_log_tail(x, ...)  as for the hyperbolic target
 """
 import ctypes
 import os
@@ -25,7 +28,7 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRC = [os.path.join(_HERE, "oracle.c"), os.path.join(_HERE, "hyperbolic.c")]
+_SRC = [os.path.join(_HERE, "oracle.c"), os.path.join(_HERE, "hyperbolic.c"), os.path.join(_HERE, "vg.c")]
 _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
@@ -69,6 +72,12 @@ def _load():
     lib.oracle_hyperbolic_masses.restype = ctypes.c_int
     lib.oracle_hyperbolic_log_tail.argtypes = [d, d, d, d]
     lib.oracle_hyperbolic_log_tail.restype = d
+    lib.oracle_vg_map.argtypes = [dp, dp, ctypes.c_size_t, d, d, d, ctypes.c_int]
+    lib.oracle_vg_map.restype = ctypes.c_int
+    lib.oracle_vg_masses.argtypes = [d, d, d, dp, dp]
+    lib.oracle_vg_masses.restype = ctypes.c_int
+    lib.oracle_vg_log_tail.argtypes = [d, d, d, d]
+    lib.oracle_vg_log_tail.restype = d
     _lib = lib
     return lib
 
@@ -136,3 +145,24 @@ def hyperbolic_masses(alpha, beta, delta):
 def hyperbolic_log_tail(x, alpha, beta, delta):
     """log(1 - F(x)) for x >= 0, log F(x) for x < 0."""
     return _load().oracle_hyperbolic_log_tail(float(x), float(alpha), float(beta), float(delta))
+
+
+def vg_map(v, lam, alpha, beta, threads=0):
+    """x = F^{-1}(F0(v)): two-sided exponential base -> variance-gamma target, integer lambda (Section 8.2)."""
+    v = _as_f64(v)
+    out = np.empty_like(v)
+    _load().oracle_vg_map(_ptr(v), _ptr(out), v.size, float(lam), float(alpha), float(beta), threads_used(threads))
+    return out
+
+
+def vg_masses(lam, alpha, beta):
+    """(log p+, log p-) of the variance-gamma density with these parameters."""
+    a, b = ctypes.c_double(), ctypes.c_double()
+    if _load().oracle_vg_masses(float(lam), float(alpha), float(beta), ctypes.byref(a), ctypes.byref(b)) != 0:
+        raise ValueError("invalid variance-gamma parameters")
+    return a.value, b.value
+
+
+def vg_log_tail(x, lam, alpha, beta):
+    """log(1 - F(x)) for x >= 0, log F(x) for x < 0."""
+    return _load().oracle_vg_log_tail(float(x), float(lam), float(alpha), float(beta))
