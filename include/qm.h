@@ -13,6 +13,8 @@
  *   qm_recycle_exp_to_hyperbolic
  *                             x = F^{-1}(F0(v)), two-sided exponential base
  *                             -> hyperbolic target        (Section 8.1)
+ *   qm_recycle_exp_to_vg      the same base -> variance-gamma target,
+ *                             integer lambda               (Section 8.2)
  *   qm_generate               the uniforms of a counter-based stream, or w
  *                             of them, drawn and mapped in one pass
  *   qm_generate_student_t, qm_generate_hyperbolic
@@ -185,6 +187,29 @@ qm_status qm_recycle_exp_to_hyperbolic(qm_ctx* ctx, const void* d_v, void* d_x, 
  */
 qm_status qm_hyperbolic_masses(qm_ctx* ctx, double alpha, double beta, double delta, double* log_p_plus,
                                double* log_p_minus);
+
+/*
+ * x[i] = mu + Q(v[i]), the exponential -> variance-gamma recycling map
+ * (Section 8.2) for integer lambda in [1, 8].  Target: the variance-gamma
+ * density
+ *   f(x) = (alpha^2 - beta^2)^lambda e^{beta (x-mu)} |x-mu|^{lambda-1/2} K_{lambda-1/2}(alpha |x-mu|)
+ *          / ((2 alpha)^{lambda-1/2} sqrt(pi) Gamma(lambda)),  |beta| < alpha,
+ * from the same two-sided exponential base as qm_recycle_exp_to_hyperbolic
+ * with this target's masses (qm_vg_masses).  For integer lambda the Bessel
+ * function is elementary, so the library solves the defining equation
+ * directly (no ODE) on the host once per (lambda, alpha, beta) and
+ * evaluates the same piecewise polynomials with the same kernel; lambda = 1
+ * is the base itself (Q(v) = v).  Accuracy as for the hyperbolic map.
+ * dtype/mode: F64 PLAIN; F32 F32_REFINE.
+ * Errors: QM_E_INVAL for lambda not an integer in [1, 8], alpha <= |beta|,
+ * a non-finite parameter or mu, NULL, unaligned or overlapping buffers.
+ */
+qm_status qm_recycle_exp_to_vg(qm_ctx* ctx, const void* d_v, void* d_x, uint64_t n, int dtype, int mode, double lambda,
+                               double alpha, double beta, double mu, void* hip_stream);
+
+/* log p+ and log p- of the variance-gamma target (as qm_hyperbolic_masses). */
+qm_status qm_vg_masses(qm_ctx* ctx, double lambda, double alpha, double beta, double* log_p_plus,
+                       double* log_p_minus);
 
 /*
  * Fused generation and transform.  Draws the open uniforms of elements

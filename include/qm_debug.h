@@ -46,7 +46,7 @@ int qm_debug_hyperbolic_dense(double alpha, double beta, double delta, const dou
 /*
  * Build the hyperbolic table on the host.  header_out (may be NULL)
  * receives the header (struct qm::HypTableHeader of csrc/qm_hyp_table.h,
- * 360 bytes: parameters, the two sides' masses, and for each side and each
+ * 392 bytes: parameters, the two sides' masses, and for each side and each
  * cell set -- FP64 outputs, FP32 outputs -- the cell layout, large-v
  * constants and the builder's check of its rounded rows); coef_out (may be
  * NULL) receives the rows of all four, at their coef_offset, if coef_cap
@@ -55,6 +55,10 @@ int qm_debug_hyperbolic_dense(double alpha, double beta, double delta, const dou
  */
 int qm_debug_hyperbolic_table(double alpha, double beta, double delta, void* header_out, double* coef_out,
                               int coef_cap);
+
+/* The same for the variance-gamma table of (lambda, alpha, beta), integer
+   lambda in [1, 8] (the header's delta field holds lambda). */
+int qm_debug_vg_table(double lambda, double alpha, double beta, void* header_out, double* coef_out, int coef_cap);
 
 #ifdef __cplusplus
 }

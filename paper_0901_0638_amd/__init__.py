@@ -152,6 +152,22 @@ def qm_hyperbolic_masses(ctx, alpha, beta, delta):
     return lp.value, lm.value
 
 
+def qm_recycle_exp_to_vg(ctx, v, x, lam, alpha, beta, mu=0.0, mode=None, stream=None):
+    """x = mu + F^{-1}(F0(v)), two-sided exponential base -> variance-gamma, integer lambda (Section 8.2)."""
+    pi, po, n, dt = _io(v, x)
+    if mode is None:
+        mode = QM_PLAIN if dt == QM_F64 else QM_F32_REFINE
+    check(load().qm_recycle_exp_to_vg(ctx.handle, pi, po, n, dt, mode, float(lam), float(alpha), float(beta),
+                                      float(mu), _stream(stream, v)))
+
+
+def qm_vg_masses(ctx, lam, alpha, beta):
+    """(log p+, log p-) of the variance-gamma target."""
+    lp, lm = ctypes.c_double(), ctypes.c_double()
+    check(load().qm_vg_masses(ctx.handle, float(lam), float(alpha), float(beta), ctypes.byref(lp), ctypes.byref(lm)))
+    return lp.value, lm.value
+
+
 def make_request(kind, inp, out, mode=None, nu=0.0, user_tag=0, hyperbolic=(0.0, 0.0, 0.0), mu=0.0):
     """qm_request for qm_run_batch / qm_submit from a pair of device tensors
     (`hyperbolic` = (alpha, beta, delta) and `mu` for QM_EXP_TO_HYPERBOLIC)."""
@@ -237,6 +253,7 @@ class HypSide(ctypes.Structure):
     """Layout of qm::HypSide (csrc/qm_hyp_table.h): the cells of one side of the hyperbolic map."""
     _fields_ = [("v0", ctypes.c_double), ("inv_v0", ctypes.c_double), ("v_top", ctypes.c_double),
                 ("far_c0", ctypes.c_double), ("far_c1", ctypes.c_double), ("far_c2", ctypes.c_double),
+                ("far_clog", ctypes.c_double),
                 ("max_rel_err", ctypes.c_double), ("noct", ctypes.c_int32), ("ncell", ctypes.c_int32),
                 ("degree", ctypes.c_int32), ("reserved", ctypes.c_int32), ("coef_offset", ctypes.c_uint64)]
 
@@ -264,6 +281,26 @@ def debug_hyperbolic_dense(alpha, beta, delta, v):
     if r != 0:
         raise ValueError("dense solution unavailable for %r" % ((alpha, beta, delta),))
     return q
+
+
+def _debug_base_table(fn, args, which):
+    import numpy as np
+    h = HypTableHeader()
+    dp = ctypes.POINTER(ctypes.c_double)
+    n = fn(*[float(a) for a in args], ctypes.byref(h), None, 0)
+    if n < 0:
+        raise ValueError("table build failed for %r" % (args,))
+    block = np.empty(n, np.float64)
+    fn(*[float(a) for a in args], None, block.ctypes.data_as(dp), n)
+    sides = (h.right, h.left) if which == "f64" else (h.right32, h.left32)
+    rows = [block[s.coef_offset:s.coef_offset + s.ncell * (s.degree + 1)].reshape(s.ncell, s.degree + 1)
+            for s in sides]
+    return h, rows[0], rows[1]
+
+
+def debug_vg_table(lam, alpha, beta, which="f64"):
+    """(header, right rows, left rows) of the host-built variance-gamma table (integer lambda)."""
+    return _debug_base_table(load().qm_debug_vg_table, (lam, alpha, beta), which)
 
 
 def debug_hyperbolic_table(alpha, beta, delta, which="f64"):

@@ -63,6 +63,8 @@ SIGNATURES = {
     "qm_recycle_exp_to_normal": (_st, [_vp, _vp, _vp, _u64, _i, _i, _vp]),
     "qm_recycle_exp_to_hyperbolic": (_st, [_vp, _vp, _vp, _u64, _i, _i, _d, _d, _d, _d, _vp]),
     "qm_hyperbolic_masses": (_st, [_vp, _d, _d, _d, ctypes.POINTER(_d), ctypes.POINTER(_d)]),
+    "qm_recycle_exp_to_vg": (_st, [_vp, _vp, _vp, _u64, _i, _i, _d, _d, _d, _d, _vp]),
+    "qm_vg_masses": (_st, [_vp, _d, _d, _d, ctypes.POINTER(_d), ctypes.POINTER(_d)]),
     "qm_generate": (_st, [_vp, _u64, _u64, _u64, _vp, _u64, _i, _i, _i, _vp]),
     "qm_generate_student_t": (_st, [_vp, _u64, _u64, _u64, _vp, _u64, _i, _i, _d, _vp]),
     "qm_generate_hyperbolic": (_st, [_vp, _u64, _u64, _u64, _vp, _u64, _i, _i, _d, _d, _d, _d, _vp]),
@@ -80,6 +82,7 @@ DEBUG_SIGNATURES = {
     "qm_debug_student_table": (ctypes.c_int, [_d, _vp, ctypes.POINTER(_d), ctypes.c_int]),
     "qm_debug_hyperbolic_dense": (ctypes.c_int, [_d, _d, _d, ctypes.POINTER(_d), ctypes.POINTER(_d), ctypes.c_int]),
     "qm_debug_hyperbolic_table": (ctypes.c_int, [_d, _d, _d, _vp, ctypes.POINTER(_d), ctypes.c_int]),
+    "qm_debug_vg_table": (ctypes.c_int, [_d, _d, _d, _vp, ctypes.POINTER(_d), ctypes.c_int]),
 }
 
 _lib = None

@@ -130,20 +130,23 @@ qm_status get_table(qm_ctx* ctx, double nu, const DeviceTable** out)
     return QM_OK;
 }
 
-/* Look up (or build and upload) the hyperbolic table for (alpha, beta,
-   delta), built outside the lock like get_table's. */
-qm_status get_hyp_table(qm_ctx* ctx, double alpha, double beta, double delta, const DeviceHypTable** out)
+/* Look up (or build and upload) a table of the two-sided exponential base:
+   hyperbolic for (alpha, beta, delta), or variance-gamma for (lambda, alpha,
+   beta) when vg; built outside the lock like get_table's. */
+static qm_status get_base_table(qm_ctx* ctx, bool vg, double p1, double p2, double p3, const DeviceHypTable** out)
 {
-    auto key = std::make_tuple(alpha, beta, delta);
+    auto key = std::make_tuple(p1, p2, p3);
+    auto& tables = vg ? ctx->vg_tables : ctx->hyp_tables;
     {
         std::lock_guard<std::mutex> lk(ctx->table_mu);
-        auto it = ctx->hyp_tables.find(key);
-        if (it != ctx->hyp_tables.end()) { *out = &it->second; return QM_OK; }
+        auto it = tables.find(key);
+        if (it != tables.end()) { *out = &it->second; return QM_OK; }
     }
     HostHypTable ht{};
     char err[256] = {0};
-    if (build_hyperbolic_table(alpha, beta, delta, &ht, err, sizeof err) != 0)
-        return fail(QM_E_INVAL, "hyperbolic table for alpha=%g beta=%g delta=%g: %s", alpha, beta, delta, err);
+    if (vg ? build_vg_table(p1, p2, p3, &ht, err, sizeof err) != 0
+           : build_hyperbolic_table(p1, p2, p3, &ht, err, sizeof err) != 0)
+        return fail(QM_E_INVAL, "%s table for (%g, %g, %g): %s", vg ? "variance-gamma" : "hyperbolic", p1, p2, p3, err);
     size_t coef_bytes = (size_t)ht.ncoef * sizeof(double);
     void* d = nullptr;
     hipError_t e = hipMalloc(&d, sizeof(HypTableHeader) + coef_bytes);
@@ -158,10 +161,20 @@ qm_status get_hyp_table(qm_ctx* ctx, double alpha, double beta, double delta, co
     dt.ncoef = ht.ncoef;
     free_hyperbolic_table(&ht);
     std::lock_guard<std::mutex> lk(ctx->table_mu);
-    auto res = ctx->hyp_tables.emplace(key, dt);
+    auto res = tables.emplace(key, dt);
     if (!res.second) (void)hipFree(d);
     *out = &res.first->second;
     return QM_OK;
+}
+
+qm_status get_hyp_table(qm_ctx* ctx, double alpha, double beta, double delta, const DeviceHypTable** out)
+{
+    return get_base_table(ctx, false, alpha, beta, delta, out);
+}
+
+qm_status get_vg_table(qm_ctx* ctx, double lambda, double alpha, double beta, const DeviceHypTable** out)
+{
+    return get_base_table(ctx, true, lambda, alpha, beta, out);
 }
 
 const TTableHeader* device_table_ptr(const DeviceTable* t) { return t->d_table; }
@@ -256,6 +269,7 @@ void qm_shutdown(qm_ctx* ctx)
     qm::runner_free(ctx);
     for (auto& kv : ctx->tables) (void)hipFree(kv.second.d_table);
     for (auto& kv : ctx->hyp_tables) (void)hipFree(kv.second.d_table);
+    for (auto& kv : ctx->vg_tables) (void)hipFree(kv.second.d_table);
     delete ctx;
 }
 
@@ -324,6 +338,59 @@ qm_status qm_recycle_exp_to_hyperbolic(qm_ctx* ctx, const void* d_v, void* d_x, 
     st = qm::get_hyp_table(ctx, alpha, beta, delta, &t);
     if (st != QM_OK) return st;
     return qm::run_single(ctx, r, (hipStream_t)s);
+}
+
+static bool vg_params_ok(double lambda, double alpha, double beta)
+{
+    return std::isfinite(lambda) && std::isfinite(alpha) && std::isfinite(beta) && lambda >= 1 && lambda <= 8 &&
+           lambda == std::floor(lambda) && alpha > std::fabs(beta);
+}
+
+qm_status qm_recycle_exp_to_vg(qm_ctx* ctx, const void* d_v, void* d_x, uint64_t n, int dtype, int mode, double lambda,
+                               double alpha, double beta, double mu, void* s)
+{
+    if (!ctx) return fail(QM_E_INVAL, "context is NULL");
+    if (dtype != QM_F32 && dtype != QM_F64) return fail(QM_E_INVAL, "unknown dtype %d", dtype);
+    if (mode != QM_PLAIN && mode != QM_F32_REFINE && mode != QM_PAPER) return fail(QM_E_INVAL, "unknown mode %d", mode);
+    if (!(dtype == QM_F64 && mode == QM_PLAIN) && !(dtype == QM_F32 && mode == QM_F32_REFINE))
+        return fail(QM_E_DTYPE, "exp->variance-gamma: F64 QM_PLAIN or F32 QM_F32_REFINE");
+    if (!vg_params_ok(lambda, alpha, beta))
+        return fail(QM_E_INVAL, "need integer lambda in [1, 8] and |beta| < alpha, all finite (got %g, %g, %g)",
+                    lambda, alpha, beta);
+    if (!std::isfinite(mu)) return fail(QM_E_INVAL, "mu must be finite");
+    const size_t es = dtype_size(dtype);
+    if (n > 0) {
+        if (!d_v || !d_x) return fail(QM_E_INVAL, "NULL buffer with n > 0");
+        uintptr_t a = (uintptr_t)d_v, b = (uintptr_t)d_x;
+        if (a % es || b % es) return fail(QM_E_INVAL, "buffers must be aligned to the element size");
+        if (n > (UINT64_MAX / 2) / es) return fail(QM_E_INVAL, "n too large");
+        uint64_t bytes = n * es;
+        if (a != b && a < b + bytes && b < a + bytes) return fail(QM_E_INVAL, "input and output partially overlap");
+    }
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    const DeviceHypTable* t = nullptr;
+    qm_status st = qm::get_vg_table(ctx, lambda, alpha, beta, &t);
+    if (st != QM_OK || n == 0) return st;
+    e = qm::launch_hyperbolic(dtype, mode, d_v, d_x, n, t->d_table, t->hdr, t->ncoef, mu, (hipStream_t)s, ctx->shape);
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    return QM_OK;
+}
+
+qm_status qm_vg_masses(qm_ctx* ctx, double lambda, double alpha, double beta, double* log_p_plus, double* log_p_minus)
+{
+    if (!ctx) return fail(QM_E_INVAL, "context is NULL");
+    if (!vg_params_ok(lambda, alpha, beta))
+        return fail(QM_E_INVAL, "need integer lambda in [1, 8] and |beta| < alpha, all finite (got %g, %g, %g)",
+                    lambda, alpha, beta);
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    const DeviceHypTable* t = nullptr;
+    qm_status st = qm::get_vg_table(ctx, lambda, alpha, beta, &t);
+    if (st != QM_OK) return st;
+    if (log_p_plus) *log_p_plus = t->hdr.log_p_plus;
+    if (log_p_minus) *log_p_minus = t->hdr.log_p_minus;
+    return QM_OK;
 }
 
 qm_status qm_hyperbolic_masses(qm_ctx* ctx, double alpha, double beta, double delta, double* log_p_plus,

@@ -32,6 +32,7 @@ struct qm_ctx {
     std::mutex table_mu;
     std::map<double, DeviceTable> tables;
     std::map<std::tuple<double, double, double>, DeviceHypTable> hyp_tables;  /* (alpha, beta, delta) */
+    std::map<std::tuple<double, double, double>, DeviceHypTable> vg_tables;   /* (lambda, alpha, beta) */
     std::mutex server_mu;
     qm::Server* server = nullptr;
     qm::BatchRunner* runner = nullptr;

@@ -158,6 +158,7 @@ static void side_far(const HypSide& s, const double* d_block, HypSideFar* f)
     f->c0 = s.far_c0;
     f->c1 = s.far_c1;
     f->c2 = s.far_c2;
+    f->clog = s.far_clog;
     f->gcoef = d_block + s.coef_offset;
     f->ncell = s.ncell;
     f->pad = 0;

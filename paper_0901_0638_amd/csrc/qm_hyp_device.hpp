@@ -23,7 +23,7 @@ static_assert(HYP_SUB == 8, "the cell index takes the top 3 mantissa bits of t")
 
 /* The far path's parameters of one side. */
 struct HypSideFar {
-    double v_top, c0, c1, c2;
+    double v_top, c0, c1, c2, clog;
     const double* gcoef;          /* the side's rows in global memory */
     int ncell, pad;
 };
@@ -78,11 +78,16 @@ __device__ __forceinline__ double hyp_near(double v, const double* __restrict__ 
    side, or a struct passed by value, would put them in scratch memory). */
 template <int DEG>
 static __device__ __noinline__ double hyp_far(double a, double v0, double inv_v0, double v_top, double c0, double c1,
-                                              double c2, const double* gcoef, int ncell)
+                                              double c2, double clog, const double* gcoef, int ncell)
 {
     if (!(a < v_top)) {
         if (!(a < __builtin_inf())) return a;
-        return a + (c0 + (c1 + c2 / a) / a);
+        if (clog == 0.0) return a + (c0 + (c1 + c2 / a) / a);
+        /* a tail with a power of x: Q = a + c0 + clog log Q + (c1 + c2/Q)/Q,
+           three fixed-point steps (each gains a factor clog/Q) */
+        double q = a + c0 - clog * neg_log_unit(a);
+        for (int i = 0; i < 3; ++i) q = a + c0 - clog * neg_log_unit(q) + (c1 + c2 / q) / q;
+        return q;
     }
     double tc;
     int j = hyp_cell(__builtin_fma(a, inv_v0, 1.0), &tc);
@@ -95,8 +100,8 @@ __device__ __forceinline__ double hyp_far_of(double v, const HypParams& P)
 {
     const bool neg = v < 0.0;
     return hyp_far<DEG>(__builtin_fabs(v), P.v0, P.inv_v0, neg ? P.l.v_top : P.r.v_top, neg ? P.l.c0 : P.r.c0,
-                   neg ? P.l.c1 : P.r.c1, neg ? P.l.c2 : P.r.c2, neg ? P.l.gcoef : P.r.gcoef,
-                   neg ? P.l.ncell : P.r.ncell);
+                   neg ? P.l.c1 : P.r.c1, neg ? P.l.c2 : P.r.c2, neg ? P.l.clog : P.r.clog,
+                   neg ? P.l.gcoef : P.r.gcoef, neg ? P.l.ncell : P.r.ncell);
 }
 
 /* Both sides' LDS rows: right side rows 0..nlds-1, left side after. */

@@ -390,17 +390,35 @@ fq solve_far(const Side& sd, fq v, fq x0)
     return x;
 }
 
+/*
+ * What the cell fitting needs of one side's map, whatever solves it: Q(v)
+ * for v > 0 to far below the cells' tolerance, Q'(0), the side's rate, and
+ * the large-v form exactly as the kernel evaluates it,
+ *     clog = 0:  Q = v + c0 + (c1 + c2/v)/v,
+ *     clog > 0:  Q = v + c0 + clog log Q + (c1 + c2/Q)/Q by three fixed-point
+ *                steps from v + c0 + clog log v (tails with a power of x).
+ */
+struct SideMap {
+    fq slope0 = 0, rate = 0;
+    fq c0 = 0, c1 = 0, c2 = 0, clog = 0;
+    virtual fq eval(fq v) const = 0;
+    virtual ~SideMap() {}
+    fq far(fq v) const
+    {
+        if (clog == 0) return v + c0 + (c1 + c2 / v) / v;
+        fq q = v + c0 + clog * logq(v);
+        for (int i = 0; i < 3; ++i) q = v + c0 + clog * logq(q) + (c1 + c2 / q) / q;
+        return q;
+    }
+};
+
 /* The solution of one side: ODE legs on [0, v_a], direct solves beyond. */
-struct SideSolution {
+struct SideSolution : SideMap {
     const Side* sd;
     std::vector<Node> fwd, bwd;
     fq v_match, v_a;
-    fq slope0;          /* Q'(0) */
-    fq c0, c1, c2;      /* Q = v + c0 + c1/v + c2/v^2 + O(v^-3) */
 
-    fq far(fq v) const { return v + c0 + (c1 + c2 / v) / v; }
-
-    fq eval(fq v) const
+    fq eval(fq v) const override
     {
         if (v > v_a) return solve_far(*sd, v, far(v));
         const std::vector<Node>& nd = v <= v_match ? fwd : bwd;
@@ -475,6 +493,7 @@ bool solve_side(const Side& sd, SideSolution* ss, char* err, int errlen)
 {
     const fq r = sd.rate;
     ss->sd = &sd;
+    ss->rate = r;
     ss->c0 = (sd.log_c - logq(r) - sd.log_p) / r;
     const fq a = sd.alpha * sd.delta * sd.delta / 2;
     ss->c1 = -a / r;
@@ -511,9 +530,9 @@ bool solve_side(const Side& sd, SideSolution* ss, char* err, int errlen)
 
 /* The smallest power of 2, P, from which on the large-v form meets tol
    (checked on [P, 3P]). */
-bool far_start(const SideSolution& ss, fq tol, fq* P)
+bool far_start(const SideMap& ss, fq tol, fq* P)
 {
-    fq p = ldexpq(1, (int)ceilq(log2q(ldexpq(1, 30) / ss.sd->rate)));
+    fq p = ldexpq(1, (int)ceilq(log2q(ldexpq(1, 30) / ss.rate)));
     auto holds = [&](fq q) {
         for (int i = 0; i <= 16; ++i) {
             fq v = q * (1 + (fq)i / 8);
@@ -533,7 +552,7 @@ bool far_start(const SideSolution& ss, fq tol, fq* P)
  * interpolant at 2 deg + 1 points against the solution; *rounded gets that
  * of the double row (which includes the rounding of R itself).
  */
-fq fit_cell(const SideSolution& ss, int deg, fq lo, fq hi, double* row, fq* rounded)
+fq fit_cell(const SideMap& ss, int deg, fq lo, fq hi, double* row, fq* rounded)
 {
     fq c = (lo + hi) / 2, hw = (hi - lo) / 2;
     fq fv[64], mono[64];
@@ -578,7 +597,7 @@ struct CellSpec {
 /* Fit cells [j0, j1) of a side for v0 into rows (deg + 1 doubles per cell,
    cell j0 first).  Returns false, with the failing cell in *bad, if one
    misses tol; *worst gets the largest error of the rounded rows. */
-bool fit_cells(const SideSolution& ss, const CellSpec& cs, fq v0, int j0, int j1, double* rows, fq* worst, int* bad)
+bool fit_cells(const SideMap& ss, const CellSpec& cs, fq v0, int j0, int j1, double* rows, fq* worst, int* bad)
 {
     const int W = cs.deg + 1;
     for (int j = j0; j < j1; ++j) {
@@ -602,7 +621,7 @@ bool fit_cells(const SideSolution& ss, const CellSpec& cs, fq v0, int j0, int j1
  * power of 2 from which on the large-v form holds to a quarter of the
  * tolerance.  Returns lv, or INT_MIN with a message if none fits.
  */
-int fit_side(const SideSolution& ss, const CellSpec& cs, int max_lv, std::vector<double>* rows_out, HypSide* hs,
+int fit_side(const SideMap& ss, const CellSpec& cs, int max_lv, std::vector<double>* rows_out, HypSide* hs,
              char* err, int errlen)
 {
     fq P;
@@ -637,6 +656,7 @@ int fit_side(const SideSolution& ss, const CellSpec& cs, int max_lv, std::vector
         hs->far_c0 = (double)ss.c0;
         hs->far_c1 = (double)ss.c1;
         hs->far_c2 = (double)ss.c2;
+        hs->far_clog = (double)ss.clog;
         hs->max_rel_err = (double)worst;
         hs->noct = noct;
         hs->ncell = ncell;
@@ -651,7 +671,7 @@ int fit_side(const SideSolution& ss, const CellSpec& cs, int max_lv, std::vector
 
 /* Both sides' cells of one set, with one v0: the smaller of the two sides'
    own choices.  Appends the right side's rows, then the left side's. */
-bool fit_set(const SideSolution& rs, const SideSolution& ls, const CellSpec& cs, HypSide* right, HypSide* left,
+bool fit_set(const SideMap& rs, const SideMap& ls, const CellSpec& cs, HypSide* right, HypSide* left,
              std::vector<double>& coef, char* err, int errlen)
 {
     std::vector<double> rr, rl;
@@ -681,6 +701,123 @@ bool check_params(double alpha, double beta, double delta)
            alpha > std::fabs(beta);
 }
 
+/*
+ * Variance-gamma sides (Section 8.2) for integer lambda = n + 1.  Then
+ * K_{n+1/2}(z) = sqrt(pi/(2z)) e^{-z} sum_{k<=n} (n+k)!/(k!(n-k)!) (2z)^{-k}
+ * (DLMF 10.49.12), so on the side's half-line the density is
+ * A e^{-r x} sum_m d_m x^m and the tail mass A e^{-r x} sum_j t_j x^j, both
+ * with positive coefficients, and Q(v) comes from the defining equation
+ * directly: Newton on the central mass int_0^x f = p (1 - e^{-r v}) (the
+ * lower incomplete gamma series, no cancellation) while r v <= ln 2, on
+ * log(1 - F) = log p - r v beyond.  No ODE is needed; the large-v form is
+ * the log one: log(1 - F(x)) = log(A t_n) - r x + n log x + log(1 + s1/x + s2/x^2 + ...),
+ * s_i = t_{n-i}/t_n, so Q = v + c0 + (n/r) log Q + (s1/Q + (s2 - s1^2/2)/Q^2)/r + O(Q^-3).
+ */
+constexpr int VG_LAMBDA_MAX = 8;
+
+struct VGSide : SideMap {
+    int n;
+    fq logA, log_p;
+    fq c[VG_LAMBDA_MAX], tp[VG_LAMBDA_MAX], dp[VG_LAMBDA_MAX];
+
+    static fq fact(int k) { return expq(lgammaq((fq)k + 1)); }
+    static fq poly(const fq* a, int deg, fq x)
+    {
+        fq r = a[deg];
+        for (int j = deg - 1; j >= 0; --j) r = r * x + a[j];
+        return r;
+    }
+    fq log_tail(fq x) const { return logA - rate * x + logq(poly(tp, n, x)); }
+    fq log_dens(fq x) const { return logA - rate * x + logq(poly(dp, n, x)); }
+
+    /* int_0^x t^m e^{-r t} dt */
+    fq lower(int m, fq x) const
+    {
+        const fq y = rate * x;
+        const fq full = fact(m) / powq(rate, m + 1);
+        if (y > m + 60) {
+            fq term = 1, sum = 1;
+            for (int j = 1; j <= m; ++j) {
+                term *= y / j;
+                sum += term;
+            }
+            return full * (1 - expq(-y) * sum);
+        }
+        fq term = expq(-y), sum = 0;
+        for (int j = 1; j <= m; ++j) term *= y / j;
+        for (int j = m + 1; j < 100000; ++j) {
+            term *= y / j;
+            sum += term;
+            if (term <= 1e-36Q * sum) break;
+        }
+        return full * sum;
+    }
+    fq central_mass(fq x) const
+    {
+        fq sum = 0;
+        for (int k = 0; k <= n; ++k) sum += c[k] * lower(n - k, x);
+        return expq(logA) * sum;
+    }
+
+    VGSide(int n_, fq alpha, fq beta) : n(n_)
+    {
+        rate = alpha - beta;
+        const fq lam = n + 1;
+        logA = lam * logq((alpha - beta) * (alpha + beta)) + logq(sqrtq(M_PIq / (2 * alpha))) -
+               (lam - 0.5Q) * logq(2 * alpha) - 0.5Q * logq(M_PIq) - lgammaq(lam);
+        for (int k = 0; k <= n; ++k)
+            c[k] = expq(lgammaq((fq)(n + k) + 1) - lgammaq((fq)k + 1) - lgammaq((fq)(n - k) + 1) - k * logq(2 * alpha));
+        for (int m = 0; m <= n; ++m) dp[m] = c[n - m];
+        for (int j = 0; j <= n; ++j) {
+            fq t = 0;
+            for (int k = 0; k <= n - j; ++k) t += c[k] * fact(n - k) / (fact(j) * powq(rate, n - k - j + 1));
+            tp[j] = t;
+        }
+        log_p = log_tail(0);
+        slope0 = expq(log_p - log_dens(0)) * rate;
+        c0 = (logA + logq(tp[n]) - log_p) / rate;
+        clog = (fq)n / rate;
+        const fq s1 = n >= 1 ? tp[n - 1] / tp[n] : 0, s2 = n >= 2 ? tp[n - 2] / tp[n] : 0;
+        c1 = s1 / rate;
+        c2 = (s2 - s1 * s1 / 2) / rate;
+    }
+
+    fq eval(fq v) const override
+    {
+        const fq a = rate * v;
+        fq x;
+        if (a <= M_LN2q) {
+            const fq target = -expq(log_p) * expm1q(-a);
+            x = slope0 * v;
+            for (int it = 0; it < 200; ++it) {
+                fq dx = (central_mass(x) - target) / expq(log_dens(x));
+                fq xn = x - dx;
+                if (!(xn > 0)) xn = x / 2;
+                if (fabsq(xn - x) <= 1e-33Q * xn) return xn;
+                x = xn;
+            }
+            return x;
+        }
+        const fq target = log_p - a;
+        x = v + c0 + (clog > 0 ? clog * logq(v) : (fq)0);
+        if (!(x > 0)) x = v;
+        for (int it = 0; it < 200; ++it) {
+            fq lt = log_tail(x);
+            fq xn = x + (lt - target) * expq(lt - log_dens(x));
+            if (!(xn > 0)) xn = x / 2;
+            if (fabsq(xn - x) <= 1e-33Q * xn) return xn;
+            x = xn;
+        }
+        return x;
+    }
+};
+
+bool check_vg_params(double lambda, double alpha, double beta)
+{
+    return std::isfinite(lambda) && std::isfinite(alpha) && std::isfinite(beta) && lambda >= 1 &&
+           lambda <= VG_LAMBDA_MAX && lambda == std::floor(lambda) && alpha > std::fabs(beta);
+}
+
 }  // namespace
 
 int build_hyperbolic_table(double alpha, double beta, double delta, HostHypTable* out, char* err, int errlen)
@@ -700,6 +837,29 @@ int build_hyperbolic_table(double alpha, double beta, double delta, HostHypTable
     std::vector<double> coef;
     if (!fit_set(rs, ls, CellSpec{HYP_DEGREE, 2e-17Q}, &H.right, &H.left, coef, err, errlen)) return -1;
     if (!fit_set(rs, ls, CellSpec{HYP_DEGREE_F32, 1e-10Q}, &H.right32, &H.left32, coef, err, errlen)) return -1;
+    out->ncoef = coef.size();
+    out->coef = (double*)malloc(out->ncoef * sizeof(double));
+    if (!out->coef) return fail(err, errlen, "out of memory");
+    memcpy(out->coef, coef.data(), out->ncoef * sizeof(double));
+    return 0;
+}
+
+int build_vg_table(double lambda, double alpha, double beta, HostHypTable* out, char* err, int errlen)
+{
+    memset(out, 0, sizeof *out);
+    if (!check_vg_params(lambda, alpha, beta))
+        return fail(err, errlen, "need integer lambda in [1, 8] and |beta| < alpha, all finite");
+    HypTableHeader& H = out->hdr;
+    H.alpha = alpha;
+    H.beta = beta;
+    H.delta = lambda;
+    const int n = (int)lambda - 1;
+    const VGSide right(n, alpha, beta), left(n, alpha, -(fq)beta);
+    H.log_p_plus = (double)right.log_p;
+    H.log_p_minus = (double)left.log_p;
+    std::vector<double> coef;
+    if (!fit_set(right, left, CellSpec{HYP_DEGREE, 2e-17Q}, &H.right, &H.left, coef, err, errlen)) return -1;
+    if (!fit_set(right, left, CellSpec{HYP_DEGREE_F32, 1e-10Q}, &H.right32, &H.left32, coef, err, errlen)) return -1;
     out->ncoef = coef.size();
     out->coef = (double*)malloc(out->ncoef * sizeof(double));
     if (!out->coef) return fail(err, errlen, "out of memory");
@@ -756,4 +916,21 @@ extern "C" int qm_debug_hyperbolic_dense(double alpha, double beta, double delta
         q[i] = (double)(x >= 0 ? Q : -Q);
     }
     return 0;
+}
+
+/* Host copy of a variance-gamma table (include/qm_debug.h). */
+extern "C" int qm_debug_vg_table(double lambda, double alpha, double beta, void* header_out, double* coef_out,
+                                 int coef_cap)
+{
+    qm::HostHypTable t;
+    char err[256];
+    if (qm::build_vg_table(lambda, alpha, beta, &t, err, sizeof err) != 0) {
+        fprintf(stderr, "qm_debug_vg_table: %s\n", err);
+        return -1;
+    }
+    int need = (int)t.ncoef;
+    if (header_out) memcpy(header_out, &t.hdr, sizeof t.hdr);
+    if (coef_out && coef_cap >= need && need > 0) memcpy(coef_out, t.coef, sizeof(double) * need);
+    qm::free_hyperbolic_table(&t);
+    return need;
 }

@@ -21,14 +21,18 @@ constexpr int HYP_MAX_OCT = 40;     /* octaves per side at most */
  * Cell j holds R = sum_k c_{j,k} d^k, d = v - centre_j, centre_j at
  * t = 2^k (1 + (i + 1/2)/HYP_SUB), highest power first, degree + 1
  * doubles per row, starting coef_offset doubles into the table's
- * coefficient block.  From v_top = v0 (2^noct - 1) on:
- * Q = v + far_c0 + (far_c1 + far_c2 / v) / v, the large-v expansion of the
- * tail condition (Section 8.1: both H and the base have constant rates far
- * out, so Q - v tends to a constant).
+ * coefficient block.  From v_top = v0 (2^noct - 1) on, the large-v
+ * expansion of the tail condition: for the hyperbolic target (Section 8.1:
+ * both H and the base have constant rates far out, so Q - v tends to a
+ * constant) Q = v + far_c0 + (far_c1 + far_c2 / v) / v; for a target whose
+ * tail carries a power of x, as variance-gamma's x^(lambda-1) (Section 8.2),
+ * Q = v + far_c0 + far_clog log Q + (far_c1 + far_c2 / Q) / Q, by three
+ * fixed-point steps from v + far_c0 + far_clog log v.
  */
 struct HypSide {
     double v0, inv_v0, v_top;
     double far_c0, far_c1, far_c2;
+    double far_clog;         /* 0: Q = v + c0 + (c1 + c2/v)/v; else the log form (qm_hyp_device.hpp) */
     double max_rel_err;      /* builder's check of the rounded coefficients */
     int32_t noct;
     int32_t ncell;           /* HYP_SUB noct */
@@ -38,14 +42,14 @@ struct HypSide {
 };
 
 struct HypTableHeader {
-    double alpha, beta, delta;
+    double alpha, beta, delta;        /* delta: lambda for a variance-gamma table */
     double log_p_plus, log_p_minus;   /* target masses on x > 0 and x < 0 */
     HypSide right;                    /* v >= 0, FP64 outputs (degree HYP_DEGREE, to 2e-17) */
     HypSide left;                     /* v < 0, as -Q(-v) of the mirrored side */
     HypSide right32, left32;          /* FP32 outputs (degree HYP_DEGREE_F32, to 1e-10) */
 };
 
-static_assert(sizeof(HypTableHeader) == 360, "the header layout is part of qm_debug.h");
+static_assert(sizeof(HypTableHeader) == 392, "the header layout is part of qm_debug.h");
 
 struct HostHypTable {
     HypTableHeader hdr;
@@ -57,5 +61,10 @@ struct HostHypTable {
    (qm_hyp_table.cpp).  Returns 0 on success. */
 int build_hyperbolic_table(double alpha, double beta, double delta, HostHypTable* out, char* err, int errlen);
 void free_hyperbolic_table(HostHypTable* t);
+
+/* The same table format for the variance-gamma target (Section 8.2) with
+   integer lambda in [1, 8] and |beta| < alpha; the header's delta field
+   holds lambda.  Returns 0 on success. */
+int build_vg_table(double lambda, double alpha, double beta, HostHypTable* out, char* err, int errlen);
 
 }  // namespace qm

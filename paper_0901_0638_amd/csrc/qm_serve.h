@@ -21,6 +21,8 @@ qm_status run_single(qm_ctx* ctx, const qm_request& r, hipStream_t s);
 qm_status get_table(qm_ctx* ctx, double nu, const DeviceTable** out);
 /* Per-(alpha, beta, delta) hyperbolic table of a context (built on first use). */
 qm_status get_hyp_table(qm_ctx* ctx, double alpha, double beta, double delta, const DeviceHypTable** out);
+/* Per-(lambda, alpha, beta) variance-gamma table (the same format). */
+qm_status get_vg_table(qm_ctx* ctx, double lambda, double alpha, double beta, const DeviceHypTable** out);
 const TTableHeader* device_table_ptr(const DeviceTable* t);
 const TTableHeader& device_table_hdr(const DeviceTable* t);
 const LaunchShape& ctx_shape(const qm_ctx* ctx);

@@ -1,0 +1,70 @@
+"""GPU parity: the exponential -> variance-gamma map (Section 8.2, integer
+lambda) against the oracle."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import qm_inputs as qi
+from tests._tol import RTOL_F32, RTOL_F64, as_f32_output, assert_close
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_0901_0638_amd as qm  # noqa: E402
+
+PARAMS = [(1, 1.0, 0.0), (2, 1.0, 0.0), (2, 1.0, 0.5), (3, 2.0, -1.0), (5, 1.0, 0.3), (8, 1.0, 0.0)]
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = qm.Context(0)
+    yield c
+    c.close()
+
+
+def run(ctx, v, p, mu=0.0, dtype=torch.float64):
+    d = torch.from_numpy(np.ascontiguousarray(v)).to(dtype).cuda()
+    x = torch.empty_like(d)
+    qm.qm_recycle_exp_to_vg(ctx, d, x, *p, mu=mu)
+    torch.cuda.synchronize()
+    return x.cpu().numpy()
+
+
+@pytest.mark.parametrize("p", PARAMS, ids=lambda p: "l%d_a%g_b%g" % p)
+def test_vg_f64_base_samples_and_far_range(ctx, p):
+    lam, a, b = p
+    lp, lm = oracle.vg_masses(*p)
+    v = qi.two_sided_exponentials(3, 4, 20001, a - b, a + b, math.exp(lm))
+    far = np.concatenate([np.geomspace(1e-300, 1e300, 300), -np.geomspace(1e-300, 1e300, 300),
+                          np.geomspace(30 / (a - b), 1e7, 100), -np.geomspace(30 / (a + b), 1e7, 100)])
+    v = np.concatenate([v, far])
+    assert_close(run(ctx, v, p), oracle.vg_map(v, *p), RTOL_F64, "vg %r" % (p,))
+
+
+@pytest.mark.parametrize("p", PARAMS[1:4], ids=lambda p: "l%d_a%g_b%g" % p)
+def test_vg_f32(ctx, p):
+    lam, a, b = p
+    lp, lm = oracle.vg_masses(*p)
+    v = qi.two_sided_exponentials(5, 4, 20003, a - b, a + b, math.exp(lm)).astype(np.float32)
+    ref = as_f32_output(oracle.vg_map(v.astype(np.float64), *p))
+    got = run(ctx, v, p, dtype=torch.float32)
+    assert_close(got, ref, RTOL_F32, "vg f32 %r" % (p,))
+
+
+def test_vg_specials_location_and_api(ctx):
+    p = (3, 1.0, 0.25)
+    got = run(ctx, np.array([0.0, np.inf, -np.inf, np.nan]), p)
+    assert got[0] == 0 and got[1] == np.inf and got[2] == -np.inf and np.isnan(got[3])
+    v = np.abs(qi.two_sided_exponentials(6, 4, 3001, 0.75, 1.25, 0.3))
+    assert_close(run(ctx, v, p, mu=-1.5), -1.5 + oracle.vg_map(v, *p), RTOL_F64, "mu")
+    lp, lm = qm.qm_vg_masses(ctx, *p)
+    olp, olm = oracle.vg_masses(*p)
+    assert abs(lp - olp) <= 1e-15 and abs(lm - olm) <= 1e-15
+    d = torch.zeros(8, dtype=torch.float64, device="cuda")
+    for bad in [(2.5, 1.0, 0.0), (9, 1.0, 0.0), (2, 1.0, 1.5)]:
+        with pytest.raises(qm.QMError):
+            qm.qm_recycle_exp_to_vg(ctx, d, d, *bad)

@@ -30,12 +30,19 @@ def table_eval(h, rr, rl, v, which="f64"):
         S, rows = (left, rl) if x < 0 else (right, rr)
         a = abs(x)
         if not a < S.v_top:
-            Q = a if not np.isfinite(a) else a + (S.far_c0 + (S.far_c1 + S.far_c2 / a) / a)
+            if not np.isfinite(a):
+                Q = a
+            elif S.far_clog == 0:
+                Q = a + (S.far_c0 + (S.far_c1 + S.far_c2 / a) / a)
+            else:
+                Q = a + S.far_c0 + S.far_clog * math.log(a)
+                for _ in range(3):
+                    Q = a + S.far_c0 + S.far_clog * math.log(Q) + (S.far_c1 + S.far_c2 / Q) / Q
         else:
             t = fma(a, S.inv_v0, 1.0)
             bits = np.float64(t).view(np.uint64)
             hi = int(bits >> np.uint64(32))
-            j = (hi >> 17) - (1023 << 3)
+            j = min((hi >> 17) - (1023 << 3), len(rows) - 1)   # the kernel's clamp (t may round up to 2^noct)
             tc = np.uint64(((hi & ~((1 << 17) - 1)) | (1 << 16)) << 32).view(np.float64)
             d = fma(-S.v0, float(tc) - 1.0, a)
             R = rows[j][0]
@@ -103,7 +110,7 @@ def test_fp32_cells_match_oracle(built):
 
 def test_header_layout(built):
     p, h, rr, rl, v, ref = built
-    assert ctypes.sizeof(qm.HypTableHeader) == 360
+    assert ctypes.sizeof(qm.HypTableHeader) == 392
     _, r32, l32 = qm.debug_hyperbolic_table(*p, which="f32")
     for S, rows, rate, deg, bound, S0 in ((h.right, rr, p[0] - p[1], qm.HYP_DEGREE, 1.2e-16, h.right),
                                          (h.left, rl, p[0] + p[1], qm.HYP_DEGREE, 1.2e-16, h.right),
