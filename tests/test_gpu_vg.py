@@ -60,7 +60,8 @@ def test_vg_specials_location_and_api(ctx):
     got = run(ctx, np.array([0.0, np.inf, -np.inf, np.nan]), p)
     assert got[0] == 0 and got[1] == np.inf and got[2] == -np.inf and np.isnan(got[3])
     v = np.abs(qi.two_sided_exponentials(6, 4, 3001, 0.75, 1.25, 0.3))
-    assert_close(run(ctx, v, p, mu=-1.5), -1.5 + oracle.vg_map(v, *p), RTOL_F64, "mu")
+    # mu > 0 with v >= 0: no cancellation in mu + Q
+    assert_close(run(ctx, v, p, mu=1.5), 1.5 + oracle.vg_map(v, *p), RTOL_F64, "mu")
     lp, lm = qm.qm_vg_masses(ctx, *p)
     olp, olm = oracle.vg_masses(*p)
     assert abs(lp - olp) <= 1e-15 and abs(lm - olm) <= 1e-15
