@@ -216,6 +216,19 @@ def run_quantile(args, torch, qm, qi):
             extra["exp_to_hyperbolic_f32"][key] = {"gsamples_s": round(m / (avg * 1e-3) / 1e9, 2),
                                                   "gbs": round(8.0 * m / (avg * 1e-3) / 1e9, 1)}
             del hv, hv32
+        # exponential -> variance-gamma, integer lambda (Section 8.2)
+        extra["exp_to_vg_f64"] = {}
+        for vp in ((2, 1.0, 0.0), (3, 2.0, -1.0)):
+            tb = time.perf_counter()
+            lp, lm = qm.qm_vg_masses(ctx, *vp)
+            tb = time.perf_counter() - tb
+            vv = torch.from_numpy(qi.two_sided_exponentials(2, 3, m, vp[1] - vp[2], vp[1] + vp[2], math.exp(lm))).cuda()
+            ds = timed_launches(torch, stream, lambda: qm.qm_recycle_exp_to_vg(ctx, vv, o, *vp), 10)
+            avg = sum(ds) / len(ds)
+            extra["exp_to_vg_f64"]["l%d_a%g_b%g" % vp] = {"gsamples_s": round(m / (avg * 1e-3) / 1e9, 2),
+                                                          "gbs": round(16.0 * m / (avg * 1e-3) / 1e9, 1),
+                                                          "table_build_s": round(tb, 3)}
+            del vv
         # fused Philox generation + quantile (write-only), vs generation alone
         g64 = torch.empty(n, dtype=torch.float64, device="cuda")
         g32 = torch.empty(n, dtype=torch.float32, device="cuda")
