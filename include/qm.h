@@ -17,9 +17,9 @@
  *                             integer lambda               (Section 8.2)
  *   qm_generate               the uniforms of a counter-based stream, or w
  *                             of them, drawn and mapped in one pass
- *   qm_generate_student_t, qm_generate_hyperbolic
- *                             Student t / hyperbolic samples drawn the same
- *                             way, through the recycling maps
+ *   qm_generate_student_t, qm_generate_hyperbolic, qm_generate_vg
+ *                             Student t / hyperbolic / variance-gamma
+ *                             samples drawn the same way, through the maps
  *   qm_run_batch              many such requests in one persistent launch
  *   qm_submit / qm_poll       continuous-batching serving loop
  *
@@ -261,6 +261,14 @@ qm_status qm_generate_student_t(qm_ctx* ctx, uint64_t seed, uint64_t stream, uin
 qm_status qm_generate_hyperbolic(qm_ctx* ctx, uint64_t seed, uint64_t stream, uint64_t first, void* d_out, uint64_t n,
                                  int dtype, int mode, double alpha, double beta, double delta, double mu,
                                  void* hip_stream);
+
+/*
+ * Fused generation of variance-gamma samples (Section 8.2, integer lambda
+ * in [1, 8]): as qm_generate_hyperbolic, with the variance-gamma target's
+ * masses (qm_vg_masses) and the map of qm_recycle_exp_to_vg.
+ */
+qm_status qm_generate_vg(qm_ctx* ctx, uint64_t seed, uint64_t stream, uint64_t first, void* d_out, uint64_t n,
+                         int dtype, int mode, double lambda, double alpha, double beta, double mu, void* hip_stream);
 
 /* One request of a batch or of the serving loop. */
 typedef struct {

@@ -119,6 +119,16 @@ def qm_generate_hyperbolic(ctx, seed, stream_id, first, out, alpha, beta, delta,
                                         float(beta), float(delta), float(mu), _stream(stream, out)))
 
 
+def qm_generate_vg(ctx, seed, stream_id, first, out, lam, alpha, beta, mu=0.0, mode=None, stream=None):
+    """Variance-gamma samples (integer lambda) of a Philox stream through the two-sided exponential base, fused."""
+    dt = _dtype_of(out)
+    if mode is None:
+        mode = QM_PLAIN if dt == QM_F64 else QM_F32_REFINE
+    check(load().qm_generate_vg(ctx.handle, int(seed), int(stream_id), int(first), ctypes.c_void_p(out.data_ptr()),
+                                out.numel(), dt, int(mode), float(lam), float(alpha), float(beta), float(mu),
+                                _stream(stream, out)))
+
+
 def qm_recycle_student_t(ctx, z, t, nu, mode=None, stream=None):
     """t = F_nu^{-1}(Phi(z)) (FP64 PLAIN or FP32 F32_REFINE)."""
     pi, po, n, dt = _io(z, t)

@@ -68,6 +68,7 @@ SIGNATURES = {
     "qm_generate": (_st, [_vp, _u64, _u64, _u64, _vp, _u64, _i, _i, _i, _vp]),
     "qm_generate_student_t": (_st, [_vp, _u64, _u64, _u64, _vp, _u64, _i, _i, _d, _vp]),
     "qm_generate_hyperbolic": (_st, [_vp, _u64, _u64, _u64, _vp, _u64, _i, _i, _d, _d, _d, _d, _vp]),
+    "qm_generate_vg": (_st, [_vp, _u64, _u64, _u64, _vp, _u64, _i, _i, _d, _d, _d, _d, _vp]),
     "qm_run_batch": (_st, [_vp, ctypes.POINTER(qm_request), _u64, _vp]),
     "qm_submit": (_st, [_vp, ctypes.POINTER(qm_request), ctypes.POINTER(_u64)]),
     "qm_poll": (_st, [_vp, _u64]),

@@ -485,6 +485,25 @@ qm_status qm_generate_hyperbolic(qm_ctx* ctx, uint64_t seed, uint64_t stream, ui
     return QM_OK;
 }
 
+qm_status qm_generate_vg(qm_ctx* ctx, uint64_t seed, uint64_t stream, uint64_t first, void* d_out, uint64_t n,
+                         int dtype, int mode, double lambda, double alpha, double beta, double mu, void* hs)
+{
+    qm_status st = check_generate(ctx, seed, stream, first, d_out, n, dtype, mode);
+    if (st != QM_OK) return st;
+    if (!vg_params_ok(lambda, alpha, beta))
+        return fail(QM_E_INVAL, "need integer lambda in [1, 8] and |beta| < alpha, all finite (got %g, %g, %g)",
+                    lambda, alpha, beta);
+    if (!std::isfinite(mu)) return fail(QM_E_INVAL, "mu must be finite");
+    const DeviceHypTable* t = nullptr;
+    st = qm::get_vg_table(ctx, lambda, alpha, beta, &t);
+    if (st != QM_OK || n == 0) return st;
+    /* the same base and table format as the hyperbolic map */
+    hipError_t e = qm::launch_generate_hyperbolic(dtype, mode, (uint32_t)seed, (uint32_t)stream, first, d_out, n,
+                                                  t->d_table, t->hdr, t->ncoef, mu, (hipStream_t)hs, ctx->shape);
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    return QM_OK;
+}
+
 const char* qm_status_string(qm_status s)
 {
     switch (s) {
