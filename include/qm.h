@@ -81,7 +81,8 @@ enum qm_dtype { QM_F32 = 0, QM_F64 = 1 };
 enum qm_mode { QM_PLAIN = 0, QM_F32_REFINE = 1, QM_PAPER = 2 };
 
 /* QM_UNIFORM (the uniforms themselves) is accepted by qm_generate only. */
-enum qm_kind { QM_NORMAL_QUANTILE = 0, QM_STUDENT_T = 1, QM_EXP_TO_NORMAL = 2, QM_UNIFORM = 3, QM_EXP_TO_HYPERBOLIC = 4 };
+enum qm_kind { QM_NORMAL_QUANTILE = 0, QM_STUDENT_T = 1, QM_EXP_TO_NORMAL = 2, QM_UNIFORM = 3, QM_EXP_TO_HYPERBOLIC = 4,
+               QM_EXP_TO_VG = 5 };
 
 typedef struct qm_ctx qm_ctx;
 
@@ -276,12 +277,13 @@ typedef struct {
     uint32_t dtype;     /* enum qm_dtype */
     uint32_t mode;      /* enum qm_mode */
     uint32_t reserved;  /* must be 0 */
-    double nu;          /* QM_STUDENT_T only */
+    double nu;          /* QM_STUDENT_T: nu; QM_EXP_TO_VG: lambda */
     const void* d_in;   /* device input, n elements of dtype */
     void* d_out;        /* device output, n elements of dtype */
     uint64_t n;
     uint64_t user_tag;  /* opaque to the library */
-    double alpha, beta, delta, mu;  /* QM_EXP_TO_HYPERBOLIC only: the target's parameters */
+    double alpha, beta, delta, mu;  /* QM_EXP_TO_HYPERBOLIC: the target's parameters;
+                                       QM_EXP_TO_VG: alpha, beta and mu (delta unused) */
 } qm_request;
 
 /*

@@ -16,7 +16,7 @@ import ctypes
 from ._lib import (  # noqa: F401
     QM_E_CLOSED, QM_E_DTYPE, QM_E_HIP, QM_E_INVAL, QM_E_NOMEM, QM_E_TICKET, QM_EXP_TO_NORMAL, QM_F32,
     QM_F32_REFINE, QM_F64, QM_NORMAL_QUANTILE, QM_OK, QM_PAPER, QM_PENDING, QM_PLAIN, QM_STUDENT_T, QM_UNIFORM, QMError,
-    QM_EXP_TO_HYPERBOLIC,
+    QM_EXP_TO_HYPERBOLIC, QM_EXP_TO_VG,
     check, load, qm_request,
 )
 

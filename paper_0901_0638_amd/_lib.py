@@ -32,6 +32,7 @@ QM_STUDENT_T = 1
 QM_EXP_TO_NORMAL = 2
 QM_UNIFORM = 3
 QM_EXP_TO_HYPERBOLIC = 4
+QM_EXP_TO_VG = 5
 
 
 class qm_request(ctypes.Structure):

@@ -80,6 +80,14 @@ qm_status check_request(const qm_request& r, int* dtype_size_out)
                         r.delta);
         if (!std::isfinite(r.mu)) return fail(QM_E_INVAL, "mu must be finite");
         break;
+    case QM_EXP_TO_VG:
+        if (!(r.dtype == QM_F64 && r.mode == QM_PLAIN) && !(r.dtype == QM_F32 && r.mode == QM_F32_REFINE))
+            return fail(QM_E_DTYPE, "exp->variance-gamma: F64 QM_PLAIN or F32 QM_F32_REFINE");
+        if (!(std::isfinite(r.nu) && r.nu >= 1 && r.nu <= 8 && r.nu == std::floor(r.nu)) ||
+            !(std::isfinite(r.alpha) && std::isfinite(r.beta) && r.alpha > std::fabs(r.beta)))
+            return fail(QM_E_INVAL, "need integer lambda (nu) in [1, 8] and |beta| < alpha, all finite");
+        if (!std::isfinite(r.mu)) return fail(QM_E_INVAL, "mu must be finite");
+        break;
     default:
         return fail(QM_E_INVAL, "unknown kind %u", r.kind);
     }
@@ -192,9 +200,10 @@ qm_status run_single(qm_ctx* ctx, const qm_request& r, hipStream_t s)
         qm_status st = get_table(ctx, r.nu, &t);
         if (st != QM_OK) return st;
         e = launch_student(r.dtype, r.mode, r.d_in, r.d_out, r.n, t->d_table, t->hdr, s, ctx->shape);
-    } else if (r.kind == QM_EXP_TO_HYPERBOLIC) {
+    } else if (r.kind == QM_EXP_TO_HYPERBOLIC || r.kind == QM_EXP_TO_VG) {
         const DeviceHypTable* t = nullptr;
-        qm_status st = get_hyp_table(ctx, r.alpha, r.beta, r.delta, &t);
+        qm_status st = r.kind == QM_EXP_TO_VG ? get_vg_table(ctx, r.nu, r.alpha, r.beta, &t)
+                                              : get_hyp_table(ctx, r.alpha, r.beta, r.delta, &t);
         if (st != QM_OK) return st;
         e = launch_hyperbolic(r.dtype, r.mode, r.d_in, r.d_out, r.n, t->d_table, t->hdr, t->ncoef, r.mu, s,
                               ctx->shape);

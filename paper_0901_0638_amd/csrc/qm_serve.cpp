@@ -151,6 +151,7 @@ static uint32_t batch_op(const qm_request& r)
         if (r.dtype == QM_F64) return r.mode == QM_PAPER ? BOP_E64_PAPER : BOP_E64_PLAIN;
         return BOP_E32_REFINE;
     case QM_EXP_TO_HYPERBOLIC:
+    case QM_EXP_TO_VG:
         return r.dtype == QM_F64 ? BOP_H64 : BOP_H32;
     default:
         return r.dtype == QM_F64 ? BOP_T64 : BOP_T32;
@@ -212,9 +213,10 @@ qm_status enqueue_batch(qm_ctx* ctx, const qm_request* reqs, uint64_t count, hip
             b.coef = table_block(t->d_table) + c.coef_offset;
             b.P = make_params(t->hdr, c, b.coef);
             if (!t->hdr.identity) lds = std::max(lds, (size_t)c.nlds * b.P.lds_stride * sizeof(double));
-        } else if (r.kind == QM_EXP_TO_HYPERBOLIC) {
+        } else if (r.kind == QM_EXP_TO_HYPERBOLIC || r.kind == QM_EXP_TO_VG) {
             const DeviceHypTable* t = nullptr;
-            qm_status st = get_hyp_table(ctx, r.alpha, r.beta, r.delta, &t);
+            qm_status st = r.kind == QM_EXP_TO_VG ? get_vg_table(ctx, r.nu, r.alpha, r.beta, &t)
+                                                  : get_hyp_table(ctx, r.alpha, r.beta, r.delta, &t);
             if (st != QM_OK) return st;
             size_t l = 0;
             if (!make_hyp_params(t->hdr, r.dtype == QM_F32, t->d_table, t->ncoef, r.mu, &b.H, &l))
@@ -454,11 +456,14 @@ qm_status qm_submit(qm_ctx* ctx, const qm_request* req, uint64_t* ticket)
     /* a table the request needs is built here, in the caller's thread, so
        that the scheduler never stalls on a build and a failed build is this
        request's error alone */
-    if (req->kind == QM_STUDENT_T || req->kind == QM_EXP_TO_HYPERBOLIC) {
+    if (req->kind == QM_STUDENT_T || req->kind == QM_EXP_TO_HYPERBOLIC || req->kind == QM_EXP_TO_VG) {
         if (hipSetDevice(ctx->device) != hipSuccess) return qm::set_error(QM_E_HIP, "hipSetDevice failed");
         if (req->kind == QM_STUDENT_T) {
             const DeviceTable* t = nullptr;
             st = qm::get_table(ctx, req->nu, &t);
+        } else if (req->kind == QM_EXP_TO_VG) {
+            const DeviceHypTable* t = nullptr;
+            st = qm::get_vg_table(ctx, req->nu, req->alpha, req->beta, &t);
         } else {
             const DeviceHypTable* t = nullptr;
             st = qm::get_hyp_table(ctx, req->alpha, req->beta, req->delta, &t);

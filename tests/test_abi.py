@@ -43,7 +43,7 @@ def test_request_layout():
     r = _lib.qm_request
     assert ctypes.sizeof(r) == 88
     assert r.user_tag.offset == 48 and r.alpha.offset == 56 and r.mu.offset == 80
-    assert qm.QM_EXP_TO_HYPERBOLIC == 4
+    assert qm.QM_EXP_TO_HYPERBOLIC == 4 and qm.QM_EXP_TO_VG == 5
 
 
 def test_status_strings():

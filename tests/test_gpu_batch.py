@@ -302,3 +302,51 @@ def test_batch_hyperbolic_validation(ctx):
             qm.qm_run_batch(ctx, [good, bad], device_tensor=d)
         with pytest.raises(qm.QMError):
             qm.qm_submit(ctx, bad)
+
+
+def test_batch_and_serving_vg(ctx):
+    """Variance-gamma requests (lambda in nu) of both dtypes beside a
+    hyperbolic one: batch and serving outputs equal the single calls bit
+    for bit."""
+    params = [(2, 1.0, 0.5), (3, 2.0, -1.0)]
+    cases, reqs = [], []
+    for i, (lam, a, b) in enumerate(params):
+        for dtype in (np.float64, np.float32):
+            x = qi.two_sided_exponentials(80 + i, 5, 5000 + 37 * i, a - b, a + b, 0.4).astype(dtype)
+            d = torch.from_numpy(x).cuda()
+            o = torch.full_like(d, float("nan"))
+            reqs.append(qm.make_request(qm.QM_EXP_TO_VG, d, o, nu=lam, hyperbolic=(a, b, 0.0), mu=0.5))
+            cases.append(((lam, a, b), d, o))
+    h = torch.from_numpy(qi.two_sided_exponentials(90, 5, 3000, 1.0, 1.0, 0.5)).cuda()
+    ho = torch.full_like(h, float("nan"))
+    reqs.append(qm.make_request(qm.QM_EXP_TO_HYPERBOLIC, h, ho, hyperbolic=(1.0, 0.0, 1.0)))
+    qm.qm_run_batch(ctx, reqs, device_tensor=h)
+    torch.cuda.synchronize()
+
+    def check():
+        for p, d, o in cases:
+            ref = torch.empty_like(d)
+            qm.qm_recycle_exp_to_vg(ctx, d, ref, *p, mu=0.5)
+            torch.cuda.synchronize()
+            assert torch.equal(o, ref), p
+        ref = torch.empty_like(h)
+        qm.qm_recycle_exp_to_hyperbolic(ctx, h, ref, 1.0, 0.0, 1.0)
+        torch.cuda.synchronize()
+        assert torch.equal(ho, ref)
+
+    check()
+    for _, _, o in cases:
+        o.fill_(float("nan"))
+    ho.fill_(float("nan"))
+    tickets = [qm.qm_submit(ctx, r) for r in reqs]
+    deadline = time.time() + 60
+    pending = set(tickets)
+    while pending and time.time() < deadline:
+        pending = {t for t in pending if qm.qm_poll(ctx, t) == qm.QM_PENDING}
+        time.sleep(0.001)
+    assert not pending
+    check()
+    d = torch.zeros(8, dtype=torch.float64, device="cuda")
+    with pytest.raises(qm.QMError):
+        qm.qm_run_batch(ctx, [qm.make_request(qm.QM_EXP_TO_VG, d, d, nu=2.5, hyperbolic=(1.0, 0.0, 0.0))],
+                        device_tensor=d)
