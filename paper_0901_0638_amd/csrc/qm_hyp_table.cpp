@@ -1,5 +1,10 @@
 /*
- * qm_hyp_table.cpp -- host builder of the exponential -> hyperbolic tables.
+ * qm_hyp_table.cpp -- host builder of the tables of the two-sided
+ * exponential base: exponential -> hyperbolic (Section 8.1, from the
+ * recycling ODE, below) and exponential -> variance-gamma with integer
+ * lambda (Section 8.2, solved directly from closed-form masses; VGSide).
+ * Both fit the same cells through one interface (SideMap), so both run in
+ * the same kernel.
  *
  * Section 8.1: the hyperbolic target (mu = 0)
  *     f(x) = C exp(-alpha sqrt(delta^2 + x^2) + beta x),
