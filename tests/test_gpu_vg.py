@@ -69,3 +69,23 @@ def test_vg_specials_location_and_api(ctx):
     for bad in [(2.5, 1.0, 0.0), (9, 1.0, 0.0), (2, 1.0, 1.5)]:
         with pytest.raises(qm.QMError):
             qm.qm_recycle_exp_to_vg(ctx, d, d, *bad)
+
+
+def test_vg_full_size_sampled(ctx):
+    """2^26 base samples of (lambda, alpha, beta) = (2, 1, 0.5) in one launch
+    (the benchmark's size); 3000 sampled outputs and the extremes against the
+    oracle, and the map's monotonicity over the whole output."""
+    p = (2, 1.0, 0.5)
+    lp, lm = oracle.vg_masses(*p)
+    n = 1 << 26
+    v = qi.two_sided_exponentials(2, 3, n, p[1] - p[2], p[1] + p[2], math.exp(lm))
+    d = torch.from_numpy(v).cuda()
+    x = torch.empty_like(d)
+    qm.qm_recycle_exp_to_vg(ctx, d, x, *p)
+    torch.cuda.synchronize()
+    got = x.cpu().numpy()
+    rng = np.random.default_rng(19)
+    idx = np.concatenate([rng.integers(0, n, 3000), [np.argmax(v), np.argmin(v), n - 1]])
+    assert_close(got[idx], oracle.vg_map(v[idx], *p), RTOL_F64, "sampled")
+    order = np.argsort(v, kind="stable")
+    assert np.all(np.diff(got[order]) >= 0)
