@@ -53,6 +53,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <thread>
 #include <vector>
 
 #include "qm_hyp_table.h"
@@ -599,19 +600,47 @@ struct CellSpec {
     fq tol;
 };
 
+/* Host threads for fitting cells: the cells are independent and each one
+   only reads the side's solution. */
+int fit_threads()
+{
+    static const int n = [] {
+        const char* e = getenv("QM_BUILD_THREADS");
+        long v = e ? strtol(e, nullptr, 10) : (long)std::thread::hardware_concurrency();
+        return (int)(v < 1 ? 1 : (v > 16 ? 16 : v));
+    }();
+    return n;
+}
+
 /* Fit cells [j0, j1) of a side for v0 into rows (deg + 1 doubles per cell,
-   cell j0 first).  Returns false, with the failing cell in *bad, if one
-   misses tol; *worst gets the largest error of the rounded rows. */
+   cell j0 first), on up to fit_threads() threads.  Returns false, with the
+   first failing cell in *bad, if one misses tol; *worst gets the largest
+   error of the rounded rows. */
 bool fit_cells(const SideMap& ss, const CellSpec& cs, fq v0, int j0, int j1, double* rows, fq* worst, int* bad)
 {
-    const int W = cs.deg + 1;
-    for (int j = j0; j < j1; ++j) {
-        fq lo, hi, r;
-        cell_bounds(v0, j, &lo, &hi);
-        fq e = fit_cell(ss, cs.deg, lo, hi, rows + (size_t)(j - j0) * W, &r);
-        if (r > *worst) *worst = r;
-        if (e > cs.tol) {
-            *bad = j;
+    const int W = cs.deg + 1, count = j1 - j0;
+    if (count <= 0) return true;
+    std::vector<fq> err(count), rerr(count);
+    auto work = [&](int first, int step) {
+        for (int i = first; i < count; i += step) {
+            fq lo, hi;
+            cell_bounds(v0, j0 + i, &lo, &hi);
+            err[i] = fit_cell(ss, cs.deg, lo, hi, rows + (size_t)i * W, &rerr[i]);
+        }
+    };
+    const int T = count < fit_threads() ? count : fit_threads();
+    if (T <= 1) {
+        work(0, 1);
+    } else {
+        std::vector<std::thread> pool;
+        for (int t = 1; t < T; ++t) pool.emplace_back(work, t, T);
+        work(0, T);
+        for (auto& th : pool) th.join();
+    }
+    for (int i = 0; i < count; ++i) {
+        if (rerr[i] > *worst) *worst = rerr[i];
+        if (err[i] > cs.tol) {
+            *bad = j0 + i;
             return false;
         }
     }
