@@ -40,6 +40,12 @@ qm_status hip_fail(hipError_t e, const char* what)
 
 size_t dtype_size(int dtype) { return dtype == QM_F64 ? 8 : 4; }
 
+static bool vg_params_ok(double lambda, double alpha, double beta)
+{
+    return std::isfinite(lambda) && std::isfinite(alpha) && std::isfinite(beta) && lambda >= 1 && lambda <= 8 &&
+           lambda == std::floor(lambda) && alpha > std::fabs(beta);
+}
+
 bool hyp_params_ok(double alpha, double beta, double delta)
 {
     return std::isfinite(alpha) && std::isfinite(beta) && std::isfinite(delta) && delta > 0 && alpha > std::fabs(beta);
@@ -83,9 +89,9 @@ qm_status check_request(const qm_request& r, int* dtype_size_out)
     case QM_EXP_TO_VG:
         if (!(r.dtype == QM_F64 && r.mode == QM_PLAIN) && !(r.dtype == QM_F32 && r.mode == QM_F32_REFINE))
             return fail(QM_E_DTYPE, "exp->variance-gamma: F64 QM_PLAIN or F32 QM_F32_REFINE");
-        if (!(std::isfinite(r.nu) && r.nu >= 1 && r.nu <= 8 && r.nu == std::floor(r.nu)) ||
-            !(std::isfinite(r.alpha) && std::isfinite(r.beta) && r.alpha > std::fabs(r.beta)))
-            return fail(QM_E_INVAL, "need integer lambda (nu) in [1, 8] and |beta| < alpha, all finite");
+        if (!vg_params_ok(r.nu, r.alpha, r.beta))
+            return fail(QM_E_INVAL, "need integer lambda in [1, 8] and |beta| < alpha, all finite (got %g, %g, %g)",
+                        r.nu, r.alpha, r.beta);
         if (!std::isfinite(r.mu)) return fail(QM_E_INVAL, "mu must be finite");
         break;
     default:
@@ -349,41 +355,32 @@ qm_status qm_recycle_exp_to_hyperbolic(qm_ctx* ctx, const void* d_v, void* d_x, 
     return qm::run_single(ctx, r, (hipStream_t)s);
 }
 
-static bool vg_params_ok(double lambda, double alpha, double beta)
-{
-    return std::isfinite(lambda) && std::isfinite(alpha) && std::isfinite(beta) && lambda >= 1 && lambda <= 8 &&
-           lambda == std::floor(lambda) && alpha > std::fabs(beta);
-}
-
 qm_status qm_recycle_exp_to_vg(qm_ctx* ctx, const void* d_v, void* d_x, uint64_t n, int dtype, int mode, double lambda,
                                double alpha, double beta, double mu, void* s)
 {
     if (!ctx) return fail(QM_E_INVAL, "context is NULL");
     if (dtype != QM_F32 && dtype != QM_F64) return fail(QM_E_INVAL, "unknown dtype %d", dtype);
     if (mode != QM_PLAIN && mode != QM_F32_REFINE && mode != QM_PAPER) return fail(QM_E_INVAL, "unknown mode %d", mode);
-    if (!(dtype == QM_F64 && mode == QM_PLAIN) && !(dtype == QM_F32 && mode == QM_F32_REFINE))
-        return fail(QM_E_DTYPE, "exp->variance-gamma: F64 QM_PLAIN or F32 QM_F32_REFINE");
-    if (!vg_params_ok(lambda, alpha, beta))
-        return fail(QM_E_INVAL, "need integer lambda in [1, 8] and |beta| < alpha, all finite (got %g, %g, %g)",
-                    lambda, alpha, beta);
-    if (!std::isfinite(mu)) return fail(QM_E_INVAL, "mu must be finite");
-    const size_t es = dtype_size(dtype);
-    if (n > 0) {
-        if (!d_v || !d_x) return fail(QM_E_INVAL, "NULL buffer with n > 0");
-        uintptr_t a = (uintptr_t)d_v, b = (uintptr_t)d_x;
-        if (a % es || b % es) return fail(QM_E_INVAL, "buffers must be aligned to the element size");
-        if (n > (UINT64_MAX / 2) / es) return fail(QM_E_INVAL, "n too large");
-        uint64_t bytes = n * es;
-        if (a != b && a < b + bytes && b < a + bytes) return fail(QM_E_INVAL, "input and output partially overlap");
-    }
+    qm_request r{};
+    r.kind = QM_EXP_TO_VG;
+    r.dtype = (uint32_t)dtype;
+    r.mode = (uint32_t)mode;
+    r.nu = lambda;
+    r.d_in = d_v;
+    r.d_out = d_x;
+    r.n = n;
+    r.alpha = alpha;
+    r.beta = beta;
+    r.mu = mu;
+    qm_status st = qm::check_request(r, nullptr);
+    if (st != QM_OK) return st;
     hipError_t e = hipSetDevice(ctx->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    /* the table is built (and cached) even for n = 0 */
     const DeviceHypTable* t = nullptr;
-    qm_status st = qm::get_vg_table(ctx, lambda, alpha, beta, &t);
-    if (st != QM_OK || n == 0) return st;
-    e = qm::launch_hyperbolic(dtype, mode, d_v, d_x, n, t->d_table, t->hdr, t->ncoef, mu, (hipStream_t)s, ctx->shape);
-    if (e != hipSuccess) return hip_fail(e, "kernel launch");
-    return QM_OK;
+    st = qm::get_vg_table(ctx, lambda, alpha, beta, &t);
+    if (st != QM_OK) return st;
+    return qm::run_single(ctx, r, (hipStream_t)s);
 }
 
 qm_status qm_vg_masses(qm_ctx* ctx, double lambda, double alpha, double beta, double* log_p_plus, double* log_p_minus)
