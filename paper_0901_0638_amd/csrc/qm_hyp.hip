@@ -12,7 +12,10 @@
  * both sides in LDS, then streams 16-byte vectors; a lane evaluates all its
  * elements' polynomials (independent chains) before one wave vote admits
  * the rare far elements: the side's further cells from global memory, and
- * from v_top on the large-v form a + c0 + c1/a + c2/a^2.
+ * from v_top on the large-v form a + c0 + c1/a + c2/a^2 (for variance-gamma
+ * targets, whose tail carries a power x^(lambda-1), the form with a log Q
+ * term, solved by three fixed-point steps).  The same kernel serves the
+ * hyperbolic (Section 8.1) and variance-gamma (Section 8.2) tables.
  */
 #include <hip/hip_runtime.h>
 #include <stdint.h>
