@@ -147,3 +147,12 @@ def test_hyperbolic_errors(ctx):
         qm.qm_recycle_exp_to_hyperbolic(ctx, d, d, 1.0, 0.0, 1.0, mu=float("inf"))
     with pytest.raises(qm.QMError):
         qm.qm_recycle_exp_to_hyperbolic(ctx, d, d, 1.0, 0.0, 1.0, mode=qm.QM_PAPER)
+    with pytest.raises(qm.QMError):
+        qm.qm_recycle_exp_to_hyperbolic(ctx, d, d, 1.0, 0.0, 1.0, mode=qm.QM_F32_REFINE)
+    f = torch.zeros(16, dtype=torch.float32, device="cuda")
+    with pytest.raises(qm.QMError):
+        qm.qm_recycle_exp_to_hyperbolic(ctx, f, f, 1.0, 0.0, 1.0, mode=qm.QM_PLAIN)
+    buf = torch.zeros(17, dtype=torch.float64, device="cuda")
+    with pytest.raises(qm.QMError):   # input and output partially overlap
+        qm.qm_recycle_exp_to_hyperbolic(ctx, buf[:16], buf[1:], 1.0, 0.0, 1.0)
+    torch.cuda.synchronize()

@@ -89,3 +89,37 @@ def test_vg_full_size_sampled(ctx):
     assert_close(got[idx], oracle.vg_map(v[idx], *p), RTOL_F64, "sampled")
     order = np.argsort(v, kind="stable")
     assert np.all(np.diff(got[order]) >= 0)
+
+
+def test_vg_ragged_misaligned_inplace_and_request_checks(ctx):
+    """Sizes around the vector width and a workgroup's tile, an input one
+    element off 16-byte alignment, in-place use, n = 0; and the request
+    checks the entry point shares with batches (dtype/mode pairs, mu, partial
+    overlap)."""
+    p = (3, 2.0, -1.0)
+    lp, lm = oracle.vg_masses(*p)
+    for n in (1, 2, 3, 7, 255, 257, 1025):
+        v = qi.two_sided_exponentials(8, n, n, 3.0, 1.0, math.exp(lm))
+        assert_close(run(ctx, v, p), oracle.vg_map(v, *p), RTOL_F64, "n=%d" % n)
+    v = qi.two_sided_exponentials(9, 1, 3001, 3.0, 1.0, math.exp(lm))
+    ref = oracle.vg_map(v, *p)
+    base = torch.from_numpy(np.concatenate([[0.0], v])).cuda()
+    out = torch.empty(3001, dtype=torch.float64, device="cuda")
+    qm.qm_recycle_exp_to_vg(ctx, base[1:], out, *p)
+    d = torch.from_numpy(v).cuda()
+    qm.qm_recycle_exp_to_vg(ctx, d, d, *p)
+    torch.cuda.synchronize()
+    assert_close(out.cpu().numpy(), ref, RTOL_F64, "misaligned")
+    assert_close(d.cpu().numpy(), ref, RTOL_F64, "in place")
+    z = torch.empty(0, dtype=torch.float64, device="cuda")
+    qm.qm_recycle_exp_to_vg(ctx, z, z, *p)
+    f = torch.zeros(16, dtype=torch.float32, device="cuda")
+    buf = torch.zeros(17, dtype=torch.float64, device="cuda")
+    for call in (lambda: qm.qm_recycle_exp_to_vg(ctx, d, d, *p, mode=qm.QM_F32_REFINE),
+                 lambda: qm.qm_recycle_exp_to_vg(ctx, d, d, *p, mode=qm.QM_PAPER),
+                 lambda: qm.qm_recycle_exp_to_vg(ctx, f, f, *p, mode=qm.QM_PLAIN),
+                 lambda: qm.qm_recycle_exp_to_vg(ctx, d, d, *p, mu=float("inf")),
+                 lambda: qm.qm_recycle_exp_to_vg(ctx, buf[:16], buf[1:], *p)):
+        with pytest.raises(qm.QMError):
+            call()
+    torch.cuda.synchronize()
