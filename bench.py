@@ -165,6 +165,13 @@ def run_quantile(args, torch, qm, qi):
                                "outer elements gathered per wave; 64 workgroups/CU x 4 vectors)",
                      "algorithmic_bytes_per_launch": bytes64, "avg_launch_ms": round(avg64, 4)},
     }
+    if not args.no_extra:
+        # context for the roofline: a plain device copy of the same bytes
+        # (2^28 doubles read and written), timed the same way, outside the
+        # timed region
+        ds = timed_launches(torch, stream, lambda: w64.copy_(u64), 10)
+        avg = sum(ds) / len(ds)
+        result["roofline"]["device_copy_same_bytes_gbs"] = round(bytes64 / (avg * 1e-3) / 1e9, 1)
     del u64, u32, w64, w32
     torch.cuda.empty_cache()
 
