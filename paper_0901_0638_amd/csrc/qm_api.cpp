@@ -252,7 +252,10 @@ qm_status qm_init(int hip_device, uint64_t hbm_budget_bytes, qm_ctx** out)
         {&c->shape.hybrid[1], "QM_SHAPE_NQ64", 64, 4}, /* FP64 quantile */
         {&c->shape.student[0], "QM_SHAPE_T32", 3, 4},  /* Student t, FP32 outputs */
         {&c->shape.student[1], "QM_SHAPE_T64", 2, 4},  /* Student t, FP64 outputs */
-        {&c->shape.hyperbolic[0], "QM_SHAPE_H32", 8, 2}, /* exp -> hyperbolic, FP32 */
+        /* exp -> hyperbolic, FP32: 76 VGPRs allow 6 waves per SIMD, so 6
+           workgroups of 4 waves per CU are all resident at once (8 left a
+           partial second pass, 4-5% slower) */
+        {&c->shape.hyperbolic[0], "QM_SHAPE_H32", 6, 2},
         {&c->shape.hyperbolic[1], "QM_SHAPE_H64", 8, 4}, /* exp -> hyperbolic, FP64 */
     };
     long env_bpc = 0, env_unroll = 0;
