@@ -516,6 +516,10 @@ def run_hyperbolic(args, torch, qm, qi):
                      "kernel": "qm::k_hyperbolic<double, true, 4, 11> (8 workgroups/CU x 4 vectors)",
                      "algorithmic_bytes_per_launch": 16.0 * n, "avg_launch_ms": round(avg64, 4)},
     }
+    # context for the roofline: a plain device copy of the same bytes, timed
+    # the same way, outside the timed region
+    ds = timed_launches(torch, stream, lambda: x64.copy_(v64), 10)
+    result["roofline"]["device_copy_same_bytes_gbs"] = round(16.0 * n / (sum(ds) / len(ds) * 1e-3) / 1e9, 1)
     del v32, x32, x64
     if not args.no_cpu:
         import oracle
