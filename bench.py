@@ -556,8 +556,8 @@ def main():
                     help="arrival rates in requests/s; 0 = burst (all requests at once)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: the hot path is elementwise and shards without "
-              "communication, so --gpus %d is not run (see DESIGN.md)." % args.gpus, file=sys.stderr)
+        print("bench.py measures one GPU only: the maps are elementwise and shard into contiguous ranges "
+              "without communication, so --gpus %d is not run." % args.gpus, file=sys.stderr)
         return 2
 
     import torch
