@@ -50,11 +50,10 @@ def kernel_source_hash(files=QUANTILE_SOURCES):
     return h.hexdigest()[:16]
 
 
-def counted_traffic(profile="quantile_mixture_2e28_hbm_counters.md", kernel="k_hybrid<double>",
-                    files=QUANTILE_SOURCES):
-    """HBM bytes per launch of a kernel from its committed rocprofv3
-    FETCH_SIZE/WRITE_SIZE summary, or None if the kernel sources changed
-    since those counters were taken."""
+def profile_figure(profile, key, files=QUANTILE_SOURCES):
+    """A figure ("<key>: <number>") from a committed rocprofv3 summary under
+    profiles/, or None if the kernel sources changed since it was taken (the
+    summary records their hash) or the figure is absent."""
     import re
     path = os.path.join(ROOT, "profiles", profile)
     try:
@@ -62,10 +61,63 @@ def counted_traffic(profile="quantile_mixture_2e28_hbm_counters.md", kernel="k_h
     except OSError:
         return None
     m = re.search(r"Kernel source hash: `([0-9a-f]+)`", text)
-    t = re.search(r"traffic_bytes_per_launch %s: ([0-9]+)" % re.escape(kernel), text)
+    t = re.search(r"^%s: ([0-9.]+)" % re.escape(key), text, flags=re.M)
     if not m or not t or m.group(1) != kernel_source_hash(files):
         return None
-    return int(t.group(1))
+    v = float(t.group(1))
+    return int(v) if v == int(v) else v
+
+
+def counted_traffic(profile="quantile_mixture_2e28_hbm_counters.md", kernel="k_hybrid<double>",
+                    files=QUANTILE_SOURCES):
+    """HBM bytes per launch of a kernel from its committed rocprofv3
+    FETCH_SIZE/WRITE_SIZE summary, or None if the kernel sources changed
+    since those counters were taken."""
+    v = profile_figure(profile, "traffic_bytes_per_launch %s" % kernel, files)
+    return None if v is None else int(v)
+
+
+def profiler_avg_ms(profile, kernel, files=QUANTILE_SOURCES):
+    """The profiler's average duration of a kernel (ms) from a committed
+    kernel-trace summary, or None if the sources changed since."""
+    us = profile_figure(profile, "profiler_avg_us %s" % kernel, files)
+    return None if us is None else round(us / 1e3, 4)
+
+
+# VALU issue peak of MI355X: 256 CUs x 4 SIMDs, one wave64 instruction per
+# SIMD every 4 cycles (16 lanes per cycle; FP64 FMA is full rate), 2.4 GHz
+VALU_PEAK_WAVE_INSTS_S = 256 * 4 * 2.4e9 / 4
+
+
+def valu_fraction(profile, kernel, avg_ms, files=QUANTILE_SOURCES):
+    """Wave-level VALU instructions per launch (SQ_INSTS_VALU, committed
+    counters) over the launch's measured duration, as a fraction of the
+    issue peak; None without current counters."""
+    insts = profile_figure(profile, "valu_insts_per_launch %s" % kernel, files)
+    if insts is None or not avg_ms:
+        return None
+    return {"insts_per_launch": int(insts), "frac": round(insts / (avg_ms * 1e-3) / VALU_PEAK_WAVE_INSTS_S, 4),
+            "peak_wave_insts_per_s": VALU_PEAK_WAVE_INSTS_S}
+
+
+def error_report(got, ref, rtol):
+    """Measured error of outputs against oracle values (FP64): the largest
+    relative error where |ref| >= 1e-3, the largest absolute error below,
+    and the count outside the tolerance rtol * max(|ref|, 1e-3) (equal
+    infinities and NaN = NaN pass)."""
+    import numpy as np
+    got = np.asarray(got, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    fin = np.isfinite(ref) & np.isfinite(got)
+    err = np.abs(np.where(fin, got, 0.0) - np.where(fin, ref, 0.0))
+    big = fin & (np.abs(ref) >= 1e-3)
+    small = fin & (np.abs(ref) < 1e-3)
+    special_ok = (~np.isfinite(ref)) & ((got == ref) | (np.isnan(got) & np.isnan(ref)))
+    ok = special_ok | (fin & (err <= rtol * np.maximum(np.abs(ref), 1e-3)))
+    return {"checked": int(ref.size),
+            "max_rel_err": float(np.max(err[big] / np.abs(ref[big]))) if big.any() else 0.0,
+            "max_abs_err_near_0": float(np.max(err[small])) if small.any() else 0.0,
+            "specials_matched": int(special_ok.sum()), "outside_tolerance": int((~ok).sum()), "tolerance": rtol}
 
 
 def percentile(xs, p):
@@ -91,11 +143,45 @@ def timed_launches(torch, stream, fn, reps):
 
 
 # ---------------------------------------------------------------------------
+def per_launch(torch, stream, fns, reps):
+    """Per-launch durations (ms) of several calls interleaved as in a step,
+    reps rounds, HIP events on the launch stream around each call."""
+    ev = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in fns]
+          for _ in range(reps)]
+    torch.cuda.synchronize()
+    for row in ev:
+        for (a, b), fn in zip(row, fns):
+            a.record(stream)
+            fn()
+            b.record(stream)
+    torch.cuda.synchronize()
+    return [[row[j][0].elapsed_time(row[j][1]) for row in ev] for j in range(len(fns))]
+
+
+def sample_indices(n, u=None, seed=7):
+    """A stratified sample of output indices for the accuracy check: 2^18
+    random ones, the last 300, and (given the inputs) every outer element
+    |u - 1/2| > 0.45 among the first 2^22."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    parts = [rng.integers(0, n, 1 << 18), np.arange(max(0, n - 300), n)]
+    if u is not None:
+        head = np.asarray(u[: 1 << 22], dtype=np.float64)
+        parts.append(np.flatnonzero(np.abs(head - 0.5) > 0.45))
+    return np.unique(np.concatenate(parts))
+
+
+def gather(torch, t, idx):
+    return t[torch.from_numpy(idx).to(t.device)].cpu().numpy()
+
+
 def run_quantile(args, torch, qm, qi):
     n = args.n
     t0 = time.time()
-    u64 = torch.from_numpy(qi.mixture_f64(n)).cuda()
-    u32 = torch.from_numpy(qi.mixture_f32(n)).cuda()
+    h64 = qi.mixture_f64(n)
+    h32 = qi.mixture_f32(n)
+    u64 = torch.from_numpy(h64).cuda()
+    u32 = torch.from_numpy(h32).cuda()
     w64 = torch.empty_like(u64)
     w32 = torch.empty_like(u32)
     torch.cuda.synchronize()
@@ -103,14 +189,16 @@ def run_quantile(args, torch, qm, qi):
 
     ctx = qm.Context(0)
     stream = torch.cuda.current_stream()
+    f64 = lambda: qm.qm_normal_quantile(ctx, u64, w64, qm.QM_PLAIN)          # noqa: E731
+    f32 = lambda: qm.qm_normal_quantile(ctx, u32, w32, qm.QM_F32_REFINE)     # noqa: E731
 
     def step(ev=None):
         if ev is not None:
             ev[0].record(stream)
-        qm.qm_normal_quantile(ctx, u64, w64, qm.QM_PLAIN)
+        f64()
         if ev is not None:
             ev[1].record(stream)
-        qm.qm_normal_quantile(ctx, u32, w32, qm.QM_F32_REFINE)
+        f32()
         if ev is not None:
             ev[2].record(stream)
 
@@ -135,8 +223,14 @@ def run_quantile(args, torch, qm, qi):
     d32 = [e[1].elapsed_time(e[2]) for e in events]
     avg64 = sum(d64) / len(d64)
     avg32 = sum(d32) / len(d32)
+    # latency percentiles over more launches than the timed steps, outside
+    # the timed region (same interleaving)
+    p64, p32 = per_launch(torch, stream, [f64, f32], args.pct_reps) if args.pct_reps > 0 else (d64, d32)
     bytes64 = 16.0 * n
     achieved = bytes64 / (avg64 * 1e-3) / 1e9
+    prof_stats = "quantile_mixture_2e28_kernel_stats.md"
+    prof_counters = "quantile_mixture_2e28_hbm_counters.md"
+    full = n == (1 << 28)
     result = {
         "metric": METRIC,
         "value": round(2.0 * n * args.steps / wall / 1e9, 3),
@@ -153,17 +247,22 @@ def run_quantile(args, torch, qm, qi):
         "config": {"workload": "gaussian-quantile 2^28 mixture (90% uniform, 10% log-uniform tail to 1e-300 "
                                "FP64 / 1e-37 FP32, mirrored p=1/2), seed 1; FP64 plain + FP32+FP64-refine",
                    "n_per_pass": n, "passes_per_step": 2},
-        "fp64": {"gsamples_s": round(n / (avg64 * 1e-3) / 1e9, 2), "p50_ms": percentile(d64, 50),
-                 "p99_ms": percentile(d64, 99), "max_rel_err_bound": 2e-15},
-        "fp32_refine": {"gsamples_s": round(n / (avg32 * 1e-3) / 1e9, 2), "p50_ms": percentile(d32, 50),
-                        "p99_ms": percentile(d32, 99), "gbs": round(8.0 * n / (avg32 * 1e-3) / 1e9, 1),
-                        "max_rel_err_bound": 2e-7},
+        "fp64": {"gsamples_s": round(n / (avg64 * 1e-3) / 1e9, 2), "avg_ms": round(avg64, 4),
+                 "p50_ms": percentile(p64, 50), "p99_ms": percentile(p64, 99), "percentile_launches": len(p64),
+                 "tolerance": 2e-15},
+        "fp32_refine": {"gsamples_s": round(n / (avg32 * 1e-3) / 1e9, 2), "avg_ms": round(avg32, 4),
+                        "p50_ms": percentile(p32, 50), "p99_ms": percentile(p32, 99),
+                        "percentile_launches": len(p32), "gbs": round(8.0 * n / (avg32 * 1e-3) / 1e9, 1),
+                        "tolerance": 2e-7},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": counted_traffic() if n == (1 << 28) else None,
+                     "traffic": counted_traffic(prof_counters) if full else None,
                      "kernel": "qm::k_hybrid<double, 4, qm::HybridNQ64> (FP64 quantile: central piece, "
-                               "outer elements gathered per wave; 64 workgroups/CU x 4 vectors)",
-                     "algorithmic_bytes_per_launch": bytes64, "avg_launch_ms": round(avg64, 4)},
+                               "outer elements gathered per wave)",
+                     "algorithmic_bytes_per_launch": bytes64, "avg_launch_ms": round(avg64, 4),
+                     "profiler_avg_launch_ms": profiler_avg_ms(prof_stats, "k_hybrid<double>") if full else None},
+        "valu": {"k_hybrid<double>": valu_fraction(prof_counters, "k_hybrid<double>", avg64) if full else None,
+                 "k_hybrid<float>": valu_fraction(prof_counters, "k_hybrid<float>", avg32) if full else None},
     }
     if not args.no_extra:
         # context for the roofline: a plain device copy of the same bytes
@@ -172,113 +271,176 @@ def run_quantile(args, torch, qm, qi):
         ds = timed_launches(torch, stream, lambda: w64.copy_(u64), 10)
         avg = sum(ds) / len(ds)
         result["roofline"]["device_copy_same_bytes_gbs"] = round(bytes64 / (avg * 1e-3) / 1e9, 1)
+        # restore the FP64 outputs the copy overwrote (kept for the accuracy check)
+        f64()
+    # outputs kept on the host for the accuracy check against the oracle
+    acc = {}
+    if not args.no_cpu:
+        torch.cuda.synchronize()
+        mm = min(args.cpu_sample, n)
+        acc["fp64"] = (h64[:mm], w64[:mm].cpu().numpy(), "norm_quantile", 2e-15)
+        idx = sample_indices(n, h32)
+        acc["fp32_refine"] = (h32[idx], gather(torch, w32, idx), "norm_quantile", 2e-7)
     del u64, u32, w64, w32
     torch.cuda.empty_cache()
 
     if not args.no_extra:
-        # secondary maps, outside the timed region (normals / Exp(1), seed 2)
-        m = 1 << 26
-        z = torch.from_numpy(qi.recycle_normals(m)).cuda()
-        x = torch.from_numpy(qi.recycle_exponentials(m)).cuda()
-        o = torch.empty_like(z)
-        extra = {"student_t_f64": {}, "n": m}
-        for nu in T_NUS:
-            qm.qm_recycle_student_t(ctx, z, o, nu)  # builds and caches the table
-            ds = timed_launches(torch, stream, lambda nu=nu: qm.qm_recycle_student_t(ctx, z, o, nu), 10)
-            avg = sum(ds) / len(ds)
-            extra["student_t_f64"][str(nu)] = {"gsamples_s": round(m / (avg * 1e-3) / 1e9, 2),
-                                               "gbs": round(16.0 * m / (avg * 1e-3) / 1e9, 1),
-                                               "p50_ms": percentile(ds, 50), "p99_ms": percentile(ds, 99)}
-        ds = timed_launches(torch, stream, lambda: qm.qm_recycle_exp_to_normal(ctx, x, o), 10)
-        avg = sum(ds) / len(ds)
-        extra["exp_to_normal_f64"] = {"gsamples_s": round(m / (avg * 1e-3) / 1e9, 2),
-                                      "gbs": round(16.0 * m / (avg * 1e-3) / 1e9, 1),
-                                      "p50_ms": percentile(ds, 50), "p99_ms": percentile(ds, 99)}
-        z32 = z.float()
-        o32 = torch.empty_like(z32)
-        extra["student_t_f32_refine"] = {}
-        for nu in (1.0, 4.0, 30.0):
-            ds = timed_launches(torch, stream, lambda nu=nu: qm.qm_recycle_student_t(ctx, z32, o32, nu), 10)
-            avg = sum(ds) / len(ds)
-            extra["student_t_f32_refine"][str(nu)] = {"gsamples_s": round(m / (avg * 1e-3) / 1e9, 2),
-                                                      "gbs": round(8.0 * m / (avg * 1e-3) / 1e9, 1)}
-        # exponential -> hyperbolic (Section 8.1), base samples with the target's masses
-        extra["exp_to_hyperbolic_f64"] = {}
-        extra["exp_to_hyperbolic_f32"] = {}
-        for hp in (qi.HYPERBOLIC_PARAMS, (1.0, 0.5, 1.0)):
-            tb = time.perf_counter()
-            lp, lm = qm.qm_hyperbolic_masses(ctx, *hp)   # builds and caches the table
-            tb = time.perf_counter() - tb
-            hv = torch.from_numpy(qi.recycle_two_sided(m, hp[0], hp[1], math.exp(lm))).cuda()
-            ds = timed_launches(torch, stream, lambda: qm.qm_recycle_exp_to_hyperbolic(ctx, hv, o, *hp), 10)
-            avg = sum(ds) / len(ds)
-            key = "a%g_b%g_d%g" % hp
-            extra["exp_to_hyperbolic_f64"][key] = {"gsamples_s": round(m / (avg * 1e-3) / 1e9, 2),
-                                                  "gbs": round(16.0 * m / (avg * 1e-3) / 1e9, 1),
-                                                  "p50_ms": percentile(ds, 50), "p99_ms": percentile(ds, 99),
-                                                  "table_build_s": round(tb, 3)}
-            hv32 = hv.float()
-            ds = timed_launches(torch, stream, lambda: qm.qm_recycle_exp_to_hyperbolic(ctx, hv32, o32, *hp), 10)
-            avg = sum(ds) / len(ds)
-            extra["exp_to_hyperbolic_f32"][key] = {"gsamples_s": round(m / (avg * 1e-3) / 1e9, 2),
-                                                  "gbs": round(8.0 * m / (avg * 1e-3) / 1e9, 1)}
-            del hv, hv32
-        # exponential -> variance-gamma, integer lambda (Section 8.2)
-        extra["exp_to_vg_f64"] = {}
-        for vp in ((2, 1.0, 0.0), (3, 2.0, -1.0)):
-            tb = time.perf_counter()
-            lp, lm = qm.qm_vg_masses(ctx, *vp)
-            tb = time.perf_counter() - tb
-            vv = torch.from_numpy(qi.two_sided_exponentials(2, 3, m, vp[1] - vp[2], vp[1] + vp[2], math.exp(lm))).cuda()
-            ds = timed_launches(torch, stream, lambda: qm.qm_recycle_exp_to_vg(ctx, vv, o, *vp), 10)
-            avg = sum(ds) / len(ds)
-            extra["exp_to_vg_f64"]["l%d_a%g_b%g" % vp] = {"gsamples_s": round(m / (avg * 1e-3) / 1e9, 2),
-                                                          "gbs": round(16.0 * m / (avg * 1e-3) / 1e9, 1),
-                                                          "table_build_s": round(tb, 3)}
-            del vv
-        # fused Philox generation + quantile (write-only), vs generation alone
-        g64 = torch.empty(n, dtype=torch.float64, device="cuda")
-        g32 = torch.empty(n, dtype=torch.float32, device="cuda")
-        fused = {"n": n}
-        for name, buf, kind in (("uniform_f64", g64, qm.QM_UNIFORM), ("quantile_f64", g64, qm.QM_NORMAL_QUANTILE),
-                                ("uniform_f32", g32, qm.QM_UNIFORM),
-                                ("quantile_f32_refine", g32, qm.QM_NORMAL_QUANTILE)):
-            ds = timed_launches(torch, stream, lambda buf=buf, kind=kind: qm.qm_generate(ctx, 1, 0, 0, buf, kind), 10)
-            avg = sum(ds) / len(ds)
-            fused[name] = {"gsamples_s": round(n / (avg * 1e-3) / 1e9, 2),
-                           "gbs": round(buf.element_size() * n / (avg * 1e-3) / 1e9, 1),
-                           "p50_ms": percentile(ds, 50), "p99_ms": percentile(ds, 99)}
-        # fused chains: Philox -> normal -> Student t (nu = 4), Philox -> base -> hyperbolic (1, 0, 1)
-        for name, buf, fn in (
-                ("student_t_f64_nu4", g64, lambda: qm.qm_generate_student_t(ctx, 1, 0, 0, g64, 4.0)),
-                ("student_t_f32_nu4", g32, lambda: qm.qm_generate_student_t(ctx, 1, 0, 0, g32, 4.0)),
-                ("hyperbolic_f64", g64, lambda: qm.qm_generate_hyperbolic(ctx, 1, 0, 0, g64, *qi.HYPERBOLIC_PARAMS)),
-                ("hyperbolic_f32", g32, lambda: qm.qm_generate_hyperbolic(ctx, 1, 0, 0, g32, *qi.HYPERBOLIC_PARAMS))):
-            ds = timed_launches(torch, stream, fn, 10)
-            avg = sum(ds) / len(ds)
-            fused[name] = {"gsamples_s": round(n / (avg * 1e-3) / 1e9, 2),
-                           "gbs": round(buf.element_size() * n / (avg * 1e-3) / 1e9, 1),
-                           "p50_ms": percentile(ds, 50), "p99_ms": percentile(ds, 99)}
-        extra["generate_fused"] = fused
-        del g64, g32
-        result["extra"] = extra
-        del z, x, o, z32, o32
-        torch.cuda.empty_cache()
+        result["extra"] = secondary_maps(args, torch, qm, qi, ctx, stream, n, acc)
+        if args.serve_extra:
+            result["extra"]["serving"] = serve_rates(torch, qm, args.serve_extra_count, args.serve_extra_rates)
 
     if not args.no_cpu:
-        import oracle
-        mm = args.cpu_sample
-        us = qi.mixture_f64(mm)
-        threads = oracle.threads_used(0)
-        c0 = time.perf_counter()
-        oracle.norm_quantile(us, threads)
-        cdt = time.perf_counter() - c0
-        result["cpu_baseline"] = {"value": round(mm / cdt / 1e9, 6), "unit": "Gsamples/s", "cores": threads,
-                                  "kind": "oracle",
-                                  "sample": "first %d elements of the FP64 mixture workload, FP64 quantile, "
-                                            "%.1f s wall on %d threads (%s)" % (mm, cdt, threads, cpu_model())}
+        result["cpu_baseline"], errors = oracle_leg(args, acc, h64)
+        result["fp64"].update(errors.pop("fp64"))
+        result["fp32_refine"].update(errors.pop("fp32_refine"))
+        if "extra" in result:
+            result["extra"]["measured_error"] = errors
     ctx.close()
     return result
+
+
+def secondary_maps(args, torch, qm, qi, ctx, stream, n, acc):
+    """Rates of the other maps, outside the timed region, and their outputs
+    at sampled indices for the accuracy check."""
+    import numpy as np
+    m = 1 << 26
+    zh = qi.recycle_normals(m)
+    xh = qi.recycle_exponentials(m)
+    z = torch.from_numpy(zh).cuda()
+    x = torch.from_numpy(xh).cuda()
+    o = torch.empty_like(z)
+    reps = 10
+    rng = np.random.default_rng(3)
+    zidx = np.unique(np.concatenate([rng.integers(0, m, 1 << 12), np.flatnonzero(np.abs(zh[: 1 << 22]) > 4.0)]))
+    extra = {"student_t_f64": {}, "n": m}
+    for nu in T_NUS:
+        qm.qm_recycle_student_t(ctx, z, o, nu)  # builds and caches the table
+        ds = timed_launches(torch, stream, lambda nu=nu: qm.qm_recycle_student_t(ctx, z, o, nu), reps)
+        avg = sum(ds) / len(ds)
+        extra["student_t_f64"][str(nu)] = {"gsamples_s": round(m / (avg * 1e-3) / 1e9, 2),
+                                           "gbs": round(16.0 * m / (avg * 1e-3) / 1e9, 1),
+                                           "p50_ms": percentile(ds, 50), "p99_ms": percentile(ds, 99)}
+        acc["student_t_f64 nu=%g" % nu] = (zh[zidx], gather(torch, o, zidx), ("student_t_map", nu), 2e-15)
+    ds = timed_launches(torch, stream, lambda: qm.qm_recycle_exp_to_normal(ctx, x, o), reps)
+    avg = sum(ds) / len(ds)
+    extra["exp_to_normal_f64"] = {"gsamples_s": round(m / (avg * 1e-3) / 1e9, 2),
+                                  "gbs": round(16.0 * m / (avg * 1e-3) / 1e9, 1),
+                                  "p50_ms": percentile(ds, 50), "p99_ms": percentile(ds, 99)}
+    xidx = sample_indices(m, None, 5)
+    acc["exp_to_normal_f64"] = (xh[xidx], gather(torch, o, xidx), "exp_to_normal", 2e-15)
+    x32 = x.float()
+    o32 = torch.empty_like(x32)
+    ds = timed_launches(torch, stream, lambda: qm.qm_recycle_exp_to_normal(ctx, x32, o32), reps)
+    avg = sum(ds) / len(ds)
+    extra["exp_to_normal_f32_refine"] = {"gsamples_s": round(m / (avg * 1e-3) / 1e9, 2),
+                                         "gbs": round(8.0 * m / (avg * 1e-3) / 1e9, 1)}
+    acc["exp_to_normal_f32_refine"] = (xh[xidx].astype(np.float32), gather(torch, o32, xidx), "exp_to_normal", 2e-7)
+    del x32, o32
+    z32 = z.float()
+    o32 = torch.empty_like(z32)
+    extra["student_t_f32_refine"] = {}
+    for nu in (1.0, 4.0, 30.0):
+        ds = timed_launches(torch, stream, lambda nu=nu: qm.qm_recycle_student_t(ctx, z32, o32, nu), reps)
+        avg = sum(ds) / len(ds)
+        extra["student_t_f32_refine"][str(nu)] = {"gsamples_s": round(m / (avg * 1e-3) / 1e9, 2),
+                                                  "gbs": round(8.0 * m / (avg * 1e-3) / 1e9, 1)}
+        acc["student_t_f32_refine nu=%g" % nu] = (zh[zidx].astype(np.float32), gather(torch, o32, zidx),
+                                                  ("student_t_map", nu), 2e-7)
+    # exponential -> hyperbolic (Section 8.1), base samples with the target's masses
+    extra["exp_to_hyperbolic_f64"] = {}
+    extra["exp_to_hyperbolic_f32"] = {}
+    for hp in (qi.HYPERBOLIC_PARAMS, (1.0, 0.5, 1.0)):
+        tb = time.perf_counter()
+        lp, lm = qm.qm_hyperbolic_masses(ctx, *hp)   # builds and caches the table
+        tb = time.perf_counter() - tb
+        hv = torch.from_numpy(qi.recycle_two_sided(m, hp[0], hp[1], math.exp(lm))).cuda()
+        ds = timed_launches(torch, stream, lambda: qm.qm_recycle_exp_to_hyperbolic(ctx, hv, o, *hp), reps)
+        avg = sum(ds) / len(ds)
+        key = "a%g_b%g_d%g" % hp
+        extra["exp_to_hyperbolic_f64"][key] = {"gsamples_s": round(m / (avg * 1e-3) / 1e9, 2),
+                                              "gbs": round(16.0 * m / (avg * 1e-3) / 1e9, 1),
+                                              "p50_ms": percentile(ds, 50), "p99_ms": percentile(ds, 99),
+                                              "table_build_s": round(tb, 3)}
+        hv32 = hv.float()
+        ds = timed_launches(torch, stream, lambda: qm.qm_recycle_exp_to_hyperbolic(ctx, hv32, o32, *hp), reps)
+        avg = sum(ds) / len(ds)
+        extra["exp_to_hyperbolic_f32"][key] = {"gsamples_s": round(m / (avg * 1e-3) / 1e9, 2),
+                                              "gbs": round(8.0 * m / (avg * 1e-3) / 1e9, 1)}
+        del hv, hv32
+    # exponential -> variance-gamma (Section 8.2)
+    extra["exp_to_vg_f64"] = {}
+    for vp in ((2, 1.0, 0.0), (3, 2.0, -1.0)):
+        tb = time.perf_counter()
+        lp, lm = qm.qm_vg_masses(ctx, *vp)
+        tb = time.perf_counter() - tb
+        vv = torch.from_numpy(qi.two_sided_exponentials(2, 3, m, vp[1] - vp[2], vp[1] + vp[2], math.exp(lm))).cuda()
+        ds = timed_launches(torch, stream, lambda: qm.qm_recycle_exp_to_vg(ctx, vv, o, *vp), reps)
+        avg = sum(ds) / len(ds)
+        extra["exp_to_vg_f64"]["l%g_a%g_b%g" % vp] = {"gsamples_s": round(m / (avg * 1e-3) / 1e9, 2),
+                                                      "gbs": round(16.0 * m / (avg * 1e-3) / 1e9, 1),
+                                                      "table_build_s": round(tb, 3)}
+        del vv
+    del z, x, o, z32, o32
+    torch.cuda.empty_cache()
+    # fused Philox generation + quantile (write-only), vs generation alone
+    g64 = torch.empty(n, dtype=torch.float64, device="cuda")
+    g32 = torch.empty(n, dtype=torch.float32, device="cuda")
+    fused = {"n": n}
+    for name, buf, kind in (("uniform_f64", g64, qm.QM_UNIFORM), ("quantile_f64", g64, qm.QM_NORMAL_QUANTILE),
+                            ("uniform_f32", g32, qm.QM_UNIFORM),
+                            ("quantile_f32_refine", g32, qm.QM_NORMAL_QUANTILE)):
+        ds = timed_launches(torch, stream, lambda buf=buf, kind=kind: qm.qm_generate(ctx, 1, 0, 0, buf, kind), reps)
+        avg = sum(ds) / len(ds)
+        fused[name] = {"gsamples_s": round(n / (avg * 1e-3) / 1e9, 2),
+                       "gbs": round(buf.element_size() * n / (avg * 1e-3) / 1e9, 1),
+                       "p50_ms": percentile(ds, 50), "p99_ms": percentile(ds, 99)}
+    # fused chains: Philox -> normal -> Student t (nu = 4), Philox -> base -> hyperbolic (1, 0, 1)
+    for name, buf, fn in (
+            ("student_t_f64_nu4", g64, lambda: qm.qm_generate_student_t(ctx, 1, 0, 0, g64, 4.0)),
+            ("student_t_f32_nu4", g32, lambda: qm.qm_generate_student_t(ctx, 1, 0, 0, g32, 4.0)),
+            ("hyperbolic_f64", g64, lambda: qm.qm_generate_hyperbolic(ctx, 1, 0, 0, g64, *qi.HYPERBOLIC_PARAMS)),
+            ("hyperbolic_f32", g32, lambda: qm.qm_generate_hyperbolic(ctx, 1, 0, 0, g32, *qi.HYPERBOLIC_PARAMS))):
+        ds = timed_launches(torch, stream, fn, reps)
+        avg = sum(ds) / len(ds)
+        fused[name] = {"gsamples_s": round(n / (avg * 1e-3) / 1e9, 2),
+                       "gbs": round(buf.element_size() * n / (avg * 1e-3) / 1e9, 1),
+                       "p50_ms": percentile(ds, 50), "p99_ms": percentile(ds, 99)}
+    extra["generate_fused"] = fused
+    del g64, g32
+    torch.cuda.empty_cache()
+    return extra
+
+
+def oracle_leg(args, acc, h64):
+    """The CPU oracle: timed on a bounded sample of the FP64 workload (the
+    CPU baseline), and, with the same outputs and on stratified samples of
+    the other results, the measured error of every result."""
+    import oracle
+    mm = min(args.cpu_sample, h64.size)
+    threads = oracle.threads_used(0)
+    c0 = time.perf_counter()
+    ref64 = oracle.norm_quantile(h64[:mm], threads)
+    cdt = time.perf_counter() - c0
+    base = {"value": round(mm / cdt / 1e9, 6), "unit": "Gsamples/s", "cores": threads, "kind": "oracle",
+            "sample": "first %d elements of the FP64 mixture workload, FP64 quantile, %.1f s wall on %d threads "
+                      "(%s)" % (mm, cdt, threads, cpu_model())}
+    errors = {}
+    for name, (x, got, fn, rtol) in acc.items():
+        if name == "fp64":
+            ref = ref64
+        elif isinstance(fn, tuple):
+            ref = getattr(oracle, fn[0])(x.astype("float64"), fn[1])
+        else:
+            ref = getattr(oracle, fn)(x.astype("float64"))
+        if got.dtype.itemsize == 4:
+            import numpy as np
+            with np.errstate(over="ignore"):
+                r32 = ref.astype(np.float32)
+            ref = np.where(np.isinf(r32) & np.isfinite(ref), r32.astype(np.float64), ref)
+        rep = error_report(got, ref, rtol)
+        rep["sample"] = ("every element of the first %d" % mm) if name == "fp64" else "stratified (%d)" % x.size
+        errors[name] = rep
+    return base, errors
 
 
 def cpu_model():
@@ -356,88 +518,100 @@ def run_batch(args, torch, qm, qi):
             "speedup_vs_sequential": round(aseq / ab, 3)}
 
 
-def run_serve(args, torch, qm, qi):
-    """Open-loop Poisson arrivals through qm_submit/qm_poll at swept rates."""
-    import numpy as np
-    seed = 5
-    count = args.serve_count
+SERVE_KINDS = {"nq_f32_refine": ("QM_NORMAL_QUANTILE", "QM_F32", "QM_F32_REFINE", 4),
+               "nq_f64": ("QM_NORMAL_QUANTILE", "QM_F64", "QM_PLAIN", 8),
+               "student_f64": ("QM_STUDENT_T", "QM_F64", "QM_PLAIN", 8),
+               "exp_f64": ("QM_EXP_TO_NORMAL", "QM_F64", "QM_PLAIN", 8)}
+
+
+def serving_trace(torch, qm, qi, seed, count):
+    """Requests of the serving workload (sizes 2^12..2^24, mix 40/20/30/10,
+    nu uniform in 1..50), each with its own inputs: request r's input is
+    drawn on the device from Philox stream 1000 + r of `seed` (uniforms as
+    the input generator defines them; normals as Phi^{-1} of such uniforms;
+    exponentials as -log of them), so no two requests share data and the
+    total far exceeds the caches.  Returns (qm_request list, keep-alive
+    tensors, spec)."""
     spec = qi.request_mix(seed, count, 12, 24)
-    pools = {}
-    maxn = 1 << 24
-    # shared read-only input pools, one per kind (the content is workload-shaped)
-    pools["nq_f32_refine"] = torch.from_numpy(qi.uniform24(seed, 1, maxn)).cuda()
-    pools["nq_f64"] = torch.from_numpy(qi.uniform53(seed, 2, maxn)).cuda()
-    pools["student_f64"] = torch.from_numpy(qi.normals(seed, 3, maxn)).cuda()
-    pools["exp_f64"] = torch.from_numpy(qi.exponentials(seed, 4, maxn)).cuda()
-    budget = 64 << 30
-    out_ring_bytes = 40 << 30
-    out_ring = torch.empty(out_ring_bytes // 8, dtype=torch.float64, device="cuda")
-    kinds = {"nq_f32_refine": (qm.QM_NORMAL_QUANTILE, qm.QM_F32, qm.QM_F32_REFINE, 4),
-             "nq_f64": (qm.QM_NORMAL_QUANTILE, qm.QM_F64, qm.QM_PLAIN, 8),
-             "student_f64": (qm.QM_STUDENT_T, qm.QM_F64, qm.QM_PLAIN, 8),
-             "exp_f64": (qm.QM_EXP_TO_NORMAL, qm.QM_F64, qm.QM_PLAIN, 8)}
-    reqs = []
-    off = 0
-    base = out_ring.data_ptr()
-    for r in spec:
-        kind, dt, mode, es = kinds[r["kind"]]
-        nbytes = r["n"] * es
-        if off + nbytes > out_ring_bytes:
-            off = 0
-        reqs.append(qm.qm_request(kind, dt, mode, 0, r["nu"], pools[r["kind"]].data_ptr(), base + off, r["n"], 0))
-        off += (nbytes + 255) // 256 * 256
-    total = sum(r.n for r in reqs)
-    rng = np.random.default_rng(seed)
-    results = []
-    warm = qm.Context(0, hbm_budget_bytes=budget)
-    for nu in range(1, 51):                  # warm the table builder's cache path
-        qm.qm_recycle_student_t(warm, pools["student_f64"][:1024], out_ring[:1024], float(nu))
-    warm.close()
-    for rate in args.rates:
-        ctx = qm.Context(0, hbm_budget_bytes=budget)
-        for nu in range(1, 51):
-            qm.qm_recycle_student_t(ctx, pools["student_f64"][:1024], out_ring[:1024], float(nu))
-        torch.cuda.synchronize()
-        if rate > 0:
-            arrivals = np.cumsum(rng.exponential(1.0 / rate, count))
-        else:                                # burst: everything arrives at once (capacity)
-            arrivals = np.zeros(count)
-        tickets = [None] * count
-        lib = qm.load()
-        import ctypes
-
-        def submitter():
-            t0 = time.perf_counter()
-            for i in range(count):
-                while time.perf_counter() - t0 < arrivals[i]:
-                    pass
-                tk = ctypes.c_uint64()
-                qm.check(lib.qm_submit(ctx.handle, ctypes.byref(reqs[i]), ctypes.byref(tk)))
-                tickets[i] = tk.value
-
-        th = threading.Thread(target=submitter)
-        t_start = time.perf_counter()
-        th.start()
-        th.join()
-        done = 0
-        while done < count:
-            done = sum(1 for t in tickets if lib.qm_poll(ctx.handle, t) == qm.QM_OK)
-            if done < count:
-                time.sleep(0.0005)
-        wall = time.perf_counter() - t_start
-        lat = qm.qm_serving_latencies(ctx)
-        ctx.close()
-        lat_ms = [x / 1e6 for x in lat]
-        results.append({"rate_req_s": rate if rate > 0 else "burst", "requests": count, "elements": total,
-                        "wall_s": round(wall, 4), "gsamples_s": round(total / wall / 1e9, 3),
-                        "offered_gsamples_s": round(total / arrivals[-1] / 1e9, 3) if rate > 0 else None,
-                        "p50_ms": round(percentile(lat_ms, 50), 4), "p99_ms": round(percentile(lat_ms, 99), 4),
-                        "max_ms": round(max(lat_ms), 4)})
-        print(json.dumps(results[-1]), file=sys.stderr, flush=True)
-    # the same trace as sequential launches, one request at a time on one stream
     ctx = qm.Context(0)
-    for nu in range(1, 51):                  # tables built before timing
-        qm.qm_recycle_student_t(ctx, pools["student_f64"][:1024], out_ring[:1024], float(nu))
+    reqs, keep = [], []
+    for i, r in enumerate(spec):
+        kind, dt, mode, es = SERVE_KINDS[r["kind"]]
+        tdt = torch.float32 if es == 4 else torch.float64
+        x = torch.empty(r["n"], dtype=tdt, device="cuda")
+        gen_kind = qm.QM_NORMAL_QUANTILE if r["kind"] == "student_f64" else qm.QM_UNIFORM
+        qm.qm_generate(ctx, seed, 1000 + i, 0, x, gen_kind, qm.QM_PLAIN)
+        if r["kind"] == "exp_f64":
+            x.log_().neg_()
+        y = torch.empty_like(x)
+        reqs.append(qm.qm_request(getattr(qm, kind), getattr(qm, dt), getattr(qm, mode), 0, r["nu"],
+                                  x.data_ptr(), y.data_ptr(), r["n"], i))
+        keep.append((x, y))
+    torch.cuda.synchronize()
+    ctx.close()
+    return reqs, keep, spec
+
+
+def serve_rates(torch, qm, count, rates, seed=5, budget=64 << 30):
+    """Open-loop Poisson arrivals through qm_submit at each rate (0 = all at
+    once): latency of each request from its scheduled arrival to the
+    scheduler's observation of its completion (qm_poll_times, monotonic
+    clock), p50/p99/max, delivered Gsamples/s, and the in-flight
+    high-water mark; then the same trace as sequential single launches."""
+    import ctypes
+
+    import numpy as np
+
+    import qm_inputs as qi
+    reqs, keep, spec = serving_trace(torch, qm, qi, seed, count)
+    total = sum(r.n for r in reqs)
+    nus = sorted({r.nu for r in reqs if r.kind == qm.QM_STUDENT_T})
+    lib = qm.load()
+    rng = np.random.default_rng(seed)
+    out = []
+    for rate in rates:
+        ctx = qm.Context(0, hbm_budget_bytes=budget)
+        z = torch.zeros(1, dtype=torch.float64, device="cuda")
+        for nu in nus:                       # tables built before the clock starts
+            qm.qm_recycle_student_t(ctx, z[:0], z[:0], nu)
+        torch.cuda.synchronize()
+        arrivals = np.cumsum(rng.exponential(1.0 / rate, count)) if rate > 0 else np.zeros(count)
+        tickets = [0] * count
+        t0_ns = time.monotonic_ns()
+        tk = ctypes.c_uint64()
+        lag = 0.0
+        for i in range(count):
+            due = t0_ns + int(arrivals[i] * 1e9)
+            while time.monotonic_ns() < due:
+                pass
+            lag = max(lag, (time.monotonic_ns() - due) / 1e6)
+            qm.check(lib.qm_submit(ctx.handle, ctypes.byref(reqs[i]), ctypes.byref(tk)))
+            tickets[i] = tk.value
+        done_ns = [None] * count
+        while any(d is None for d in done_ns):
+            for i in range(count):
+                if done_ns[i] is None:
+                    st, _, d = qm.qm_poll_times(ctx, tickets[i])
+                    if st == qm.QM_OK:
+                        done_ns[i] = d
+            time.sleep(0.0002)
+        wall = (max(done_ns) - t0_ns) / 1e9
+        lat_ms = [(done_ns[i] - (t0_ns + int(arrivals[i] * 1e9))) / 1e6 for i in range(count)]
+        stats = qm.qm_serving_stats_of(ctx)
+        ctx.close()
+        row = {"rate_req_s": rate if rate > 0 else "burst", "requests": count, "elements": total,
+               "wall_s": round(wall, 4), "gsamples_s": round(total / wall / 1e9, 3),
+               "offered_gsamples_s": round(total / arrivals[-1] / 1e9, 3) if rate > 0 else None,
+               "p50_ms": round(percentile(lat_ms, 50), 4), "p99_ms": round(percentile(lat_ms, 99), 4),
+               "max_ms": round(max(lat_ms), 4), "max_submit_lag_ms": round(lag, 4),
+               "in_flight_high_water_bytes": stats["in_flight_bytes_high_water"]}
+        out.append(row)
+        print(json.dumps(row), file=sys.stderr, flush=True)
+    # the same trace as sequential single launches on one stream
+    ctx = qm.Context(0)
+    z = torch.zeros(1, dtype=torch.float64, device="cuda")
+    for nu in nus:
+        qm.qm_recycle_student_t(ctx, z[:0], z[:0], nu)
     stream = torch.cuda.current_stream()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -446,13 +620,23 @@ def run_serve(args, torch, qm, qi):
     torch.cuda.synchronize()
     seq_wall = time.perf_counter() - t0
     ctx.close()
-    return {"metric": "serving p50/p99 latency and Gsamples/s (continuous batching)",
-            "value": max(r["gsamples_s"] for r in results),
-            "unit": "Gsamples/s", "n_gpus": 1, "higher_is_better": True, "dtype": "f64+f32", "data": "synthetic",
-            "config": {"workload": "serving: Poisson arrivals, %d requests per rate, sizes log-uniform 2^12..2^24, "
-                                   "mix 40/20/30/10, HBM budget 64 GB, seed 5" % count},
-            "rates": results,
+    del keep
+    torch.cuda.empty_cache()
+    return {"config": "Poisson arrivals, %d requests per rate, sizes log-uniform 2^12..2^24, mix 40/20/30/10, "
+                      "distinct inputs per request, HBM budget %d GB, seed %d; latency from scheduled arrival"
+                      % (count, budget >> 30, seed),
+            "rates": out,
             "sequential_launches": {"wall_s": round(seq_wall, 4), "gsamples_s": round(total / seq_wall / 1e9, 3)}}
+
+
+def run_serve(args, torch, qm, qi):
+    """Open-loop Poisson arrivals through qm_submit/qm_poll at swept rates."""
+    r = serve_rates(torch, qm, args.serve_count, args.rates)
+    return {"metric": "serving p50/p99 latency and Gsamples/s (continuous batching)",
+            "value": max(x["gsamples_s"] for x in r["rates"]),
+            "unit": "Gsamples/s", "n_gpus": 1, "higher_is_better": True, "dtype": "f64+f32", "data": "synthetic",
+            "config": {"workload": "serving: " + r["config"]},
+            "rates": r["rates"], "sequential_launches": r["sequential_launches"]}
 
 
 # ---------------------------------------------------------------------------
@@ -554,6 +738,12 @@ def main():
     ap.add_argument("--serve-count", type=int, default=2000)
     ap.add_argument("--rates", type=float, nargs="+", default=[1000, 2000, 5000, 10000, 20000, 50000, 100000, 0],
                     help="arrival rates in requests/s; 0 = burst (all requests at once)")
+    ap.add_argument("--pct-reps", type=int, default=64,
+                    help="extra launches per kernel for the p50/p99 latencies (outside the timed region)")
+    ap.add_argument("--serve-extra", type=int, default=1,
+                    help="quantile workload: also run a bounded serving trace (0 = skip)")
+    ap.add_argument("--serve-extra-count", type=int, default=500)
+    ap.add_argument("--serve-extra-rates", type=float, nargs="+", default=[10000, 50000])
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the maps are elementwise and shard into contiguous ranges "

@@ -220,8 +220,11 @@ qm_status qm_vg_masses(qm_ctx* ctx, double lambda, double alpha, double beta, do
  *   F64: block e/2 (counter (e/2 mod 2^32, e/2 div 2^32, 0, 0)); the 64-bit
  *        value of words (0,1) for even e, (2,3) for odd e (low word
  *        first); its top 53 bits k give u = (k + 1/2) 2^-53.
- *   F32: word e mod 4 of block e/4; its top 24 bits k give
- *        u = (k + 1/2) 2^-24.
+ *   F32: word e mod 4 of block e/4; its top 23 bits k give
+ *        u = (k + 1/2) 2^-23, exact, in [2^-24, 1 - 2^-24].
+ *   (F64: the sum k + 1/2 rounds to nearest, a tie to even for k >= 2^52,
+ *   so u lies in [2^-54, 1] and is 1 with probability 2^-53; Phi^{-1}
+ *   maps it to +inf.)
  * kind QM_UNIFORM writes u (mode QM_PLAIN); kind QM_NORMAL_QUANTILE writes
  * Phi^{-1}(u), bitwise equal to qm_normal_quantile of the same u, with the
  * dtype/mode pairs of qm_normal_quantile.  Any sub-range of a stream can be
@@ -301,6 +304,7 @@ typedef struct {
  */
 qm_status qm_run_batch(qm_ctx* ctx, const qm_request* reqs, uint64_t count, void* hip_stream);
 
+
 /*
  * Serving loop.  qm_submit validates and enqueues one request and returns a
  * ticket; it returns at once unless the request needs a Student t or
@@ -311,23 +315,56 @@ qm_status qm_run_batch(qm_ctx* ctx, const qm_request* reqs, uint64_t count, void
  * previous launch as one batch; batches run on several streams, so requests
  * admitted while others are on the GPU overlap with them.  Per-request state
  * (descriptors, chunk counters) lives on the device for the batch's life.
- * Buffers must stay alive until qm_poll returns QM_OK or an error.
+ * Ordering: the serving streams are the library's own and are not ordered
+ * after any stream of the caller.  The request's input must therefore be
+ * complete in device memory, and its output no longer read or written by
+ * other work, when qm_submit is called (synchronize the stream that
+ * produced the input first).  Buffers must stay alive until qm_poll returns
+ * QM_OK or an error.
  * qm_submit errors: QM_E_INVAL (as qm_run_batch, or request larger than the
  * whole budget), QM_E_DTYPE, QM_E_CLOSED.
  * qm_poll returns QM_OK once the request's output is complete in device
  * memory, QM_PENDING before that, QM_E_TICKET for an unknown ticket, and
- * QM_E_CLOSED for a request failed by qm_shutdown.  A ticket reports QM_OK
- * on every poll after completion.
+ * QM_E_CLOSED for a request failed by qm_shutdown.  A finished ticket keeps
+ * reporting its final status until 65536 later requests have finished;
+ * then it is forgotten and reports QM_E_TICKET (the server's memory stays
+ * bounded however long it runs).
  */
 qm_status qm_submit(qm_ctx* ctx, const qm_request* req, uint64_t* ticket);
 qm_status qm_poll(qm_ctx* ctx, uint64_t ticket);
 
 /*
- * Serving statistics since qm_init: requests completed, and the submit ->
- * completion latency of each, in nanoseconds, written into lat_ns (up to cap
- * entries, completion order).  Returns the number of completed requests.
+ * qm_poll, also giving the request's submit time and (with QM_OK) the time
+ * the scheduler observed its completion, in nanoseconds of the monotonic
+ * clock (CLOCK_MONOTONIC, the clock of C++ steady_clock), so that a caller
+ * can measure latency from its own scheduled arrival times.  Either pointer
+ * may be NULL.
+ */
+qm_status qm_poll_times(qm_ctx* ctx, uint64_t ticket, uint64_t* submit_ns, uint64_t* done_ns);
+
+/*
+ * Serving statistics since qm_init.  Returns the number of completed
+ * requests and writes the submit -> completion latencies, in nanoseconds, of
+ * the most recent min(cap, completed, 2^20) of them into lat_ns, oldest
+ * first (lat_ns may be NULL).
  */
 uint64_t qm_serving_latencies(qm_ctx* ctx, uint64_t* lat_ns, uint64_t cap);
+
+/* Counters of the serving loop (all zero before the first qm_submit). */
+typedef struct {
+    uint64_t submitted;                  /* requests accepted by qm_submit */
+    uint64_t completed;                  /* requests finished with QM_OK */
+    uint64_t failed;                     /* requests whose launch failed */
+    uint64_t queued;                     /* waiting for admission now */
+    uint64_t in_flight_requests;         /* admitted, not yet observed complete */
+    uint64_t in_flight_bytes;            /* their input + output bytes */
+    uint64_t in_flight_bytes_high_water; /* the largest in_flight_bytes so far (never above budget_bytes) */
+    uint64_t budget_bytes;               /* the context's HBM budget */
+    uint64_t tickets_kept;               /* tickets the server holds state for */
+} qm_serving_counters;
+
+/* Errors: QM_E_INVAL for a NULL argument. */
+qm_status qm_serving_stats(qm_ctx* ctx, qm_serving_counters* out);
 
 /* Static text for a status code. */
 const char* qm_status_string(qm_status s);

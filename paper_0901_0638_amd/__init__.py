@@ -17,7 +17,7 @@ from ._lib import (  # noqa: F401
     QM_E_CLOSED, QM_E_DTYPE, QM_E_HIP, QM_E_INVAL, QM_E_NOMEM, QM_E_TICKET, QM_EXP_TO_NORMAL, QM_F32,
     QM_F32_REFINE, QM_F64, QM_NORMAL_QUANTILE, QM_OK, QM_PAPER, QM_PENDING, QM_PLAIN, QM_STUDENT_T, QM_UNIFORM, QMError,
     QM_EXP_TO_HYPERBOLIC, QM_EXP_TO_VG,
-    check, load, qm_request,
+    check, load, qm_request, qm_serving_counters,
 )
 
 _DTYPES = {"torch.float64": QM_F64, "torch.float32": QM_F32}
@@ -207,10 +207,27 @@ def qm_poll(ctx, ticket):
     return check(load().qm_poll(ctx.handle, int(ticket)))
 
 
+def qm_poll_times(ctx, ticket):
+    """(status, submit_ns, done_ns) of a ticket; times on the monotonic
+    clock (time.monotonic_ns), done_ns only with QM_OK; raises on errors."""
+    a, b = ctypes.c_uint64(), ctypes.c_uint64()
+    st = check(load().qm_poll_times(ctx.handle, int(ticket), ctypes.byref(a), ctypes.byref(b)))
+    return st, a.value, (b.value if st == QM_OK else None)
+
+
 def qm_serving_latencies(ctx, cap=1 << 20):
+    """Submit -> completion latencies (ns) of the most recent completed
+    requests, oldest first."""
     buf = (ctypes.c_uint64 * cap)()
     n = load().qm_serving_latencies(ctx.handle, buf, cap)
     return [buf[i] for i in range(min(n, cap))]
+
+
+def qm_serving_stats_of(ctx):
+    """The serving loop's counters as a dict (qm_serving_stats)."""
+    st = qm_serving_counters()
+    check(load().qm_serving_stats(ctx.handle, ctypes.byref(st)))
+    return {name: getattr(st, name) for name, _ in qm_serving_counters._fields_}
 
 
 class TCells(ctypes.Structure):

@@ -53,6 +53,12 @@ class qm_request(ctypes.Structure):
     ]
 
 
+class qm_serving_counters(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_uint64) for name in (
+        "submitted", "completed", "failed", "queued", "in_flight_requests", "in_flight_bytes",
+        "in_flight_bytes_high_water", "budget_bytes", "tickets_kept")]
+
+
 # name -> (restype, argtypes), exactly the declarations of include/qm.h
 _vp, _u64, _i, _d = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int, ctypes.c_double
 _st = ctypes.c_int32
@@ -73,6 +79,8 @@ SIGNATURES = {
     "qm_run_batch": (_st, [_vp, ctypes.POINTER(qm_request), _u64, _vp]),
     "qm_submit": (_st, [_vp, ctypes.POINTER(qm_request), ctypes.POINTER(_u64)]),
     "qm_poll": (_st, [_vp, _u64]),
+    "qm_poll_times": (_st, [_vp, _u64, ctypes.POINTER(_u64), ctypes.POINTER(_u64)]),
+    "qm_serving_stats": (_st, [_vp, ctypes.POINTER(qm_serving_counters)]),
     "qm_serving_latencies": (_u64, [_vp, ctypes.POINTER(_u64), _u64]),
     "qm_status_string": (ctypes.c_char_p, [_st]),
     "qm_last_error": (ctypes.c_char_p, []),

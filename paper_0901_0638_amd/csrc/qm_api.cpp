@@ -144,6 +144,29 @@ qm_status get_table(qm_ctx* ctx, double nu, const DeviceTable** out)
     return QM_OK;
 }
 
+qm_status find_table(qm_ctx* ctx, double nu, const DeviceTable** out)
+{
+    std::lock_guard<std::mutex> lk(ctx->table_mu);
+    auto it = ctx->tables.find(nu);
+    if (it == ctx->tables.end())
+        return fail(QM_E_INVAL, "no Student t table for nu=%g in the context yet (one call with this nu, "
+                                "even with n = 0, builds it)", nu);
+    *out = &it->second;
+    return QM_OK;
+}
+
+qm_status find_base_table(qm_ctx* ctx, bool vg, double p1, double p2, double p3, const DeviceHypTable** out)
+{
+    std::lock_guard<std::mutex> lk(ctx->table_mu);
+    auto& tables = vg ? ctx->vg_tables : ctx->hyp_tables;
+    auto it = tables.find(std::make_tuple(p1, p2, p3));
+    if (it == tables.end())
+        return fail(QM_E_INVAL, "no %s table for (%g, %g, %g) in the context yet (one call with these parameters, "
+                                "even with n = 0, builds it)", vg ? "variance-gamma" : "hyperbolic", p1, p2, p3);
+    *out = &it->second;
+    return QM_OK;
+}
+
 /* Look up (or build and upload) a table of the two-sided exponential base:
    hyperbolic for (alpha, beta, delta), or variance-gamma for (lambda, alpha,
    beta) when vg; built outside the lock like get_table's. */
@@ -199,21 +222,23 @@ uint64_t ctx_budget(const qm_ctx* ctx) { return ctx->budget; }
 
 qm_status run_single(qm_ctx* ctx, const qm_request& r, hipStream_t s)
 {
-    if (r.n == 0) return QM_OK;
+    /* a table is built (and cached) even for n = 0, so that a call can
+       prepare it ahead of time */
     hipError_t e;
     if (r.kind == QM_STUDENT_T) {
         const DeviceTable* t = nullptr;
         qm_status st = get_table(ctx, r.nu, &t);
-        if (st != QM_OK) return st;
+        if (st != QM_OK || r.n == 0) return st;
         e = launch_student(r.dtype, r.mode, r.d_in, r.d_out, r.n, t->d_table, t->hdr, s, ctx->shape);
     } else if (r.kind == QM_EXP_TO_HYPERBOLIC || r.kind == QM_EXP_TO_VG) {
         const DeviceHypTable* t = nullptr;
         qm_status st = r.kind == QM_EXP_TO_VG ? get_vg_table(ctx, r.nu, r.alpha, r.beta, &t)
                                               : get_hyp_table(ctx, r.alpha, r.beta, r.delta, &t);
-        if (st != QM_OK) return st;
+        if (st != QM_OK || r.n == 0) return st;
         e = launch_hyperbolic(r.dtype, r.mode, r.d_in, r.d_out, r.n, t->d_table, t->hdr, t->ncoef, r.mu, s,
                               ctx->shape);
     } else {
+        if (r.n == 0) return QM_OK;
         e = launch_elementwise(r.kind, r.dtype, r.mode, r.d_in, r.d_out, r.n, s, ctx->shape);
     }
     if (e != hipSuccess) return hip_fail(e, "kernel launch");

@@ -53,7 +53,7 @@ __device__ __forceinline__ void block_uniforms(uint64_t b, uint32_t k0, uint32_t
 {
     PhiloxWords w = philox4x32_10(b, k0, k1);
 #pragma unroll
-    for (int j = 0; j < 4; ++j) u[j] = open_u24(w.w[j]);
+    for (int j = 0; j < 4; ++j) u[j] = open_u23(w.w[j]);
 }
 
 /* H: the per-element map (Op), or with GATHER the hybrid (HybridNQ64/32). */
@@ -281,7 +281,10 @@ struct HypBase {
     {
         const bool neg = u < p_minus;
         const double ratio = neg ? u / p_minus : (1.0 - u) / p_plus;
-        return neg_log_unit(ratio) * (neg ? -inv_rate_minus : inv_rate_plus);
+        /* u = 1 (an FP64 uniform of the top 53-bit value rounds to 1) is the
+           base's right end, v = +inf (mapped to +inf) */
+        const double l = ratio > 0.0 ? neg_log_unit(ratio) : __builtin_inf();
+        return l * (neg ? -inv_rate_minus : inv_rate_plus);
     }
 };
 

@@ -11,9 +11,12 @@
  * Stream layout: key = (seed, stream) (32 bits each); the block of index b
  * has counter (b mod 2^32, b div 2^32, 0, 0).  FP64 element e takes block
  * e/2, words (0,1) for even e and (2,3) for odd e as one 64-bit value (low
- * word first) whose top 53 bits k give u = (k + 1/2) 2^-53.  FP32 element e
- * takes word e mod 4 of block e/4, whose top 24 bits k give
- * u = (k + 1/2) 2^-24.  Both are open: 0 < u < 1.
+ * word first) whose top 53 bits k give u = (k + 1/2) 2^-53, rounded to
+ * nearest: exact for k < 2^52, a tie (to even) above, so u lies in
+ * [2^-54, 1] and equals 1 only for k = 2^53 - 1 (probability 2^-53).  FP32
+ * element e takes word e mod 4 of block e/4, whose top 23 bits k give
+ * u = (k + 1/2) 2^-23, exact in FP32 (at most 24 significant bits): u lies
+ * in [2^-24, 1 - 2^-24], open at both ends.
  */
 #pragma once
 #include <hip/hip_runtime.h>
@@ -51,17 +54,19 @@ __device__ __forceinline__ PhiloxWords philox4x32_10(uint64_t block, uint32_t k0
 }
 
 /* u = (k + 1/2) 2^-53, k the top 53 bits of (hi:lo): k is exact in FP64,
-   the addition rounds to nearest even, the scaling is exact */
+   the addition rounds to nearest even (a tie for k >= 2^52; 1.0 for
+   k = 2^53 - 1), the scaling is exact */
 __device__ __forceinline__ double open_u53(uint32_t lo, uint32_t hi)
 {
     uint64_t k = ((((uint64_t)hi) << 32) | lo) >> 11;
     return ((double)k + 0.5) * 0x1p-53;
 }
 
-/* u = (k + 1/2) 2^-24, k the top 24 bits of the word */
-__device__ __forceinline__ float open_u24(uint32_t word)
+/* u = (k + 1/2) 2^-23, k the top 23 bits of the word: k + 1/2 has at most
+   24 significant bits, so every step is exact and 0 < u < 1 */
+__device__ __forceinline__ float open_u23(uint32_t word)
 {
-    return ((float)(word >> 8) + 0.5f) * 0x1p-24f;
+    return ((float)(word >> 9) + 0.5f) * 0x1p-23f;
 }
 
 /* element e of the stream, one at a time (heads, tails, unaligned outputs) */
@@ -75,7 +80,7 @@ template <> __device__ __forceinline__ float stream_uniform<float>(uint64_t e, u
 {
     PhiloxWords b = philox4x32_10(e >> 2, k0, k1);
     uint32_t lo = (e & 1) ? b.w[1] : b.w[0], hi = (e & 1) ? b.w[3] : b.w[2];
-    return open_u24((e & 2) ? hi : lo);
+    return open_u23((e & 2) ? hi : lo);
 }
 
 }  // namespace qm

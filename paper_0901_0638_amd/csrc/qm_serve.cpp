@@ -158,27 +158,11 @@ static uint32_t batch_op(const qm_request& r)
     }
 }
 
-/*
- * Validate and enqueue `count` requests as one persistent launch on s.  If
- * done is not NULL, an event that completes with the launch is recorded
- * into it (the caller owns the event).
- */
-qm_status enqueue_batch(qm_ctx* ctx, const qm_request* reqs, uint64_t count, hipStream_t s, hipEvent_t done)
+/* Chunk size of a batch of total_n elements: about 4 chunks for each of the
+   cus x 8 workgroups, within [chunk_floor, QM_CHUNK_MAX], a multiple of
+   QM_CHUNK_MIN. */
+static uint64_t batch_chunk(uint64_t total_n, int cus)
 {
-    if (!ctx) return set_error(QM_E_INVAL, "context is NULL");
-    if (count > 0 && !reqs) return set_error(QM_E_INVAL, "reqs is NULL");
-    for (uint64_t i = 0; i < count; ++i) {
-        qm_status st = check_request(reqs[i], nullptr);
-        if (st != QM_OK) return st;
-    }
-    if (hipSetDevice(ctx->device) != hipSuccess) return set_error(QM_E_HIP, "hipSetDevice failed");
-    std::vector<BatchReq> d;
-    d.reserve(count);
-    /* chunk size: aim at 4 chunks for each of the cus x 8 workgroups, within
-       [QM_CHUNK_MIN, QM_CHUNK_MAX], a multiple of QM_CHUNK_MIN */
-    uint64_t total_n = 0;
-    for (uint64_t i = 0; i < count; ++i) total_n += reqs[i].n;
-    const uint64_t blocks_max = (uint64_t)ctx->cus * 8;
     static const uint64_t chunk_floor = [] {
         /* tuning: lower bound of the chunk size.  Default QM_CHUNK_MAX:
            measured on the serving trace, smaller chunks (2048..8192) cut
@@ -189,10 +173,27 @@ qm_status enqueue_batch(qm_ctx* ctx, const qm_request* reqs, uint64_t count, hip
         v = (v / QM_CHUNK_MIN) * QM_CHUNK_MIN;
         return v < QM_CHUNK_MIN ? QM_CHUNK_MIN : (v > QM_CHUNK_MAX ? QM_CHUNK_MAX : v);
     }();
+    const uint64_t blocks_max = (uint64_t)cus * 8;
     uint64_t chunk = total_n / (blocks_max * 4);
     chunk = (chunk / QM_CHUNK_MIN) * QM_CHUNK_MIN;
-    chunk = chunk < chunk_floor ? chunk_floor : (chunk > QM_CHUNK_MAX ? QM_CHUNK_MAX : chunk);
+    return chunk < chunk_floor ? chunk_floor : (chunk > QM_CHUNK_MAX ? QM_CHUNK_MAX : chunk);
+}
+
+/*
+ * The descriptors of a validated batch, in request order (requests with
+ * n = 0 are skipped), each handed to emit(const BatchReq&); h receives the
+ * header.  Tables the requests need are fetched from the context and, when
+ * build_tables, built on first use; otherwise a missing table is an error.
+ */
+template <class Emit>
+static qm_status plan_batch(qm_ctx* ctx, const qm_request* reqs, uint64_t count, bool build_tables, BatchHeader* h,
+                            size_t* lds_out, Emit emit)
+{
+    uint64_t total_n = 0;
+    for (uint64_t i = 0; i < count; ++i) total_n += reqs[i].n;
+    const uint64_t chunk = batch_chunk(total_n, ctx->cus);
     uint64_t chunks = 0;
+    uint32_t nreq = 0;
     size_t lds = 0;
     for (uint64_t i = 0; i < count; ++i) {
         const qm_request& r = reqs[i];
@@ -207,47 +208,89 @@ qm_status enqueue_batch(qm_ctx* ctx, const qm_request* reqs, uint64_t count, hip
         chunks += (r.n + chunk - 1) / chunk;
         if (r.kind == QM_STUDENT_T) {
             const DeviceTable* t = nullptr;
-            qm_status st = get_table(ctx, r.nu, &t);
+            qm_status st = build_tables ? get_table(ctx, r.nu, &t) : find_table(ctx, r.nu, &t);
             if (st != QM_OK) return st;
             const TCells& c = r.dtype == QM_F64 ? t->hdr.f64 : t->hdr.f32;
             b.coef = table_block(t->d_table) + c.coef_offset;
             b.P = make_params(t->hdr, c, b.coef);
             if (!t->hdr.identity) lds = std::max(lds, (size_t)c.nlds * b.P.lds_stride * sizeof(double));
         } else if (r.kind == QM_EXP_TO_HYPERBOLIC || r.kind == QM_EXP_TO_VG) {
+            const bool vg = r.kind == QM_EXP_TO_VG;
             const DeviceHypTable* t = nullptr;
-            qm_status st = r.kind == QM_EXP_TO_VG ? get_vg_table(ctx, r.nu, r.alpha, r.beta, &t)
-                                                  : get_hyp_table(ctx, r.alpha, r.beta, r.delta, &t);
+            qm_status st = vg ? (build_tables ? get_vg_table(ctx, r.nu, r.alpha, r.beta, &t)
+                                              : find_base_table(ctx, true, r.nu, r.alpha, r.beta, &t))
+                              : (build_tables ? get_hyp_table(ctx, r.alpha, r.beta, r.delta, &t)
+                                              : find_base_table(ctx, false, r.alpha, r.beta, r.delta, &t));
             if (st != QM_OK) return st;
             size_t l = 0;
             if (!make_hyp_params(t->hdr, r.dtype == QM_F32, t->d_table, t->ncoef, r.mu, &b.H, &l))
                 return set_error(QM_E_INVAL, "invalid hyperbolic table");
             lds = std::max(lds, l);
         }
-        d.push_back(b);
+        qm_status st = emit(b);
+        if (st != QM_OK) return st;
+        ++nreq;
     }
     if (lds > QM_BATCH_DYNAMIC_LDS_MAX) return set_error(QM_E_INVAL, "table larger than the LDS a launch may use");
+    memset(h, 0, sizeof *h);
+    h->counter = 0;
+    h->total_chunks = chunks;
+    h->nreq = nreq;
+    h->chunk = chunk;
+    *lds_out = lds;
+    return QM_OK;
+}
+
+static qm_status validate_batch(qm_ctx* ctx, const qm_request* reqs, uint64_t count)
+{
+    if (!ctx) return set_error(QM_E_INVAL, "context is NULL");
+    if (count > 0 && !reqs) return set_error(QM_E_INVAL, "reqs is NULL");
+    for (uint64_t i = 0; i < count; ++i) {
+        qm_status st = check_request(reqs[i], nullptr);
+        if (st != QM_OK) return st;
+    }
+    if (hipSetDevice(ctx->device) != hipSuccess) return set_error(QM_E_HIP, "hipSetDevice failed");
+    return QM_OK;
+}
+
+static uint64_t batch_blocks(const qm_ctx* ctx, uint64_t chunks)
+{
+    uint64_t blocks = (uint64_t)ctx->cus * 8;
+    return blocks > chunks ? chunks : blocks;
+}
+
+/*
+ * Validate and enqueue `count` requests as one persistent launch on s.  If
+ * done is not NULL, an event that completes with the launch is recorded
+ * into it (the caller owns the event).
+ */
+qm_status enqueue_batch(qm_ctx* ctx, const qm_request* reqs, uint64_t count, hipStream_t s, hipEvent_t done)
+{
+    qm_status st = validate_batch(ctx, reqs, count);
+    if (st != QM_OK) return st;
+    std::vector<BatchReq> d;
+    d.reserve(count);
+    BatchHeader h;
+    size_t lds = 0;
+    st = plan_batch(ctx, reqs, count, true, &h, &lds, [&](const BatchReq& b) {
+        d.push_back(b);
+        return (qm_status)QM_OK;
+    });
+    if (st != QM_OK) return st;
     if (d.empty()) {
         if (done && hipEventRecord(done, s) != hipSuccess) return set_error(QM_E_HIP, "hipEventRecord failed");
         return QM_OK;
     }
     size_t bytes = sizeof(BatchHeader) + d.size() * sizeof(BatchReq);
     Staging* slot = nullptr;
-    qm_status st = acquire_slot(runner_of(ctx), bytes, &slot);
+    st = acquire_slot(runner_of(ctx), bytes, &slot);
     if (st != QM_OK) return st;
-    BatchHeader h;
-    memset(&h, 0, sizeof h);
-    h.counter = 0;
-    h.total_chunks = chunks;
-    h.nreq = (uint32_t)d.size();
-    h.chunk = chunk;
     memcpy(slot->host, &h, sizeof h);
     memcpy((char*)slot->host + sizeof h, d.data(), d.size() * sizeof(BatchReq));
     hipError_t e = hipMemcpyAsync(slot->dev, slot->host, bytes, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) {
-        uint64_t blocks = blocks_max;
-        if (blocks > chunks) blocks = chunks;
-        e = launch_batch((BatchHeader*)slot->dev, (const BatchReq*)((char*)slot->dev + sizeof h), lds, blocks, s);
-    }
+    if (e == hipSuccess)
+        e = launch_batch((BatchHeader*)slot->dev, (const BatchReq*)((char*)slot->dev + sizeof h), lds,
+                         batch_blocks(ctx, h.total_chunks), s);
     hipError_t e2 = hipEventRecord(slot->ev, s);
     {
         std::lock_guard<std::mutex> g(runner_of(ctx)->mu);
@@ -272,7 +315,15 @@ struct Ticket {
     uint64_t bytes;
     int state;
     clk::time_point t_submit;
+    clk::time_point t_done;
 };
+
+/* Finished tickets are kept for the most recent SERVE_KEEP_FINISHED
+   completions (then forgotten: qm_poll reports QM_E_TICKET); latencies for
+   the most recent SERVE_KEEP_LATENCIES.  Both bound a long-running
+   server's memory. */
+constexpr size_t SERVE_KEEP_FINISHED = 1 << 16;
+constexpr size_t SERVE_KEEP_LATENCIES = 1 << 20;
 
 struct InFlight {
     hipEvent_t ev;
@@ -297,8 +348,22 @@ struct Server {
     bool stream_busy[SERVE_STREAMS] = {};
     std::vector<InFlight> inflight;
     std::vector<hipEvent_t> free_events;
-    std::vector<uint64_t> latencies_ns;
+    std::deque<uint64_t> finished;        /* terminal tickets, oldest first */
+    std::vector<uint64_t> latencies_ns;   /* ring of SERVE_KEEP_LATENCIES */
+    uint64_t completed = 0, failed = 0, submitted = 0;
+    uint64_t in_flight_bytes_hwm = 0;
+    uint64_t in_flight_requests = 0;
 };
+
+/* A ticket reached a terminal state: keep it among the recent ones. */
+static void finish_ticket(Server* S, uint64_t t)
+{
+    S->finished.push_back(t);
+    while (S->finished.size() > SERVE_KEEP_FINISHED) {
+        S->tickets.erase(S->finished.front());
+        S->finished.pop_front();
+    }
+}
 
 static void server_loop(Server* S)
 {
@@ -323,9 +388,15 @@ static void server_loop(Server* S)
                 for (uint64_t t : S->inflight[i].tickets) {
                     Ticket& tk = S->tickets[t];
                     tk.state = T_DONE;
-                    S->latencies_ns.push_back(
-                        (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(now - tk.t_submit).count());
+                    tk.t_done = now;
+                    uint64_t lat =
+                        (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(now - tk.t_submit).count();
+                    if (S->latencies_ns.size() < SERVE_KEEP_LATENCIES) S->latencies_ns.push_back(lat);
+                    else S->latencies_ns[S->completed % SERVE_KEEP_LATENCIES] = lat;
+                    ++S->completed;
+                    finish_ticket(S, t);
                 }
+                S->in_flight_requests -= S->inflight[i].tickets.size();
                 S->in_flight_bytes -= S->inflight[i].bytes;
                 S->stream_busy[S->inflight[i].stream] = false;
                 S->free_events.push_back(S->inflight[i].ev);
@@ -354,7 +425,10 @@ static void server_loop(Server* S)
             }
         }
         if (S->stop && S->inflight.empty() && admit.empty()) {
-            for (uint64_t t : S->queue) S->tickets[t].state = T_CLOSED;
+            for (uint64_t t : S->queue) {
+                S->tickets[t].state = T_CLOSED;
+                finish_ticket(S, t);
+            }
             S->queue.clear();
             return;
         }
@@ -375,6 +449,8 @@ static void server_loop(Server* S)
         reqs.clear();
         for (uint64_t t : admit) reqs.push_back(S->tickets[t].req);
         S->in_flight_bytes += bytes;
+        S->in_flight_requests += admit.size();
+        if (S->in_flight_bytes > S->in_flight_bytes_hwm) S->in_flight_bytes_hwm = S->in_flight_bytes;
         hipEvent_t ev = nullptr;
         if (!S->free_events.empty()) { ev = S->free_events.back(); S->free_events.pop_back(); }
         hipStream_t st = S->streams[idle];
@@ -384,7 +460,12 @@ static void server_loop(Server* S)
         qm_status rc = enqueue_batch(S->ctx, reqs.data(), reqs.size(), st, ev);
         lk.lock();
         if (rc != QM_OK) {
-            for (uint64_t t : admit) S->tickets[t].state = T_FAILED;
+            for (uint64_t t : admit) {
+                S->tickets[t].state = T_FAILED;
+                finish_ticket(S, t);
+            }
+            S->failed += admit.size();
+            S->in_flight_requests -= admit.size();
             S->in_flight_bytes -= bytes;
             S->stream_busy[idle] = false;
             S->free_events.push_back(ev);
@@ -484,46 +565,82 @@ qm_status qm_submit(qm_ctx* ctx, const qm_request* req, uint64_t* ticket)
         tk.t_submit = qm::clk::now();
         S->tickets.emplace(t, tk);
         S->queue.push_back(t);
+        ++S->submitted;
         *ticket = t;
     }
     S->cv.notify_one();
     return QM_OK;
 }
 
-qm_status qm_poll(qm_ctx* ctx, uint64_t ticket)
+static qm::Server* server_if_any(qm_ctx* ctx)
+{
+    std::lock_guard<std::mutex> lk(ctx->server_mu);
+    return ctx->server;
+}
+
+static uint64_t steady_ns(qm::clk::time_point t)
+{
+    return (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(t.time_since_epoch()).count();
+}
+
+qm_status qm_poll_times(qm_ctx* ctx, uint64_t ticket, uint64_t* submit_ns, uint64_t* done_ns)
 {
     if (!ctx) return qm::set_error(QM_E_INVAL, "context is NULL");
-    qm::Server* S;
-    {
-        std::lock_guard<std::mutex> lk(ctx->server_mu);
-        S = ctx->server;
-    }
+    qm::Server* S = server_if_any(ctx);
     if (!S) return qm::set_error(QM_E_TICKET, "unknown ticket");
     std::lock_guard<std::mutex> lk(S->mu);
     auto it = S->tickets.find(ticket);
-    if (it == S->tickets.end()) return qm::set_error(QM_E_TICKET, "unknown ticket");
+    if (it == S->tickets.end()) return qm::set_error(QM_E_TICKET, "unknown or forgotten ticket");
+    if (submit_ns) *submit_ns = steady_ns(it->second.t_submit);
     switch (it->second.state) {
-    case qm::T_DONE: return QM_OK;
+    case qm::T_DONE:
+        if (done_ns) *done_ns = steady_ns(it->second.t_done);
+        return QM_OK;
     case qm::T_CLOSED: return qm::set_error(QM_E_CLOSED, "request failed by shutdown");
     case qm::T_FAILED: return qm::set_error(QM_E_HIP, "request launch failed");
     default: return QM_PENDING;
     }
 }
 
+qm_status qm_poll(qm_ctx* ctx, uint64_t ticket) { return qm_poll_times(ctx, ticket, nullptr, nullptr); }
+
 uint64_t qm_serving_latencies(qm_ctx* ctx, uint64_t* lat_ns, uint64_t cap)
 {
     if (!ctx) return 0;
-    qm::Server* S;
-    {
-        std::lock_guard<std::mutex> lk(ctx->server_mu);
-        S = ctx->server;
-    }
+    qm::Server* S = server_if_any(ctx);
     if (!S) return 0;
     std::lock_guard<std::mutex> lk(S->mu);
-    uint64_t n = S->latencies_ns.size();
-    if (lat_ns)
-        for (uint64_t i = 0; i < n && i < cap; ++i) lat_ns[i] = S->latencies_ns[i];
-    return n;
+    const uint64_t kept = S->latencies_ns.size();
+    if (lat_ns && kept) {
+        /* the most recent min(cap, kept), oldest first; once the ring has
+           wrapped, its oldest entry is at completed mod its size */
+        uint64_t m = cap < kept ? cap : kept;
+        uint64_t start = (S->completed - m) % qm::SERVE_KEEP_LATENCIES;
+        for (uint64_t i = 0; i < m; ++i) {
+            uint64_t j = kept < qm::SERVE_KEEP_LATENCIES ? (S->completed - m + i) : (start + i) % kept;
+            lat_ns[i] = S->latencies_ns[j];
+        }
+    }
+    return S->completed;
+}
+
+qm_status qm_serving_stats(qm_ctx* ctx, qm_serving_counters* out)
+{
+    if (!ctx || !out) return qm::set_error(QM_E_INVAL, "NULL argument");
+    memset(out, 0, sizeof *out);
+    out->budget_bytes = ctx->budget;
+    qm::Server* S = server_if_any(ctx);
+    if (!S) return QM_OK;
+    std::lock_guard<std::mutex> lk(S->mu);
+    out->submitted = S->submitted;
+    out->completed = S->completed;
+    out->failed = S->failed;
+    out->queued = S->queue.size();
+    out->in_flight_requests = S->in_flight_requests;
+    out->in_flight_bytes = S->in_flight_bytes;
+    out->in_flight_bytes_high_water = S->in_flight_bytes_hwm;
+    out->tickets_kept = S->tickets.size();
+    return QM_OK;
 }
 
 }  /* extern "C" */

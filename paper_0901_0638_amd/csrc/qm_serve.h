@@ -23,6 +23,10 @@ qm_status get_table(qm_ctx* ctx, double nu, const DeviceTable** out);
 qm_status get_hyp_table(qm_ctx* ctx, double alpha, double beta, double delta, const DeviceHypTable** out);
 /* Per-(lambda, alpha, beta) variance-gamma table (the same format). */
 qm_status get_vg_table(qm_ctx* ctx, double lambda, double alpha, double beta, const DeviceHypTable** out);
+/* The same lookups without building: QM_E_INVAL if the table is not in the
+   context yet. */
+qm_status find_table(qm_ctx* ctx, double nu, const DeviceTable** out);
+qm_status find_base_table(qm_ctx* ctx, bool vg, double p1, double p2, double p3, const DeviceHypTable** out);
 const TTableHeader* device_table_ptr(const DeviceTable* t);
 const TTableHeader& device_table_hdr(const DeviceTable* t);
 const LaunchShape& ctx_shape(const qm_ctx* ctx);

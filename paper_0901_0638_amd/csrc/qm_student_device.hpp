@@ -70,6 +70,9 @@ static __device__ __noinline__ double student_far(double s, const StudentParams&
     const double INV_SQRT2 = 0.70710678118654752440, LN2 = 0.69314718055994530942;
     if (!(s < __builtin_inf())) return s;              /* z = +-inf -> +-inf; NaN -> NaN */
     double yh = s * s;
+    /* s^2 overflows (s above 1.3e154): log t is about s^2/(2 nu) > 700 for
+       every nu below 1e300, so t overflows too */
+    if (!(yh < __builtin_inf())) return yh;
     if (yh <= P.y_max) {
         double d;
         int j = cell_of(s, yh, P.ncell - 1, P, &d);

@@ -8,6 +8,10 @@ regenerate any sampled element without the full array.
 Workloads (sizes and seeds as used by the tests and the benchmark):
 
   uniform53      u = (k + 1/2) 2^-53, k the top 53 bits of a Philox word pair
+                 (rounded to nearest: a tie to even for k >= 2^52, and 1.0
+                 for k = 2^53 - 1)
+  uniform23      u = (k + 1/2) 2^-23 in FP32, k the top 23 bits of a word
+                 (exact, 0 < u < 1)
   mixture        90% open uniform, 10% tail t log-uniform in [lo, 1e-2],
                  mirrored to 1 - t with probability 1/2
   normals        Box-Muller pairs from two open uniforms
@@ -50,10 +54,14 @@ def _load():
     vp = ctypes.c_void_p
     lib.qmi_philox4x32_10.argtypes = [vp, vp, vp]
     lib.qmi_philox4x32_10.restype = None
-    for name in ("qmi_uniform53", "qmi_uniform24", "qmi_normals", "qmi_exponentials"):
+    for name in ("qmi_uniform53", "qmi_uniform23", "qmi_normals", "qmi_exponentials"):
         f = getattr(lib, name)
         f.argtypes = [u64, u64, vp, sz, ci]
         f.restype = ci
+    for name in ("qmi_u53_of_bits", "qmi_u23_of_words"):
+        f = getattr(lib, name)
+        f.argtypes = [vp, vp, sz]
+        f.restype = None
     for name in ("qmi_mixture_f64", "qmi_mixture_f32"):
         f = getattr(lib, name)
         f.argtypes = [u64, u64, cd, cd, vp, sz, ci]
@@ -71,15 +79,33 @@ def philox4x32_10(counter, key):
     return out
 
 
+def u53_of_bits(bits):
+    """The FP64 open-uniform formula (k + 1/2) 2^-53 of the top 53 bits k of
+    each 64-bit value."""
+    b = np.ascontiguousarray(bits, dtype=np.uint64)
+    out = np.empty(b.size, np.float64)
+    _load().qmi_u53_of_bits(b.ctypes.data, out.ctypes.data, b.size)
+    return out
+
+
+def u23_of_words(words):
+    """The FP32 open-uniform formula (k + 1/2) 2^-23 of the top 23 bits k of
+    each 32-bit word."""
+    w = np.ascontiguousarray(words, dtype=np.uint32)
+    out = np.empty(w.size, np.float32)
+    _load().qmi_u23_of_words(w.ctypes.data, out.ctypes.data, w.size)
+    return out
+
+
 def uniform53(seed, stream, n, threads=0, out=None):
     out = np.empty(n, np.float64) if out is None else out
     _load().qmi_uniform53(seed, stream, out.ctypes.data, n, threads)
     return out
 
 
-def uniform24(seed, stream, n, threads=0, out=None):
+def uniform23(seed, stream, n, threads=0, out=None):
     out = np.empty(n, np.float32) if out is None else out
-    _load().qmi_uniform24(seed, stream, out.ctypes.data, n, threads)
+    _load().qmi_uniform23(seed, stream, out.ctypes.data, n, threads)
     return out
 
 
@@ -181,7 +207,7 @@ def request_input(seed, req):
     """The input array of one request of request_mix."""
     k, n, s = req["kind"], req["n"], req["stream"]
     if k == "nq_f32_refine":
-        return uniform24(seed, s, n)
+        return uniform23(seed, s, n)
     if k == "nq_f64":
         return uniform53(seed, s, n)
     if k == "student_f64":

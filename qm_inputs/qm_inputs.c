@@ -60,11 +60,13 @@ static uint64_t bits64(uint64_t seed, uint64_t stream, uint64_t i)
     return (i & 1) ? (((uint64_t)w[3] << 32) | w[2]) : (((uint64_t)w[1] << 32) | w[0]);
 }
 
-/* open uniform on (0,1): (k + 1/2) 2^-53 with the top 53 bits k */
+/* uniform (k + 1/2) 2^-53 with the top 53 bits k, rounded to nearest: a
+   tie (to even) for k >= 2^52, and 1.0 for k = 2^53 - 1 */
 static double u53(uint64_t bits) { return ((double)(bits >> 11) + 0.5) * 0x1p-53; }
 
-/* open uniform in FP32: (k + 1/2) 2^-24 with the top 24 bits of a word */
-static float u24(uint32_t word) { return ((float)(word >> 8) + 0.5f) * 0x1p-24f; }
+/* open uniform in FP32: (k + 1/2) 2^-23 with the top 23 bits of a word
+   (exact: k + 1/2 has at most 24 significant bits, so 0 < u < 1) */
+static float u23(uint32_t word) { return ((float)(word >> 9) + 0.5f) * 0x1p-23f; }
 
 /* ---------------------------------------------------------------------- */
 typedef struct {
@@ -77,7 +79,7 @@ typedef struct {
 
 enum {
     G_U53 = 0,        /* open uniform f64 */
-    G_U24 = 1,        /* open uniform f32 */
+    G_U23 = 1,        /* open uniform f32 */
     G_MIX64 = 2,      /* bulk/tail mixture f64 */
     G_MIX32 = 3,      /* bulk/tail mixture f32 */
     G_NORMAL = 4,     /* Box-Muller normals f64 */
@@ -106,10 +108,10 @@ static void* gen_run(void* p)
         case G_U53:
             ((double*)g->out)[i] = u53(bits64(g->seed, g->stream, i));
             break;
-        case G_U24: {
+        case G_U23: {
             uint32_t w[4];
             block(g->seed, g->stream, i >> 2, w);
-            ((float*)g->out)[i] = u24(w[i & 3]);
+            ((float*)g->out)[i] = u23(w[i & 3]);
             break;
         }
         case G_MIX64: {
@@ -130,7 +132,7 @@ static void* gen_run(void* p)
             if (!tail) {
                 uint32_t w[4];
                 block(g->seed, g->stream, i >> 2, w);
-                u = u24(w[i & 3]);
+                u = u23(w[i & 3]);
             } else {
                 float t = (float)mix_tail(g->seed, g->stream, i, g->b, 1e-2);
                 int mirror = u53(bits64(g->seed, g->stream + 3, i)) < 0.5;
@@ -188,11 +190,18 @@ static int gen_parallel(int kind, uint64_t seed, uint64_t stream, void* out, siz
     return 0;
 }
 
+/* the open-uniform formulas applied to given words (tests of the formulas) */
+void qmi_u53_of_bits(const uint64_t* bits, double* out, size_t n)
+{ for (size_t i = 0; i < n; ++i) out[i] = u53(bits[i]); }
+
+void qmi_u23_of_words(const uint32_t* words, float* out, size_t n)
+{ for (size_t i = 0; i < n; ++i) out[i] = u23(words[i]); }
+
 int qmi_uniform53(uint64_t seed, uint64_t stream, double* out, size_t n, int nthreads)
 { return gen_parallel(G_U53, seed, stream, out, n, 0, 0, nthreads); }
 
-int qmi_uniform24(uint64_t seed, uint64_t stream, float* out, size_t n, int nthreads)
-{ return gen_parallel(G_U24, seed, stream, out, n, 0, 0, nthreads); }
+int qmi_uniform23(uint64_t seed, uint64_t stream, float* out, size_t n, int nthreads)
+{ return gen_parallel(G_U23, seed, stream, out, n, 0, 0, nthreads); }
 
 int qmi_mixture_f64(uint64_t seed, uint64_t stream, double p_tail, double tail_lo,
                     double* out, size_t n, int nthreads)

@@ -114,6 +114,7 @@ def test_batch_validation_rejects_whole_batch(ctx):
 
 def test_serving_results_equal_single_calls(ctx):
     reqs, ins, outs, qreqs = build(5, 120, 10, 18)
+    torch.cuda.synchronize()        # inputs and NaN fills complete before submit
     tickets = [qm.qm_submit(ctx, q) for q in qreqs]
     deadline = time.time() + 60
     pending = set(tickets)
@@ -145,6 +146,7 @@ def test_serving_shutdown_with_work_in_flight():
     c = qm.Context(0, hbm_budget_bytes=64 << 20)
     xs = [torch.from_numpy(qi.uniform53(6, i, 1 << 20)).cuda() for i in range(16)]
     ys = [torch.empty_like(x) for x in xs]
+    torch.cuda.synchronize()
     for x, y in zip(xs, ys):
         qm.qm_submit(c, qm.make_request(qm.QM_NORMAL_QUANTILE, x, y))
     t0 = time.time()
@@ -282,6 +284,7 @@ def test_batch_hyperbolic_bitwise_equal_to_single(ctx):
 
 def test_serving_hyperbolic(ctx):
     reqs, cases, others = hyperbolic_requests(70)
+    torch.cuda.synchronize()
     tickets = [qm.qm_submit(ctx, r) for r in reqs]
     deadline = time.time() + 60
     pending = set(tickets)
@@ -338,6 +341,7 @@ def test_batch_and_serving_vg(ctx):
     for _, _, o in cases:
         o.fill_(float("nan"))
     ho.fill_(float("nan"))
+    torch.cuda.synchronize()
     tickets = [qm.qm_submit(ctx, r) for r in reqs]
     deadline = time.time() + 60
     pending = set(tickets)
@@ -350,3 +354,93 @@ def test_batch_and_serving_vg(ctx):
     with pytest.raises(qm.QMError):
         qm.qm_run_batch(ctx, [qm.make_request(qm.QM_EXP_TO_VG, d, d, nu=2.5, hyperbolic=(1.0, 0.0, 0.0))],
                         device_tensor=d)
+
+
+def wait_all(ctx, tickets, limit_s=120):
+    deadline = time.time() + limit_s
+    pending = set(tickets)
+    while pending and time.time() < deadline:
+        pending = {t for t in pending if qm.qm_poll(ctx, t) == qm.QM_PENDING}
+        time.sleep(0.001)
+    assert not pending, "%d requests did not complete" % len(pending)
+
+
+def test_serving_full_size_alone_vs_mix():
+    """The serving workload's shape: 200 requests, sizes log-uniform in
+    2^12..2^24, the 40/20/30/10 mix (nu uniform in 1..50), each with its own
+    inputs, arriving as a Poisson stream at 5000 requests/s so that they are
+    admitted while earlier ones run, HBM budget 64 GB.  Every output is
+    bitwise the same request run alone, 16 sampled outputs per request are
+    within tolerance of the oracle, and the bytes in flight never exceeded
+    the budget."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    budget = 64 << 30
+    c = qm.Context(0, hbm_budget_bytes=budget)
+    try:
+        reqs, ins, outs, qreqs = build(5, 200, 12, 24)
+        print("serving full size: %d requests, %d elements" % (len(reqs), sum(r["n"] for r in reqs)), flush=True)
+        for r in reqs:                      # tables first, as a server warms up
+            if r["kind"] == "student_f64":
+                qm.qm_recycle_student_t(c, ins[0][:0].double(), outs[0][:0].double(), r["nu"])
+        torch.cuda.synchronize()
+        rng = np.random.default_rng(55)
+        gaps = rng.exponential(1.0 / 5000, len(qreqs))
+        t0 = time.perf_counter()
+        due = 0.0
+        tickets = []
+        for q, g in zip(qreqs, gaps):
+            due += g
+            while time.perf_counter() - t0 < due:
+                pass
+            tickets.append(qm.qm_submit(c, q))
+        wait_all(c, tickets)
+        st = qm.qm_serving_stats_of(c)
+        print("serving stats", st, flush=True)
+        assert st["completed"] == len(tickets) and st["failed"] == 0 and st["queued"] == 0
+        assert 0 < st["in_flight_bytes_high_water"] <= budget
+        for r, d, o in zip(reqs, ins, outs):
+            kind, mode = KIND[r["kind"]]
+            alone = single(c, kind, mode, r["nu"], d)
+            bits = torch.int32 if o.dtype == torch.float32 else torch.int64
+            assert torch.equal(o.view(bits), alone.view(bits)), ("alone vs mix", r)
+            del alone
+        torch.cuda.synchronize()
+        for r, d, o in zip(reqs, ins, outs):
+            idx = torch.from_numpy(np.unique(rng.integers(0, d.numel(), 16))).cuda()
+            x = d[idx].cpu().numpy()
+            got = o[idx].cpu().numpy()
+            assert_close(got, oracle_of(r, x), RTOL_F32 if got.dtype == np.float32 else RTOL_F64, str(r))
+        del ins, outs
+    finally:
+        c.close()
+        torch.cuda.empty_cache()
+
+
+def test_serving_budget_high_water_under_burst():
+    """A burst of 96 requests of 1 MiB in + 1 MiB out against a 16 MiB
+    budget: the server admits at most 8 at a time, so the bytes in flight
+    never exceed the budget, and every request completes."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    budget = 16 << 20
+    c = qm.Context(0, hbm_budget_bytes=budget)
+    try:
+        xs = [torch.from_numpy(qi.uniform53(8, i, 1 << 17)).cuda() for i in range(96)]
+        ys = [torch.empty_like(x) for x in xs]
+        torch.cuda.synchronize()
+        tickets = [qm.qm_submit(c, qm.make_request(qm.QM_NORMAL_QUANTILE, x, y)) for x, y in zip(xs, ys)]
+        wait_all(c, tickets)
+        st = qm.qm_serving_stats_of(c)
+        assert st["completed"] == 96 and st["in_flight_bytes"] == 0 and st["in_flight_requests"] == 0
+        assert (2 << 20) <= st["in_flight_bytes_high_water"] <= budget, st
+        assert st["budget_bytes"] == budget
+        for t in tickets:
+            status, sub, done = qm.qm_poll_times(c, t)
+            assert status == qm.QM_OK and done >= sub > 0
+        ref = torch.empty_like(xs[0])
+        qm.qm_normal_quantile(c, xs[-1], ref)
+        torch.cuda.synchronize()
+        assert torch.equal(ref, ys[-1])
+    finally:
+        c.close()

@@ -9,7 +9,7 @@ import pytest
 
 import oracle
 import qm_inputs as qi
-from tests._tol import RTOL_F32, RTOL_F64, assert_close
+from tests._tol import RTOL_F32, RTOL_F64, as_f32_output, assert_close
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -187,7 +187,7 @@ def test_quantile_f32_refine_central_outer_boundary(ctx):
             edges.append(x)
     rng = np.random.default_rng(23)
     u = np.concatenate([np.array(edges, np.float32), rng.uniform(0.04, 0.96, 20000).astype(np.float32),
-                        qi.uniform24(6, 0, 1 << 16)])
+                        qi.uniform23(6, 0, 1 << 16)])
     ref = oracle.norm_quantile(u.astype(np.float64))
     got = run_nq(ctx, u, qm.QM_F32_REFINE)
     assert_close(got, ref, RTOL_F32, "f32 refine centre/outer")
@@ -202,7 +202,7 @@ def test_quantile_f32_refine_central_outer_boundary(ctx):
 def test_quantile_f32_paper_mode(ctx):
     """Paper (5,6) in FP32 (Appendix A): realized error of order 3e-7 down to
     u ~ 1e-11 (Section 6.3); checked at 5e-7 on its domain v <= 25."""
-    u = qi.uniform24(5, 0, 1 << 18)
+    u = qi.uniform23(5, 0, 1 << 18)
     u = u[np.minimum(u, 1 - u) > 1e-11]
     ref = oracle.norm_quantile(u.astype(np.float64))
     assert_close(run_nq(ctx, u, qm.QM_PAPER), ref, 5e-7, "f32 paper")
@@ -233,19 +233,63 @@ def test_exp_to_normal_f32_refine(ctx):
     assert_close(run_e(ctx, x), ref, RTOL_F32, "exp->normal f32 refine")
 
 
-def test_quantile_f64_full_size_sampled(ctx):
-    """The FP64 mixture at its full size 2^28 in the launch configuration the
-    benchmark times; 2^16 sampled outputs (plus every tail element among the
-    first 2^20) against the oracle, inputs regenerated on the host by index."""
-    n = 1 << 28
-    u = qi.mixture_f64(n)
+def full_size_indices(n, seed, tail_of=None):
+    """Output indices checked at a full benchmark size: 2^16 random ones,
+    whole contiguous runs of 4096 (every element of the waves that wrote
+    them) at the start, in the middle of the grid-stride passes and in the
+    last pass, the last 300, and, given the inputs, every outer element
+    (|u - 1/2| > 0.45) among the first 2^20."""
+    rng = np.random.default_rng(seed)
+    runs = [np.arange(s, s + 4096) for s in (0, n // 2 + 12288, n - (n >> 4) + 4096, n - 8192)]
+    parts = [rng.integers(0, n, 1 << 16), np.arange(n - 300, n)] + runs
+    if tail_of is not None:
+        head = tail_of[: 1 << 20].astype(np.float64)
+        parts.append(np.flatnonzero(np.abs(head - 0.5) > 0.45))
+    return np.unique(np.concatenate(parts))
+
+
+def check_full_size(ctx, u, fn, rtol, what, seed, ref_fn):
     d = torch.from_numpy(u).cuda()
     w = torch.empty_like(d)
-    qm.qm_normal_quantile(ctx, d, w)
+    fn(ctx, d, w)
     torch.cuda.synchronize()
-    rng = np.random.default_rng(12)
-    idx = np.unique(np.concatenate([rng.integers(0, n, 1 << 16), np.arange(n - 300, n)]))
+    idx = full_size_indices(u.size, seed, u if ref_fn is oracle.norm_quantile else None)
     got = w[torch.from_numpy(idx).cuda()].cpu().numpy()
-    assert_close(got, oracle.norm_quantile(u[idx]), RTOL_F64, "2^28 sampled")
+    ref = ref_fn(u[idx].astype(np.float64))
+    if got.dtype == np.float32:
+        ref = as_f32_output(ref)
+    rep = assert_close(got, ref, rtol, what)
+    print(what, len(idx), rep, flush=True)
     del d, w
     torch.cuda.empty_cache()
+
+
+def test_quantile_f64_full_size_sampled(ctx):
+    """The FP64 mixture at its full size 2^28 in the launch configuration the
+    benchmark times; 2^16 random outputs, whole runs of 4096 in the first,
+    a middle and the last grid-stride passes, the last 300 and every outer
+    element among the first 2^20, against the oracle."""
+    check_full_size(ctx, qi.mixture_f64(1 << 28), lambda c, d, w: qm.qm_normal_quantile(c, d, w), RTOL_F64,
+                    "f64 2^28", 12, oracle.norm_quantile)
+
+
+def test_quantile_f32_refine_full_size_sampled(ctx):
+    """FP32 + FP64 refine on the FP32 mixture at its full size 2^28 (16
+    grid-stride passes of the benchmark's launch), sampled as the FP64 test.
+    About 4.2% of its elements are fl(1 - t) = 1.0 (t < 2^-25) and compare as
+    +inf on both sides; the upper tail is otherwise covered by the exact
+    symmetry of the formulas and the edge tests."""
+    check_full_size(ctx, qi.mixture_f32(1 << 28),
+                    lambda c, d, w: qm.qm_normal_quantile(c, d, w, qm.QM_F32_REFINE), RTOL_F32,
+                    "f32 refine 2^28", 13, oracle.norm_quantile)
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_exp_to_normal_full_size_sampled(ctx, dtype):
+    """Exponential -> normal on the 2^26 Exp(1) recycling workload in the
+    benchmark's launch (several grid-stride passes), FP64 and FP32+refine,
+    sampled like the quantile."""
+    x = qi.recycle_exponentials(1 << 26).astype(dtype)
+    check_full_size(ctx, x, lambda c, d, w: qm.qm_recycle_exp_to_normal(c, d, w),
+                    RTOL_F64 if dtype == np.float64 else RTOL_F32, "exp->normal 2^26 %s" % np.dtype(dtype).name, 14,
+                    oracle.exp_to_normal)

@@ -82,6 +82,21 @@ def test_student_identity_and_large_nu(ctx):
     assert_close(t, oracle.student_t_map(z, 2e5), RTOL_F64, "nu=2e5")
 
 
+def test_student_huge_z_overflows_to_inf(ctx):
+    """|z| from 1e150 to the largest double: log t is about z^2/(2 nu), far
+    beyond the FP64 range for every nu below 1e300, so t is +-inf (z^2 itself
+    overflows from 1.3e154 on).  The oracle saturates where its upper-tail
+    probability underflows (|z| about 150), so the exact value is the check."""
+    z = np.array([1e150, -1e150, 1.4e154, 1e155, -1e200, 1e300, -1.7976931348623157e308])
+    for nu in (0.5, 1, 4, 30, 1000, 1e5, 2e5):
+        got = run_t(ctx, z, nu)
+        assert np.array_equal(got, np.copysign(np.inf, z)), (nu, got)
+    z32 = np.array([1e20, -3e38, 3.4028235e38], np.float32)
+    for nu in (1.0, 4.0, 30.0):
+        got = run_t(ctx, z32, nu)
+        assert np.array_equal(got, np.copysign(np.float32(np.inf), z32)), (nu, got)
+
+
 def test_student_invalid_nu(ctx):
     d = torch.zeros(8, dtype=torch.float64, device="cuda")
     for nu in (0.25, -1.0, float("nan"), float("-inf")):
@@ -185,3 +200,27 @@ def test_student_full_size_sampled(ctx):
     idx = np.unique(np.concatenate([rng.integers(0, n, 1 << 14), np.argsort(np.abs(z))[-64:]]))
     got = t[torch.from_numpy(idx).cuda()].cpu().numpy()
     assert_close(got, oracle.student_t_map(z[idx], 4.0), RTOL_F64, "2^26 sampled")
+
+
+@pytest.mark.parametrize("nu", [1.0, 4.0, 30.0])
+def test_student_f32_full_size_sampled(ctx, nu):
+    """T-R (FP32 in/out) on the 2^26 recycling normals at the benchmark's
+    launch shape (several grid-stride passes): 2^13 random outputs, whole
+    runs of 1024 in the first, a middle and the last passes, the last 300,
+    and every element with |z| > 4, against the oracle."""
+    n = 1 << 26
+    z = qi.recycle_normals(n).astype(np.float32)
+    d = torch.from_numpy(z).cuda()
+    t = torch.empty_like(d)
+    qm.qm_recycle_student_t(ctx, d, t, nu)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(int(nu) + 40)
+    runs = [np.arange(s, s + 1024) for s in (0, n // 2 + 3072, n - (n >> 4) + 1024, n - 2048)]
+    idx = np.unique(np.concatenate([rng.integers(0, n, 1 << 13), np.arange(n - 300, n),
+                                    np.flatnonzero(np.abs(z) > 4.0)] + runs))
+    got = t[torch.from_numpy(idx).cuda()].cpu().numpy()
+    ref = as_f32_output(oracle.student_t_map(z[idx].astype(np.float64), nu))
+    rep = assert_close(got, ref, RTOL_F32, "T-R 2^26 nu=%s" % nu)
+    print("T-R 2^26 nu", nu, len(idx), rep, flush=True)
+    del d, t
+    torch.cuda.empty_cache()
