@@ -304,6 +304,38 @@ typedef struct {
  */
 qm_status qm_run_batch(qm_ctx* ctx, const qm_request* reqs, uint64_t count, void* hip_stream);
 
+/* Most requests with n > 0 that one qm_run_batch_noalloc call takes. */
+#define QM_BATCH_NOALLOC_MAX_REQUESTS 4096
+
+/*
+ * qm_run_batch for callers that cannot allocate memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * Same requests, same kernel, bitwise the same outputs as qm_run_batch;
+ * the call itself allocates nothing, on the device or the host.
+ *
+ * Memory: the batch header and descriptors go to a fixed device array
+ * (QM_BATCH_NOALLOC_MAX_REQUESTS records, about 768 KiB) that the library
+ * holds once per GPU until the process ends, its address looked up by
+ * qm_init; they are staged through the context's pinned host buffer, also
+ * set up by qm_init.  The claim counter is rewritten to 0 by every call.
+ *
+ * Ordering: the upload and the launch are ordered on hip_stream.  All calls
+ * on one GPU share that device array, so two calls whose work overlaps on
+ * the GPU (different streams, or several contexts on one GPU) race and give
+ * undefined results: order them on one stream, or synchronize between.
+ * Calls on one context from several host threads are serialized.  A call
+ * waits until the previous call's descriptor upload has left the host
+ * buffer.
+ *
+ * Errors: as qm_run_batch, plus QM_E_INVAL when more than
+ * QM_BATCH_NOALLOC_MAX_REQUESTS requests have n > 0, and QM_E_INVAL when a
+ * request needs a Student t, hyperbolic or variance-gamma table that the
+ * context does not hold yet (this call does not build tables: make one
+ * call with those parameters first, n = 0 is enough).  Nothing is launched
+ * on error.
+ */
+qm_status qm_run_batch_noalloc(qm_ctx* ctx, const qm_request* reqs, uint64_t count, void* hip_stream);
+
 
 /*
  * Serving loop.  qm_submit validates and enqueues one request and returns a

@@ -16,7 +16,7 @@ import ctypes
 from ._lib import (  # noqa: F401
     QM_E_CLOSED, QM_E_DTYPE, QM_E_HIP, QM_E_INVAL, QM_E_NOMEM, QM_E_TICKET, QM_EXP_TO_NORMAL, QM_F32,
     QM_F32_REFINE, QM_F64, QM_NORMAL_QUANTILE, QM_OK, QM_PAPER, QM_PENDING, QM_PLAIN, QM_STUDENT_T, QM_UNIFORM, QMError,
-    QM_EXP_TO_HYPERBOLIC, QM_EXP_TO_VG,
+    QM_EXP_TO_HYPERBOLIC, QM_EXP_TO_VG, QM_BATCH_NOALLOC_MAX_REQUESTS,
     check, load, qm_request, qm_serving_counters,
 )
 
@@ -193,6 +193,14 @@ def qm_run_batch(ctx, reqs, stream=None, device_tensor=None):
     arr = (qm_request * len(reqs))(*reqs)
     s = ctypes.c_void_p(int(stream)) if stream is not None else _stream(None, device_tensor) if device_tensor is not None else ctypes.c_void_p(0)
     check(load().qm_run_batch(ctx.handle, arr, len(reqs), s))
+
+
+def qm_run_batch_noalloc(ctx, reqs, stream=None, device_tensor=None):
+    """qm_run_batch through the allocation-free entry point (tables must
+    already be in the context)."""
+    arr = (qm_request * len(reqs))(*reqs)
+    s = ctypes.c_void_p(int(stream)) if stream is not None else _stream(None, device_tensor) if device_tensor is not None else ctypes.c_void_p(0)
+    check(load().qm_run_batch_noalloc(ctx.handle, arr, len(reqs), s))
 
 
 def qm_submit(ctx, req):

@@ -20,6 +20,8 @@ QM_E_HIP = -4
 QM_E_CLOSED = -5
 QM_E_TICKET = -6
 
+QM_BATCH_NOALLOC_MAX_REQUESTS = 4096
+
 QM_F32 = 0
 QM_F64 = 1
 
@@ -77,6 +79,7 @@ SIGNATURES = {
     "qm_generate_hyperbolic": (_st, [_vp, _u64, _u64, _u64, _vp, _u64, _i, _i, _d, _d, _d, _d, _vp]),
     "qm_generate_vg": (_st, [_vp, _u64, _u64, _u64, _vp, _u64, _i, _i, _d, _d, _d, _d, _vp]),
     "qm_run_batch": (_st, [_vp, ctypes.POINTER(qm_request), _u64, _vp]),
+    "qm_run_batch_noalloc": (_st, [_vp, ctypes.POINTER(qm_request), _u64, _vp]),
     "qm_submit": (_st, [_vp, ctypes.POINTER(qm_request), ctypes.POINTER(_u64)]),
     "qm_poll": (_st, [_vp, _u64]),
     "qm_poll_times": (_st, [_vp, _u64, ctypes.POINTER(_u64), ctypes.POINTER(_u64)]),

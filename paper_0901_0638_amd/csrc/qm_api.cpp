@@ -14,6 +14,7 @@
 #include <mutex>
 #include <string>
 
+#include "qm_batch.h"
 #include "qm_context.h"
 #include "qm_serve.h"
 
@@ -300,6 +301,16 @@ qm_status qm_init(int hip_device, uint64_t hbm_budget_bytes, qm_ctx** out)
     }
     const char* ec = getenv("QM_COMPACT");
     c->shape.compact = ec ? (int)strtol(ec, nullptr, 10) != 0 : 1;
+    /* set-up of the allocation-free batch entry point (this device is
+       current): the device array's address, its host staging and event */
+    e = qm::batch_scratch_address(hip_device, &c->noalloc_dev);
+    if (e == hipSuccess) e = hipHostMalloc(&c->noalloc_host, qm::BATCH_SCRATCH_BYTES, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->noalloc_ev, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        if (c->noalloc_host) (void)hipHostFree(c->noalloc_host);
+        delete c;
+        return hip_fail(e, "set-up of the allocation-free batch path");
+    }
     *out = c;
     return QM_OK;
 }
@@ -313,6 +324,11 @@ void qm_shutdown(qm_ctx* ctx)
     for (auto& kv : ctx->tables) (void)hipFree(kv.second.d_table);
     for (auto& kv : ctx->hyp_tables) (void)hipFree(kv.second.d_table);
     for (auto& kv : ctx->vg_tables) (void)hipFree(kv.second.d_table);
+    if (ctx->noalloc_ev) {
+        (void)hipEventSynchronize(ctx->noalloc_ev);
+        (void)hipEventDestroy(ctx->noalloc_ev);
+    }
+    if (ctx->noalloc_host) (void)hipHostFree(ctx->noalloc_host);
     delete ctx;
 }
 

@@ -50,6 +50,16 @@ struct BatchReq {
     };
 };
 
+/* The allocation-free entry point's device array: one header and
+   QM_BATCH_NOALLOC_MAX_REQUESTS records (768 KiB) per GPU. */
+constexpr size_t BATCH_SCRATCH_BYTES = sizeof(BatchHeader) + QM_BATCH_NOALLOC_MAX_REQUESTS * sizeof(BatchReq);
+constexpr int BATCH_SCRATCH_MAX_DEVICES = 64;
+
+/* Device address of that array on `device`, which must be the current
+   device; looked up on the first call per device and kept (qm_init calls
+   it). */
+hipError_t batch_scratch_address(int device, void** out);
+
 StudentParams make_params(const TTableHeader& h, const TCells& c, const double* d_rows);
 hipError_t launch_batch(BatchHeader* d_hdr, const BatchReq* d_reqs, size_t lds_bytes, uint64_t blocks,
                         hipStream_t s);

@@ -17,6 +17,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "qm_batch.h"
 #include "qm_device.hpp"
 #include "qm_hybrid.hpp"
@@ -250,6 +252,37 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
             break;
         }
     }
+}
+
+/*
+ * Descriptor memory of the allocation-free batch entry point: a header and
+ * up to QM_BATCH_NOALLOC_MAX_REQUESTS records, one copy per GPU, held until
+ * the process ends.  Host code never passes the array's name to a kernel or
+ * a copy (on the host it is only a stand-in for the symbol): it uses the
+ * device address that batch_scratch_address looks up once per device.
+ */
+static __device__ __align__(256) unsigned char scratch[BATCH_SCRATCH_BYTES];
+
+hipError_t batch_scratch_address(int device, void** out)
+{
+    static std::mutex mu;
+    static void* addr[BATCH_SCRATCH_MAX_DEVICES] = {};
+    *out = nullptr;
+    if (device < 0 || device >= BATCH_SCRATCH_MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(mu);
+    if (!addr[device]) {
+        int cur = -1;
+        hipError_t e = hipGetDevice(&cur);
+        if (e != hipSuccess) return e;
+        if (cur != device) return hipErrorInvalidDevice;   /* the caller makes `device` current */
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        addr[device] = p;
+    }
+    *out = addr[device];
+    return hipSuccess;
 }
 
 hipError_t launch_batch(BatchHeader* d_hdr, const BatchReq* d_reqs, size_t lds_bytes, uint64_t blocks, hipStream_t s)

@@ -37,5 +37,12 @@ struct qm_ctx {
     qm::Server* server = nullptr;
     qm::BatchRunner* runner = nullptr;
     int cus = 256;
+    /* qm_run_batch_noalloc: the device array of this GPU (looked up at
+       init), a pinned host buffer of the same size and the event that
+       marks the last upload from it, all set up by qm_init */
+    void* noalloc_dev = nullptr;
+    void* noalloc_host = nullptr;
+    hipEvent_t noalloc_ev = nullptr;
+    std::mutex noalloc_mu;
 };
 

@@ -302,6 +302,51 @@ qm_status enqueue_batch(qm_ctx* ctx, const qm_request* reqs, uint64_t count, hip
     return QM_OK;
 }
 
+/*
+ * The allocation-free form of enqueue_batch: descriptors are planned into
+ * the context's pinned host buffer (once the previous upload from it has
+ * completed), copied to the GPU's fixed descriptor array on s and launched
+ * from there.  No table is built and nothing is allocated.
+ */
+qm_status enqueue_batch_noalloc(qm_ctx* ctx, const qm_request* reqs, uint64_t count, hipStream_t s)
+{
+    qm_status st = validate_batch(ctx, reqs, count);
+    if (st != QM_OK) return st;
+    uint64_t live = 0;
+    for (uint64_t i = 0; i < count; ++i) live += reqs[i].n != 0;
+    if (live > QM_BATCH_NOALLOC_MAX_REQUESTS) {
+        char msg[160];
+        snprintf(msg, sizeof msg, "%llu requests with n > 0; the allocation-free batch takes at most %d",
+                 (unsigned long long)live, QM_BATCH_NOALLOC_MAX_REQUESTS);
+        return set_error(QM_E_INVAL, msg);
+    }
+    if (!ctx->noalloc_dev || !ctx->noalloc_host || !ctx->noalloc_ev)
+        return set_error(QM_E_HIP, "allocation-free batch path not set up");
+    std::lock_guard<std::mutex> lk(ctx->noalloc_mu);
+    hipError_t e = hipEventSynchronize(ctx->noalloc_ev);
+    if (e != hipSuccess) return set_error(QM_E_HIP, hipGetErrorString(e));
+    BatchHeader h;
+    size_t lds = 0;
+    BatchReq* staged = reinterpret_cast<BatchReq*>(static_cast<char*>(ctx->noalloc_host) + sizeof(BatchHeader));
+    uint64_t k = 0;
+    st = plan_batch(ctx, reqs, count, false, &h, &lds, [&](const BatchReq& b) {
+        staged[k++] = b;
+        return (qm_status)QM_OK;
+    });
+    if (st != QM_OK) return st;
+    if (k == 0) return QM_OK;
+    memcpy(ctx->noalloc_host, &h, sizeof h);
+    const size_t bytes = sizeof(BatchHeader) + k * sizeof(BatchReq);
+    e = hipMemcpyAsync(ctx->noalloc_dev, ctx->noalloc_host, bytes, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipEventRecord(ctx->noalloc_ev, s);
+    if (e == hipSuccess)
+        e = launch_batch(static_cast<BatchHeader*>(ctx->noalloc_dev),
+                         reinterpret_cast<const BatchReq*>(static_cast<char*>(ctx->noalloc_dev) + sizeof h), lds,
+                         batch_blocks(ctx, h.total_chunks), s);
+    if (e != hipSuccess) return set_error(QM_E_HIP, hipGetErrorString(e));
+    return QM_OK;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Serving loop                                                             */
 /* ------------------------------------------------------------------------ */
@@ -524,6 +569,11 @@ extern "C" {
 qm_status qm_run_batch(qm_ctx* ctx, const qm_request* reqs, uint64_t count, void* hip_stream)
 {
     return qm::enqueue_batch(ctx, reqs, count, (hipStream_t)hip_stream, nullptr);
+}
+
+qm_status qm_run_batch_noalloc(qm_ctx* ctx, const qm_request* reqs, uint64_t count, void* hip_stream)
+{
+    return qm::enqueue_batch_noalloc(ctx, reqs, count, (hipStream_t)hip_stream);
 }
 
 qm_status qm_submit(qm_ctx* ctx, const qm_request* req, uint64_t* ticket)
