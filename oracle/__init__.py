@@ -20,6 +20,9 @@ precision, see oracle.c):
   vg_map(v, lam, alpha, beta)  F^{-1}(F0(v)), the same base -> variance-gamma
                           target with integer lambda (Section 8.2; vg.c)
   vg_masses(...), vg_log_tail(x, ...)  as for the hyperbolic target
+  vgr_map(v, lam, alpha, beta)  the same map for real lambda >= 1, by the
+                          Bessel-integral form of the masses (vg_real.c)
+  vgr_masses(...), vgr_log_tail(x, ...), vgr_central_mass(x, ...)
 """
 import ctypes
 import os
@@ -28,7 +31,7 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRC = [os.path.join(_HERE, "oracle.c"), os.path.join(_HERE, "hyperbolic.c"), os.path.join(_HERE, "vg.c")]
+_SRC = [os.path.join(_HERE, f) for f in ("oracle.c", "hyperbolic.c", "vg.c", "vg_real.c")]
 _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
@@ -78,6 +81,18 @@ def _load():
     lib.oracle_vg_masses.restype = ctypes.c_int
     lib.oracle_vg_log_tail.argtypes = [d, d, d, d]
     lib.oracle_vg_log_tail.restype = d
+    lib.oracle_vgr_map.argtypes = [dp, dp, ctypes.c_size_t, d, d, d, ctypes.c_int]
+    lib.oracle_vgr_map.restype = ctypes.c_int
+    lib.oracle_vgr_masses.argtypes = [d, d, d, dp, dp]
+    lib.oracle_vgr_masses.restype = ctypes.c_int
+    for name in ("oracle_vgr_log_tail", "oracle_vgr_central_mass"):
+        f = getattr(lib, name)
+        f.argtypes = [d, d, d, d]
+        f.restype = d
+    for name in ("oracle_vgr_log_upper_gamma", "oracle_vgr_log_lower_gamma"):
+        f = getattr(lib, name)
+        f.argtypes = [d, d]
+        f.restype = d
     _lib = lib
     return lib
 
@@ -166,3 +181,37 @@ def vg_masses(lam, alpha, beta):
 def vg_log_tail(x, lam, alpha, beta):
     """log(1 - F(x)) for x >= 0, log F(x) for x < 0."""
     return _load().oracle_vg_log_tail(float(x), float(lam), float(alpha), float(beta))
+
+
+def vgr_map(v, lam, alpha, beta, threads=0):
+    """x = F^{-1}(F0(v)): two-sided exponential base -> variance-gamma target, real lambda >= 1 (Section 8.2)."""
+    v = _as_f64(v)
+    out = np.empty_like(v)
+    _load().oracle_vgr_map(_ptr(v), _ptr(out), v.size, float(lam), float(alpha), float(beta), threads_used(threads))
+    return out
+
+
+def vgr_masses(lam, alpha, beta):
+    """(log p+, log p-) of the variance-gamma density, real lambda (Bessel-integral form)."""
+    a, b = ctypes.c_double(), ctypes.c_double()
+    if _load().oracle_vgr_masses(float(lam), float(alpha), float(beta), ctypes.byref(a), ctypes.byref(b)) != 0:
+        raise ValueError("invalid variance-gamma parameters")
+    return a.value, b.value
+
+
+def vgr_log_tail(x, lam, alpha, beta):
+    """log(1 - F(x)) for x >= 0, log F(x) for x < 0, real lambda."""
+    return _load().oracle_vgr_log_tail(float(x), float(lam), float(alpha), float(beta))
+
+
+def vgr_central_mass(x, lam, alpha, beta):
+    """int_0^|x| f on the side of x, real lambda."""
+    return _load().oracle_vgr_central_mass(float(x), float(lam), float(alpha), float(beta))
+
+
+def vgr_log_upper_gamma(a, y):
+    return _load().oracle_vgr_log_upper_gamma(float(a), float(y))
+
+
+def vgr_log_lower_gamma(a, y):
+    return _load().oracle_vgr_log_lower_gamma(float(a), float(y))
