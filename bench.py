@@ -574,6 +574,15 @@ def serve_rates(torch, qm, count, rates, seed=5, budget=64 << 30):
         z = torch.zeros(1, dtype=torch.float64, device="cuda")
         for nu in nus:                       # tables built before the clock starts
             qm.qm_recycle_student_t(ctx, z[:0], z[:0], nu)
+        # one request through the loop before the clock starts: the first
+        # submit starts the scheduler (thread, streams, events) and the first
+        # batch launch loads the kernel's code
+        wu = torch.full((4096,), 0.25, dtype=torch.float64, device="cuda")
+        wo = torch.empty_like(wu)
+        torch.cuda.synchronize()
+        wt = qm.qm_submit(ctx, qm.make_request(qm.QM_NORMAL_QUANTILE, wu, wo))
+        while qm.qm_poll(ctx, wt) == qm.QM_PENDING:
+            time.sleep(0.0002)
         torch.cuda.synchronize()
         arrivals = np.cumsum(rng.exponential(1.0 / rate, count)) if rate > 0 else np.zeros(count)
         tickets = [0] * count

@@ -14,7 +14,7 @@
  *                             x = F^{-1}(F0(v)), two-sided exponential base
  *                             -> hyperbolic target        (Section 8.1)
  *   qm_recycle_exp_to_vg      the same base -> variance-gamma target,
- *                             integer lambda               (Section 8.2)
+ *                             lambda in [1, 8]             (Section 8.2)
  *   qm_generate               the uniforms of a counter-based stream, or w
  *                             of them, drawn and mapped in one pass
  *   qm_generate_student_t, qm_generate_hyperbolic, qm_generate_vg
@@ -93,11 +93,13 @@ typedef struct qm_ctx qm_ctx;
  * The context owns the per-nu Student t tables and the serving state.
  * Each kernel family has its own launch shape (workgroups of 256 per compute
  * unit x 16-byte vectors in flight per lane, from measured sweeps: light
- * maps 2 x 4, FP64 quantile 64 x 4, FP32+refine quantile 32 x 2, Student t
- * 2 x 4 (FP64) and 3 x 4 (FP32)); the environment variables
- * QM_BLOCKS_PER_CU (1..64) and QM_UNROLL (1, 2 or 4), read here, override
- * every family, and QM_SHAPE_STREAM, QM_SHAPE_NQ64, QM_SHAPE_NQ32,
- * QM_SHAPE_T64, QM_SHAPE_T32 ("blocks,unroll") one family each.  QM_COMPACT=0 turns off the quantiles' gathering of
+ * maps 2 x 4, FP64 quantile 64 x 4, FP32+refine quantile 16 x 4, fused
+ * generation 64 x 4 (FP64) and 32 x 2 (FP32), Student t 2 x 4 (FP64) and
+ * 3 x 4 (FP32)); the environment variables QM_BLOCKS_PER_CU (1..64) and
+ * QM_UNROLL (1, 2 or 4), read here, override every family, and
+ * QM_SHAPE_STREAM, QM_SHAPE_NQ64, QM_SHAPE_NQ32, QM_SHAPE_GEN64,
+ * QM_SHAPE_GEN32, QM_SHAPE_T64, QM_SHAPE_T32, QM_SHAPE_H64, QM_SHAPE_H32
+ * ("blocks,unroll") one family each.  QM_COMPACT=0 turns off the quantiles' gathering of
  * non-central lanes across the wave (the results are bitwise the same
  * either way).
  * Errors: QM_E_INVAL (out == NULL or no such device), QM_E_HIP, QM_E_NOMEM.
@@ -129,7 +131,7 @@ qm_status qm_normal_quantile(qm_ctx* ctx, const void* d_u, void* d_w, uint64_t n
 /*
  * t[i] = F_nu^{-1}(Phi(z[i])), the normal -> Student t recycling map
  * (Section 1 recycling composite, Section 3).  nu is the real number of
- * degrees of freedom: finite and >= 0.5, or +inf (identity).  The map is
+ * degrees of freedom: finite and >= 0.3, or +inf (identity).  The map is
  * the solution of the Gaussian-background recycling ODE (Section 3.1) with
  * centre conditions Q(0) = 0, Q'(0) = gamma (Section 3.1); the library
  * integrates it on the host once per nu (cached in the context) and
@@ -141,7 +143,8 @@ qm_status qm_normal_quantile(qm_ctx* ctx, const void* d_u, void* d_w, uint64_t n
  * w = K q(|z|).  z = +-inf -> +-inf, NaN -> NaN, and t may overflow to
  * +-inf for small nu.
  * dtype/mode: F64 PLAIN; F32 F32_REFINE.
- * Errors: QM_E_INVAL for nu < 0.5, NaN or -inf.
+ * Errors: QM_E_INVAL for nu < 0.3, NaN or -inf (below 0.3 the per-nu
+ * cells that meet 2e-15 no longer fit the 64 KB of LDS a launch may use).
  */
 qm_status qm_recycle_student_t(qm_ctx* ctx, const void* d_z, void* d_t, uint64_t n,
                                int dtype, int mode, double nu, void* hip_stream);
@@ -191,19 +194,27 @@ qm_status qm_hyperbolic_masses(qm_ctx* ctx, double alpha, double beta, double de
 
 /*
  * x[i] = mu + Q(v[i]), the exponential -> variance-gamma recycling map
- * (Section 8.2) for integer lambda in [1, 8].  Target: the variance-gamma
+ * (Section 8.2) for real lambda in [1, 8].  Target: the variance-gamma
  * density
  *   f(x) = (alpha^2 - beta^2)^lambda e^{beta (x-mu)} |x-mu|^{lambda-1/2} K_{lambda-1/2}(alpha |x-mu|)
  *          / ((2 alpha)^{lambda-1/2} sqrt(pi) Gamma(lambda)),  |beta| < alpha,
  * from the same two-sided exponential base as qm_recycle_exp_to_hyperbolic
- * with this target's masses (qm_vg_masses).  For integer lambda the Bessel
- * function is elementary, so the library solves the defining equation
- * directly (no ODE) on the host once per (lambda, alpha, beta) and
- * evaluates the same piecewise polynomials with the same kernel; lambda = 1
- * is the base itself (Q(v) = v).  Accuracy as for the hyperbolic map.
+ * with this target's masses (qm_vg_masses).  The library builds, on the
+ * host once per (lambda, alpha, beta), the same piecewise polynomials as
+ * for the hyperbolic map and evaluates them with the same kernel.  For
+ * integer lambda the Bessel function is elementary and each side's map is
+ * solved directly from its closed-form masses; lambda = 1 is the base
+ * itself (Q(v) = v).  For other lambda the recycling ODE of Section 8.2 is
+ * integrated, with H = alpha K_{lambda-3/2}/K_{lambda-1/2} - beta from the
+ * Riccati equation of that Bessel ratio and the origin's non-analytic
+ * neighbourhood from its expansion (a build takes a few seconds).  Near
+ * lambda = 1 that neighbourhood needs cells finer than the table layout
+ * holds: lambda below about 1.3 (non-integer) is reported as QM_E_INVAL
+ * with the builder's message.  Accuracy as for the hyperbolic map.
  * dtype/mode: F64 PLAIN; F32 F32_REFINE.
- * Errors: QM_E_INVAL for lambda not an integer in [1, 8], alpha <= |beta|,
- * a non-finite parameter or mu, NULL, unaligned or overlapping buffers.
+ * Errors: QM_E_INVAL for lambda outside [1, 8] or a table the builder
+ * cannot meet the accuracy for, alpha <= |beta|, a non-finite parameter or
+ * mu, NULL, unaligned or overlapping buffers.
  */
 qm_status qm_recycle_exp_to_vg(qm_ctx* ctx, const void* d_v, void* d_x, uint64_t n, int dtype, int mode, double lambda,
                                double alpha, double beta, double mu, void* hip_stream);
@@ -267,8 +278,8 @@ qm_status qm_generate_hyperbolic(qm_ctx* ctx, uint64_t seed, uint64_t stream, ui
                                  void* hip_stream);
 
 /*
- * Fused generation of variance-gamma samples (Section 8.2, integer lambda
- * in [1, 8]): as qm_generate_hyperbolic, with the variance-gamma target's
+ * Fused generation of variance-gamma samples (Section 8.2, lambda in
+ * [1, 8]): as qm_generate_hyperbolic, with the variance-gamma target's
  * masses (qm_vg_masses) and the map of qm_recycle_exp_to_vg.
  */
 qm_status qm_generate_vg(qm_ctx* ctx, uint64_t seed, uint64_t stream, uint64_t first, void* d_out, uint64_t n,

@@ -121,7 +121,7 @@ __global__ __launch_bounds__(256) void k_generate(GenArgs<T> a)
 template <typename T, class H, bool GATHER>
 static hipError_t launch_gen(GenArgs<T> a, hipStream_t s, const LaunchShape& shape_all)
 {
-    const KernelShape shape = shape_all.hybrid[sizeof(T) == 8];
+    const KernelShape shape = shape_all.generate[sizeof(T) == 8];
     constexpr int NV = vec16<T>::n;
     a.head = (NV - a.first % NV) % NV;
     bool vector = a.head <= a.n && (a.n - a.head) >= (uint64_t)NV &&
@@ -421,7 +421,7 @@ hipError_t launch_generate_student(int dtype, int mode, uint32_t seed, uint32_t 
     const double* coef = table_block(d_table) + c.coef_offset;
     const StudentParams P = make_params(h, c, coef);
     const size_t lds = (size_t)c.nlds * P.lds_stride * sizeof(double);
-    const KernelShape ks = shape.hybrid[f64];
+    const KernelShape ks = shape.generate[f64];
     /* the quantile stage gathers per wave when its buffer fits beside the
        table (bitwise the same results either way) */
     const bool gather = shape.compact &&

@@ -176,7 +176,7 @@ bool make_hyp_params(const HypTableHeader& h, bool f32, const HypTableHeader* d_
     if (!side_valid(R, deg, ncoef) || !side_valid(L, deg, ncoef) || R.v0 != L.v0 || R.inv_v0 != L.inv_v0)
         return false;
     const double* d_block = reinterpret_cast<const double*>(reinterpret_cast<const char*>(d_table) + sizeof(HypTableHeader));
-    const int stride = deg + 2;   /* HypRow<deg>::lds */
+    const int stride = f32 ? HypRow<HYP_DEGREE_F32>::lds : HypRow<HYP_DEGREE>::lds;
     /* LDS cells per side: through the octave reaching 64 / rate on either
        side, within both sides' cells and the LDS budget */
     int noct = std::max(octaves_to(R.v0, h.alpha - h.beta), octaves_to(R.v0, h.alpha + h.beta));

@@ -12,12 +12,19 @@
 
 namespace qm {
 
-/* Rows of DEG + 1 doubles; in LDS one double of padding staggers the rows
-   over the banks (rows of 12 or 8 doubles would otherwise start on the
-   same few banks). */
+/* Rows of DEG + 1 doubles in global memory.  In LDS, the FP64-output
+   cells keep their doubles with one of padding, which staggers the rows
+   over the banks (rows of 12 doubles would otherwise start on the same few
+   banks).  The FP32-output cells (degree 7) are stored mixed: the constant
+   term as a double (dwords 0-1), the seven higher coefficients as floats,
+   highest power first (dwords 2-8), padded to 12 dwords.  Such a row is
+   two 16-byte reads and one 4-byte read (36 bytes, against 64 for eight
+   doubles), and rows on 16-byte boundaries either share a 16-byte bank
+   group or none, so lanes on different cells never half-overlap.  lds is
+   the row stride in doubles. */
 template <int DEG> struct HypRow {
     static constexpr int n = DEG + 1;
-    static constexpr int lds = DEG + 2;
+    static constexpr int lds = DEG == HYP_DEGREE_F32 ? 6 : DEG + 2;
 };
 static_assert(HYP_SUB == 8, "the cell index takes the top 3 mantissa bits of t");
 
@@ -56,6 +63,39 @@ __device__ __forceinline__ double hyp_poly(const double* __restrict__ c, double 
     return R;
 }
 
+/*
+ * R of LDS row `row` at d.  FP64-output cells: Horner in FP64.  FP32-output
+ * cells: R = c0 + d S(d), S the seven higher terms by Horner in FP32 from
+ * float coefficients, c0 and the last step in FP64.  Across every cell the
+ * builder produces, |R - c0| stays a small part of |R| (below 6% for the
+ * parameters tested), so the FP32 part adds a relative error of about
+ * 0.06 x 2^-22 to R, far below the half-ulp of the FP32 result.
+ */
+template <int DEG>
+__device__ __forceinline__ double hyp_cell(const double* __restrict__ lds, int row, double d)
+{
+    if constexpr (DEG == HYP_DEGREE_F32) {
+        typedef float f4v __attribute__((ext_vector_type(4)));
+        typedef double d2v __attribute__((ext_vector_type(2)));
+        const double* r = lds + row * HypRow<DEG>::lds;
+        const d2v a = *reinterpret_cast<const d2v*>(r);            /* c0, then the top two floats */
+        const f4v b = *reinterpret_cast<const f4v*>(r + 2);
+        const float last = reinterpret_cast<const float*>(r + 4)[0];
+        const double c0 = a.x;
+        const float f0 = __int_as_float(__double2loint(a.y)), f1 = __int_as_float(__double2hiint(a.y));
+        const float df = (float)d;
+        float S = __builtin_fmaf(f0, df, f1);
+        S = __builtin_fmaf(S, df, b.x);
+        S = __builtin_fmaf(S, df, b.y);
+        S = __builtin_fmaf(S, df, b.z);
+        S = __builtin_fmaf(S, df, b.w);
+        S = __builtin_fmaf(S, df, last);
+        return __builtin_fma(d, (double)S, c0);
+    } else {
+        return hyp_poly<DEG>(lds + row * HypRow<DEG>::lds, d);
+    }
+}
+
 /* |Q(v)| from the LDS cells; *far for lanes beyond them (and NaN). */
 template <int DEG>
 __device__ __forceinline__ double hyp_near(double v, const double* __restrict__ lds, const HypParams& P, bool* far)
@@ -69,7 +109,7 @@ __device__ __forceinline__ double hyp_near(double v, const double* __restrict__ 
     j = out ? P.nlds - 1 : j;                     /* far and NaN lanes stay in bounds */
     const int row = j + (v < 0.0 ? P.nlds : 0);
     const double d = __builtin_fma(-P.v0, tc - 1.0, a);   /* a - centre; tc - 1 is exact */
-    return a * hyp_poly<DEG>(lds + row * HypRow<DEG>::lds, d);
+    return a * hyp_cell<DEG>(lds, row, d);
 }
 
 /* |Q(v)| beyond the LDS cells: the side's global-memory cells up to v_top,
@@ -104,7 +144,8 @@ __device__ __forceinline__ double hyp_far_of(double v, const HypParams& P)
                    neg ? P.l.gcoef : P.r.gcoef, neg ? P.l.ncell : P.r.ncell);
 }
 
-/* Both sides' LDS rows: right side rows 0..nlds-1, left side after. */
+/* Both sides' LDS rows: right side rows 0..nlds-1, left side after (for
+   the FP32-output cells in the mixed layout of HypRow). */
 template <int DEG>
 __device__ __forceinline__ void stage_hyp(double* lds, const HypParams& P)
 {
@@ -114,7 +155,14 @@ __device__ __forceinline__ void stage_hyp(double* lds, const HypParams& P)
         const bool left = i >= n;
         const int e = left ? i - n : i;
         const int row = e / W, col = e - row * W;
-        lds[((left ? P.nlds : 0) + row) * HypRow<DEG>::lds + col] = (left ? P.l.gcoef : P.r.gcoef)[e];
+        const int r = (left ? P.nlds : 0) + row;
+        const double c = (left ? P.l.gcoef : P.r.gcoef)[e];
+        if constexpr (DEG == HYP_DEGREE_F32) {
+            if (col == DEG) lds[r * HypRow<DEG>::lds] = c;
+            else reinterpret_cast<float*>(lds)[2 * r * HypRow<DEG>::lds + 2 + col] = (float)c;
+        } else {
+            lds[r * HypRow<DEG>::lds + col] = c;
+        }
     }
 }
 

@@ -568,7 +568,7 @@ fq fit_cell(const SideMap& ss, int deg, fq lo, fq hi, double* row, fq* rounded)
     }
     cheb_to_monomial(fv, deg, hw, mono);
     for (int k = 0; k <= deg; ++k) row[deg - k] = (double)mono[k];
-    fq worst = 0, worst_r = 0;
+    fq worst = 0, worst_r = 0, share = 0;
     const int NT = 2 * deg;
     for (int t = 0; t <= NT; ++t) {
         fq d = -hw + 2 * hw * t / NT;
@@ -580,7 +580,13 @@ fq fit_cell(const SideMap& ss, int deg, fq lo, fq hi, double* row, fq* rounded)
         fq et = fabsq(pe / ref - 1), er = fabsq(pr / ref - 1);
         if (et > worst) worst = et;
         if (er > worst_r) worst_r = er;
+        fq sh = fabsq((pe - mono[0]) / ref);
+        if (sh > share) share = sh;
     }
+    /* the FP32-output cells are evaluated as c0 + d S(d) with S in FP32
+       (qm_hyp_device.hpp), which needs the non-constant part to stay a small
+       share of R: a cell where it exceeds 1/8 counts as missing the target */
+    if (deg == HYP_DEGREE_F32 && share > 0.125Q) worst = 1;
     *rounded = worst_r;
     return worst;
 }
@@ -846,10 +852,449 @@ struct VGSide : SideMap {
     }
 };
 
+/*
+ * Variance-gamma sides (Section 8.2) for real lambda in (1, 8]: the
+ * recycling ODE, as the paper prescribes ("solved as before"),
+ *     Q'' + r Q' = H(Q) Q'^2,  H(x) = alpha K_{nu-1}(alpha x)/K_nu(alpha x) - beta,
+ * r = alpha - beta, nu = lambda - 1/2 (Section 8.2 gives H).  Two pieces of
+ * analysis carry it:
+ *
+ * The Bessel ratio R(z) = K_{nu-1}(z)/K_nu(z).  From K'_nu = -K_{nu-1} - (nu/z) K_nu
+ * and K'_{nu-1} = -K_nu + ((nu-1)/z) K_{nu-1} (DLMF 10.29.2), R solves the
+ * Riccati equation R' = R^2 + (2 nu - 1) R / z - 1, and L(z) = log(z^nu K_nu(z)) + z
+ * solves L' = 1 - R.  Both are integrated by the Taylor-series method
+ * backwards from z = 45, where the large-z expansion
+ *     K_mu(z) ~ sqrt(pi/(2z)) e^{-z} sum_k a_k(mu) z^{-k},
+ *     a_k = a_{k-1} (4 mu^2 - (2k-1)^2) / (8k)     (DLMF 10.40.2)
+ * is good to e^{-2z}, down to z = 1e-30: backwards R is the decaying
+ * (minimal) solution, so errors shrink.  The build checks L near 0 against
+ * its exact limit log(2^{nu-1} Gamma(nu)).  The density is then
+ *     log f(x) = log A - nu log alpha + L(alpha x) - r x.
+ *
+ * The origin.  For non-integer lambda the density has a term in x^{2 lambda - 1}
+ * at 0, so Q is not analytic at v = 0 (the paper leaves these cases to an
+ * analytical estimate in a small neighbourhood of the origin, the numerical
+ * solution starting a small distance away).  Here that estimate is
+ * Q = Q'(0) v + Q''(0) v^2 / 2, Q''(0) = -r Q'(0) - beta Q'(0)^2 (H(0) = -beta
+ * for lambda > 1), whose remainder is O(v^2, v^{2 lambda - 1}) relative;
+ * it holds to 1e-34 below v_min = min(1e-17, 10^{-34/(2 lambda - 1)}).  A
+ * leg starts there and runs forwards, with steps growing with v, to
+ * v_s = 1/(8 max(1, r)), where it must agree with a direct solve of
+ * int_0^Q f = p (1 - e^{-r v_s}) (Gauss-Legendre on panels halving towards
+ * 0).  (Integrated towards 0 instead, the ODE's translation mode, an
+ * absolute shift of Q(v + d), would turn rounding into a relative error d/v
+ * that grows without bound.)
+ *
+ * As for the hyperbolic target, a forward leg from v_s meets, at
+ * v = 20/r, a backward leg from an anchor where Q solves the tail
+ * condition log(1 - F(Q)) = log p - r v_a directly (Gauss-Laguerre in
+ * the distance past Q, exact for the tail's slowly varying factor once
+ * r Q >= 24), and Q is that direct solve beyond the anchor.  In v the
+ * system is Q' = P, P' = -r P + (alpha R - beta) P^2,
+ * R' = alpha P (R^2 - 1) + (2 nu - 1) R P / Q; forwards in z the Riccati
+ * equation is unstable (its dominant solutions are I-type), so every
+ * step takes R(alpha Q) afresh from the backward Bessel solution and the
+ * recurrence only supplies its higher Taylor coefficients.
+ *
+ * The masses are the paper's closed form (A&S 6.621.3), with the Pfaff
+ * transformation 2F1(a, b; c; z) = (1 - z)^{-b} 2F1(c - a, b; c; z/(z - 1))
+ * (DLMF 15.8.1) turning it into a series in w = (1 + beta/alpha)/2 < 1:
+ *     p+ = 2^{lambda-1} (1 + beta/alpha)^lambda Gamma(lambda + 1/2)
+ *          2F1(1 - lambda, lambda; lambda + 1; w) / (sqrt(pi) Gamma(lambda + 1));
+ * the build checks them against quadrature of f.  The large-v form is the
+ * log one, from K_nu's expansion: 1 - F(x) ~ (A sqrt(pi/(2 alpha))/r)
+ * e^{-r x} x^{lambda-1} (1 + s1/x + s2/x^2), s1 = (lambda - 1)/r + e1,
+ * s2 = (lambda - 1)(lambda - 2)/r^2 + e1 (lambda - 2)/r + e2, e_k = a_k(nu)/alpha^k.
+ */
+struct BesselRatio {
+    struct Node {
+        fq z0, h;
+        fq R[TM + 1], L[TM + 1];
+    };
+    fq nu = 0;
+    fq z_big = 45, z_min = 1e-30Q;
+    fq L0 = 0;                 /* log(2^{nu-1} Gamma(nu)), the limit of L at 0 */
+    std::vector<Node> nodes;   /* z decreasing */
+
+    static fq series(fq mu, fq z)
+    {
+        fq a = 1, sum = 1;
+        for (int k = 1; k < 200; ++k) {
+            fq an = a * (4 * mu * mu - (fq)(2 * k - 1) * (fq)(2 * k - 1)) / (8 * k * z);
+            if (fabsq(an) >= fabsq(a) && k > 1) break;   /* past the smallest term */
+            a = an;
+            sum += a;
+            if (fabsq(a) <= 1e-38Q * fabsq(sum)) break;
+        }
+        return sum;
+    }
+    void asym(fq z, fq* R, fq* L) const
+    {
+        const fq sn = series(nu, z);
+        *R = series(nu - 1, z) / sn;
+        *L = nu * logq(z) + 0.5Q * logq(M_PIq / (2 * z)) + logq(sn);
+    }
+    /* Taylor coefficients of R and L about z0 from R[0], L[0] */
+    void step(Node& n) const
+    {
+        fq W[TM + 1], RR[TM + 1], RW[TM + 1];
+        for (int k = 0; k <= TM; ++k) W[k] = (k % 2 ? -1 : 1) / powq(n.z0, k + 1);   /* 1/z */
+        for (int k = 0; k < TM; ++k) {
+            fq rr = 0, rw = 0;
+            for (int i = 0; i <= k; ++i) {
+                rr += n.R[i] * n.R[k - i];
+                rw += n.R[i] * W[k - i];
+            }
+            RR[k] = rr;
+            RW[k] = rw;
+            n.R[k + 1] = (RR[k] + (2 * nu - 1) * RW[k] - (k == 0 ? 1 : 0)) / (k + 1);
+            n.L[k + 1] = ((k == 0 ? 1 : 0) - n.R[k]) / (k + 1);
+        }
+    }
+    bool build(fq nu_, char* err, int errlen)
+    {
+        nu = nu_;
+        L0 = (nu - 1) * M_LN2q + lgammaq(nu);
+        Node n;
+        n.z0 = z_big;
+        asym(z_big, &n.R[0], &n.L[0]);
+        for (int guard = 0; guard < 100000; ++guard) {
+            step(n);
+            fq scale = fabsq(n.R[0]) + fabsq(n.L[0]) + 1e-300Q, h = n.z0 / 4;
+            for (int k = TM - 1; k <= TM; ++k) {
+                fq m = fabsq(n.R[k]) + fabsq(n.L[k]);
+                if (m == 0) continue;
+                fq hk = powq(1e-36Q * scale / m, 1.0Q / k);
+                if (hk < h) h = hk;
+            }
+            const bool last = n.z0 - h <= z_min;
+            if (last) h = n.z0 - z_min;
+            n.h = -h;
+            nodes.push_back(n);
+            Node m;
+            m.z0 = n.z0 - h;
+            m.R[0] = horner(n.R, n.h);
+            m.L[0] = horner(n.L, n.h);
+            n = m;
+            if (last) {
+                /* L(z) - z tends to log(2^{nu-1} Gamma(nu)); at 1e-30 the
+                   remaining terms are O(z^{min(2 nu, 2)} log z) */
+                if (!(fabsq(m.L[0] - m.z0 - L0) < 1e-28Q)) {
+                    snprintf(err, errlen, "Bessel ratio integration missed its limit at 0 by %.3e",
+                             (double)fabsq(m.L[0] - m.z0 - L0));
+                    return false;
+                }
+                return true;
+            }
+        }
+        snprintf(err, errlen, "Bessel ratio integration exceeded its step budget");
+        return false;
+    }
+    /* R(z) and L(z) for z > 0 */
+    void eval(fq z, fq* R, fq* L) const
+    {
+        if (z >= z_big) {
+            asym(z, R, L);
+            return;
+        }
+        if (z <= z_min) {            /* z^nu K_nu -> 2^{nu-1} Gamma(nu); R -> 0 (nu > 1/2) */
+            *R = 0;
+            *L = L0 + z;
+            return;
+        }
+        size_t lo = 0, hi = nodes.size() - 1;     /* node with z0 + h <= z <= z0 */
+        while (lo < hi) {
+            size_t mid = (lo + hi) / 2;
+            if (z < nodes[mid].z0 + nodes[mid].h) lo = mid + 1; else hi = mid;
+        }
+        const Node& n = nodes[lo];
+        *R = horner(n.R, z - n.z0);
+        *L = horner(n.L, z - n.z0);
+    }
+};
+
+struct VGRealSide : SideMap {
+    struct VNode {
+        fq v0, h;
+        fq Q[TM + 1], P[TM + 1];
+    };
+    fq lambda, nu, alpha, beta;
+    fq logA, log_p, log_f0, q2;
+    BesselRatio bes;
+    std::vector<VNode> zero, fwd, bwd;     /* legs: v_min -> v_s, v_s -> v_match, v_a -> v_match */
+    fq v_min, v_s, v_match, v_a;
+
+    fq log_f(fq x) const
+    {
+        fq R, L;
+        bes.eval(alpha * x, &R, &L);
+        return logA - nu * logq(alpha) + L - rate * x;
+    }
+    /* int_0^x f by 24-point Gauss-Legendre on [x/2^{k+1}, x/2^k], k < 120 (the
+       panels keep the x^{2 lambda - 1} term at 0 a panel-width away), plus
+       f(0) times the rest */
+    fq central_mass(fq x) const
+    {
+        const GL& g = gl();
+        fq sum = 0;
+        fq b = x;
+        for (int k = 0; k < 120; ++k) {
+            const fq a = b / 2, c = (a + b) / 2, r = (b - a) / 2;
+            fq p = 0;
+            for (int i = 0; i < GLN; ++i) p += g.w[i] * expq(log_f(c + r * g.x[i]));
+            sum += p * r;
+            b = a;
+        }
+        return sum + expq(log_f0) * b;
+    }
+    /* log(1 - F(x)) far out (r x >= 80, alpha x >= 45): with K_nu's expansion
+       f(t) = A sqrt(pi/(2 alpha)) t^{lambda-1} e^{-r t} sum_j e_j t^{-j},
+       e_j = a_j(nu) alpha^{-j}, and int_x^inf t^mu e^{-r t} dt =
+       e^{-r x} x^mu / r sum_m mu (mu - 1) ... (mu - m + 1) (r x)^{-m}, both
+       asymptotic series good to e^{-min(2 alpha x, r x)} < 1e-34 here. */
+    fq log_tail_far(fq x) const
+    {
+        fq B = 0, e = 1;
+        for (int j = 0; j < 200; ++j) {
+            if (j > 0) {
+                const fq en = e * (4 * nu * nu - (fq)(2 * j - 1) * (fq)(2 * j - 1)) / (8 * j * alpha * x);
+                if (fabsq(en) >= fabsq(e) && j > 1) break;
+                e = en;
+            }
+            const fq mu = lambda - 1 - j;
+            fq term = e, inner = 0;
+            for (int m = 0; m < 400; ++m) {
+                inner += term;
+                const fq tn = term * (mu - m) / (rate * x);
+                if (fabsq(tn) >= fabsq(term) && m > 0) break;
+                term = tn;
+                if (fabsq(term) <= 1e-38Q * fabsq(B + inner)) break;
+            }
+            B += inner;
+            if (fabsq(e) <= 1e-38Q * fabsq(B)) break;
+        }
+        return logA + 0.5Q * logq(M_PIq / (2 * alpha)) - logq(rate) - rate * x + (lambda - 1) * logq(x) + logq(B);
+    }
+    /* log(1 - F(x)) for r x >= 24: with t = x + u/r,
+       1 - F(x) = e^{-r x}/r int_0^inf e^{-u} [f(t) e^{r t}] du by Gauss-Laguerre;
+       far out, the expansion above */
+    fq log_tail(fq x) const
+    {
+        if (rate * x >= 80 && alpha * x >= 45) return log_tail_far(x);
+        const Laguerre& G = laguerre();
+        fq s = 0;
+        for (int i = 0; i < GLAG; ++i) {
+            fq t = x + G.t[i] / rate;
+            s += G.w[i] * expq(log_f(t) + rate * t);
+        }
+        return logq(s) - rate * x - logq(rate);
+    }
+    /* p+ from the paper's 2F1 closed form (series after the Pfaff transformation) */
+    static fq log_mass(fq lam, fq alpha, fq beta)
+    {
+        const fq w = (1 + beta / alpha) / 2;
+        fq term = 1, F = 1;
+        for (int n = 0; n < 200000; ++n) {
+            term *= (1 - lam + n) * (lam + n) / ((lam + 1 + n) * (n + 1)) * w;
+            F += term;
+            if (fabsq(term) <= 1e-36Q * fabsq(F)) break;
+        }
+        return (lam - 1) * M_LN2q + lam * logq(1 + beta / alpha) + lgammaq(lam + 0.5Q) + logq(F) -
+               0.5Q * logq(M_PIq) - lgammaq(lam + 1);
+    }
+
+    /* Taylor coefficients of (Q, P) about v0 from Q[0], P[0], with R(alpha Q0)
+       from the Bessel solution */
+    void vstep(VNode& n) const
+    {
+        fq R[TM + 1], PP[TM + 1], RPP[TM + 1], RRm[TM + 1], PRR[TM + 1], RP[TM + 1], D[TM + 1];
+        fq L;
+        bes.eval(alpha * n.Q[0], &R[0], &L);
+        for (int k = 0; k < TM; ++k) {
+            fq pp = 0, rr = 0, rp = 0;
+            for (int i = 0; i <= k; ++i) {
+                pp += n.P[i] * n.P[k - i];
+                rr += R[i] * R[k - i];
+                rp += R[i] * n.P[k - i];
+            }
+            PP[k] = pp;
+            RRm[k] = rr - (k == 0 ? 1 : 0);
+            RP[k] = rp;
+            fq rpp = 0, prr = 0, qd = 0;
+            for (int i = 0; i <= k; ++i) {
+                rpp += R[i] * PP[k - i];
+                prr += n.P[i] * RRm[k - i];
+            }
+            for (int i = 1; i <= k; ++i) qd += n.Q[i] * D[k - i];
+            RPP[k] = rpp;
+            PRR[k] = prr;
+            D[k] = (RP[k] - qd) / n.Q[0];                      /* R P / Q */
+            n.Q[k + 1] = n.P[k] / (k + 1);
+            n.P[k + 1] = (-rate * n.P[k] + alpha * RPP[k] - beta * PP[k]) / (k + 1);
+            R[k + 1] = (alpha * PRR[k] + (2 * nu - 1) * D[k]) / (k + 1);
+        }
+    }
+    /* Taylor steps from (v, Q, P) to v1 (steps also within |v|/3 of the
+       current point, the distance to the origin's singularity) */
+    bool leg(fq v, fq Q, fq P, fq v1, std::vector<VNode>& out) const
+    {
+        const fq dir = v1 > v ? 1 : -1;
+        for (int guard = 0; guard < 20000; ++guard) {
+            VNode n;
+            n.v0 = v;
+            n.Q[0] = Q;
+            n.P[0] = P;
+            vstep(n);
+            fq scale = fabsq(n.Q[0]) + fabsq(n.P[0]) * 1e-3Q + 1e-300Q;
+            fq h = fminq(0.25Q + 0.05Q * fabsq(v), fabsq(v) / 3);
+            for (int k = TM - 1; k <= TM; ++k) {
+                if (n.Q[k] == 0) continue;
+                fq hk = powq(1e-36Q * scale / fabsq(n.Q[k]), 1.0Q / k);
+                if (hk < h) h = hk;
+            }
+            const bool last = fabsq(v1 - v) <= h;
+            if (last) h = fabsq(v1 - v);
+            n.h = dir * h;
+            out.push_back(n);
+            Q = horner(n.Q, n.h);
+            P = horner(n.P, n.h);
+            v += n.h;
+            if (last) return true;
+        }
+        return false;
+    }
+    static fq leg_eval(const std::vector<VNode>& nd, fq v)
+    {
+        size_t lo = 0, hi = nd.size() - 1;
+        const bool up = nd.front().h > 0;
+        while (lo < hi) {
+            size_t mid = (lo + hi) / 2;
+            fq a = nd[mid].v0, b = nd[mid].v0 + nd[mid].h;
+            fq lo_v = up ? a : b, hi_v = up ? b : a;
+            if (v < lo_v) {
+                if (up) hi = mid; else lo = mid + 1;
+            } else if (v > hi_v) {
+                if (up) lo = mid + 1; else hi = mid;
+            } else {
+                lo = hi = mid;
+            }
+        }
+        return horner(nd[lo].Q, v - nd[lo].v0);
+    }
+    /* Newton on the central form int_0^x f = p (1 - e^{-r v}) */
+    fq solve_central(fq v) const
+    {
+        const fq target = -expq(log_p) * expm1q(-rate * v);
+        fq x = slope0 * v;
+        for (int it = 0; it < 60; ++it) {
+            fq dx = (central_mass(x) - target) / expq(log_f(x));
+            fq xn = x - dx;
+            if (!(xn > 0)) xn = x / 2;
+            if (fabsq(xn - x) <= 1e-33Q * xn) return xn;
+            x = xn;
+        }
+        return x;
+    }
+    /* Newton on log(1 - F(x)) = log p - r v (r x >= 24) */
+    fq solve_tail(fq v, fq x0) const
+    {
+        const fq target = log_p - rate * v;
+        fq x = x0;
+        for (int it = 0; it < 60; ++it) {
+            fq lt = log_tail(x);
+            fq xn = x + (lt - target) * expq(lt - log_f(x));
+            if (fabsq(xn - x) <= 1e-33Q * xn) return xn;
+            x = xn;
+        }
+        return x;
+    }
+
+    fq eval(fq v) const override
+    {
+        if (v <= v_min) return v * (slope0 + q2 * v);
+        if (v <= v_s) return leg_eval(zero, v);
+        if (v <= v_match) return leg_eval(fwd, v);
+        if (v <= v_a) return leg_eval(bwd, v);
+        return solve_tail(v, far(v));
+    }
+
+    bool build(fq lam, fq alpha_, fq beta_, char* err, int errlen)
+    {
+        lambda = lam;
+        nu = lam - 0.5Q;
+        alpha = alpha_;
+        beta = beta_;
+        rate = alpha - beta;
+        if (!bes.build(nu, err, errlen)) return false;
+        logA = lam * logq((alpha - beta) * (alpha + beta)) - nu * logq(2 * alpha) - 0.5Q * logq(M_PIq) - lgammaq(lam);
+        log_f0 = logA - nu * logq(alpha) + bes.L0;
+        log_p = log_mass(lam, alpha, beta);
+        slope0 = expq(log_p - log_f0) * rate;
+        q2 = (-rate * slope0 - beta * slope0 * slope0) / 2;
+        /* the large-v form */
+        const fq e1 = (4 * nu * nu - 1) / (8 * alpha);
+        const fq e2 = (4 * nu * nu - 1) * (4 * nu * nu - 9) / (128 * alpha * alpha);
+        const fq s1 = (lam - 1) / rate + e1;
+        const fq s2 = (lam - 1) * (lam - 2) / (rate * rate) + e1 * (lam - 2) / rate + e2;
+        c0 = (logA + 0.5Q * logq(M_PIq / (2 * alpha)) - logq(rate) - log_p) / rate;
+        clog = (lam - 1) / rate;
+        c1 = s1 / rate;
+        c2 = (s2 - s1 * s1 / 2) / rate;
+        /* the masses against quadrature of f: int_0^{x1} by halving panels, the
+           tail by Gauss-Laguerre */
+        {
+            const fq x1 = 24 / rate;
+            const fq q = central_mass(x1) + expq(log_tail(x1));
+            if (!(fabsq(q / expq(log_p) - 1) < 1e-28Q)) {
+                snprintf(err, errlen, "variance-gamma mass: 2F1 form and quadrature differ by %.3e",
+                         (double)fabsq(q / expq(log_p) - 1));
+                return false;
+            }
+        }
+        v_s = fminq(0.125Q, 0.125Q / rate);
+        v_match = 20 / rate;
+        fq va = 40 / rate;
+        for (int it = 0; it < 100 && rate * far(va) < 30; ++it) va *= 1.25Q;
+        v_a = va;
+        v_min = fminq(1e-17Q, powq(10, -34 / (2 * lam - 1)));
+        const fq Qs = solve_central(v_s);
+        const fq Ps = expq(log_p + logq(rate) - rate * v_s - log_f(Qs));
+        const fq Qa = solve_tail(v_a, far(v_a));
+        if (!(rate * Qa >= 24)) {
+            snprintf(err, errlen, "variance-gamma anchor too close to the centre");
+            return false;
+        }
+        const fq Pa = expq(log_p + logq(rate) - rate * v_a - log_f(Qa));
+        if (!leg(v_min, v_min * (slope0 + q2 * v_min), slope0 + 2 * q2 * v_min, v_s, zero) ||
+            !leg(v_s, Qs, Ps, v_match, fwd) || !leg(v_a, Qa, Pa, v_match, bwd)) {
+            snprintf(err, errlen, "the ODE integration exceeded its step budget");
+            return false;
+        }
+        const VNode& f = fwd.back();
+        const VNode& b = bwd.back();
+        const fq qf = horner(f.Q, f.h), qb = horner(b.Q, b.h);
+        const fq pf = horner(f.P, f.h), pb = horner(b.P, b.h);
+        const fq mis = fabsq(qf / qb - 1) + fabsq(pf / pb - 1);
+        if (!(mis < 1e-19Q)) {
+            snprintf(err, errlen, "legs disagree at v=%g by %.3e", (double)v_match, (double)mis);
+            return false;
+        }
+        /* the leg from the origin's series must meet the direct solve at v_s */
+        const VNode& z = zero.back();
+        const fq mz = fabsq(horner(z.Q, z.h) / Qs - 1) + fabsq(horner(z.P, z.h) / Ps - 1);
+        if (!(mz < 1e-19Q)) {
+            snprintf(err, errlen, "the leg from the origin misses the direct solve at v=%g by %.3e", (double)v_s,
+                     (double)mz);
+            return false;
+        }
+        return true;
+    }
+};
+
 bool check_vg_params(double lambda, double alpha, double beta)
 {
     return std::isfinite(lambda) && std::isfinite(alpha) && std::isfinite(beta) && lambda >= 1 &&
-           lambda <= VG_LAMBDA_MAX && lambda == std::floor(lambda) && alpha > std::fabs(beta);
+           lambda <= VG_LAMBDA_MAX && alpha > std::fabs(beta);
 }
 
 }  // namespace
@@ -882,18 +1327,32 @@ int build_vg_table(double lambda, double alpha, double beta, HostHypTable* out, 
 {
     memset(out, 0, sizeof *out);
     if (!check_vg_params(lambda, alpha, beta))
-        return fail(err, errlen, "need integer lambda in [1, 8] and |beta| < alpha, all finite");
+        return fail(err, errlen, "need lambda in [1, 8] and |beta| < alpha, all finite");
     HypTableHeader& H = out->hdr;
     H.alpha = alpha;
     H.beta = beta;
     H.delta = lambda;
-    const int n = (int)lambda - 1;
-    const VGSide right(n, alpha, beta), left(n, alpha, -(fq)beta);
-    H.log_p_plus = (double)right.log_p;
-    H.log_p_minus = (double)left.log_p;
     std::vector<double> coef;
-    if (!fit_set(right, left, CellSpec{HYP_DEGREE, 2e-17Q}, &H.right, &H.left, coef, err, errlen)) return -1;
-    if (!fit_set(right, left, CellSpec{HYP_DEGREE_F32, 1e-10Q}, &H.right32, &H.left32, coef, err, errlen)) return -1;
+    if (lambda == std::floor(lambda)) {
+        /* integer lambda: each side solved directly from its closed form */
+        const int n = (int)lambda - 1;
+        const VGSide right(n, alpha, beta), left(n, alpha, -(fq)beta);
+        H.log_p_plus = (double)right.log_p;
+        H.log_p_minus = (double)left.log_p;
+        if (!fit_set(right, left, CellSpec{HYP_DEGREE, 2e-17Q}, &H.right, &H.left, coef, err, errlen)) return -1;
+        if (!fit_set(right, left, CellSpec{HYP_DEGREE_F32, 1e-10Q}, &H.right32, &H.left32, coef, err, errlen))
+            return -1;
+    } else {
+        /* real lambda: the recycling ODE */
+        VGRealSide right, left;
+        if (!right.build(lambda, alpha, beta, err, errlen) || !left.build(lambda, alpha, -(fq)beta, err, errlen))
+            return -1;
+        H.log_p_plus = (double)right.log_p;
+        H.log_p_minus = (double)left.log_p;
+        if (!fit_set(right, left, CellSpec{HYP_DEGREE, 2e-17Q}, &H.right, &H.left, coef, err, errlen)) return -1;
+        if (!fit_set(right, left, CellSpec{HYP_DEGREE_F32, 1e-10Q}, &H.right32, &H.left32, coef, err, errlen))
+            return -1;
+    }
     out->ncoef = coef.size();
     out->coef = (double*)malloc(out->ncoef * sizeof(double));
     if (!out->coef) return fail(err, errlen, "out of memory");

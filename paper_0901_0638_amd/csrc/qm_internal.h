@@ -26,7 +26,8 @@ struct KernelShape {
    many. */
 struct LaunchShape {
     KernelShape stream;      /* k_map: exp -> normal, paper modes, FP32 plain */
-    KernelShape hybrid[2];   /* [0] FP32+refine, [1] FP64 quantile: k_hybrid, k_generate */
+    KernelShape hybrid[2];   /* [0] FP32+refine, [1] FP64 quantile: k_hybrid */
+    KernelShape generate[2]; /* [0] FP32, [1] FP64 outputs: k_generate, k_generate_t */
     KernelShape student[2];  /* [0] FP32, [1] FP64 outputs: k_student */
     KernelShape hyperbolic[2]; /* [0] FP32, [1] FP64: k_hyperbolic */
     int compact;             /* quantiles: gather non-central lanes across the wave */

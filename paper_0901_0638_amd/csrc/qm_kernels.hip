@@ -81,29 +81,61 @@ __global__ __launch_bounds__(256) void k_map(MapArgs<T> a)
     }
 }
 
-/* The hybrid quantile over a memory stream (see qm_hybrid.hpp). */
+/* The first lane's value of x, as a wave-uniform (scalar) value. */
+__device__ __forceinline__ uint64_t wave_uniform(uint64_t x)
+{
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)x);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(x >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+/*
+ * The hybrid quantile over a memory stream (see qm_hybrid.hpp).  Each wave
+ * streams whole tiles of 64 UNROLL consecutive 16-byte vectors (UNROLL rows
+ * of 1 KB, lane l reading vector l of each row), the tiles dealt out to the
+ * waves of the grid in turn.  Measured on MI355X (2^28 FP64 and FP32
+ * mixtures), these wave-contiguous tiles stream 2-5% faster than the
+ * grid-stride layout (lane vectors a whole grid apart), as they do for a
+ * plain copy.  Only the last tile of the array can be partial; the
+ * unaligned head and the ragged tail elements are done element by element
+ * by workgroup 0.
+ */
 template <typename T, int UNROLL, class H>
 __global__ __launch_bounds__(256) void k_hybrid(MapArgs<T> a)
 {
     typedef typename vec16<T>::type V;
     constexpr int NV = vec16<T>::n;
     constexpr int K = NV * UNROLL;
+    constexpr uint64_t TILE = 64ull * UNROLL;
     __shared__ T outer_buf[4][64 * K];
     T* buf = outer_buf[threadIdx.x >> 6];
     const uint32_t lane = __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const V* vin = reinterpret_cast<const V*>(a.in + a.head);
     V* vout = reinterpret_cast<V*>(a.out + a.head);
-    /* whole waves iterate together: the trip count is uniform per wave because
-       the bound is tested on the wave's first lane */
-    const uint64_t wave_first = tid - lane;
-    for (uint64_t i0 = wave_first; i0 < a.nvec; i0 += UNROLL * stride) {
-        const uint64_t i = i0 + lane;
+    const uint64_t step = (uint64_t)gridDim.x * 4 * TILE;
+    uint64_t t = wave_uniform(((uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * TILE);
+    for (; t + TILE <= a.nvec; t += step) {
         T u[K], w[K];
 #pragma unroll
         for (int k = 0; k < UNROLL; ++k) {
-            uint64_t idx = i + k * stride;
+            V x = __builtin_nontemporal_load(vin + t + 64 * k + lane);
+#pragma unroll
+            for (int j = 0; j < NV; ++j) u[NV * k + j] = x[j];
+        }
+        hybrid_eval<T, K, H>(u, w, buf, lane);
+#pragma unroll
+        for (int k = 0; k < UNROLL; ++k) {
+            V y;
+#pragma unroll
+            for (int j = 0; j < NV; ++j) y[j] = w[NV * k + j];
+            __builtin_nontemporal_store(y, vout + t + 64 * k + lane);
+        }
+    }
+    if (t < a.nvec) {      /* the one partial tile (whole waves enter together) */
+        T u[K], w[K];
+#pragma unroll
+        for (int k = 0; k < UNROLL; ++k) {
+            const uint64_t idx = t + 64 * k + lane;
             V x = idx < a.nvec ? __builtin_nontemporal_load(vin + idx) : (V)(T)0.5;
 #pragma unroll
             for (int j = 0; j < NV; ++j) u[NV * k + j] = x[j];
@@ -111,7 +143,7 @@ __global__ __launch_bounds__(256) void k_hybrid(MapArgs<T> a)
         hybrid_eval<T, K, H>(u, w, buf, lane);
 #pragma unroll
         for (int k = 0; k < UNROLL; ++k) {
-            uint64_t idx = i + k * stride;
+            const uint64_t idx = t + 64 * k + lane;
             V y;
 #pragma unroll
             for (int j = 0; j < NV; ++j) y[j] = w[NV * k + j];

@@ -37,6 +37,7 @@
  */
 #include <quadmath.h>
 
+#include <cfloat>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -394,7 +395,7 @@ void cornish_fisher_cells(fq n, int K, std::vector<double>& coef, TCells* c)
 int build_student_table(double nu_d, HostTTable* out, char* err, int errlen)
 {
     memset(out, 0, sizeof *out);
-    if (!(nu_d >= 0.5)) return fail(err, errlen, "nu must be >= 0.5");
+    if (!(nu_d >= T_NU_MIN)) return fail(err, errlen, "nu below the smallest tabulated value");
     TTableHeader& H = out->hdr;
     H.nu = nu_d;
     if (std::isinf(nu_d)) {
@@ -425,7 +426,25 @@ int build_student_table(double nu_d, HostTTable* out, char* err, int errlen)
         const fq a = -(nu + 1) / (2 * (nu + 2));
         const fq z64 = tail_formula_z(nu, lbeta, logK, a, tol64);
         const fq z32 = tail_formula_z(nu, lbeta, logK, a, tol32);
-        const double y64 = (double)(z64 * z64), y32 = (double)(z32 * z32);
+        double y64 = (double)(z64 * z64);
+        const double y32 = (double)(z32 * z32);
+        /* Below nu = 1/2 the device's evaluation of the tail formula is the
+           limit, not its truncation: rounding in log w (erfcx, log) reaches t
+           multiplied by 1/nu, 2e-15 at nu = 0.3 against a 2e-15 budget.
+           There the FP64 cells continue, from global memory, until t passes
+           the largest double (the products z R then overflow to +-inf as
+           the map does; FP32 outputs overflow long before their cells end). */
+        if (nu_d < 0.5) {
+            /* the first z (to 0.005) with log t past log(DBL_MAX) + 1; the last
+               cell ends at most h later in y, so R = t/z, and its Taylor
+               coefficients (about R/(2 nu)^k/k!), stay finite doubles */
+            fq zo = (fq)Z_TAIL0;
+            for (; zo < (fq)Z_CAP; zo += 0.005Q) {
+                const fq lw = logK + logq(erfcq(zo / sqrtq(2)) / 2);
+                if (0.5Q * logq(nu) - lw / nu > logq((fq)DBL_MAX) + 1) break;
+            }
+            if ((double)(zo * zo) > y64) y64 = (double)(zo * zo);
+        }
         /* the solution must reach the last cell's upper edge (y rounded up by < 8) */
         fq z_far = sqrtq((fq)(y64 > Y_LDS ? y64 : Y_LDS) + 8) + 0.25Q;
         if (z_far < (fq)Z_FAR) z_far = Z_FAR;
@@ -459,7 +478,7 @@ void free_student_table(HostTTable* t)
 extern "C" int qm_debug_student_dense(double nu_d, const double* z, double* q, int n)
 {
     using namespace qm;
-    if (!(nu_d >= 0.5) || nu_d > NU_CF) return -1;
+    if (!(nu_d >= T_NU_MIN) || nu_d > NU_CF) return -1;
     fq zmax = 0;
     for (int i = 0; i < n; ++i) {
         fq a = fabsq((fq)z[i]);

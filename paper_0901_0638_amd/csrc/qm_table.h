@@ -18,6 +18,13 @@ constexpr int T_DEGREE_HIGH = 15;
 constexpr int T_DEGREE_F32 = T_DEGREE_LOW;
 constexpr int T_LDS_CELLS_LOW = 200;
 
+/* Smallest nu tabulated.  log R grows like y / (2 nu), so the cells in y
+   that meet the tolerances multiply as nu falls: at nu = 0.3 the FP64 set
+   needs 400 rows of degree 15 and the FP32 set 400 of degree 7 up to
+   y = 100, 54 KB and 29 KB of LDS; from about nu = 0.27 down the FP32 set
+   no longer fits its 720 rows (and the FP64 set its 480 soon after). */
+constexpr double T_NU_MIN = 0.3;
+
 /*
  * One piecewise-polynomial approximation of R(y) = t(z)/z, y = z^2 <= y_max:
  * cell j = floor(y / h) (clamped to ncell - 1) holds R = sum_k c_{j,k} d^k,

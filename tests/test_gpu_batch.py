@@ -352,7 +352,7 @@ def test_batch_and_serving_vg(ctx):
     check()
     d = torch.zeros(8, dtype=torch.float64, device="cuda")
     with pytest.raises(qm.QMError):
-        qm.qm_run_batch(ctx, [qm.make_request(qm.QM_EXP_TO_VG, d, d, nu=2.5, hyperbolic=(1.0, 0.0, 0.0))],
+        qm.qm_run_batch(ctx, [qm.make_request(qm.QM_EXP_TO_VG, d, d, nu=8.5, hyperbolic=(1.0, 0.0, 0.0))],
                         device_tensor=d)
 
 

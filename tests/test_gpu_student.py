@@ -45,7 +45,7 @@ def test_student_f64_workload_normals(ctx, normals, nu):
     print("nu", nu, rep)
 
 
-@pytest.mark.parametrize("nu", [0.5, 2.5, 7.5, 50])
+@pytest.mark.parametrize("nu", [0.3, 0.4, 0.5, 2.5, 7.5, 50])
 def test_student_f64_other_nu(ctx, nu):
     rng = np.random.default_rng(int(nu * 10))
     z = np.concatenate([rng.normal(size=20000), rng.uniform(-10, 10, 20000)])
@@ -99,13 +99,13 @@ def test_student_huge_z_overflows_to_inf(ctx):
 
 def test_student_invalid_nu(ctx):
     d = torch.zeros(8, dtype=torch.float64, device="cuda")
-    for nu in (0.25, -1.0, float("nan"), float("-inf")):
+    for nu in (0.29, 0.25, 0.1, 1e-300, 0.0, -1.0, float("nan"), float("-inf")):
         with pytest.raises(qm.QMError) as e:
             qm.qm_recycle_student_t(ctx, d, d, nu)
         assert e.value.status == qm.QM_E_INVAL
 
 
-@pytest.mark.parametrize("nu", [0.5, 1, 2, 4, 8, 10, 20, 30, 50, 80, 100, 1000, 1e5])
+@pytest.mark.parametrize("nu", [0.3, 0.5, 1, 2, 4, 8, 10, 20, 30, 50, 80, 100, 1000, 1e5])
 def test_student_far_tail(ctx, nu):
     """|z| > 10: the table's further cells (read from global memory) and,
     beyond them, the two-term tail of Section 3.5, which the builder only
@@ -150,7 +150,7 @@ def test_student_f32_refine(ctx, normals, nu):
     assert_close(got, ref, RTOL_F32, "f32 nu=%s" % nu)
 
 
-@pytest.mark.parametrize("nu", [0.5, 0.75, 1.5, 2.5, 7.5, 50, 1000, 2e5, float("inf")])
+@pytest.mark.parametrize("nu", [0.3, 0.5, 0.75, 1.5, 2.5, 7.5, 50, 1000, 2e5, float("inf")])
 def test_student_f32_refine_other_nu(ctx, nu):
     """FP32 outputs from the degree-7 cells: bulk, the whole table range, and
     the far tail (|z| > 10) including the largest finite floats."""

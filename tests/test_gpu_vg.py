@@ -1,5 +1,6 @@
-"""GPU parity: the exponential -> variance-gamma map (Section 8.2, integer
-lambda) against the oracle."""
+"""GPU parity: the exponential -> variance-gamma map (Section 8.2) against
+the oracle: integer lambda (closed-form sides; vg.c) and real lambda (the
+recycling-ODE sides; the Bessel-integral oracle vg_real.c)."""
 import math
 
 import numpy as np
@@ -15,6 +16,7 @@ pytestmark = pytest.mark.gpu
 import paper_0901_0638_amd as qm  # noqa: E402
 
 PARAMS = [(1, 1.0, 0.0), (2, 1.0, 0.0), (2, 1.0, 0.5), (3, 2.0, -1.0), (5, 1.0, 0.3), (8, 1.0, 0.0)]
+REAL = [(1.5, 1.0, 0.5), (2.5, 2.0, -1.0), (4.25, 1.0, 0.3)]
 
 
 @pytest.fixture(scope="module")
@@ -66,7 +68,7 @@ def test_vg_specials_location_and_api(ctx):
     olp, olm = oracle.vg_masses(*p)
     assert abs(lp - olp) <= 1e-15 and abs(lm - olm) <= 1e-15
     d = torch.zeros(8, dtype=torch.float64, device="cuda")
-    for bad in [(2.5, 1.0, 0.0), (9, 1.0, 0.0), (2, 1.0, 1.5)]:
+    for bad in [(0.5, 1.0, 0.0), (9, 1.0, 0.0), (8.5, 1.0, 0.0), (1.1, 1.0, 0.0), (2, 1.0, 1.5)]:
         with pytest.raises(qm.QMError):
             qm.qm_recycle_exp_to_vg(ctx, d, d, *bad)
 
@@ -123,3 +125,48 @@ def test_vg_ragged_misaligned_inplace_and_request_checks(ctx):
         with pytest.raises(qm.QMError):
             call()
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("p", REAL, ids=lambda p: "l%g_a%g_b%g" % p)
+def test_vg_real_lambda_f64(ctx, p):
+    """Real lambda: base samples with the target's masses, the first cells
+    (where the density's x^(2 lambda - 1) term at 0 bends Q), and the far
+    range out to 1e300."""
+    lam, a, b = p
+    lp, lm = oracle.vgr_masses(*p)
+    v = qi.two_sided_exponentials(7, 4, 3001, a - b, a + b, math.exp(lm))
+    far = np.concatenate([np.geomspace(1e-300, 1e300, 120), -np.geomspace(1e-300, 1e300, 120),
+                          np.geomspace(1e-7, 1e-2, 60), -np.geomspace(1e-7, 1e-2, 60),
+                          np.geomspace(30 / (a - b), 1e7, 40), -np.geomspace(30 / (a + b), 1e7, 40)])
+    v = np.concatenate([v, far])
+    print("case: vg real lambda f64 %r, %d elements" % (p, v.size), flush=True)
+    assert_close(run(ctx, v, p), oracle.vgr_map(v, *p), RTOL_F64, "vg real %r" % (p,))
+
+
+@pytest.mark.parametrize("p", REAL, ids=lambda p: "l%g_a%g_b%g" % p)
+def test_vg_real_lambda_f32(ctx, p):
+    lam, a, b = p
+    lp, lm = oracle.vgr_masses(*p)
+    v = qi.two_sided_exponentials(8, 4, 3003, a - b, a + b, math.exp(lm)).astype(np.float32)
+    ref = as_f32_output(oracle.vgr_map(v.astype(np.float64), *p))
+    got = run(ctx, v, p, dtype=torch.float32)
+    assert_close(got, ref, RTOL_F32, "vg real f32 %r" % (p,))
+
+
+def test_vg_real_lambda_batch_equals_single(ctx):
+    """A real-lambda request in a batch beside an integer-lambda one: bitwise
+    the single call."""
+    reqs, cases = [], []
+    for p in ((2.5, 2.0, -1.0), (2, 1.0, 0.5)):
+        x = qi.two_sided_exponentials(9, 5, 4097, p[1] - p[2], p[1] + p[2], 0.4)
+        d = torch.from_numpy(x).cuda()
+        o = torch.full_like(d, float("nan"))
+        reqs.append(qm.make_request(qm.QM_EXP_TO_VG, d, o, nu=p[0], hyperbolic=(p[1], p[2], 0.0)))
+        cases.append((p, d, o))
+    qm.qm_run_batch(ctx, reqs, device_tensor=cases[0][1])
+    torch.cuda.synchronize()
+    for p, d, o in cases:
+        ref = torch.empty_like(d)
+        qm.qm_recycle_exp_to_vg(ctx, d, ref, *p)
+        torch.cuda.synchronize()
+        assert torch.equal(o, ref), p

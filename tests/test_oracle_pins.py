@@ -267,7 +267,7 @@ def test_student_closed_forms(nu):
             assert abs(mp.mpf(ti) / ref - 1) <= 1.2e-16, (nu, zi, ti)
 
 
-@pytest.mark.parametrize("nu", [0.7, 2.5, 3, 5, 10, 30, 50])
+@pytest.mark.parametrize("nu", [0.3, 0.4, 0.7, 2.5, 3, 5, 10, 30, 50])
 def test_student_vs_mpmath_betainc_root(nu):
     """Root of I_{nu/(nu+t^2)}(nu/2, 1/2)/2 = q (or the central form) found by
     mpmath at 60 digits, bracketing the oracle's value."""

@@ -10,7 +10,7 @@ import oracle
 import paper_0901_0638_amd as qm
 from tests import _golden
 
-NUS = [0.5, 1, 2, 3, 4, 7.5, 10, 30, 50]
+NUS = [0.3, 0.4, 0.5, 1, 2, 3, 4, 7.5, 10, 30, 50]
 
 
 def grid():
@@ -108,12 +108,18 @@ def test_table_polynomials_match_oracle(nu):
     assert h.identity == 0
     check_cells(c, 7 if nu >= 3 else 15)
     assert c.nlds <= (200 if c.degree == 7 else 480)
+    assert c.nlds * (c.degree + 2) * 8 <= 57088        # the LDS the batch kernel leaves a table
     assert c.max_rel_err < 3e-16
     z = table_grid(c)
     t = eval_table_exact(c, coef, z)
     ref = oracle.student_t_map(z, nu)
-    rel = np.abs(t / ref - 1)
-    assert rel.max() <= 4e-16, (nu, rel.max(), z[np.argmax(rel)])
+    # below nu = 1/2 the cells run on to where t overflows, as the map does
+    fin = np.isfinite(ref)
+    assert np.array_equal(np.isinf(t), ~fin), (nu, z[np.isinf(t) != ~fin][:3])
+    rel = np.abs(t[fin] / ref[fin] - 1)
+    assert rel.max() <= 4e-16, (nu, rel.max(), z[fin][np.argmax(rel)])
+    if nu < 0.5:
+        assert not fin.all() and c.y_max > 400
 
 
 @pytest.mark.parametrize("nu", NUS + [0.75, 1.5])

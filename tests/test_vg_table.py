@@ -63,6 +63,6 @@ def test_lambda_one_table_is_the_identity():
 
 
 def test_invalid_lambda_rejected():
-    for p in [(1.5, 1.0, 0.0), (0, 1.0, 0.0), (9, 1.0, 0.0), (2, 1.0, 1.0), (2, float("inf"), 0.0)]:
+    for p in [(0.5, 1.0, 0.0), (0, 1.0, 0.0), (9, 1.0, 0.0), (8.5, 1.0, 0.0), (2, 1.0, 1.0), (2, float("inf"), 0.0)]:
         with pytest.raises(ValueError):
             qm.debug_vg_table(*p)
