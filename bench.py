@@ -264,6 +264,8 @@ def run_quantile(args, torch, qm, qi):
         "valu": {"k_hybrid<double>": valu_fraction(prof_counters, "k_hybrid<double>", avg64) if full else None,
                  "k_hybrid<float>": valu_fraction(prof_counters, "k_hybrid<float>", avg32) if full else None},
     }
+    # outputs kept on the host for the accuracy check against the oracle
+    acc = {}
     if not args.no_extra:
         # context for the roofline: a plain device copy of the same bytes
         # (2^28 doubles read and written), timed the same way, outside the
@@ -271,10 +273,9 @@ def run_quantile(args, torch, qm, qi):
         ds = timed_launches(torch, stream, lambda: w64.copy_(u64), 10)
         avg = sum(ds) / len(ds)
         result["roofline"]["device_copy_same_bytes_gbs"] = round(bytes64 / (avg * 1e-3) / 1e9, 1)
-        # restore the FP64 outputs the copy overwrote (kept for the accuracy check)
+        forms = fp64_forms(torch, qm, ctx, stream, u64, w64, acc)
+        # restore the FP64 outputs the copy and the forms overwrote (kept for the accuracy check)
         f64()
-    # outputs kept on the host for the accuracy check against the oracle
-    acc = {}
     if not args.no_cpu:
         torch.cuda.synchronize()
         mm = min(args.cpu_sample, n)
@@ -286,6 +287,7 @@ def run_quantile(args, torch, qm, qi):
 
     if not args.no_extra:
         result["extra"] = secondary_maps(args, torch, qm, qi, ctx, stream, n, acc)
+        result["extra"]["fp64_forms"] = forms
         if args.serve_extra:
             result["extra"]["serving"] = serve_rates(torch, qm, args.serve_extra_count, args.serve_extra_rates)
 
@@ -297,6 +299,32 @@ def run_quantile(args, torch, qm, qi):
             result["extra"]["measured_error"] = errors
     ctx.close()
     return result
+
+
+def fp64_forms(torch, qm, ctx, stream, u64, w64, acc, reps=10):
+    """The FP64 hybrid beside the paper's own FP64 forms -- the branchless
+    (13,13) rational (Appendix B) and the T2 hybrid with its whole-wave vote
+    (Appendix C) -- on the mixture and on open uniforms of the same size (the
+    input the paper times), outside the timed region.  The T2 form's outputs
+    on the uniforms are kept at sampled indices for the accuracy check."""
+    n = u64.numel()
+    uu = torch.empty_like(u64)
+    qm.qm_generate(ctx, 2, 0, 0, uu, qm.QM_UNIFORM)
+    forms = {}
+    for name, inp in (("mixture", u64), ("uniforms", uu)):
+        forms[name] = {}
+        for form, mode in (("hybrid", qm.QM_PLAIN), ("paper_branchless", qm.QM_PAPER),
+                           ("paper_t2_vote", qm.QM_PAPER_T2)):
+            ds = timed_launches(torch, stream, lambda: qm.qm_normal_quantile(ctx, inp, w64, mode), reps)
+            avg = sum(ds) / len(ds)
+            forms[name][form] = {"gsamples_s": round(n / (avg * 1e-3) / 1e9, 2), "avg_ms": round(avg, 4),
+                                 "p50_ms": percentile(ds, 50)}
+    torch.cuda.synchronize()
+    idx = sample_indices(n, None, 9)
+    acc["fp64_paper_t2 uniforms"] = (gather(torch, uu, idx), gather(torch, w64, idx), "norm_quantile", 2e-15)
+    del uu
+    torch.cuda.empty_cache()
+    return forms
 
 
 def secondary_maps(args, torch, qm, qi, ctx, stream, n, acc):
@@ -697,9 +725,10 @@ def run_hyperbolic(args, torch, qm, qi):
         "config": {"workload": "exp->hyperbolic, 2^26 two-sided exponential base samples of (alpha, beta, delta) = "
                                "(1, 0, 1), seed 2 stream 2; FP64 then FP32 in/out",
                    "n_per_pass": n, "passes_per_step": 2, "table_build_s": round(tb, 3)},
-        "fp64": {"gsamples_s": round(n / (avg64 * 1e-3) / 1e9, 2), "p50_ms": percentile(d64, 50),
-                 "p99_ms": percentile(d64, 99), "max_rel_err_bound": 2e-15},
-        "fp32": {"gsamples_s": round(n / (avg32 * 1e-3) / 1e9, 2), "p50_ms": percentile(d32, 50),
+        "fp64": {"gsamples_s": round(n / (avg64 * 1e-3) / 1e9, 2), "avg_ms": round(avg64, 4),
+                 "p50_ms": percentile(d64, 50), "p99_ms": percentile(d64, 99), "max_rel_err_bound": 2e-15},
+        "fp32": {"gsamples_s": round(n / (avg32 * 1e-3) / 1e9, 2), "avg_ms": round(avg32, 4),
+                 "p50_ms": percentile(d32, 50),
                  "p99_ms": percentile(d32, 99), "gbs": round(8.0 * n / (avg32 * 1e-3) / 1e9, 1),
                  "max_rel_err_bound": 2e-7},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -707,7 +736,13 @@ def run_hyperbolic(args, torch, qm, qi):
                      "traffic": counted_traffic("hyperbolic_exp_2e26_hbm_counters.md", "k_hyperbolic<double>",
                                                 HYPERBOLIC_SOURCES),
                      "kernel": "qm::k_hyperbolic<double, true, 4, 11> (8 workgroups/CU x 4 vectors)",
-                     "algorithmic_bytes_per_launch": 16.0 * n, "avg_launch_ms": round(avg64, 4)},
+                     "algorithmic_bytes_per_launch": 16.0 * n, "avg_launch_ms": round(avg64, 4),
+                     "profiler_avg_launch_ms": profiler_avg_ms("hyperbolic_exp_2e26_kernel_stats.md",
+                                                               "k_hyperbolic<double>", HYPERBOLIC_SOURCES)},
+        "valu": {"k_hyperbolic<double>": valu_fraction("hyperbolic_exp_2e26_hbm_counters.md", "k_hyperbolic<double>",
+                                                       avg64, HYPERBOLIC_SOURCES),
+                 "k_hyperbolic<float>": valu_fraction("hyperbolic_exp_2e26_hbm_counters.md", "k_hyperbolic<float>",
+                                                      avg32, HYPERBOLIC_SOURCES)},
     }
     # context for the roofline: a plain device copy of the same bytes, timed
     # the same way, outside the timed region

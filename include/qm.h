@@ -77,8 +77,18 @@ enum qm_dtype { QM_F32 = 0, QM_F64 = 1 };
  *                  B (v <= 42, u >= 2.875e-19), F32 the (5,6) rational of
  *                  Section 6.1 / Appendix A (v <= 25).  Outside that domain the
  *                  result degrades as the rational does.
+ *   QM_PAPER_T2    qm_normal_quantile with dtype QM_F64 only: the paper's
+ *                  own hybrid of Section 7.3 / Appendix C, constants
+ *                  verbatim -- the T2 intermediate v = |u - 1/2| /
+ *                  sqrt(u(1-u)) and its (14,15) rational when v < 15.5 on
+ *                  every lane of a 64-lane wave, else the whole wave takes
+ *                  QM_PAPER's (13,13) path.  Same domain and accuracy as
+ *                  QM_PAPER.  Which path an element takes depends on the
+ *                  other elements of its wave, so batches, serving and
+ *                  qm_generate (whose outputs are bitwise those of single
+ *                  calls) reject it with QM_E_INVAL.
  */
-enum qm_mode { QM_PLAIN = 0, QM_F32_REFINE = 1, QM_PAPER = 2 };
+enum qm_mode { QM_PLAIN = 0, QM_F32_REFINE = 1, QM_PAPER = 2, QM_PAPER_T2 = 3 };
 
 /* QM_UNIFORM (the uniforms themselves) is accepted by qm_generate only. */
 enum qm_kind { QM_NORMAL_QUANTILE = 0, QM_STUDENT_T = 1, QM_EXP_TO_NORMAL = 2, QM_UNIFORM = 3, QM_EXP_TO_HYPERBOLIC = 4,
@@ -122,8 +132,9 @@ void qm_shutdown(qm_ctx* ctx);
  * paper's T2 intermediate variable), and the exponential-coordinate path
  * elsewhere, with a fitted rational in sqrt(v) for 42 < v (beyond the
  * paper's domain, Section 4.3).  u = 0 -> -inf, u = 1 -> +inf, u outside
- * [0,1] or NaN -> NaN, u = 1/2 -> +0.
- * dtype/mode: F64 {PLAIN, PAPER}; F32 {PLAIN, F32_REFINE, PAPER}.
+ * [0,1] or NaN -> NaN, u = 1/2 -> +0.  QM_PAPER_T2: the paper's hybrid
+ * as printed, for comparison (see enum qm_mode).
+ * dtype/mode: F64 {PLAIN, PAPER, PAPER_T2}; F32 {PLAIN, F32_REFINE, PAPER}.
  */
 qm_status qm_normal_quantile(qm_ctx* ctx, const void* d_u, void* d_w, uint64_t n,
                              int dtype, int mode, void* hip_stream);

@@ -15,7 +15,7 @@ import ctypes
 
 from ._lib import (  # noqa: F401
     QM_E_CLOSED, QM_E_DTYPE, QM_E_HIP, QM_E_INVAL, QM_E_NOMEM, QM_E_TICKET, QM_EXP_TO_NORMAL, QM_F32,
-    QM_F32_REFINE, QM_F64, QM_NORMAL_QUANTILE, QM_OK, QM_PAPER, QM_PENDING, QM_PLAIN, QM_STUDENT_T, QM_UNIFORM, QMError,
+    QM_F32_REFINE, QM_F64, QM_NORMAL_QUANTILE, QM_OK, QM_PAPER, QM_PAPER_T2, QM_PENDING, QM_PLAIN, QM_STUDENT_T, QM_UNIFORM, QMError,
     QM_EXP_TO_HYPERBOLIC, QM_EXP_TO_VG, QM_BATCH_NOALLOC_MAX_REQUESTS,
     check, load, qm_request, qm_serving_counters,
 )
@@ -82,7 +82,7 @@ def _io(inp, out):
 
 
 def qm_normal_quantile(ctx, u, w, mode=QM_PLAIN, stream=None):
-    """w = Phi^{-1}(u) on the device (FP64: PLAIN/PAPER; FP32: PLAIN/F32_REFINE/PAPER)."""
+    """w = Phi^{-1}(u) on the device (FP64: PLAIN/PAPER/PAPER_T2; FP32: PLAIN/F32_REFINE/PAPER)."""
     pi, po, n, dt = _io(u, w)
     check(load().qm_normal_quantile(ctx.handle, pi, po, n, dt, mode, _stream(stream, u)))
 
@@ -90,7 +90,7 @@ def qm_normal_quantile(ctx, u, w, mode=QM_PLAIN, stream=None):
 def qm_generate(ctx, seed, stream_id, first, out, kind=QM_NORMAL_QUANTILE, mode=None, stream=None):
     """out[i] = map of the open uniform of element first + i of the Philox4x32-10
     stream with key (seed, stream_id): kind QM_UNIFORM (u itself) or
-    QM_NORMAL_QUANTILE (Phi^{-1}(u); FP64 PLAIN/PAPER, FP32 F32_REFINE/PLAIN/PAPER)."""
+    QM_NORMAL_QUANTILE (Phi^{-1}(u); FP64 PLAIN/PAPER/PAPER_T2, FP32 F32_REFINE/PLAIN/PAPER)."""
     if out.device.type != "cuda" or not out.is_contiguous():
         raise ValueError("output must be a contiguous tensor on a HIP device")
     dt = _dtype_of(out)

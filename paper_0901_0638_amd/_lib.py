@@ -28,6 +28,7 @@ QM_F64 = 1
 QM_PLAIN = 0
 QM_F32_REFINE = 1
 QM_PAPER = 2
+QM_PAPER_T2 = 3
 
 QM_NORMAL_QUANTILE = 0
 QM_STUDENT_T = 1

@@ -47,6 +47,8 @@ static bool vg_params_ok(double lambda, double alpha, double beta)
            alpha > std::fabs(beta);
 }
 
+bool mode_known(uint32_t m) { return m == QM_PLAIN || m == QM_F32_REFINE || m == QM_PAPER || m == QM_PAPER_T2; }
+
 bool hyp_params_ok(double alpha, double beta, double delta)
 {
     return std::isfinite(alpha) && std::isfinite(beta) && std::isfinite(delta) && delta > 0 && alpha > std::fabs(beta);
@@ -56,18 +58,24 @@ bool hyp_params_ok(double alpha, double beta, double delta)
 
 namespace qm {
 
-qm_status check_request(const qm_request& r, int* dtype_size_out)
+qm_status check_request(const qm_request& r, int* dtype_size_out, bool single_call)
 {
     if (r.reserved != 0) return fail(QM_E_INVAL, "reserved field must be 0");
     if (r.dtype != QM_F32 && r.dtype != QM_F64) return fail(QM_E_INVAL, "unknown dtype %u", r.dtype);
-    if (r.mode != QM_PLAIN && r.mode != QM_F32_REFINE && r.mode != QM_PAPER)
-        return fail(QM_E_INVAL, "unknown mode %u", r.mode);
+    if (!mode_known(r.mode)) return fail(QM_E_INVAL, "unknown mode %u", r.mode);
     switch (r.kind) {
     case QM_NORMAL_QUANTILE:
         if (r.dtype == QM_F64 && r.mode == QM_F32_REFINE)
             return fail(QM_E_DTYPE, "QM_F32_REFINE needs dtype QM_F32");
+        if (r.dtype == QM_F32 && r.mode == QM_PAPER_T2) return fail(QM_E_DTYPE, "QM_PAPER_T2 needs dtype QM_F64");
+        /* its wave vote ties an element's path to the other elements of its
+           wave, so it would break the batch's bitwise equality with the
+           single call */
+        if (r.mode == QM_PAPER_T2 && !single_call)
+            return fail(QM_E_INVAL, "QM_PAPER_T2 is a qm_normal_quantile mode only");
         break;
     case QM_EXP_TO_NORMAL:
+        if (r.mode == QM_PAPER_T2) return fail(QM_E_DTYPE, "QM_PAPER_T2 is for the normal quantile only");
         if (r.dtype == QM_F64 && r.mode == QM_F32_REFINE)
             return fail(QM_E_DTYPE, "QM_F32_REFINE needs dtype QM_F32");
         if (r.dtype == QM_F32 && r.mode != QM_F32_REFINE)
@@ -351,8 +359,8 @@ static qm_status single(qm_ctx* ctx, uint32_t kind, const void* in, void* out, u
     r.d_out = out;
     r.n = n;
     if (dtype != QM_F32 && dtype != QM_F64) return fail(QM_E_INVAL, "unknown dtype %d", dtype);
-    if (mode != QM_PLAIN && mode != QM_F32_REFINE && mode != QM_PAPER) return fail(QM_E_INVAL, "unknown mode %d", mode);
-    qm_status st = qm::check_request(r, nullptr);
+    if (!mode_known((uint32_t)mode)) return fail(QM_E_INVAL, "unknown mode %d", mode);
+    qm_status st = qm::check_request(r, nullptr, true);
     if (st != QM_OK) return st;
     hipError_t e = hipSetDevice(ctx->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
@@ -381,7 +389,7 @@ qm_status qm_recycle_exp_to_hyperbolic(qm_ctx* ctx, const void* d_v, void* d_x, 
 {
     if (!ctx) return fail(QM_E_INVAL, "context is NULL");
     if (dtype != QM_F32 && dtype != QM_F64) return fail(QM_E_INVAL, "unknown dtype %d", dtype);
-    if (mode != QM_PLAIN && mode != QM_F32_REFINE && mode != QM_PAPER) return fail(QM_E_INVAL, "unknown mode %d", mode);
+    if (!mode_known((uint32_t)mode)) return fail(QM_E_INVAL, "unknown mode %d", mode);
     qm_request r{};
     r.kind = QM_EXP_TO_HYPERBOLIC;
     r.dtype = (uint32_t)dtype;
@@ -393,7 +401,7 @@ qm_status qm_recycle_exp_to_hyperbolic(qm_ctx* ctx, const void* d_v, void* d_x, 
     r.beta = beta;
     r.delta = delta;
     r.mu = mu;
-    qm_status st = qm::check_request(r, nullptr);
+    qm_status st = qm::check_request(r, nullptr, true);
     if (st != QM_OK) return st;
     hipError_t e = hipSetDevice(ctx->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
@@ -410,7 +418,7 @@ qm_status qm_recycle_exp_to_vg(qm_ctx* ctx, const void* d_v, void* d_x, uint64_t
 {
     if (!ctx) return fail(QM_E_INVAL, "context is NULL");
     if (dtype != QM_F32 && dtype != QM_F64) return fail(QM_E_INVAL, "unknown dtype %d", dtype);
-    if (mode != QM_PLAIN && mode != QM_F32_REFINE && mode != QM_PAPER) return fail(QM_E_INVAL, "unknown mode %d", mode);
+    if (!mode_known((uint32_t)mode)) return fail(QM_E_INVAL, "unknown mode %d", mode);
     qm_request r{};
     r.kind = QM_EXP_TO_VG;
     r.dtype = (uint32_t)dtype;
@@ -422,7 +430,7 @@ qm_status qm_recycle_exp_to_vg(qm_ctx* ctx, const void* d_v, void* d_x, uint64_t
     r.alpha = alpha;
     r.beta = beta;
     r.mu = mu;
-    qm_status st = qm::check_request(r, nullptr);
+    qm_status st = qm::check_request(r, nullptr, true);
     if (st != QM_OK) return st;
     hipError_t e = hipSetDevice(ctx->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
@@ -471,11 +479,12 @@ qm_status qm_generate(qm_ctx* ctx, uint64_t seed, uint64_t stream, uint64_t firs
     if (!ctx) return fail(QM_E_INVAL, "context is NULL");
     if (seed > 0xFFFFFFFFull || stream > 0xFFFFFFFFull) return fail(QM_E_INVAL, "seed and stream must be < 2^32");
     if (dtype != QM_F32 && dtype != QM_F64) return fail(QM_E_INVAL, "unknown dtype %d", dtype);
-    if (mode != QM_PLAIN && mode != QM_F32_REFINE && mode != QM_PAPER) return fail(QM_E_INVAL, "unknown mode %d", mode);
+    if (!mode_known((uint32_t)mode)) return fail(QM_E_INVAL, "unknown mode %d", mode);
     if (kind == QM_UNIFORM) {
         if (mode != QM_PLAIN) return fail(QM_E_DTYPE, "QM_UNIFORM takes mode QM_PLAIN");
     } else if (kind == QM_NORMAL_QUANTILE) {
         if (dtype == QM_F64 && mode == QM_F32_REFINE) return fail(QM_E_DTYPE, "QM_F32_REFINE needs dtype QM_F32");
+        if (mode == QM_PAPER_T2) return fail(QM_E_INVAL, "QM_PAPER_T2 is a qm_normal_quantile mode only");
     } else {
         return fail(QM_E_INVAL, "qm_generate: kind must be QM_UNIFORM or QM_NORMAL_QUANTILE (got %d)", kind);
     }
@@ -498,7 +507,7 @@ static qm_status check_generate(qm_ctx* ctx, uint64_t seed, uint64_t stream, uin
     if (!ctx) return fail(QM_E_INVAL, "context is NULL");
     if (seed > 0xFFFFFFFFull || stream > 0xFFFFFFFFull) return fail(QM_E_INVAL, "seed and stream must be < 2^32");
     if (dtype != QM_F32 && dtype != QM_F64) return fail(QM_E_INVAL, "unknown dtype %d", dtype);
-    if (mode != QM_PLAIN && mode != QM_F32_REFINE && mode != QM_PAPER) return fail(QM_E_INVAL, "unknown mode %d", mode);
+    if (!mode_known((uint32_t)mode)) return fail(QM_E_INVAL, "unknown mode %d", mode);
     if (!(dtype == QM_F64 && mode == QM_PLAIN) && !(dtype == QM_F32 && mode == QM_F32_REFINE))
         return fail(QM_E_DTYPE, "F64 QM_PLAIN or F32 QM_F32_REFINE");
     if (first > (1ull << 63) || n > (1ull << 63) - first) return fail(QM_E_INVAL, "first + n beyond 2^63");

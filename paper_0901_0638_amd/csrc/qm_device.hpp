@@ -224,6 +224,48 @@ __device__ __forceinline__ double normal_quantile_f64(double u)
     return w;
 }
 
+/* 1/sqrt(x) for positive normal x, within about an ulp: the hardware
+   reciprocal square root y (~5e-8), then y (1 + e/2 + 3e^2/8) with
+   e = 1 - x y^2 (second-order Newton; e is exact up to the rounding of x y).
+   Zero, denormal, negative or NaN x give values that callers must not use. */
+__device__ __forceinline__ double rsqrt_pos(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+    double h = x * y;
+    double e = __builtin_fma(-h, y, 1.0);
+    double c = __builtin_fma(0.375, e, 0.5);
+    return __builtin_fma(y * e, c, y);
+}
+
+/*
+ * The paper's own FP64 hybrid (Section 7.3, Appendix C), constants as
+ * printed.  Every lane forms the T2 coordinate v = |u - 1/2| / sqrt(u(1-u));
+ * if v < 15.5 on every lane of the wave, the wave takes Psi(v) = v P14/Q15,
+ * otherwise the whole wave takes the branchless (13,13) path of Appendix B.
+ * u(1-u) is formed as a product rather than the printed u - u*u, which
+ * cancels near u = 1 (relative error up to 5e-14 at u = 0.999 there, 1.5
+ * ulp here).  u = 1/2 -> +0; u = 0, 1, NaN or outside [0,1] give v >= 15.5
+ * or NaN, so the branchless path's specials apply.
+ */
+__device__ __forceinline__ double t2_coord(double u, double& q)
+{
+    q = u - 0.5;
+    return __builtin_fabs(q) * rsqrt_pos(u * (1.0 - u));
+}
+
+__device__ __forceinline__ double t2_psi(double v, double q)
+{
+    return __builtin_copysign(div_pos(v * horner(v, QM_PAPER_T2_P14), horner(v, QM_PAPER_T2_Q15)), q);
+}
+
+__device__ __forceinline__ double normal_quantile_f64_t2(double u)
+{
+    double q;
+    double v = t2_coord(u, q);
+    if (__all((int)(v < QM_PAPER_T2_VMAX))) return t2_psi(v, q);
+    return quantile_finish(u, expcoord_q_paper(quantile_v(u)));
+}
+
 /* Exponential -> normal, FP64: v = |x| directly, odd extension. */
 template <bool PAPER>
 __device__ __forceinline__ double exp_to_normal_f64(double x)

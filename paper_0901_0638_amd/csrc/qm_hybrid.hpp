@@ -20,6 +20,7 @@ template <> struct vec16<float> { typedef f4 type; static constexpr int n = 4; }
 
 struct OpNQ64Plain { __device__ double operator()(double u) const { return normal_quantile_f64<false>(u); } };
 struct OpNQ64Paper { __device__ double operator()(double u) const { return normal_quantile_f64<true>(u); } };
+struct OpNQ64PaperT2 { __device__ double operator()(double u) const { return normal_quantile_f64_t2(u); } };
 struct OpE64Plain  { __device__ double operator()(double x) const { return exp_to_normal_f64<false>(x); } };
 struct OpE64Paper  { __device__ double operator()(double x) const { return exp_to_normal_f64<true>(x); } };
 struct OpNQ32Refine { __device__ float operator()(float u) const { return normal_quantile_f32_refine(u); } };

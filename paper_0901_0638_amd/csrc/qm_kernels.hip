@@ -231,6 +231,7 @@ hipError_t launch_elementwise(int kind, int dtype, int mode, const void* in, voi
     if (kind == QM_NORMAL_QUANTILE) {
         if (dtype == QM_F64 && mode == QM_PLAIN) return launch_op<double, OpNQ64Plain>(in, out, n, s, shape);
         if (dtype == QM_F64 && mode == QM_PAPER) return launch_op<double, OpNQ64Paper>(in, out, n, s, shape);
+        if (dtype == QM_F64 && mode == QM_PAPER_T2) return launch_op<double, OpNQ64PaperT2>(in, out, n, s, shape);
         if (dtype == QM_F32 && mode == QM_F32_REFINE) return launch_op<float, OpNQ32Refine>(in, out, n, s, shape);
         if (dtype == QM_F32 && mode == QM_PAPER) return launch_op<float, OpNQ32Paper>(in, out, n, s, shape);
         if (dtype == QM_F32 && mode == QM_PLAIN) return launch_op<float, OpNQ32Plain>(in, out, n, s, shape);

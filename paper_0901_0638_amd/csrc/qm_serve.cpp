@@ -246,7 +246,7 @@ static qm_status validate_batch(qm_ctx* ctx, const qm_request* reqs, uint64_t co
     if (!ctx) return set_error(QM_E_INVAL, "context is NULL");
     if (count > 0 && !reqs) return set_error(QM_E_INVAL, "reqs is NULL");
     for (uint64_t i = 0; i < count; ++i) {
-        qm_status st = check_request(reqs[i], nullptr);
+        qm_status st = check_request(reqs[i], nullptr, false);
         if (st != QM_OK) return st;
     }
     if (hipSetDevice(ctx->device) != hipSuccess) return set_error(QM_E_HIP, "hipSetDevice failed");
@@ -580,7 +580,7 @@ qm_status qm_submit(qm_ctx* ctx, const qm_request* req, uint64_t* ticket)
 {
     if (!ctx || !req || !ticket) return qm::set_error(QM_E_INVAL, "NULL argument");
     int es = 0;
-    qm_status st = qm::check_request(*req, &es);
+    qm_status st = qm::check_request(*req, &es, false);
     if (st != QM_OK) return st;
     uint64_t bytes = 2 * req->n * (uint64_t)es;
     if (bytes > ctx->budget) return qm::set_error(QM_E_INVAL, "request larger than the HBM budget");

@@ -14,7 +14,7 @@ namespace qm {
 struct Server;
 
 /* Validate one request; sets the last error. */
-qm_status check_request(const qm_request& r, int* dtype_size_out);
+qm_status check_request(const qm_request& r, int* dtype_size_out, bool single_call);
 /* Run one validated request on a stream. */
 qm_status run_single(qm_ctx* ctx, const qm_request& r, hipStream_t s);
 /* Per-nu table of a context (built on first use). */

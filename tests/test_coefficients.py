@@ -150,3 +150,78 @@ def test_fp32_central_newton_step_emulated():
     ref = oracle.norm_quantile(u)
     nz = ref != 0
     assert np.max(np.abs(z1[nz] / ref[nz] - 1)) <= 1e-9
+
+
+PAPER_HDR = os.path.join(os.path.dirname(__file__), "..", "paper_0901_0638_amd", "csrc", "qm_paper_coeffs.h")
+
+
+def paper_arrays():
+    """The paper's constants as the header spells them (decimal strings)."""
+    s = open(PAPER_HDR).read()
+    return {m.group(1): [x.strip().rstrip("f") for x in m.group(2).split(",") if x.strip()]
+            for m in re.finditer(r"static constexpr (?:double|float) (\w+)\[\d+\] = \{([^}]*)\};", s)}
+
+
+def psi_t2(v):
+    """Psi(v) = Phi^{-1}((1 + v/sqrt(1 + v^2))/2) (Section 7.3), by mpmath."""
+    return mp.sqrt(2) * mp.erfinv(v / mp.sqrt(1 + v * v))
+
+
+def test_paper_branchless_meets_its_bound():
+    """Section 7.2 / Appendix B: Q(v) = v p13(v)/q13(v) within the paper's
+    5.4e-17 of Phi^{-1}(1 - e^{-v}/2) on 0 < v <= 42, with the printed
+    decimals (a mistyped digit fails) and with the stored doubles (plus the
+    coefficients' own rounding)."""
+    c = paper_arrays()
+    with mp.workdps(60):
+        P = [mp.mpf(x) for x in c["QM_PAPER_P13"]]
+        Q = [mp.mpf(x) for x in c["QM_PAPER_Q13"]]
+        Pd = [mp.mpf(float(x)) for x in c["QM_PAPER_P13"]]
+        Qd = [mp.mpf(float(x)) for x in c["QM_PAPER_Q13"]]
+        for v in np.concatenate([np.linspace(0.001, 42.0, 700), [1e-12, 42.0]]):
+            vv = mp.mpf(v)
+            ref = mp.sqrt(2) * mp.erfinv(1 - mp.exp(-vv))
+            assert abs(vv * horner(P, vv) / horner(Q, vv) / ref - 1) <= 5.4e-17, v
+            assert abs(vv * horner(Pd, vv) / horner(Qd, vv) / ref - 1) <= 5.4e-17 + 2 ** -52, v
+
+
+def test_paper_t2_rational_meets_its_bound():
+    """Section 7.3 / Appendix C: Psi(v) = v P14(v)/Q15(v) within the paper's
+    bound 5.55e-17 on 0 < v <= 15.5 (printed decimals and stored doubles);
+    Psi(15.5) = 3.07933; and the rational leaves the bound just beyond
+    v = 15.5, which is why the hybrid switches there."""
+    c = paper_arrays()
+    with mp.workdps(40):
+        P = [mp.mpf(x) for x in c["QM_PAPER_T2_P14"]]
+        Q = [mp.mpf(x) for x in c["QM_PAPER_T2_Q15"]]
+        Pd = [mp.mpf(float(x)) for x in c["QM_PAPER_T2_P14"]]
+        Qd = [mp.mpf(float(x)) for x in c["QM_PAPER_T2_Q15"]]
+        for v in np.concatenate([np.linspace(0.001, 15.5, 700), [1e-9, 15.5]]):
+            vv = mp.mpf(v)
+            ref = psi_t2(vv)
+            assert abs(vv * horner(P, vv) / horner(Q, vv) / ref - 1) <= 5.55e-17, v
+            assert abs(vv * horner(Pd, vv) / horner(Qd, vv) / ref - 1) <= 5.55e-17 + 2 ** -52, v
+        assert abs(psi_t2(mp.mpf(15.5)) - mp.mpf("3.07933")) < 5e-6
+        v = mp.mpf(17)
+        assert abs(v * horner(P, v) / horner(Q, v) / psi_t2(v) - 1) > 1e-14
+    cst = re.search(r"QM_PAPER_T2_VMAX = ([0-9.]+);", open(PAPER_HDR).read())
+    assert float(cst.group(1)) == 15.5
+
+
+def test_t2_coordinate_emulated():
+    """The T2 coordinate as the kernel forms it, v = |u - 1/2| / sqrt(u (1 - u))
+    (plain numpy, correctly rounded sqrt), against its exact value: the
+    product form stays within 5 ulps where the printed u - u*u loses up to
+    5e-14 relative near u = 0.999."""
+    u = np.concatenate([np.linspace(1e-3, 1 - 1e-3, 20001), 1 - np.geomspace(1.04e-3, 0.5, 2000),
+                        np.geomspace(1e-3, 0.5, 2000)])
+    v_prod = np.abs(u - 0.5) / np.sqrt(u * (1.0 - u))
+    v_print = np.abs(u - 0.5) / np.sqrt(u - u * u)
+    with mp.workdps(40):
+        ex = np.array([float(abs(mp.mpf(x) - mp.mpf("0.5")) / mp.sqrt(mp.mpf(x) * (1 - mp.mpf(x)))) for x in u])
+    nz = ex != 0
+    assert np.all(v_prod[~nz] == 0)
+    rel_prod = np.abs(v_prod[nz] / ex[nz] - 1)
+    rel_print = np.abs(v_print[nz] / ex[nz] - 1)
+    assert rel_prod.max() <= 5 * 2.0 ** -53
+    assert rel_print.max() > 1e-14

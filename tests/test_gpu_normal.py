@@ -149,6 +149,69 @@ def test_quantile_f64_paper_mode_on_its_domain(ctx):
     assert_close(run_nq(ctx, u, qm.QM_PAPER), oracle.norm_quantile(u), RTOL_F64, "paper 13,13")
 
 
+PAPER_U_MIN = 2.875e-19          # v = 42, the end of the (13,13) rational's domain
+
+
+def test_quantile_f64_paper_t2_hybrid(ctx):
+    """The paper's hybrid as printed (Section 7.3, Appendix C): the T2
+    rational behind a whole-wave vote, the (13,13) path otherwise.  2^20
+    open uniforms (about 87% of waves all-central, the rest on the branchless
+    path), a mixture whose tail stays in the paper's domain (every wave on
+    the branchless path), arrays that hold only central values, and the
+    values either side of the switch at v = 15.5: all against the oracle."""
+    u = qi.uniforms_2e20()
+    rep = assert_close(run_nq(ctx, u, qm.QM_PAPER_T2), oracle.norm_quantile(u), RTOL_F64, "t2 uniforms")
+    print("t2 uniforms", rep)
+    m = qi.mixture(3, 0, 1 << 18, np.float64, 0.1, PAPER_U_MIN)
+    assert_close(run_nq(ctx, m, qm.QM_PAPER_T2), oracle.norm_quantile(m), RTOL_F64, "t2 mixture")
+    c = np.linspace(0.0011, 0.9989, 100003)
+    assert_close(run_nq(ctx, c, qm.QM_PAPER_T2), oracle.norm_quantile(c), RTOL_F64, "t2 central")
+    # u where v = |u - 1/2|/sqrt(u(1-u)) crosses 15.5: 1/2 +- (1/2) 15.5/sqrt(1 + 15.5^2)
+    edge = 0.5 * 15.5 / np.sqrt(1 + 15.5 ** 2)
+    e = np.concatenate([0.5 + edge + np.linspace(-1e-6, 1e-6, 4097), 0.5 - edge + np.linspace(-1e-6, 1e-6, 4097)])
+    assert_close(run_nq(ctx, e, qm.QM_PAPER_T2), oracle.norm_quantile(e), RTOL_F64, "t2 switch")
+
+
+def test_quantile_f64_paper_t2_specials_and_checks(ctx):
+    """Specials as in the other forms (the vote sends their waves to the
+    branchless path); the mode is FP64 qm_normal_quantile only."""
+    sp = np.array([0.0, 1.0, 0.5, np.nan, -0.25, 1.5, -0.0, np.inf, -np.inf, 0.25, 0.75, 1 - 2.0 ** -53,
+                   0.5 - 2.0 ** -54, 0.5 + 2.0 ** -53, PAPER_U_MIN, 1e-10, 1 - 1e-10])
+    got = run_nq(ctx, sp, qm.QM_PAPER_T2)
+    ref = oracle.norm_quantile(sp)
+    assert_close(got, ref, RTOL_F64, "t2 specials")
+    assert got[0] == -np.inf and got[1] == np.inf and got[6] == -np.inf
+    assert got[2] == 0 and not np.signbit(got[2]) and np.all(np.isnan(got[[3, 4, 5, 7, 8]]))
+    # an all-central array with u = 1/2 in it: +0 from the T2 branch
+    c = np.full(256, 0.5)
+    c[1::2] = 0.3
+    got = run_nq(ctx, c, qm.QM_PAPER_T2)
+    assert np.all(got[::2] == 0) and not np.any(np.signbit(got[::2]))
+    f = torch.zeros(64, dtype=torch.float32, device="cuda")
+    d = torch.full((64,), 0.25, dtype=torch.float64, device="cuda")
+    with pytest.raises(qm.QMError) as e:
+        qm.qm_normal_quantile(ctx, f, f, qm.QM_PAPER_T2)
+    assert e.value.status == qm.QM_E_DTYPE
+    with pytest.raises(qm.QMError) as e:
+        qm.qm_recycle_exp_to_normal(ctx, d, d, qm.QM_PAPER_T2)
+    assert e.value.status == qm.QM_E_DTYPE
+    with pytest.raises(qm.QMError) as e:
+        qm.qm_run_batch(ctx, [qm.make_request(qm.QM_NORMAL_QUANTILE, d, d, mode=qm.QM_PAPER_T2)], device_tensor=d)
+    assert e.value.status == qm.QM_E_INVAL
+    with pytest.raises(qm.QMError) as e:
+        qm.qm_generate(ctx, 0, 0, 0, d, qm.QM_NORMAL_QUANTILE, qm.QM_PAPER_T2)
+    assert e.value.status == qm.QM_E_INVAL
+    torch.cuda.synchronize()
+
+
+def test_quantile_f64_paper_t2_full_size_sampled(ctx):
+    """2^28 open uniforms (the paper's timing input) in the launch the
+    benchmark times for this form, sampled as the other full-size tests."""
+    u = qi.uniform53(2, 0, 1 << 28)
+    check_full_size(ctx, u, lambda c, d, w: qm.qm_normal_quantile(c, d, w, qm.QM_PAPER_T2), RTOL_F64,
+                    "t2 2^28", 15, oracle.norm_quantile)
+
+
 def test_quantile_f32_refine_mixture(ctx):
     """FP32 + FP64-refine on the FP32 mixture (tail down to 1e-37), 2^20."""
     u = qi.mixture(1, 0, 1 << 20, np.float32, 0.1, 1e-37)
