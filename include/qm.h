@@ -105,7 +105,8 @@ typedef struct qm_ctx qm_ctx;
  * unit x 16-byte vectors in flight per lane, from measured sweeps: light
  * maps 2 x 4, FP64 quantile 64 x 4, FP32+refine quantile 16 x 4, fused
  * generation 64 x 4 (FP64) and 32 x 2 (FP32), Student t 2 x 4 (FP64) and
- * 3 x 4 (FP32)); the environment variables QM_BLOCKS_PER_CU (1..64) and
+ * 3 x 4 (FP32), exp -> hyperbolic or variance-gamma 16 x 4 (FP64) and 16 x 2
+ * (FP32)); the environment variables QM_BLOCKS_PER_CU (1..64) and
  * QM_UNROLL (1, 2 or 4), read here, override every family, and
  * QM_SHAPE_STREAM, QM_SHAPE_NQ64, QM_SHAPE_NQ32, QM_SHAPE_GEN64,
  * QM_SHAPE_GEN32, QM_SHAPE_T64, QM_SHAPE_T32, QM_SHAPE_H64, QM_SHAPE_H32

@@ -56,7 +56,7 @@ int qm_debug_hyperbolic_dense(double alpha, double beta, double delta, const dou
 int qm_debug_hyperbolic_table(double alpha, double beta, double delta, void* header_out, double* coef_out,
                               int coef_cap);
 
-/* The same for the variance-gamma table of (lambda, alpha, beta), integer
+/* The same for the variance-gamma table of (lambda, alpha, beta), real
    lambda in [1, 8] (the header's delta field holds lambda). */
 int qm_debug_vg_table(double lambda, double alpha, double beta, void* header_out, double* coef_out, int coef_cap);
 

@@ -120,7 +120,7 @@ def qm_generate_hyperbolic(ctx, seed, stream_id, first, out, alpha, beta, delta,
 
 
 def qm_generate_vg(ctx, seed, stream_id, first, out, lam, alpha, beta, mu=0.0, mode=None, stream=None):
-    """Variance-gamma samples (integer lambda) of a Philox stream through the two-sided exponential base, fused."""
+    """Variance-gamma samples (lambda in [1, 8]) of a Philox stream through the two-sided exponential base, fused."""
     dt = _dtype_of(out)
     if mode is None:
         mode = QM_PLAIN if dt == QM_F64 else QM_F32_REFINE
@@ -163,7 +163,7 @@ def qm_hyperbolic_masses(ctx, alpha, beta, delta):
 
 
 def qm_recycle_exp_to_vg(ctx, v, x, lam, alpha, beta, mu=0.0, mode=None, stream=None):
-    """x = mu + F^{-1}(F0(v)), two-sided exponential base -> variance-gamma, integer lambda (Section 8.2)."""
+    """x = mu + F^{-1}(F0(v)), two-sided exponential base -> variance-gamma, lambda in [1, 8] (Section 8.2)."""
     pi, po, n, dt = _io(v, x)
     if mode is None:
         mode = QM_PLAIN if dt == QM_F64 else QM_F32_REFINE
@@ -334,7 +334,7 @@ def _debug_base_table(fn, args, which):
 
 
 def debug_vg_table(lam, alpha, beta, which="f64"):
-    """(header, right rows, left rows) of the host-built variance-gamma table (integer lambda)."""
+    """(header, right rows, left rows) of the host-built variance-gamma table (lambda in [1, 8])."""
     return _debug_base_table(load().qm_debug_vg_table, (lam, alpha, beta), which)
 
 

@@ -99,7 +99,7 @@ qm_status check_request(const qm_request& r, int* dtype_size_out, bool single_ca
         if (!(r.dtype == QM_F64 && r.mode == QM_PLAIN) && !(r.dtype == QM_F32 && r.mode == QM_F32_REFINE))
             return fail(QM_E_DTYPE, "exp->variance-gamma: F64 QM_PLAIN or F32 QM_F32_REFINE");
         if (!vg_params_ok(r.nu, r.alpha, r.beta))
-            return fail(QM_E_INVAL, "need integer lambda in [1, 8] and |beta| < alpha, all finite (got %g, %g, %g)",
+            return fail(QM_E_INVAL, "need lambda in [1, 8] and |beta| < alpha, all finite (got %g, %g, %g)",
                         r.nu, r.alpha, r.beta);
         if (!std::isfinite(r.mu)) return fail(QM_E_INVAL, "mu must be finite");
         break;
@@ -292,11 +292,12 @@ qm_status qm_init(int hip_device, uint64_t hbm_budget_bytes, qm_ctx** out)
         {&c->shape.generate[1], "QM_SHAPE_GEN64", 64, 4},
         {&c->shape.student[0], "QM_SHAPE_T32", 3, 4},  /* Student t, FP32 outputs */
         {&c->shape.student[1], "QM_SHAPE_T64", 2, 4},  /* Student t, FP64 outputs */
-        /* exp -> hyperbolic, FP32: 76 VGPRs allow 6 waves per SIMD, so 6
-           workgroups of 4 waves per CU are all resident at once (8 left a
-           partial second pass, 4-5% slower) */
-        {&c->shape.hyperbolic[0], "QM_SHAPE_H32", 6, 2},
-        {&c->shape.hyperbolic[1], "QM_SHAPE_H64", 8, 4}, /* exp -> hyperbolic, FP64 */
+        /* exp -> hyperbolic, FP32, wave-contiguous tiles: 16 x 2 (670 Gs/s on
+           2^26 base samples; 645 at 6 x 2, 658-673 at 8..16 x 2..4) */
+        {&c->shape.hyperbolic[0], "QM_SHAPE_H32", 16, 2},
+        /* exp -> hyperbolic, FP64, wave-contiguous tiles: 16 x 4 (0.185-0.186
+           ms on 2^26 base samples, against 0.189-0.199 at 4..8 x 2..4) */
+        {&c->shape.hyperbolic[1], "QM_SHAPE_H64", 16, 4},
     };
     long env_bpc = 0, env_unroll = 0;
     if (const char* ev = getenv("QM_BLOCKS_PER_CU")) env_bpc = strtol(ev, nullptr, 10);
@@ -445,7 +446,7 @@ qm_status qm_vg_masses(qm_ctx* ctx, double lambda, double alpha, double beta, do
 {
     if (!ctx) return fail(QM_E_INVAL, "context is NULL");
     if (!vg_params_ok(lambda, alpha, beta))
-        return fail(QM_E_INVAL, "need integer lambda in [1, 8] and |beta| < alpha, all finite (got %g, %g, %g)",
+        return fail(QM_E_INVAL, "need lambda in [1, 8] and |beta| < alpha, all finite (got %g, %g, %g)",
                     lambda, alpha, beta);
     hipError_t e = hipSetDevice(ctx->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
@@ -557,7 +558,7 @@ qm_status qm_generate_vg(qm_ctx* ctx, uint64_t seed, uint64_t stream, uint64_t f
     qm_status st = check_generate(ctx, seed, stream, first, d_out, n, dtype, mode);
     if (st != QM_OK) return st;
     if (!vg_params_ok(lambda, alpha, beta))
-        return fail(QM_E_INVAL, "need integer lambda in [1, 8] and |beta| < alpha, all finite (got %g, %g, %g)",
+        return fail(QM_E_INVAL, "need lambda in [1, 8] and |beta| < alpha, all finite (got %g, %g, %g)",
                     lambda, alpha, beta);
     if (!std::isfinite(mu)) return fail(QM_E_INVAL, "mu must be finite");
     const DeviceHypTable* t = nullptr;

@@ -67,7 +67,7 @@ __device__ __forceinline__ void chunk_map(const T* __restrict__ in, T* __restric
     }
 }
 
-extern __shared__ double lds_tab[];
+extern __shared__ __attribute__((aligned(16))) double lds_tab[];
 
 /* One chunk per op.  Each is a separate, non-inlined function so that its
    constants and registers are its own: inlined together, the union of all

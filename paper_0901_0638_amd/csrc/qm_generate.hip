@@ -205,7 +205,7 @@ static void hyp_base_constants(const HypTableHeader& h, double* p_minus, double*
 template <typename T, int UNROLL, class H, bool GATHER, bool VECTOR, int DEG>
 __global__ __launch_bounds__(256) void k_generate_t(GenArgs<T> a, const double* __restrict__ coef, StudentParams P)
 {
-    extern __shared__ double lds_gt[];
+    extern __shared__ __attribute__((aligned(16))) double lds_gt[];
     stage_table(lds_gt, coef, P);
     __syncthreads();
     typedef typename vec16<T>::type V;
@@ -294,7 +294,7 @@ struct HypBase {
 template <typename T, int UNROLL, bool VECTOR, int DEG>
 __global__ __launch_bounds__(256) void k_generate_h(GenArgs<T> a, HypParams P, HypBase B)
 {
-    extern __shared__ double lds_gh[];
+    extern __shared__ __attribute__((aligned(16))) double lds_gh[];
     stage_hyp<DEG>(lds_gh, P);
     __syncthreads();
     typedef typename vec16<T>::type V;

@@ -76,50 +76,75 @@ __device__ __forceinline__ void hyp_lane(const T (&v)[K], T (&y)[K], const doubl
     for (int e = 0; e < K; ++e) y[e] = hyp_out<T>(q[e], v[e], P);
 }
 
+/* The first lane's value of x, as a wave-uniform (scalar) value. */
+__device__ __forceinline__ uint64_t wave_uniform_u64(uint64_t x)
+{
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)x);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(x >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+/*
+ * VECTOR: each wave streams whole tiles of 64 UNROLL consecutive 16-byte
+ * vectors (lane l reads vector l of each 1 KB row), the tiles dealt out to
+ * the waves of the grid in turn; only the array's last tile can be partial,
+ * and whole waves enter it together (the wave votes need every lane).  The
+ * unaligned head and the ragged tail are done by workgroup 0.  Otherwise
+ * (input and output not co-aligned) a grid-stride loop over elements.
+ */
 template <typename T, bool VECTOR, int UNROLL, int DEG>
 __global__ __launch_bounds__(256) void k_hyperbolic(HypArgs<T> a)
 {
-    extern __shared__ double lds_hyp[];
+    extern __shared__ __attribute__((aligned(16))) double lds_hyp[];
     const HypParams P = a.P;
     stage_hyp<DEG>(lds_hyp, P);
     __syncthreads();
 
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (VECTOR) {
         typedef typename hvec<T>::type V;
         constexpr int NV = hvec<T>::n;
+        constexpr int K = UNROLL * NV;
+        constexpr uint64_t TILE = 64ull * UNROLL;
+        const uint32_t lane = __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
         const V* vin = reinterpret_cast<const V*>(a.in + a.head);
         V* vout = reinterpret_cast<V*>(a.out + a.head);
-        uint64_t i = tid;
-        for (; i + (UNROLL - 1) * stride < a.nvec; i += UNROLL * stride) {
-            V x[UNROLL];
+        const uint64_t step = (uint64_t)gridDim.x * 4 * TILE;
+        uint64_t t = wave_uniform_u64(((uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * TILE);
+        for (; t + TILE <= a.nvec; t += step) {
+            T v[K], y[K];
 #pragma unroll
-            for (int k = 0; k < UNROLL; ++k) x[k] = __builtin_nontemporal_load(vin + i + k * stride);
-            T v[UNROLL * NV], y[UNROLL * NV];
+            for (int k = 0; k < UNROLL; ++k) {
+                V x = __builtin_nontemporal_load(vin + t + 64 * k + lane);
 #pragma unroll
-            for (int k = 0; k < UNROLL; ++k)
-#pragma unroll
-                for (int j = 0; j < NV; ++j) v[k * NV + j] = x[k][j];
-            hyp_lane<T, UNROLL * NV, DEG>(v, y, lds_hyp, P);
+                for (int j = 0; j < NV; ++j) v[k * NV + j] = x[j];
+            }
+            hyp_lane<T, K, DEG>(v, y, lds_hyp, P);
 #pragma unroll
             for (int k = 0; k < UNROLL; ++k) {
                 V o;
 #pragma unroll
                 for (int j = 0; j < NV; ++j) o[j] = y[k * NV + j];
-                __builtin_nontemporal_store(o, vout + i + k * stride);
+                __builtin_nontemporal_store(o, vout + t + 64 * k + lane);
             }
         }
-        for (; i < a.nvec; i += stride) {
-            V x = __builtin_nontemporal_load(vin + i);
-            T v[NV], y[NV];
+        if (t < a.nvec) {
+            T v[K], y[K];
 #pragma unroll
-            for (int j = 0; j < NV; ++j) v[j] = x[j];
-            hyp_lane<T, NV, DEG>(v, y, lds_hyp, P);
-            V o;
+            for (int k = 0; k < UNROLL; ++k) {
+                const uint64_t idx = t + 64 * k + lane;
+                V x = idx < a.nvec ? __builtin_nontemporal_load(vin + idx) : (V)(T)0;
 #pragma unroll
-            for (int j = 0; j < NV; ++j) o[j] = y[j];
-            __builtin_nontemporal_store(o, vout + i);
+                for (int j = 0; j < NV; ++j) v[k * NV + j] = x[j];
+            }
+            hyp_lane<T, K, DEG>(v, y, lds_hyp, P);
+#pragma unroll
+            for (int k = 0; k < UNROLL; ++k) {
+                const uint64_t idx = t + 64 * k + lane;
+                V o;
+#pragma unroll
+                for (int j = 0; j < NV; ++j) o[j] = y[k * NV + j];
+                if (idx < a.nvec) __builtin_nontemporal_store(o, vout + idx);
+            }
         }
         if (blockIdx.x == 0) {
             uint64_t extra = a.head + (a.n - a.tail_begin);
@@ -131,7 +156,8 @@ __global__ __launch_bounds__(256) void k_hyperbolic(HypArgs<T> a)
             }
         }
     } else {
-        for (uint64_t i = tid; i < a.n; i += stride) {
+        const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+        for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n; i += stride) {
             T v[1] = {a.in[i]}, y[1];
             hyp_lane<T, 1, DEG>(v, y, lds_hyp, P);
             a.out[i] = y[0];

@@ -1,8 +1,9 @@
 /*
  * qm_hyp_table.cpp -- host builder of the tables of the two-sided
  * exponential base: exponential -> hyperbolic (Section 8.1, from the
- * recycling ODE, below) and exponential -> variance-gamma with integer
- * lambda (Section 8.2, solved directly from closed-form masses; VGSide).
+ * recycling ODE, below) and exponential -> variance-gamma for real lambda in
+ * [1, 8] (Section 8.2: integer lambda solved directly from closed-form
+ * masses, VGSide; other lambda from the recycling ODE, VGRealSide).
  * Both fit the same cells through one interface (SideMap), so both run in
  * the same kernel.
  *

@@ -63,7 +63,7 @@ int build_hyperbolic_table(double alpha, double beta, double delta, HostHypTable
 void free_hyperbolic_table(HostHypTable* t);
 
 /* The same table format for the variance-gamma target (Section 8.2) with
-   integer lambda in [1, 8] and |beta| < alpha; the header's delta field
+   real lambda in [1, 8] and |beta| < alpha; the header's delta field
    holds lambda.  Returns 0 on success. */
 int build_vg_table(double lambda, double alpha, double beta, HostHypTable* out, char* err, int errlen);
 
