@@ -15,8 +15,11 @@ These approximations are fitted here, the rest are the paper's constants:
     FP32 range v in [0, 103.3] (the paper's (5,6) of Section 6.1 stops at
     v = 25), accurate to ~1e-5 -- only a seed for the FP64 correction step.
   * Mills ratio M(x) = (1 - Phi(x))/phi(x) on [0, 14.5] as P6(x)/Q7(x), the
-    only non-trivial part of the FP64 erfc used by that correction step
-    (erfc(x/sqrt2) = 2 phi(x) M(x)).
+    only non-trivial part of the FP64 erfc used by the exponential -> normal
+    correction step (erfc(x/sqrt2) = 2 phi(x) M(x)), whose x starts at 0;
+    and on [1.6, 14.5] as P3(x)/Q4(x) (8.5e-9) for the quantile's outer
+    correction, where |z| > 1.6449 and an error e in M moves the result by
+    about e/z^2 relative.
   * Central piece of the FP64 quantile (the hybrid of Section 7.3 /
     Appendix C, with a log-free central variable): for |q| <= 0.45,
     q = u - 1/2, Phi^{-1}(u) = q P8(r)/Q8(r), r = 0.2025 - q^2.  All
@@ -24,9 +27,12 @@ These approximations are fitted here, the rest are the paper's constants:
     an ulp.  Outside, the exponential-coordinate path above.
   * Central piece of the FP32+refine form, |q| <= 0.45: an FP32 seed
     q S2(r)/S3(r) (2.6e-6), then one FP64 Newton step against
-    Phi(z) - u = erf(z/sqrt2)/2 - q with erf(z/sqrt2)/(2z) = E8(z^2) and
-    1/phi(z) = G5(z^2), polynomials good to 1.1e-11 and 4.2e-6 on
-    |z| <= 1.646.
+    Phi(z) - u = erf(z/sqrt2)/2 - q with erf(z/sqrt2)/(2z) = E6(z^2) and
+    1/phi(z) = G3(z^2), polynomials good to 9.3e-9 and 1.1e-3 on
+    |z| <= 1.646.  The result then carries at most 2.7 x 9.3e-9 from E
+    (the residual's error divided by phi(z), relative to z) and
+    1.1e-3 x 2.6e-6 from G, before its rounding to FP32 (half an ulp,
+    6e-8): within the form's 2e-7.
   * The FP64 logarithm of the change of variable v = -log(2 min(u,1-u)):
     log m = 2 atanh f = 2f + f s R6(s), f = (m-1)/(m+1), s = f^2, for the
     reduced argument m in [sqrt(1/2), sqrt(2)] (so s <= 0.0294).
@@ -211,6 +217,18 @@ def main():
     out.append(carr("QM_MILLS_P", p, "Mills ratio numerator in x; rel err %.2e on [0,14.5]" % e_m))
     out.append(carr("QM_MILLS_Q", q, "Mills ratio denominator in x (constant term 1)"))
 
+    # --- Mills ratio P3/Q4 on [1.6, 14.5] (the quantile's outer step) --------
+    a, b = mp.mpf("1.6"), mp.mpf("14.5")
+    xs = cheb_nodes(a, b, 120)
+    fs = [mills(x) for x in xs]
+    _, p, q = fit_rational(xs, fs, 3, 4)
+    dense = [a + (b - a) * k / 1500 for k in range(1501)]
+    dfs = [mills(x) for x in dense]
+    e_m32 = rounded_error(p, q, dense, dfs)
+    print("mills (3,4) on [1.6, 14.5]: max rel %.3e" % e_m32, file=sys.stderr)
+    out.append(carr("QM_MILLS32_P", p, "Mills ratio numerator in x; rel err %.2e on [1.6,14.5]" % e_m32))
+    out.append(carr("QM_MILLS32_Q", q, "Mills ratio denominator in x (constant term 1)"))
+
     # --- central piece, Phi^{-1}(1/2 + q)/q = P8(r)/Q8(r), r = X - q^2 ---------
     QC, X = mp.mpf(float(0.45)), mp.mpf(float(0.2025))
     r_lo = X - QC * QC - mp.mpf("1e-12")          # |q| <= 0.45 as FP64 values, with margin
@@ -242,11 +260,11 @@ def main():
     zmax = mp.sqrt(2) * mp.erfinv(2 * QC) * (1 + mp.mpf("1e-3"))
     Y = zmax * zmax
     erfh = lambda y: mp.erf(mp.sqrt(y / 2)) / (2 * mp.sqrt(y)) if y > 0 else 1 / mp.sqrt(2 * mp.pi)
-    coef, e_e = fit_poly(erfh, mp.mpf(0), Y, 8)
-    print("central erf E8: max rel %.3e" % e_e, file=sys.stderr)
+    coef, e_e = fit_poly(erfh, mp.mpf(0), Y, 6)
+    print("central erf E6: max rel %.3e" % e_e, file=sys.stderr)
     out.append(carr("QM_C32_E", coef, "erf(z/sqrt2)/(2z) in y = z^2 <= %.4f; rel err %.2e" % (float(Y), e_e)))
-    coef, e_g = fit_poly(lambda y: mp.sqrt(2 * mp.pi) * mp.exp(y / 2), mp.mpf(0), Y, 5)
-    print("central 1/phi G5: max rel %.3e" % e_g, file=sys.stderr)
+    coef, e_g = fit_poly(lambda y: mp.sqrt(2 * mp.pi) * mp.exp(y / 2), mp.mpf(0), Y, 3)
+    print("central 1/phi G3: max rel %.3e" % e_g, file=sys.stderr)
     out.append(carr("QM_C32_G", coef, "1/phi(z) = sqrt(2 pi) e^{y/2} in y = z^2 <= %.4f; rel err %.2e" % (float(Y), e_g)))
 
     # --- FP64 log kernel: R6(s) ----------------------------------------------

@@ -299,25 +299,26 @@ __device__ __forceinline__ float expcoord_seed_f32(float v)
     return num * __builtin_amdgcn_rcpf(den);
 }
 
-/* e^a for |a| <= 700, relative error < 1e-11 (all the correction step
-   needs): a = k ln2 + r, |r| <= ln2/2, degree-9 Taylor polynomial in r
-   (remainder r^10/10! < 7e-12), then scale by 2^k. */
+/* e^a for |a| <= 700 for the correction steps: a = k ln2 + r,
+   |r| <= ln2/2, the degree-DEG Taylor polynomial in r, then scale by 2^k.
+   Relative error below the remainder (ln2/2)^(DEG+1)/(DEG+1)!: 7e-12 for
+   degree 9, 5.3e-9 for degree 7. */
+template <int DEG>
 __device__ __forceinline__ double exp_refine(double a)
 {
     const double LOG2E = 1.4426950408889634074, LN2_HI = 0.69314718055994528623, LN2_LO = 2.3190468138462996154e-17;
     double k = __builtin_rint(a * LOG2E);
     double r = __builtin_fma(-k, LN2_HI, a);
     r = __builtin_fma(-k, LN2_LO, r);
-    double p = 1.0 / 362880.0;
-    p = __builtin_fma(p, r, 1.0 / 40320.0);
-    p = __builtin_fma(p, r, 1.0 / 5040.0);
-    p = __builtin_fma(p, r, 1.0 / 720.0);
-    p = __builtin_fma(p, r, 1.0 / 120.0);
-    p = __builtin_fma(p, r, 1.0 / 24.0);
-    p = __builtin_fma(p, r, 1.0 / 6.0);
-    p = __builtin_fma(p, r, 0.5);
-    p = __builtin_fma(p, r, 1.0);
-    p = __builtin_fma(p, r, 1.0);
+    double f = 1.0;
+#pragma unroll
+    for (int i = 2; i <= DEG; ++i) f *= i;           /* DEG!, folded at compile time */
+    double p = 1.0 / f;
+#pragma unroll
+    for (int i = DEG; i >= 1; --i) {
+        f /= i;                                       /* (i-1)! */
+        p = __builtin_fma(p, r, 1.0 / f);
+    }
     return __builtin_ldexp(p, (int)k);
 }
 
@@ -341,16 +342,21 @@ __device__ __forceinline__ double div_pos_fast(double a, double b)
  * (the expansion drops O(x0^2 t^3), below 1e-10 relative for a 1e-5 seed).
  * The caller supplies p/phi(x0), formed so that it stays in range.
  */
-__device__ __forceinline__ double halley_upper(double x0, double p_over_phi)
+template <int NP, int NQ>
+__device__ __forceinline__ double halley_upper(double x0, double p_over_phi, const double (&MP)[NP],
+                                               const double (&MQ)[NQ])
 {
-    double M = div_pos_fast(horner(x0, QM_MILLS_P), horner(x0, QM_MILLS_Q));
+    double M = div_pos_fast(horner(x0, MP), horner(x0, MQ));
     double t = M - p_over_phi;
     double h = 0.5 * x0 * t;
     return __builtin_fma(t, 1.0 + h, x0);
 }
 
 /* Phi^{-1}(u) for FP32 u outside the centre: FP32 seed in the exponential
-   coordinate + one FP64 Halley step, rounded to FP32. */
+   coordinate + one FP64 Halley step, rounded to FP32.  Here z > 1.6449, so
+   the step takes the Mills ratio of [1.6, 14.5] (8.5e-9, moving the result
+   by about 8.5e-9 / z^2 relative) and the degree-7 exponential (5.3e-9, by
+   about 5.3e-9 / z^2). */
 __device__ __forceinline__ float outer_quantile_f32_refine(float u)
 {
     const double SQRT2PI = 2.5066282746310005024;
@@ -361,8 +367,8 @@ __device__ __forceinline__ float outer_quantile_f32_refine(float u)
     double x0 = (double)z0;
     double pd = (double)p;
     /* x0 has a 24-bit significand, so x0*x0/2 is exact in FP64 */
-    double p_over_phi = pd * SQRT2PI * exp_refine(0.5 * (x0 * x0));
-    double x1 = halley_upper(x0, p_over_phi);
+    double p_over_phi = pd * SQRT2PI * exp_refine<7>(0.5 * (x0 * x0));
+    double x1 = halley_upper(x0, p_over_phi, QM_MILLS32_P, QM_MILLS32_Q);
     float w = __builtin_copysignf((float)x1, u - 0.5f);
     w = (u == 0.0f) ? -__builtin_inff() : w;
     w = (u == 1.0f) ? __builtin_inff() : w;
@@ -372,17 +378,19 @@ __device__ __forceinline__ float outer_quantile_f32_refine(float u)
 }
 
 /*
- * Central piece of the FP32+refine form, |q| <= 0.45, q = u - 1/2 (exact in
- * FP64 for FP32 u): the FP32 seed z0 = q S2(r)/S3(r), r = 0.2025 - q^2
- * (2.6e-6 relative), then one FP64 Newton step on Phi(z) = u,
+ * Central piece of the FP32+refine form, |q| <= 0.45, q = u - 1/2 (qd, exact
+ * in FP64 for FP32 u; qf, its FP32 value, serves the seed only): the FP32
+ * seed z0 = q S2(r)/S3(r), r = 0.2025 - q^2 (2.6e-6 relative), then one
+ * FP64 Newton step on Phi(z) = u,
  *   z1 = z0 - (erf(z0/sqrt2)/2 - q) / phi(z0),
- * with erf(z/sqrt2)/2 = z E8(z^2) (1.1e-11) and 1/phi(z) = G5(z^2) (4.2e-6:
- * the step is about 2.6e-6 z, so this costs 1.1e-11 z).  Newton's own error
- * is (z0/2) e0^2, below 1e-11 z here.  No logarithm and no exponential.
+ * with erf(z/sqrt2)/2 = z E6(z^2) (9.2e-9) and 1/phi(z) = G3(z^2) (1.1e-3).
+ * E's error reaches z1 divided by phi(z) (at most 2.7 x 9.2e-9 relative, at
+ * |q| = 0.45); G's only scales the step, about 2.6e-6 z, so it costs 2.9e-9
+ * z; Newton's own error is (z0/2) e0^2, below 1e-11 z.  About 3e-8 in all,
+ * before the rounding to FP32.  No logarithm and no exponential.
  */
-__device__ __forceinline__ float central_quantile_f32_refine(double qd)
+__device__ __forceinline__ float central_quantile_f32_refine(float qf, double qd)
 {
-    float qf = (float)qd;
     float rf = __builtin_fmaf(-qf, qf, (float)QM_CENTRAL_X);
     float z0 = qf * hornerf_d(rf, QM_C32_SP) * __builtin_amdgcn_rcpf(hornerf_d(rf, QM_C32_SQ));
     double x0 = (double)z0;
@@ -398,7 +406,7 @@ __device__ __forceinline__ float normal_quantile_f32_refine(float u)
 {
     double qd = (double)u - 0.5;
     bool central = is_central(qd);          /* NaN: false */
-    float w = central_quantile_f32_refine(qd);
+    float w = central_quantile_f32_refine(u - 0.5f, qd);
     if (wave_any(!central)) {
         float wo = outer_quantile_f32_refine(u);
         w = central ? w : wo;
@@ -447,7 +455,7 @@ __device__ __forceinline__ float exp_to_normal_f32_refine(float x)
     float vs = big ? 1.0f : v;
     double x0 = (double)expcoord_seed_f32(vs);
     double a = __builtin_fma(0.5 * x0, x0, -(double)vs);
-    double x1 = halley_upper(x0, SQRT_HALF_PI * exp_refine(a));
+    double x1 = halley_upper(x0, SQRT_HALF_PI * exp_refine<9>(a), QM_MILLS_P, QM_MILLS_Q);
     float mag = (float)x1;
     mag = (vs == 0.0f) ? 0.0f : mag;
     if (wave_any(big)) {

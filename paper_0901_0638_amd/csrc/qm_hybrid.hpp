@@ -59,7 +59,7 @@ struct HybridNQ32 {
     static __device__ __forceinline__ bool split(float u, float& w)
     {
         double q = (double)u - 0.5;
-        w = central_quantile_f32_refine(q);
+        w = central_quantile_f32_refine(u - 0.5f, q);
         return !is_central(q);
     }
     static __device__ __forceinline__ float outer(float u) { return outer_quantile_f32_refine(u); }

@@ -67,7 +67,8 @@ def test_deep_tail_piece_against_oracle():
 
 def test_fp32_seed_and_mills_ratio():
     """The FP32 seed is a seed (1.2e-5); the Mills ratio M(x) = (1 - Phi(x))/phi(x)
-    behind the correction step's erfc is good to 1.1e-12 on [0, 14.5]."""
+    behind the exp -> normal correction step's erfc is good to 1.1e-12 on
+    [0, 14.5], and the quantile's outer one to 8.6e-9 on [1.6, 14.5]."""
     c = arrays()
     with mp.workdps(30):
         for v in np.linspace(0.01, 103.0, 300):
@@ -80,6 +81,10 @@ def test_fp32_seed_and_mills_ratio():
             m = horner(c["QM_MILLS_P"], x) / horner(c["QM_MILLS_Q"], x)
             ref = mp.erfc(mp.mpf(x) / mp.sqrt(2)) / 2 * mp.sqrt(2 * mp.pi) * mp.exp(mp.mpf(x) ** 2 / 2)
             assert abs(m / ref - 1) <= 1.1e-12
+        for x in np.linspace(1.6, 14.5, 300):
+            m = horner(c["QM_MILLS32_P"], x) / horner(c["QM_MILLS32_Q"], x)
+            ref = mp.erfc(mp.mpf(x) / mp.sqrt(2)) / 2 * mp.sqrt(2 * mp.pi) * mp.exp(mp.mpf(x) ** 2 / 2)
+            assert abs(m / ref - 1) <= 8.6e-9
 
 
 def test_log_kernel_polynomial():
@@ -102,8 +107,8 @@ def f32(x):
 
 def test_fp32_central_pieces():
     """FP32+refine central piece: the seed (with FP32 coefficients) within
-    2.7e-6, erf(z/sqrt2)/(2z) = E8(z^2) within 1.2e-11 and
-    1/phi(z) = G5(z^2) within 4.3e-6, over |q| <= 0.45 (|z| <= 1.646)."""
+    2.7e-6, erf(z/sqrt2)/(2z) = E6(z^2) within 9.3e-9 and
+    1/phi(z) = G3(z^2) within 1.1e-3, over |q| <= 0.45 (|z| <= 1.646)."""
     c = arrays()
     u = np.linspace(0.05, 0.95, 901)
     ref = oracle.norm_quantile(u)
@@ -117,20 +122,21 @@ def test_fp32_central_pieces():
             assert abs(z0 / mp.mpf(wi) - 1) <= 2.7e-6, (ui, float(z0), wi)
             y = mp.mpf(wi) ** 2
             e = horner(c["QM_C32_E"], y) * 2 * mp.mpf(wi)
-            assert abs(e / mp.erf(mp.mpf(wi) / mp.sqrt(2)) - 1) <= 1.2e-11
+            assert abs(e / mp.erf(mp.mpf(wi) / mp.sqrt(2)) - 1) <= 9.3e-9
             g = horner(c["QM_C32_G"], y)
-            assert abs(g / (mp.sqrt(2 * mp.pi) * mp.exp(y / 2)) - 1) <= 4.3e-6
+            assert abs(g / (mp.sqrt(2 * mp.pi) * mp.exp(y / 2)) - 1) <= 1.1e-3
 
 
 def test_fp32_central_newton_step_emulated():
     """The whole central FP32+refine evaluation emulated in float32/float64
-    (plain numpy, no FMA): within 1e-9 of the oracle before the final
-    rounding, so the FP32 result is the oracle value rounded (or, within
-    1e-9 of a midpoint, its neighbour)."""
+    (plain numpy, no FMA): within 4e-8 of the oracle before the final
+    rounding (the error budget: 2.7 x 9.2e-9 from E, 2.9e-9 from G), so with
+    the rounding's half ulp (6e-8) the FP32 result stays within 1e-7 of the
+    oracle, inside the form's 2e-7."""
     c = arrays()
     u = np.linspace(0.05, 0.95, 20001).astype(np.float32).astype(np.float64)
     qd = u - 0.5
-    qf = qd.astype(np.float32)
+    qf = u.astype(np.float32) - np.float32(0.5)
     rf = np.float32(0.2025) - qf * qf
     sp = np.zeros_like(rf)
     for x in c["QM_C32_SP"]:
@@ -149,7 +155,9 @@ def test_fp32_central_newton_step_emulated():
     z1 = z0 - (z0 * e - qd) * g
     ref = oracle.norm_quantile(u)
     nz = ref != 0
-    assert np.max(np.abs(z1[nz] / ref[nz] - 1)) <= 1e-9
+    assert np.max(np.abs(z1[nz] / ref[nz] - 1)) <= 4e-8
+    rounded = z1.astype(np.float32).astype(np.float64)
+    assert np.max(np.abs(rounded[nz] / ref[nz] - 1)) <= 1e-7
 
 
 PAPER_HDR = os.path.join(os.path.dirname(__file__), "..", "paper_0901_0638_amd", "csrc", "qm_paper_coeffs.h")

@@ -236,8 +236,11 @@ def test_quantile_f32_refine_central_outer_boundary(ctx):
     """FP32+refine switches between its central piece (FP32 seed + FP64
     Newton against erf) and the exponential-coordinate seed + Halley against
     erfc at |u - 1/2| = 0.45; both sides and the switch points, every float
-    in a window around them, in mixed and single-piece waves.  The result is
-    the oracle value rounded to float except within 1e-9 of a midpoint."""
+    in a window around them, in mixed and single-piece waves.  Before its
+    rounding to float the result is within 2.5e-8 of the oracle (central
+    piece: E6 and G3 of the Newton step; outer: the Mills ratio and the
+    exponential of the Halley step), so it is the oracle value rounded to
+    float except within 4e-8 of a midpoint, where it may be the neighbour."""
     edges = []
     for c in (0.05, 0.95, 0.25, 0.75, 0.5):
         x = np.float32(c)
@@ -257,9 +260,10 @@ def test_quantile_f32_refine_central_outer_boundary(ctx):
     r32 = ref.astype(np.float32)
     other = np.nextafter(r32, np.where(ref > r32, np.float32(np.inf), np.float32(-np.inf)))
     mid = (r32.astype(np.float64) + other.astype(np.float64)) / 2
-    near = np.abs(ref - mid) <= 1e-9 * np.abs(ref)
+    near = np.abs(ref - mid) <= 4e-8 * np.abs(ref)
     bad = (got != r32) & ~near & (ref != 0)
     assert not bad.any(), (int(bad.sum()), u[bad][:5], got[bad][:5], r32[bad][:5])
+    assert np.all((got == r32) | (got == other) | (ref == 0))
 
 
 def test_quantile_f32_paper_mode(ctx):
