@@ -48,40 +48,67 @@ __device__ __forceinline__ T student_op(T z, const double* tab, const StudentPar
     return (T)student_eval<DEG>((double)z, tab, P);
 }
 
+/* The first lane's value of x, as a wave-uniform (scalar) value. */
+__device__ __forceinline__ uint64_t wave_uniform_u64(uint64_t x)
+{
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)x);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(x >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+/*
+ * VECTOR: each wave streams whole tiles of 64 UNROLL consecutive 16-byte
+ * vectors (lane l reads vector l of each 1 KB row), the tiles dealt out to
+ * the waves of the grid in turn; only the array's last tile can be partial,
+ * and whole waves enter it together (the far path's wave vote needs every
+ * lane).  The unaligned head and the ragged tail are done by workgroup 0.
+ * Otherwise (input and output not co-aligned) a grid-stride loop over
+ * elements.
+ */
 template <typename T, bool VECTOR, int UNROLL, int DEG>
 __global__ __launch_bounds__(256) void k_student(StudentArgs<T> a)
 {
-    extern __shared__ double lds_tab[];
+    extern __shared__ __attribute__((aligned(16))) double lds_tab[];
     const StudentParams P = a.P;
     stage_table(lds_tab, a.coef, P);
     __syncthreads();
 
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (VECTOR) {
         typedef typename svec<T>::type V;
         constexpr int NV = svec<T>::n;
+        constexpr uint64_t TILE = 64ull * UNROLL;
+        const uint32_t lane = __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
         const V* vin = reinterpret_cast<const V*>(a.in + a.head);
         V* vout = reinterpret_cast<V*>(a.out + a.head);
-        uint64_t i = tid;
-        for (; i + (UNROLL - 1) * stride < a.nvec; i += UNROLL * stride) {
+        const uint64_t step = (uint64_t)gridDim.x * 4 * TILE;
+        uint64_t t = wave_uniform_u64(((uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * TILE);
+        for (; t + TILE <= a.nvec; t += step) {
             V x[UNROLL];
 #pragma unroll
-            for (int k = 0; k < UNROLL; ++k) x[k] = __builtin_nontemporal_load(vin + i + k * stride);
+            for (int k = 0; k < UNROLL; ++k) x[k] = __builtin_nontemporal_load(vin + t + 64 * k + lane);
 #pragma unroll
             for (int k = 0; k < UNROLL; ++k) {
                 V y;
 #pragma unroll
                 for (int j = 0; j < NV; ++j) y[j] = student_op<T, DEG>(x[k][j], lds_tab, P);
-                __builtin_nontemporal_store(y, vout + i + k * stride);
+                __builtin_nontemporal_store(y, vout + t + 64 * k + lane);
             }
         }
-        for (; i < a.nvec; i += stride) {
-            V x = __builtin_nontemporal_load(vin + i);
-            V y;
+        if (t < a.nvec) {
+            V x[UNROLL];
 #pragma unroll
-            for (int j = 0; j < NV; ++j) y[j] = student_op<T, DEG>(x[j], lds_tab, P);
-            __builtin_nontemporal_store(y, vout + i);
+            for (int k = 0; k < UNROLL; ++k) {
+                const uint64_t idx = t + 64 * k + lane;
+                x[k] = idx < a.nvec ? __builtin_nontemporal_load(vin + idx) : (V)(T)0;
+            }
+#pragma unroll
+            for (int k = 0; k < UNROLL; ++k) {
+                const uint64_t idx = t + 64 * k + lane;
+                V y;
+#pragma unroll
+                for (int j = 0; j < NV; ++j) y[j] = student_op<T, DEG>(x[k][j], lds_tab, P);
+                if (idx < a.nvec) __builtin_nontemporal_store(y, vout + idx);
+            }
         }
         if (blockIdx.x == 0) {
             uint64_t extra = a.head + (a.n - a.tail_begin);
@@ -91,7 +118,9 @@ __global__ __launch_bounds__(256) void k_student(StudentArgs<T> a)
             }
         }
     } else {
-        for (uint64_t i = tid; i < a.n; i += stride) a.out[i] = student_op<T, DEG>(a.in[i], lds_tab, P);
+        const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+        for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n; i += stride)
+            a.out[i] = student_op<T, DEG>(a.in[i], lds_tab, P);
     }
 }
 
@@ -103,23 +132,24 @@ __global__ __launch_bounds__(256) void k_identity(const T* in, T* out, uint64_t 
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) out[i] = in[i];
 }
 
-/* LDS row stride in doubles for rows of `row` coefficients.  Rows of a
-   power-of-2 length all start on the same bank, so lanes reading different
-   cells conflict; one double of padding spreads them (measured, rows of 16:
-   nu = 1 from 200 to 271 Gsamples/s).  QM_T_LDS_STRIDE (16..24) overrides
-   the stride of rows of 16, QM_T8_LDS_STRIDE (8..24) that of rows of 8
-   (tuning). */
-static int stride_from_env(const char* name, int row)
+/* LDS row stride in doubles for rows of `row` coefficients: even, so that
+   every row starts on a 16-byte boundary and is read in 16-byte pieces.
+   Defaults: 10 for rows of 8 (five 16-byte groups, an odd number, so
+   consecutive rows start in different groups), 16 for rows of 16 (the
+   widest, degree-15 sets take up to 480 rows, which must fit the 64 KB a
+   launch may use).  QM_T_LDS_STRIDE (16..24) and QM_T8_LDS_STRIDE (8..24),
+   even values only, override them (tuning). */
+static int stride_from_env(const char* name, int row, int dflt)
 {
     const char* e = getenv(name);
-    int v = e ? atoi(e) : row + 1;
-    return (v >= row && v <= 24) ? v : row + 1;
+    int v = e ? atoi(e) : dflt;
+    return (v >= row && v <= 24 && v % 2 == 0) ? v : dflt;
 }
 
 int student_lds_stride(int row)
 {
-    static const int s16 = stride_from_env("QM_T_LDS_STRIDE", T_DEGREE_HIGH + 1);
-    static const int s8 = stride_from_env("QM_T8_LDS_STRIDE", T_DEGREE_LOW + 1);
+    static const int s16 = stride_from_env("QM_T_LDS_STRIDE", T_DEGREE_HIGH + 1, T_DEGREE_HIGH + 1);
+    static const int s8 = stride_from_env("QM_T8_LDS_STRIDE", T_DEGREE_LOW + 1, T_DEGREE_LOW + 3);
     return row == T_DEGREE_HIGH + 1 ? s16 : s8;
 }
 

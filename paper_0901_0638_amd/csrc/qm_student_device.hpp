@@ -19,7 +19,7 @@ struct StudentParams {
     int nlds;         /* rows staged in LDS, covering y <= y_lds */
     int identity;
     int row_shift;    /* log2 of the coefficients per row in memory (degree + 1) */
-    int lds_stride;   /* doubles between cell rows in LDS (> row; padding spreads banks) */
+    int lds_stride;   /* doubles between cell rows in LDS: even, >= the row */
 };
 
 /* Copy the first nlds cell rows (2^row_shift doubles each) into LDS rows of
@@ -39,6 +39,24 @@ __device__ __forceinline__ double cell_poly(const double* __restrict__ c, double
 #pragma unroll
     for (int k = 1; k <= DEG; ++k) R = __builtin_fma(R, d, c[k]);
     return R;
+}
+
+/* The same from a row in LDS, read in 16-byte pieces (ds_read_b128): the
+   rows start on 16-byte boundaries (even stride, 16-byte aligned LDS), so
+   lanes on different cells either share a 16-byte bank group or none. */
+template <int DEG>
+__device__ __forceinline__ double cell_poly_lds(const double* __restrict__ row, double d)
+{
+    static_assert((DEG + 1) % 2 == 0, "rows of an even number of doubles");
+    typedef double d2v __attribute__((ext_vector_type(2)));
+    double c[DEG + 1];
+#pragma unroll
+    for (int k = 0; k < (DEG + 1) / 2; ++k) {
+        const d2v x = *reinterpret_cast<const d2v*>(row + 2 * k);
+        c[2 * k] = x.x;
+        c[2 * k + 1] = x.y;
+    }
+    return cell_poly<DEG>(c, d);
 }
 
 /* Cell index and offset for s = |z|: j from y = s^2 by one multiply,
@@ -100,7 +118,7 @@ __device__ __forceinline__ double student_eval(double z, const double* __restric
     double yh = s * s;                      /* only selects the cell */
     double d;
     int j = cell_of(s, yh, P.nlds - 1, P, &d);
-    double t = z * cell_poly<DEG>(tab + j * P.lds_stride, d);
+    double t = z * cell_poly_lds<DEG>(tab + j * P.lds_stride, d);
     bool far = !(yh <= P.y_lds);            /* also NaN: NaN propagates either way */
     if (wave_any(far)) {
         double tf = __builtin_copysign(student_far<DEG>(far ? s : 1.0, P), z);
