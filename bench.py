@@ -128,13 +128,18 @@ def percentile(xs, p):
     return xs[k]
 
 
-def timed_launches(torch, stream, fn, reps):
+def timed_launches(torch, stream, fn, reps, scrub=None):
     """Per-launch durations (ms) with HIP events on the launch stream, after
-    one untimed call (the first launch of a kernel also loads its code)."""
+    one untimed call (the first launch of a kernel also loads its code).
+    scrub, if given, runs untimed on the same stream before every timed
+    launch (a copy larger than the 256 MB last-level cache, so that no
+    launch finds the previous one's data there)."""
     fn()
     torch.cuda.synchronize()
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
     for a, b in ev:
+        if scrub is not None:
+            scrub()
         a.record(stream)
         fn()
         b.record(stream)
@@ -311,18 +316,21 @@ def fp64_forms(torch, qm, ctx, stream, u64, w64, acc, reps=10):
     uu = torch.empty_like(u64)
     qm.qm_generate(ctx, 2, 0, 0, uu, qm.QM_UNIFORM)
     forms = {}
+    scrub_in = torch.empty(1 << 26, dtype=torch.float64, device="cuda")
+    scrub_out = torch.empty_like(scrub_in)
+    scrub = lambda: scrub_out.copy_(scrub_in)     # noqa: E731
     for name, inp in (("mixture", u64), ("uniforms", uu)):
         forms[name] = {}
         for form, mode in (("hybrid", qm.QM_PLAIN), ("paper_branchless", qm.QM_PAPER),
                            ("paper_t2_vote", qm.QM_PAPER_T2)):
-            ds = timed_launches(torch, stream, lambda: qm.qm_normal_quantile(ctx, inp, w64, mode), reps)
+            ds = timed_launches(torch, stream, lambda: qm.qm_normal_quantile(ctx, inp, w64, mode), reps, scrub)
             avg = sum(ds) / len(ds)
             forms[name][form] = {"gsamples_s": round(n / (avg * 1e-3) / 1e9, 2), "avg_ms": round(avg, 4),
                                  "p50_ms": percentile(ds, 50)}
     torch.cuda.synchronize()
     idx = sample_indices(n, None, 9)
     acc["fp64_paper_t2 uniforms"] = (gather(torch, uu, idx), gather(torch, w64, idx), "norm_quantile", 2e-15)
-    del uu
+    del uu, scrub_in, scrub_out
     torch.cuda.empty_cache()
     return forms
 
@@ -338,18 +346,24 @@ def secondary_maps(args, torch, qm, qi, ctx, stream, n, acc):
     x = torch.from_numpy(xh).cuda()
     o = torch.empty_like(z)
     reps = 10
+    # every timed launch below starts with none of its data in the 256 MB
+    # last-level cache (back-to-back launches over 2^26 elements would
+    # otherwise find part of their input there)
+    scrub_in = torch.empty(1 << 26, dtype=torch.float64, device="cuda")
+    scrub_out = torch.empty_like(scrub_in)
+    scrub = lambda: scrub_out.copy_(scrub_in)     # noqa: E731
     rng = np.random.default_rng(3)
     zidx = np.unique(np.concatenate([rng.integers(0, m, 1 << 12), np.flatnonzero(np.abs(zh[: 1 << 22]) > 4.0)]))
     extra = {"student_t_f64": {}, "n": m}
     for nu in T_NUS:
         qm.qm_recycle_student_t(ctx, z, o, nu)  # builds and caches the table
-        ds = timed_launches(torch, stream, lambda nu=nu: qm.qm_recycle_student_t(ctx, z, o, nu), reps)
+        ds = timed_launches(torch, stream, lambda nu=nu: qm.qm_recycle_student_t(ctx, z, o, nu), reps, scrub)
         avg = sum(ds) / len(ds)
         extra["student_t_f64"][str(nu)] = {"gsamples_s": round(m / (avg * 1e-3) / 1e9, 2),
                                            "gbs": round(16.0 * m / (avg * 1e-3) / 1e9, 1),
                                            "p50_ms": percentile(ds, 50), "p99_ms": percentile(ds, 99)}
         acc["student_t_f64 nu=%g" % nu] = (zh[zidx], gather(torch, o, zidx), ("student_t_map", nu), 2e-15)
-    ds = timed_launches(torch, stream, lambda: qm.qm_recycle_exp_to_normal(ctx, x, o), reps)
+    ds = timed_launches(torch, stream, lambda: qm.qm_recycle_exp_to_normal(ctx, x, o), reps, scrub)
     avg = sum(ds) / len(ds)
     extra["exp_to_normal_f64"] = {"gsamples_s": round(m / (avg * 1e-3) / 1e9, 2),
                                   "gbs": round(16.0 * m / (avg * 1e-3) / 1e9, 1),
@@ -358,7 +372,7 @@ def secondary_maps(args, torch, qm, qi, ctx, stream, n, acc):
     acc["exp_to_normal_f64"] = (xh[xidx], gather(torch, o, xidx), "exp_to_normal", 2e-15)
     x32 = x.float()
     o32 = torch.empty_like(x32)
-    ds = timed_launches(torch, stream, lambda: qm.qm_recycle_exp_to_normal(ctx, x32, o32), reps)
+    ds = timed_launches(torch, stream, lambda: qm.qm_recycle_exp_to_normal(ctx, x32, o32), reps, scrub)
     avg = sum(ds) / len(ds)
     extra["exp_to_normal_f32_refine"] = {"gsamples_s": round(m / (avg * 1e-3) / 1e9, 2),
                                          "gbs": round(8.0 * m / (avg * 1e-3) / 1e9, 1)}
@@ -368,7 +382,7 @@ def secondary_maps(args, torch, qm, qi, ctx, stream, n, acc):
     o32 = torch.empty_like(z32)
     extra["student_t_f32_refine"] = {}
     for nu in (1.0, 4.0, 30.0):
-        ds = timed_launches(torch, stream, lambda nu=nu: qm.qm_recycle_student_t(ctx, z32, o32, nu), reps)
+        ds = timed_launches(torch, stream, lambda nu=nu: qm.qm_recycle_student_t(ctx, z32, o32, nu), reps, scrub)
         avg = sum(ds) / len(ds)
         extra["student_t_f32_refine"][str(nu)] = {"gsamples_s": round(m / (avg * 1e-3) / 1e9, 2),
                                                   "gbs": round(8.0 * m / (avg * 1e-3) / 1e9, 1)}
@@ -382,7 +396,7 @@ def secondary_maps(args, torch, qm, qi, ctx, stream, n, acc):
         lp, lm = qm.qm_hyperbolic_masses(ctx, *hp)   # builds and caches the table
         tb = time.perf_counter() - tb
         hv = torch.from_numpy(qi.recycle_two_sided(m, hp[0], hp[1], math.exp(lm))).cuda()
-        ds = timed_launches(torch, stream, lambda: qm.qm_recycle_exp_to_hyperbolic(ctx, hv, o, *hp), reps)
+        ds = timed_launches(torch, stream, lambda: qm.qm_recycle_exp_to_hyperbolic(ctx, hv, o, *hp), reps, scrub)
         avg = sum(ds) / len(ds)
         key = "a%g_b%g_d%g" % hp
         extra["exp_to_hyperbolic_f64"][key] = {"gsamples_s": round(m / (avg * 1e-3) / 1e9, 2),
@@ -390,7 +404,7 @@ def secondary_maps(args, torch, qm, qi, ctx, stream, n, acc):
                                               "p50_ms": percentile(ds, 50), "p99_ms": percentile(ds, 99),
                                               "table_build_s": round(tb, 3)}
         hv32 = hv.float()
-        ds = timed_launches(torch, stream, lambda: qm.qm_recycle_exp_to_hyperbolic(ctx, hv32, o32, *hp), reps)
+        ds = timed_launches(torch, stream, lambda: qm.qm_recycle_exp_to_hyperbolic(ctx, hv32, o32, *hp), reps, scrub)
         avg = sum(ds) / len(ds)
         extra["exp_to_hyperbolic_f32"][key] = {"gsamples_s": round(m / (avg * 1e-3) / 1e9, 2),
                                               "gbs": round(8.0 * m / (avg * 1e-3) / 1e9, 1)}
@@ -402,7 +416,7 @@ def secondary_maps(args, torch, qm, qi, ctx, stream, n, acc):
         lp, lm = qm.qm_vg_masses(ctx, *vp)
         tb = time.perf_counter() - tb
         vv = torch.from_numpy(qi.two_sided_exponentials(2, 3, m, vp[1] - vp[2], vp[1] + vp[2], math.exp(lm))).cuda()
-        ds = timed_launches(torch, stream, lambda: qm.qm_recycle_exp_to_vg(ctx, vv, o, *vp), reps)
+        ds = timed_launches(torch, stream, lambda: qm.qm_recycle_exp_to_vg(ctx, vv, o, *vp), reps, scrub)
         avg = sum(ds) / len(ds)
         extra["exp_to_vg_f64"]["l%g_a%g_b%g" % vp] = {"gsamples_s": round(m / (avg * 1e-3) / 1e9, 2),
                                                       "gbs": round(16.0 * m / (avg * 1e-3) / 1e9, 1),
@@ -417,7 +431,7 @@ def secondary_maps(args, torch, qm, qi, ctx, stream, n, acc):
     for name, buf, kind in (("uniform_f64", g64, qm.QM_UNIFORM), ("quantile_f64", g64, qm.QM_NORMAL_QUANTILE),
                             ("uniform_f32", g32, qm.QM_UNIFORM),
                             ("quantile_f32_refine", g32, qm.QM_NORMAL_QUANTILE)):
-        ds = timed_launches(torch, stream, lambda buf=buf, kind=kind: qm.qm_generate(ctx, 1, 0, 0, buf, kind), reps)
+        ds = timed_launches(torch, stream, lambda buf=buf, kind=kind: qm.qm_generate(ctx, 1, 0, 0, buf, kind), reps, scrub)
         avg = sum(ds) / len(ds)
         fused[name] = {"gsamples_s": round(n / (avg * 1e-3) / 1e9, 2),
                        "gbs": round(buf.element_size() * n / (avg * 1e-3) / 1e9, 1),
@@ -428,7 +442,7 @@ def secondary_maps(args, torch, qm, qi, ctx, stream, n, acc):
             ("student_t_f32_nu4", g32, lambda: qm.qm_generate_student_t(ctx, 1, 0, 0, g32, 4.0)),
             ("hyperbolic_f64", g64, lambda: qm.qm_generate_hyperbolic(ctx, 1, 0, 0, g64, *qi.HYPERBOLIC_PARAMS)),
             ("hyperbolic_f32", g32, lambda: qm.qm_generate_hyperbolic(ctx, 1, 0, 0, g32, *qi.HYPERBOLIC_PARAMS))):
-        ds = timed_launches(torch, stream, fn, reps)
+        ds = timed_launches(torch, stream, fn, reps, scrub)
         avg = sum(ds) / len(ds)
         fused[name] = {"gsamples_s": round(n / (avg * 1e-3) / 1e9, 2),
                        "gbs": round(buf.element_size() * n / (avg * 1e-3) / 1e9, 1),
@@ -735,7 +749,7 @@ def run_hyperbolic(args, torch, qm, qi):
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": counted_traffic("hyperbolic_exp_2e26_hbm_counters.md", "k_hyperbolic<double>",
                                                 HYPERBOLIC_SOURCES),
-                     "kernel": "qm::k_hyperbolic<double, true, 4, 11> (8 workgroups/CU x 4 vectors)",
+                     "kernel": "qm::k_hyperbolic<double, true, 4, 11> (16 workgroups/CU x 4 vectors, wave-contiguous tiles)",
                      "algorithmic_bytes_per_launch": 16.0 * n, "avg_launch_ms": round(avg64, 4),
                      "profiler_avg_launch_ms": profiler_avg_ms("hyperbolic_exp_2e26_kernel_stats.md",
                                                                "k_hyperbolic<double>", HYPERBOLIC_SOURCES)},

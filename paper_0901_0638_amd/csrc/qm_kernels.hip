@@ -2,7 +2,7 @@
  * qm_kernels.hip -- streaming elementwise kernels for gfx950.
  *
  * One template covers every (kind, dtype, mode) of the normal quantile and
- * the exponential -> normal map: a grid-stride loop over 16-byte vectors
+ * the exponential -> normal map: wave-contiguous tiles of 16-byte vectors
  * (two doubles or four floats per lane), UNROLL vectors in flight per lane,
  * non-temporal loads and stores (each byte is touched once), and the
  * unaligned head and tail elements handled by the first workgroup.  The
@@ -37,36 +37,63 @@ struct MapArgs {
     uint64_t n;
 };
 
+/* The first lane's value of x, as a wave-uniform (scalar) value. */
+__device__ __forceinline__ uint64_t wave_uniform(uint64_t x)
+{
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)x);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(x >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+/*
+ * VECTOR: each wave streams whole tiles of 64 UNROLL consecutive 16-byte
+ * vectors (lane l reads vector l of each 1 KB row), the tiles dealt out to
+ * the waves of the grid in turn, as in k_hybrid below; only the array's
+ * last tile can be partial, and whole waves enter it together (the maps'
+ * wave votes need every lane).  The unaligned head and the ragged tail are
+ * done by workgroup 0.  Otherwise (input and output not co-aligned) a
+ * grid-stride loop over elements.
+ */
 template <typename T, bool VECTOR, int UNROLL, class Op>
 __global__ __launch_bounds__(256) void k_map(MapArgs<T> a)
 {
     Op op;
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (VECTOR) {
         typedef typename vec16<T>::type V;
         constexpr int NV = vec16<T>::n;
+        constexpr uint64_t TILE = 64ull * UNROLL;
+        const uint32_t lane = __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
         const V* vin = reinterpret_cast<const V*>(a.in + a.head);
         V* vout = reinterpret_cast<V*>(a.out + a.head);
-        uint64_t i = tid;
-        for (; i + (UNROLL - 1) * stride < a.nvec; i += UNROLL * stride) {
+        const uint64_t step = (uint64_t)gridDim.x * 4 * TILE;
+        uint64_t t = wave_uniform(((uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * TILE);
+        for (; t + TILE <= a.nvec; t += step) {
             V x[UNROLL];
 #pragma unroll
-            for (int k = 0; k < UNROLL; ++k) x[k] = __builtin_nontemporal_load(vin + i + k * stride);
+            for (int k = 0; k < UNROLL; ++k) x[k] = __builtin_nontemporal_load(vin + t + 64 * k + lane);
 #pragma unroll
             for (int k = 0; k < UNROLL; ++k) {
                 V y;
 #pragma unroll
                 for (int j = 0; j < NV; ++j) y[j] = op(x[k][j]);
-                __builtin_nontemporal_store(y, vout + i + k * stride);
+                __builtin_nontemporal_store(y, vout + t + 64 * k + lane);
             }
         }
-        for (; i < a.nvec; i += stride) {
-            V x = __builtin_nontemporal_load(vin + i);
-            V y;
+        if (t < a.nvec) {
+            V x[UNROLL];
 #pragma unroll
-            for (int j = 0; j < NV; ++j) y[j] = op(x[j]);
-            __builtin_nontemporal_store(y, vout + i);
+            for (int k = 0; k < UNROLL; ++k) {
+                const uint64_t idx = t + 64 * k + lane;
+                x[k] = idx < a.nvec ? __builtin_nontemporal_load(vin + idx) : (V)(T)0.5;
+            }
+#pragma unroll
+            for (int k = 0; k < UNROLL; ++k) {
+                const uint64_t idx = t + 64 * k + lane;
+                V y;
+#pragma unroll
+                for (int j = 0; j < NV; ++j) y[j] = op(x[k][j]);
+                if (idx < a.nvec) __builtin_nontemporal_store(y, vout + idx);
+            }
         }
         /* unaligned head and ragged tail: fewer than 2 vectors' worth */
         if (blockIdx.x == 0) {
@@ -77,16 +104,10 @@ __global__ __launch_bounds__(256) void k_map(MapArgs<T> a)
             }
         }
     } else {
-        for (uint64_t i = tid; i < a.n; i += stride) a.out[i] = op(a.in[i]);
+        const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+        for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n; i += stride)
+            a.out[i] = op(a.in[i]);
     }
-}
-
-/* The first lane's value of x, as a wave-uniform (scalar) value. */
-__device__ __forceinline__ uint64_t wave_uniform(uint64_t x)
-{
-    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)x);
-    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(x >> 32));
-    return ((uint64_t)hi << 32) | lo;
 }
 
 /*

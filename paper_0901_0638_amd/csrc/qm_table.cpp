@@ -417,8 +417,8 @@ int build_student_table(double nu_d, HostTTable* out, char* err, int errlen)
            coefficients (about an ulp of R) dominate; FP32 outputs, 1e-10.
            The cells reach as far as the tail formula needs to meet the same
            tolerance; those up to Y_LDS are the ones staged in LDS (for FP64,
-           degree 7 if at most 200 rows of 9 doubles do, else degree 15 in at
-           most 480 rows of 17 doubles, the 64 KB of LDS a launch may use). */
+           degree 7 if at most 200 rows of 10 doubles do, else degree 15 in at
+           most 480 rows of 16 doubles, the 64 KB of LDS a launch may use). */
         const fq tol64 = 2e-17Q, tol32 = 1e-10Q;
         /* the formula's truncation error, with its constants exact (their
            rounding to FP64 is part of the device's evaluation error) */
