@@ -219,10 +219,12 @@ qm_status qm_hyperbolic_masses(qm_ctx* ctx, double alpha, double beta, double de
  * itself (Q(v) = v).  For other lambda the recycling ODE of Section 8.2 is
  * integrated, with H = alpha K_{lambda-3/2}/K_{lambda-1/2} - beta from the
  * Riccati equation of that Bessel ratio and the origin's non-analytic
- * neighbourhood from its expansion (a build takes a few seconds).  Near
- * lambda = 1 that neighbourhood needs cells finer than the table layout
- * holds: lambda below about 1.3 (non-integer) is reported as QM_E_INVAL
- * with the builder's message.  Accuracy as for the hyperbolic map.
+ * neighbourhood from its expansion (a build takes a few seconds).  Where
+ * 2 lambda is not an integer the density carries |x|^(2 lambda - 1) at 0,
+ * which no polynomial cell matches near v = 0: the table's first octave
+ * (v < v0) is then one series in v and v^(2 lambda - 1), evaluated on the
+ * kernel's far path (one pow per element there).  Accuracy as for the
+ * hyperbolic map.
  * dtype/mode: F64 PLAIN; F32 F32_REFINE.
  * Errors: QM_E_INVAL for lambda outside [1, 8] or a table the builder
  * cannot meet the accuracy for, alpha <= |beta|, a non-finite parameter or

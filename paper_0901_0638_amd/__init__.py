@@ -290,7 +290,7 @@ class HypSide(ctypes.Structure):
                 ("far_c0", ctypes.c_double), ("far_c1", ctypes.c_double), ("far_c2", ctypes.c_double),
                 ("far_clog", ctypes.c_double),
                 ("max_rel_err", ctypes.c_double), ("noct", ctypes.c_int32), ("ncell", ctypes.c_int32),
-                ("degree", ctypes.c_int32), ("reserved", ctypes.c_int32), ("coef_offset", ctypes.c_uint64)]
+                ("degree", ctypes.c_int32), ("origin", ctypes.c_int32), ("coef_offset", ctypes.c_uint64)]
 
 
 class HypTableHeader(ctypes.Structure):

@@ -170,7 +170,8 @@ constexpr size_t HYP_LDS_MAX = 48 * 1024;   /* bytes of LDS per workgroup for th
 static bool side_valid(const HypSide& s, int degree, uint64_t ncoef)
 {
     return s.degree == degree && s.noct >= 1 && s.noct <= HYP_MAX_OCT && s.ncell == HYP_SUB * s.noct &&
-           s.coef_offset + (uint64_t)s.ncell * (degree + 1) <= ncoef && s.v0 > 0 && s.v_top > 0;
+           s.coef_offset + (uint64_t)s.ncell * (degree + 1) <= ncoef && s.v0 > 0 && s.v_top > 0 &&
+           (s.origin == 0 || s.origin == 1);
 }
 
 /* Octaves of t = 1 + v/v0 that reach 64 / rate. */
@@ -190,7 +191,7 @@ static void side_far(const HypSide& s, const double* d_block, HypSideFar* f)
     f->clog = s.far_clog;
     f->gcoef = d_block + s.coef_offset;
     f->ncell = s.ncell;
-    f->pad = 0;
+    f->origin = s.origin;
 }
 
 bool make_hyp_params(const HypTableHeader& h, bool f32, const HypTableHeader* d_table, uint64_t ncoef, double mu,
@@ -214,7 +215,7 @@ bool make_hyp_params(const HypTableHeader& h, bool f32, const HypTableHeader* d_
     side_far(R, d_block, &P->r);
     side_far(L, d_block, &P->l);
     P->nlds = HYP_SUB * noct;
-    P->pad = 0;
+    P->jlo = (R.origin || L.origin) ? HYP_SUB : 0;
     *lds_bytes = (size_t)2 * P->nlds * stride * sizeof(double);
     return true;
 }

@@ -37,14 +37,16 @@ static_assert(HYP_SUB == 8, "the cell index takes the top 3 mantissa bits of t")
 struct HypSideFar {
     double v_top, c0, c1, c2, clog;
     const double* gcoef;          /* the side's rows in global memory */
-    int ncell, pad;
+    int ncell;
+    int origin;                   /* 1: v < v0 is the origin series of row 0 */
 };
 
 struct HypParams {
     double v0, inv_v0, mu;        /* v0 is shared by both sides */
     HypSideFar r, l;              /* v >= 0, v < 0 */
     int nlds;                     /* cells per side in LDS, right side's first */
-    int pad;
+    int jlo;                      /* first cell the LDS path takes: 0, or HYP_SUB when the sides
+                                     hold the origin series (their first octave goes the far way) */
 };
 
 
@@ -118,7 +120,7 @@ __device__ __forceinline__ double hyp_near(double v, const double* __restrict__ 
     const double t = __builtin_fma(a, P.inv_v0, 1.0);
     double tc;
     int j = hyp_cell(t, &tc);                    /* >= 0: t >= 1 */
-    const bool out = !((unsigned)j < (unsigned)P.nlds);
+    const bool out = !((unsigned)(j - P.jlo) < (unsigned)(P.nlds - P.jlo));
     *far = out;
     j = out ? P.nlds - 1 : j;                     /* far and NaN lanes stay in bounds */
     const int row = j + (v < 0.0 ? P.nlds : 0);
@@ -126,14 +128,41 @@ __device__ __forceinline__ double hyp_near(double v, const double* __restrict__ 
     return a * hyp_cell<DEG>(lds, row, d);
 }
 
+/* R in the first octave of a side with the origin series (row 0 of its
+   cells, layout in qm_hyp_table.h): R = P0(a) + w (P1(a) + w (P2(a) +
+   w P3(a))), w = a^rho; FP32-output cells have no P3.  The terms in w are
+   a small part of R near 0, so the library pow's accuracy is ample. */
+template <int DEG>
+__device__ __forceinline__ double hyp_origin(const double* __restrict__ row, double a)
+{
+    /* the families in row order, from the highest power of w down, and
+       their degrees in v */
+    constexpr int NFAM = DEG == HYP_DEGREE ? 4 : 3;
+    constexpr int DG64[4] = {0, 1, 2, 4}, DG32[4] = {0, 1, 3, 0};
+    const double w = ::pow(a, row[0]);
+    double R = 0;
+    int k = 1;
+#pragma unroll
+    for (int n = 0; n < NFAM; ++n) {
+        const int dg = DEG == HYP_DEGREE ? DG64[n] : DG32[n];
+        double p = 0;
+#pragma unroll
+        for (int m = 0; m <= dg; ++m, ++k) p = __builtin_fma(p, a, row[k]);
+        R = __builtin_fma(R, w, p);
+    }
+    return R;
+}
+
 /* |Q(v)| beyond the LDS cells: the side's global-memory cells up to v_top,
-   then the large-v form; inf -> inf, NaN -> NaN.  The side's parameters
-   come as plain values selected per lane (a reference to a lane-dependent
-   side, or a struct passed by value, would put them in scratch memory). */
+   then the large-v form; inf -> inf, NaN -> NaN; below v0 on a side with the
+   origin series, that series.  The side's parameters come as plain values
+   selected per lane (a reference to a lane-dependent side, or a struct
+   passed by value, would put them in scratch memory). */
 template <int DEG>
 static __device__ __noinline__ double hyp_far(double a, double v0, double inv_v0, double v_top, double c0, double c1,
-                                              double c2, double clog, const double* gcoef, int ncell)
+                                              double c2, double clog, const double* gcoef, int ncell, int origin)
 {
+    if (origin && a < v0) return a * hyp_origin<DEG>(gcoef, a);
     if (!(a < v_top)) {
         if (!(a < __builtin_inf())) return a;
         if (clog == 0.0) return a + (c0 + (c1 + c2 / a) / a);
@@ -155,7 +184,7 @@ __device__ __forceinline__ double hyp_far_of(double v, const HypParams& P)
     const bool neg = v < 0.0;
     return hyp_far<DEG>(__builtin_fabs(v), P.v0, P.inv_v0, neg ? P.l.v_top : P.r.v_top, neg ? P.l.c0 : P.r.c0,
                    neg ? P.l.c1 : P.r.c1, neg ? P.l.c2 : P.r.c2, neg ? P.l.clog : P.r.clog,
-                   neg ? P.l.gcoef : P.r.gcoef, neg ? P.l.ncell : P.r.ncell);
+                   neg ? P.l.gcoef : P.r.gcoef, neg ? P.l.ncell : P.r.ncell, neg ? P.l.origin : P.r.origin);
 }
 
 /* Both sides' LDS rows: right side rows 0..nlds-1, left side after (for

@@ -408,6 +408,12 @@ fq solve_far(const Side& sd, fq v, fq x0)
 struct SideMap {
     fq slope0 = 0, rate = 0;
     fq c0 = 0, c1 = 0, c2 = 0, clog = 0;
+    /* rho > 0: the target density carries a factor |x|^rho at 0 with rho not
+       an integer (variance-gamma, rho = 2 lambda - 1), so R = Q/v has terms
+       in v^(m + n rho) there, which no polynomial cell near v = 0 can match;
+       the first octave of cells is then one series in v and v^rho
+       (fit_origin) */
+    fq rho = 0;
     virtual fq eval(fq v) const = 0;
     virtual ~SideMap() {}
     fq far(fq v) const
@@ -655,6 +661,118 @@ bool fit_cells(const SideMap& ss, const CellSpec& cs, fq v0, int j0, int j1, dou
 }
 
 /*
+ * The first octave of t (v in [0, v0)) of a side with rho > 0, as one
+ * series in v and w = v^rho (the terms v^(m + n rho) of R near the origin):
+ *     R = P0(v) + w (P1(v) + w (P2(v) + w P3(v))),
+ * P0..P3 of degrees 4, 2, 1, 0 for the FP64-output cells (row of 12
+ * doubles: rho, then the coefficients of P3, P2, P1 and P0, each highest
+ * power first) and P0..P2 of degrees 3, 1, 0 for the FP32-output cells
+ * (row of 8).  The smallest exponent left out is at least 4 (3 for FP32
+ * outputs), since rho > 1.  Where two terms have the same exponent (rho a
+ * fraction such as 3/2: v^3 and w^2), or exponents within 1e-9, the term
+ * of the higher family is left out (its coefficient is 0).  Fitted by
+ * least squares (Householder QR, in __float128) on Chebyshev nodes of
+ * s = v/v0 in [0, 1], in the scaled basis s^(m + n rho), then checked like
+ * a cell, as the kernel evaluates it (w = v^rho rounded to a double, the
+ * row's rounded coefficients), on a uniform and a geometric grid down to
+ * v = v0 1e-30.  Returns the worst truncation error; *rounded gets that of
+ * the rounded row.
+ */
+constexpr int ORIGIN_DEG64[4] = {4, 2, 1, 0};
+constexpr int ORIGIN_DEG32[3] = {3, 1, 0};
+
+fq fit_origin(const SideMap& ss, int deg, fq v0, double* row, fq* rounded)
+{
+    const bool f64 = deg == HYP_DEGREE;
+    const int nfam = f64 ? 4 : 3;
+    const int* dg = f64 ? ORIGIN_DEG64 : ORIGIN_DEG32;
+    const fq rho = (fq)(double)ss.rho;           /* the kernel's rho */
+    int pw_m[16], pw_n[16], K = 0;
+    for (int n = nfam - 1; n >= 0; --n)
+        for (int m = dg[n]; m >= 0; --m) {
+            pw_m[K] = m;
+            pw_n[K] = n;
+            ++K;
+        }
+    /* the fitted terms: all but those whose exponent a lower family has */
+    int col[16], J = 0;
+    for (int k = 0; k < K; ++k) {
+        bool dup = false;
+        for (int l = 0; l < K; ++l)
+            if (pw_n[l] < pw_n[k] && fabsq(pw_m[l] + pw_n[l] * rho - (pw_m[k] + pw_n[k] * rho)) < 1e-9Q) dup = true;
+        if (!dup) col[J++] = k;
+    }
+    /* least squares: A a = f, A_ij = s_i^(m_k + n_k rho), k = col[j] */
+    const int N = 4 * K;
+    std::vector<fq> A((size_t)N * J), f(N);
+    for (int i = 0; i < N; ++i) {
+        const fq sn = (1 - cosq(M_PIq * (i + 0.5Q) / N)) / 2;
+        const fq v = v0 * sn;
+        f[i] = ss.eval(v) / v;
+        for (int j = 0; j < J; ++j) A[(size_t)i * J + j] = powq(sn, pw_m[col[j]] + pw_n[col[j]] * rho);
+    }
+    /* Householder QR applied to [A | f] */
+    for (int k = 0; k < J; ++k) {
+        fq nrm = 0;
+        for (int i = k; i < N; ++i) nrm += A[(size_t)i * J + k] * A[(size_t)i * J + k];
+        nrm = sqrtq(nrm);
+        const fq akk = A[(size_t)k * J + k];
+        const fq alpha = akk > 0 ? -nrm : nrm;
+        std::vector<fq> u(N, 0);
+        u[k] = akk - alpha;
+        for (int i = k + 1; i < N; ++i) u[i] = A[(size_t)i * J + k];
+        fq uu = 0;
+        for (int i = k; i < N; ++i) uu += u[i] * u[i];
+        if (uu == 0) continue;
+        for (int j = k; j < J; ++j) {
+            fq d = 0;
+            for (int i = k; i < N; ++i) d += u[i] * A[(size_t)i * J + j];
+            d = 2 * d / uu;
+            for (int i = k; i < N; ++i) A[(size_t)i * J + j] -= d * u[i];
+        }
+        fq d = 0;
+        for (int i = k; i < N; ++i) d += u[i] * f[i];
+        d = 2 * d / uu;
+        for (int i = k; i < N; ++i) f[i] -= d * u[i];
+    }
+    std::vector<fq> a(J);
+    for (int k = J - 1; k >= 0; --k) {
+        fq t = f[k];
+        for (int j = k + 1; j < J; ++j) t -= A[(size_t)k * J + j] * a[j];
+        a[k] = t / A[(size_t)k * J + k];
+    }
+    /* unscaled coefficients of v^m w^n, the row as the kernel reads it */
+    fq c[16];
+    for (int k = 0; k < K; ++k) c[k] = 0;
+    for (int j = 0; j < J; ++j) c[col[j]] = a[j] / powq(v0, pw_m[col[j]] + pw_n[col[j]] * rho);
+    row[0] = (double)rho;
+    for (int k = 0; k < K; ++k) row[1 + k] = (double)c[k];
+    auto eval = [&](fq v, fq w, bool use_row) {
+        /* Horner in v within each family, then in w, highest family first */
+        fq R = 0;
+        int k = 0;
+        for (int n = nfam - 1; n >= 0; --n) {
+            fq p = 0;
+            for (int m = dg[n]; m >= 0; --m, ++k) p = p * v + (use_row ? (fq)row[1 + k] : c[k]);
+            R = R * w + p;
+        }
+        return R;
+    };
+    fq worst = 0, worst_r = 0;
+    for (int t = 0; t <= 400; ++t) {
+        const fq v = t <= 200 ? v0 * t / 200 : v0 * powq(10, -30 * (fq)(t - 201) / 199);
+        const fq ref = v > 0 ? ss.eval(v) / v : ss.slope0;
+        const fq w = powq(v, rho);
+        const fq wd = (fq)(double)powq((fq)(double)v, rho);
+        const fq et = fabsq(eval(v, w, false) / ref - 1), er = fabsq(eval((fq)(double)v, wd, true) / ref - 1);
+        if (et > worst) worst = et;
+        if (er > worst_r) worst_r = er;
+    }
+    *rounded = worst_r;
+    return worst;
+}
+
+/*
  * Cells of one side for v0 = 2^lv, lv <= max_lv: the largest lv whose
  * cells all meet the tolerance (the first octave of t, uniform cells on
  * [0, v0), and the next two decide it; the rest are then fitted and
@@ -684,7 +802,17 @@ int fit_side(const SideMap& ss, const CellSpec& cs, int max_lv, std::vector<doub
         fq worst = 0;
         int bad = -1;
         const int head = ncell < 3 * HYP_SUB ? ncell : 3 * HYP_SUB;
-        if (!fit_cells(ss, cs, v0, 0, head, rows.data(), &worst, &bad)) continue;
+        const bool origin = ss.rho > 0;
+        if (origin) {
+            /* the first octave: one series in v and v^rho in row 0 (rows 1..7
+               are not read); the cells from the second octave on as usual */
+            fq ow = 0;
+            if (fit_origin(ss, cs.deg, v0, rows.data(), &ow) > cs.tol || !(ow < 6 * cs.tol + 1.2e-16Q)) continue;
+            if (ow > worst) worst = ow;
+            if (!fit_cells(ss, cs, v0, HYP_SUB, head, rows.data() + (size_t)HYP_SUB * W, &worst, &bad)) continue;
+        } else if (!fit_cells(ss, cs, v0, 0, head, rows.data(), &worst, &bad)) {
+            continue;
+        }
         if (!fit_cells(ss, cs, v0, head, ncell, rows.data() + (size_t)head * W, &worst, &bad)) {
             fq lo, hi;
             cell_bounds(v0, bad, &lo, &hi);
@@ -702,7 +830,7 @@ int fit_side(const SideMap& ss, const CellSpec& cs, int max_lv, std::vector<doub
         hs->noct = noct;
         hs->ncell = ncell;
         hs->degree = cs.deg;
-        hs->reserved = 0;
+        hs->origin = origin ? 1 : 0;
         *rows_out = std::move(rows);
         return lv;
     }
@@ -1226,6 +1354,9 @@ struct VGRealSide : SideMap {
         alpha = alpha_;
         beta = beta_;
         rate = alpha - beta;
+        /* |x|^(2 lambda - 1) at 0 (the z^(2 nu) series of K_nu); analytic when
+           2 lambda is an integer */
+        rho = fmodq(2 * lam, 1) != 0 ? 2 * lam - 1 : 0;
         if (!bes.build(nu, err, errlen)) return false;
         logA = lam * logq((alpha - beta) * (alpha + beta)) - nu * logq(2 * alpha) - 0.5Q * logq(M_PIq) - lgammaq(lam);
         log_f0 = logA - nu * logq(alpha) + bes.L0;

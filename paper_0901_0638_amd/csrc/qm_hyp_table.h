@@ -21,7 +21,13 @@ constexpr int HYP_MAX_OCT = 40;     /* octaves per side at most */
  * Cell j holds R = sum_k c_{j,k} d^k, d = v - centre_j, centre_j at
  * t = 2^k (1 + (i + 1/2)/HYP_SUB), highest power first, degree + 1
  * doubles per row, starting coef_offset doubles into the table's
- * coefficient block.  From v_top = v0 (2^noct - 1) on, the large-v
+ * coefficient block.  A side with origin = 1 (a variance-gamma target
+ * whose density carries |x|^rho at 0, rho = 2 lambda - 1 not an integer)
+ * instead holds in row 0 the first octave v < v0 as one series in v and
+ * w = v^rho, R = P0(v) + w (P1(v) + w (P2(v) + w P3(v))): rho, then the
+ * coefficients of P3, P2, P1, P0, highest power first, degrees 4, 2, 1, 0
+ * (FP64-output cells) or, without P3, 3, 1, 0 (FP32-output cells); rows 1
+ * to HYP_SUB - 1 are then not read.  From v_top = v0 (2^noct - 1) on, the large-v
  * expansion of the tail condition: for the hyperbolic target (Section 8.1:
  * both H and the base have constant rates far out, so Q - v tends to a
  * constant) Q = v + far_c0 + (far_c1 + far_c2 / v) / v; for a target whose
@@ -37,7 +43,7 @@ struct HypSide {
     int32_t noct;
     int32_t ncell;           /* HYP_SUB noct */
     int32_t degree;          /* rows of degree + 1 doubles */
-    int32_t reserved;
+    int32_t origin;          /* 1: the first octave (v < v0) is the series in v and v^rho of row 0 */
     uint64_t coef_offset;
 };
 

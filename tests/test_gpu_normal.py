@@ -204,6 +204,33 @@ def test_quantile_f64_paper_t2_specials_and_checks(ctx):
     torch.cuda.synchronize()
 
 
+def test_map_kernel_ragged_sizes(ctx):
+    """The per-element map kernel (the paper's forms, exp -> normal) streams
+    tiles of 256 vectors per wave: sizes below, at and past a tile, with a
+    partial last tile, and an input one element off 16-byte alignment."""
+    for n in (1, 3, 255, 513, 1025, 5001):
+        u = qi.uniform53(9, n, n)
+        ref = oracle.norm_quantile(u)
+        assert_close(run_nq(ctx, u, qm.QM_PAPER), ref, RTOL_F64, "paper n=%d" % n)
+        assert_close(run_nq(ctx, u, qm.QM_PAPER_T2), ref, RTOL_F64, "t2 n=%d" % n)
+        x = qi.exponentials(9, n, n)
+        x[::3] *= -1
+        assert_close(run_e(ctx, x), oracle.exp_to_normal(x), RTOL_F64, "exp n=%d" % n)
+        x32 = x.astype(np.float32)
+        ref32 = oracle.exp_to_normal(x32.astype(np.float64))
+        assert_close(run_e(ctx, x32), ref32, RTOL_F32, "exp f32 n=%d" % n)
+    x = qi.exponentials(10, 1, 5001)
+    base = torch.from_numpy(np.concatenate([[0.0], x])).cuda()
+    out = torch.empty(5001, dtype=torch.float64, device="cuda")
+    out2 = torch.empty(5002, dtype=torch.float64, device="cuda")
+    qm.qm_recycle_exp_to_normal(ctx, base[1:], out)        # not co-aligned: element-wise
+    qm.qm_recycle_exp_to_normal(ctx, base[1:], out2[1:])   # co-aligned: a head element, tiles, a tail
+    torch.cuda.synchronize()
+    ref = oracle.exp_to_normal(x)
+    assert_close(out.cpu().numpy(), ref, RTOL_F64, "exp misaligned")
+    assert_close(out2[1:].cpu().numpy(), ref, RTOL_F64, "exp head and tail")
+
+
 def test_quantile_f64_paper_t2_full_size_sampled(ctx):
     """2^28 open uniforms (the paper's timing input) in the launch the
     benchmark times for this form, sampled as the other full-size tests."""

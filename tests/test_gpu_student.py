@@ -58,8 +58,9 @@ def test_student_f64_edges(ctx):
     for nu in (1, 4, 30):
         got = run_t(ctx, z, nu)
         assert_close(got, oracle.student_t_map(z, nu), RTOL_F64, "edges nu=%s" % nu)
-    # ragged sizes, misaligned and in place
-    for n in (1, 2, 3, 7, 255, 257):
+    # ragged sizes (below, at and past a wave's tile of 256 vectors, with a
+    # partial last tile), misaligned and in place
+    for n in (1, 2, 3, 7, 255, 257, 513, 1025, 5001):
         zz = qi.normals(5, n, n)
         assert_close(run_t(ctx, zz, 3), oracle.student_t_map(zz, 3), RTOL_F64, "n=%d" % n)
     zz = qi.normals(6, 0, 3001)
@@ -169,6 +170,10 @@ def test_student_f32_edges(ctx):
         ref = as_f32_output(oracle.student_t_map(z.astype(np.float64), nu))
         assert_close(got, ref, RTOL_F32, "f32 edges nu=%s" % nu)
         assert np.signbit(got[1]) and np.signbit(got[3])
+    for n in (1, 5, 1023, 1025, 2049, 9001):      # tiles of 1024 floats per wave
+        zz = qi.normals(7, n, n).astype(np.float32)
+        ref = as_f32_output(oracle.student_t_map(zz.astype(np.float64), 4.0))
+        assert_close(run_t(ctx, zz, 4.0), ref, RTOL_F32, "f32 n=%d" % n)
 
 
 @pytest.mark.parametrize("nu", [1, 4, 30])

@@ -16,7 +16,7 @@ pytestmark = pytest.mark.gpu
 import paper_0901_0638_amd as qm  # noqa: E402
 
 PARAMS = [(1, 1.0, 0.0), (2, 1.0, 0.0), (2, 1.0, 0.5), (3, 2.0, -1.0), (5, 1.0, 0.3), (8, 1.0, 0.0)]
-REAL = [(1.5, 1.0, 0.5), (2.5, 2.0, -1.0), (4.25, 1.0, 0.3)]
+REAL = [(1.5, 1.0, 0.5), (2.5, 2.0, -1.0), (4.25, 1.0, 0.3), (1.05, 1.0, 0.3), (1.2, 2.0, -1.0)]
 
 
 @pytest.fixture(scope="module")
@@ -68,7 +68,7 @@ def test_vg_specials_location_and_api(ctx):
     olp, olm = oracle.vg_masses(*p)
     assert abs(lp - olp) <= 1e-15 and abs(lm - olm) <= 1e-15
     d = torch.zeros(8, dtype=torch.float64, device="cuda")
-    for bad in [(0.5, 1.0, 0.0), (9, 1.0, 0.0), (8.5, 1.0, 0.0), (1.1, 1.0, 0.0), (2, 1.0, 1.5)]:
+    for bad in [(0.5, 1.0, 0.0), (0.99, 1.0, 0.0), (9, 1.0, 0.0), (8.5, 1.0, 0.0), (2, 1.0, 1.5)]:
         with pytest.raises(qm.QMError):
             qm.qm_recycle_exp_to_vg(ctx, d, d, *bad)
 
@@ -129,14 +129,16 @@ def test_vg_ragged_misaligned_inplace_and_request_checks(ctx):
 
 @pytest.mark.parametrize("p", REAL, ids=lambda p: "l%g_a%g_b%g" % p)
 def test_vg_real_lambda_f64(ctx, p):
-    """Real lambda: base samples with the target's masses, the first cells
-    (where the density's x^(2 lambda - 1) term at 0 bends Q), and the far
-    range out to 1e300."""
+    """Real lambda: base samples with the target's masses, the first octave
+    (where the density's x^(2 lambda - 1) term at 0 bends Q; for 2 lambda
+    not an integer the origin series on the far path), across v0, and the
+    far range out to 1e300."""
     lam, a, b = p
     lp, lm = oracle.vgr_masses(*p)
     v = qi.two_sided_exponentials(7, 4, 3001, a - b, a + b, math.exp(lm))
     far = np.concatenate([np.geomspace(1e-300, 1e300, 120), -np.geomspace(1e-300, 1e300, 120),
                           np.geomspace(1e-7, 1e-2, 60), -np.geomspace(1e-7, 1e-2, 60),
+                          np.geomspace(1e-3, 0.03, 64), -np.geomspace(1e-3, 0.03, 64),
                           np.geomspace(30 / (a - b), 1e7, 40), -np.geomspace(30 / (a + b), 1e7, 40)])
     v = np.concatenate([v, far])
     print("case: vg real lambda f64 %r, %d elements" % (p, v.size), flush=True)

@@ -19,17 +19,36 @@ PARAMS = [(1.0, 0.0, 1.0), (1.0, 0.5, 1.0), (2.0, -1.5, 0.3), (1.0, 0.9, 5.0), (
           (50.0, 10.0, 0.1)]
 
 
+def origin_eval(row, a, which):
+    """A side's first octave in the origin form (row 0: rho, then the
+    coefficients of P3..P0 or P2..P0, highest power first): R = P0(a) +
+    w (P1(a) + w (P2(a) + w P3(a))), w = a^rho, as the kernel evaluates it."""
+    degs = (0, 1, 2, 4) if which == "f64" else (0, 1, 3)
+    w = a ** row[0]
+    R, k = 0.0, 1
+    for dg in degs:
+        p = 0.0
+        for _ in range(dg + 1):
+            p = p * a + row[k]
+            k += 1
+        R = R * w + p
+    return R
+
+
 def table_eval(h, rr, rl, v, which="f64"):
     """The kernel's evaluation of a table, in numpy FP64: t = 1 + |v|/v0 by
     one fused multiply-add, the cell from the exponent and top three
-    mantissa bits of t, its centre from t with the lower bits replaced."""
+    mantissa bits of t, its centre from t with the lower bits replaced; a
+    side with an origin form takes it below v0."""
     v = np.asarray(v, np.float64)
     out = np.empty_like(v)
     right, left = (h.right, h.left) if which == "f64" else (h.right32, h.left32)
     for i, x in enumerate(v):
         S, rows = (left, rl) if x < 0 else (right, rr)
         a = abs(x)
-        if not a < S.v_top:
+        if S.origin and a < S.v0:
+            Q = a * origin_eval(rows[0], a, which)
+        elif not a < S.v_top:
             if not np.isfinite(a):
                 Q = a
             elif S.far_clog == 0:

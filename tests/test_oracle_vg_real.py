@@ -98,23 +98,37 @@ def test_tail_and_central_mass_match_quadrature(lam, al, be, xs):
         assert abs(oracle.vgr_central_mass(x, lam, al, be) / float(ref) - 1) < 2e-15, x
 
 
-@pytest.mark.parametrize("lam,al,be,v", [(1.5, 1.0, 0.5, 4.0), (4.25, 1.0, 0.3, 0.9), (4.25, 1.0, 0.3, 15.0)])
+@pytest.mark.parametrize("lam,al,be,v", [(1.5, 1.0, 0.5, 4.0), (4.25, 1.0, 0.3, 0.9), (4.25, 1.0, 0.3, 15.0),
+                                         (1.05, 1.0, 0.3, 0.002), (1.2, 2.0, -1.0, -0.001)])
 def test_map_solves_its_equation(lam, al, be, v):
-    """1 - F(Q) = p+ e^{-(alpha - beta) v} (v >= 0) at the oracle's Q, with
-    the tail by mpmath quadrature of the Bessel-function density: the
-    residual in log(1 - F), divided by its derivative f/(1 - F), moves Q by
-    at most a few parts in 1e16."""
+    """1 - F(Q) = p+ e^{-(alpha - beta) v} (v >= 0; v < 0 on the mirrored
+    side) at the oracle's Q, with the tail by mpmath quadrature of the
+    Bessel-function density (near the origin its central form, the integral
+    from 0 to Q): the residual, divided by its derivative, moves Q by at
+    most a few parts in 1e16."""
     mp.mp.dps = 20
+    if v < 0:                       # v < 0 is the mirrored side: beta -> -beta
+        lam, al, be, sgn = lam, al, -be, -1
+    else:
+        sgn = 1
     f = density(lam, al, be)
     lp, _ = oracle.vgr_masses(lam, al, be)
-    x0 = oracle.vgr_map(np.array([v]), lam, al, be)[0]
-    tail = mp.quad(f, [x0, x0 + 2, x0 + 12, x0 + 60, mp.inf])
-    resid = mp.log(tail) - (mp.mpf(lp) - (al - be) * mp.mpf(v))
-    dx = resid * tail / f(mp.mpf(x0))
+    x0 = sgn * oracle.vgr_map(np.array([v]), lam, al, -be if sgn < 0 else be)[0]
+    va = abs(v)
+    if (al - be) * va < 0.5:
+        # near the origin the central form, int_0^Q f = p+ (1 - e^{-(alpha - beta) v}), is the well-conditioned one
+        mp.mp.dps = 30
+        cen = mp.quad(f, [0, x0])
+        dx = (mp.exp(lp) * -mp.expm1(-(al - be) * mp.mpf(va)) - cen) / f(mp.mpf(x0))
+    else:
+        tail = mp.quad(f, [x0, x0 + 2, x0 + 12, x0 + 60, mp.inf])
+        resid = mp.log(tail) - (mp.mpf(lp) - (al - be) * mp.mpf(va))
+        dx = resid * tail / f(mp.mpf(x0))
     assert abs(float(dx) / x0) < 4e-16, (v, x0, float(dx))
 
 
-@pytest.mark.parametrize("lam,al,be", [(1.5, 1.0, 0.5), (2.5, 2.0, -1.0), (4.25, 1.0, 0.3)])
+@pytest.mark.parametrize("lam,al,be", [(1.5, 1.0, 0.5), (2.5, 2.0, -1.0), (4.25, 1.0, 0.3), (1.05, 1.0, 0.3),
+                                       (1.2, 2.0, -1.0)])
 def test_slope_at_zero(lam, al, be):
     """Q(v) ~ Q'(0) v, Q'(0) = p+ (alpha - beta) / f(0), f(0) = A Gamma(nu) 2^(nu-1) alpha^(-nu)."""
     mp.mp.dps = 30

@@ -10,7 +10,7 @@ import oracle
 import paper_0901_0638_amd as qm
 from tests.test_hyp_table import table_eval
 
-PARAMS = [(1.5, 1.0, 0.5), (2.5, 2.0, -1.0), (4.25, 1.0, 0.3)]
+PARAMS = [(1.5, 1.0, 0.5), (2.5, 2.0, -1.0), (4.25, 1.0, 0.3), (1.05, 1.0, 0.3), (1.2, 2.0, -1.0)]
 
 
 @pytest.fixture(scope="module", params=PARAMS, ids=lambda p: "l%g_a%g_b%g" % p)
@@ -56,9 +56,31 @@ def test_header(built):
         assert S.max_rel_err < 1.2e-16
 
 
-def test_lambda_near_one_is_rejected():
-    """lambda = 1.2: the density's x^(2 lambda - 1) = x^1.4 term at 0 would need
-    first cells narrower than 40 octaves of the cell layout allow; the
-    builder reports it instead of a table that misses its accuracy."""
-    with pytest.raises(ValueError):
-        qm.debug_vg_table(1.2, 1.0, 0.0)
+def test_origin_series_where_the_density_is_not_analytic():
+    """2 lambda not an integer: the density's |x|^(2 lambda - 1) at 0 puts
+    terms v^(m + n rho) in R near the origin, so both sides' first octave
+    holds the series in v and v^rho (row 0 starts with rho); 2 lambda an
+    integer (lambda = 1.5, 2.5): plain cells throughout."""
+    for p, want in (((1.05, 1.0, 0.3), 1), ((1.2, 2.0, -1.0), 1), ((4.25, 1.0, 0.3), 1), ((1.5, 1.0, 0.5), 0),
+                    ((2.5, 2.0, -1.0), 0)):
+        for which in ("f64", "f32"):
+            h, rr, rl = qm.debug_vg_table(*p, which=which)
+            sides = (h.right, h.left) if which == "f64" else (h.right32, h.left32)
+            for S, rows in zip(sides, (rr, rl)):
+                assert S.origin == want, (p, which)
+                if want:
+                    assert rows[0][0] == 2 * p[0] - 1
+
+
+def test_origin_series_near_zero_and_at_v0():
+    """lambda = 1.05 and 1.2 (rho = 1.1 and 1.4, far from analytic): the
+    origin series against the oracle from v = 1e-300 up to v0 and across
+    the switch to the cells at v0, on both sides."""
+    for p in ((1.05, 1.0, 0.3), (1.2, 2.0, -1.0)):
+        h, rr, rl = qm.debug_vg_table(*p)
+        v0 = h.right.v0
+        v = np.concatenate([np.geomspace(1e-300, v0, 300), v0 * np.array([0.999999, 1.0, 1.000001, 1.3, 2.0])])
+        v = np.concatenate([v, -v])
+        ref = oracle.vgr_map(v, *p)
+        rel = np.abs(table_eval(h, rr, rl, v) - ref) / np.abs(ref)
+        assert rel.max() <= 6e-16, (p, rel.max(), v[rel.argmax()])
