@@ -90,7 +90,7 @@ def qm_normal_quantile(ctx, u, w, mode=QM_PLAIN, stream=None):
 def qm_generate(ctx, seed, stream_id, first, out, kind=QM_NORMAL_QUANTILE, mode=None, stream=None):
     """out[i] = map of the open uniform of element first + i of the Philox4x32-10
     stream with key (seed, stream_id): kind QM_UNIFORM (u itself) or
-    QM_NORMAL_QUANTILE (Phi^{-1}(u); FP64 PLAIN/PAPER/PAPER_T2, FP32 F32_REFINE/PLAIN/PAPER)."""
+    QM_NORMAL_QUANTILE (Phi^{-1}(u); FP64 PLAIN/PAPER, FP32 F32_REFINE/PLAIN/PAPER)."""
     if out.device.type != "cuda" or not out.is_contiguous():
         raise ValueError("output must be a contiguous tensor on a HIP device")
     dt = _dtype_of(out)
