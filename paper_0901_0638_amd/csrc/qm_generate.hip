@@ -57,6 +57,14 @@ __device__ __forceinline__ void block_uniforms(uint64_t b, uint32_t k0, uint32_t
 }
 
 /* H: the per-element map (Op), or with GATHER the hybrid (HybridNQ64/32). */
+/* The first lane's value of x, as a wave-uniform (scalar) value. */
+__device__ __forceinline__ uint64_t gen_wave_uniform(uint64_t x)
+{
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)x);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(x >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
 template <typename T, int UNROLL, class H, bool GATHER, bool VECTOR>
 __global__ __launch_bounds__(256) void k_generate(GenArgs<T> a)
 {
@@ -73,14 +81,19 @@ __global__ __launch_bounds__(256) void k_generate(GenArgs<T> a)
         const uint64_t block0 = (a.first + a.head) / NV;
         /* whole waves iterate together (the bound is tested on the wave's
            first lane), as the gather needs */
-        const uint64_t wave_first = tid - lane;
-        for (uint64_t i0 = wave_first; i0 < a.nvec; i0 += UNROLL * stride) {
-            const uint64_t i = i0 + lane;
+        /* wave-contiguous tiles of 64 UNROLL vectors, dealt out to the waves
+           in turn; whole waves iterate together, as the gather needs, and the
+           blocks of a partial last tile past the end are drawn but not stored */
+        constexpr uint64_t TILE = 64ull * UNROLL;
+        const uint64_t step = (uint64_t)gridDim.x * 4 * TILE;
+        for (uint64_t t = gen_wave_uniform(((uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * TILE); t < a.nvec;
+             t += step) {
+            const uint64_t i = t + lane;
             T u[K], w[K];
 #pragma unroll
             for (int k = 0; k < UNROLL; ++k) {
                 T b[NV];
-                block_uniforms(block0 + i + k * stride, a.k0, a.k1, b);
+                block_uniforms(block0 + i + 64 * k, a.k0, a.k1, b);
 #pragma unroll
                 for (int j = 0; j < NV; ++j) u[NV * k + j] = b[j];
             }
@@ -93,7 +106,7 @@ __global__ __launch_bounds__(256) void k_generate(GenArgs<T> a)
             }
 #pragma unroll
             for (int k = 0; k < UNROLL; ++k) {
-                uint64_t idx = i + k * stride;
+                uint64_t idx = i + 64 * k;
                 V y;
 #pragma unroll
                 for (int j = 0; j < NV; ++j) y[j] = w[NV * k + j];
@@ -220,14 +233,19 @@ __global__ __launch_bounds__(256) void k_generate_t(GenArgs<T> a, const double* 
         T* buf = outer_buf[GATHER ? (threadIdx.x >> 6) : 0];
         V* vout = reinterpret_cast<V*>(a.out + a.head);
         const uint64_t block0 = (a.first + a.head) / NV;
-        const uint64_t wave_first = tid - lane;
-        for (uint64_t i0 = wave_first; i0 < a.nvec; i0 += UNROLL * stride) {
-            const uint64_t i = i0 + lane;
+        /* wave-contiguous tiles of 64 UNROLL vectors, dealt out to the waves
+           in turn; whole waves iterate together, as the gather needs, and the
+           blocks of a partial last tile past the end are drawn but not stored */
+        constexpr uint64_t TILE = 64ull * UNROLL;
+        const uint64_t step = (uint64_t)gridDim.x * 4 * TILE;
+        for (uint64_t t = gen_wave_uniform(((uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * TILE); t < a.nvec;
+             t += step) {
+            const uint64_t i = t + lane;
             T u[K], w[K];
 #pragma unroll
             for (int k = 0; k < UNROLL; ++k) {
                 T b[NV];
-                block_uniforms(block0 + i + k * stride, a.k0, a.k1, b);
+                block_uniforms(block0 + i + 64 * k, a.k0, a.k1, b);
 #pragma unroll
                 for (int j = 0; j < NV; ++j) u[NV * k + j] = b[j];
             }
@@ -242,7 +260,7 @@ __global__ __launch_bounds__(256) void k_generate_t(GenArgs<T> a, const double* 
             for (int k = 0; k < K; ++k) w[k] = tmap(w[k]);
 #pragma unroll
             for (int k = 0; k < UNROLL; ++k) {
-                uint64_t idx = i + k * stride;
+                uint64_t idx = i + 64 * k;
                 V y;
 #pragma unroll
                 for (int j = 0; j < NV; ++j) y[j] = w[NV * k + j];
@@ -309,8 +327,13 @@ __global__ __launch_bounds__(256) void k_generate_h(GenArgs<T> a, HypParams P, H
     if (VECTOR) {
         V* vout = reinterpret_cast<V*>(a.out + a.head);
         const uint64_t block0 = (a.first + a.head) / NV;
-        uint64_t i = tid;
-        for (; i < a.nvec; i += UNROLL * stride) {
+        const uint32_t lane = __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+        /* wave-contiguous tiles, as k_generate */
+        constexpr uint64_t TILE = 64ull * UNROLL;
+        const uint64_t step = (uint64_t)gridDim.x * 4 * TILE;
+        for (uint64_t t = gen_wave_uniform(((uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * TILE); t < a.nvec;
+             t += step) {
+            const uint64_t i = t + lane;
             double v[K], q[K];
             bool far[K];
             bool anyfar = false;
@@ -318,7 +341,7 @@ __global__ __launch_bounds__(256) void k_generate_h(GenArgs<T> a, HypParams P, H
             for (int k = 0; k < UNROLL; ++k) {
                 T b[NV];
                 /* blocks past the end are drawn but never stored */
-                block_uniforms(block0 + i + k * stride, a.k0, a.k1, b);
+                block_uniforms(block0 + i + 64 * k, a.k0, a.k1, b);
 #pragma unroll
                 for (int j = 0; j < NV; ++j) v[NV * k + j] = B((double)b[j]);
             }
@@ -338,7 +361,7 @@ __global__ __launch_bounds__(256) void k_generate_h(GenArgs<T> a, HypParams P, H
             }
 #pragma unroll
             for (int k = 0; k < UNROLL; ++k) {
-                uint64_t idx = i + k * stride;
+                uint64_t idx = i + 64 * k;
                 V y;
 #pragma unroll
                 for (int j = 0; j < NV; ++j) y[j] = (T)(P.mu + __builtin_copysign(q[NV * k + j], v[NV * k + j]));
