@@ -73,10 +73,12 @@ def test_origin_series_where_the_density_is_not_analytic():
 
 
 def test_origin_series_near_zero_and_at_v0():
-    """lambda = 1.05 and 1.2 (rho = 1.1 and 1.4, far from analytic): the
+    """lambda = 1.05 and 1.2 (rho = 1.1 and 1.4, far from analytic), 1.25
+    (rho = 3/2: v^3 and w^2, v^4 and v w^2 coincide, so only the lower
+    family's terms are fitted) and 1.1666... (rho = 4/3: v^4 and w^3): the
     origin series against the oracle from v = 1e-300 up to v0 and across
     the switch to the cells at v0, on both sides."""
-    for p in ((1.05, 1.0, 0.3), (1.2, 2.0, -1.0)):
+    for p in ((1.05, 1.0, 0.3), (1.2, 2.0, -1.0), (1.25, 1.0, 0.3), (7.0 / 6.0, 1.0, -0.2)):
         h, rr, rl = qm.debug_vg_table(*p)
         v0 = h.right.v0
         v = np.concatenate([np.geomspace(1e-300, v0, 300), v0 * np.array([0.999999, 1.0, 1.000001, 1.3, 2.0])])
