@@ -168,7 +168,8 @@ qm_status qm_recycle_student_t(qm_ctx* ctx, const void* d_z, void* d_t, uint64_t
  * (Section 6).  Exp(1) inputs give half-normal magnitudes; signed (Laplace)
  * inputs give N(0,1).  No logarithm is taken: v = |x| is the rational's
  * variable directly.  +-0 -> +-0, +-inf -> +-inf, NaN -> NaN.
- * dtype/mode: F64 {PLAIN, PAPER}; F32 F32_REFINE.
+ * dtype/mode: F64 {PLAIN, PAPER}; F32 {F32_REFINE, PLAIN} (PLAIN: the FP64
+ * map of the widened input, rounded once to FP32).
  */
 qm_status qm_recycle_exp_to_normal(qm_ctx* ctx, const void* d_x, void* d_z, uint64_t n,
                                    int dtype, int mode, void* hip_stream);

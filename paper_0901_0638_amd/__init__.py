@@ -138,7 +138,7 @@ def qm_recycle_student_t(ctx, z, t, nu, mode=None, stream=None):
 
 
 def qm_recycle_exp_to_normal(ctx, x, z, mode=None, stream=None):
-    """z = sign(x) Phi^{-1}(1 - e^{-|x|}/2) (FP64 PLAIN/PAPER or FP32 F32_REFINE)."""
+    """z = sign(x) Phi^{-1}(1 - e^{-|x|}/2) (FP64 PLAIN/PAPER or FP32 F32_REFINE/PLAIN)."""
     pi, po, n, dt = _io(x, z)
     if mode is None:
         mode = QM_PLAIN if dt == QM_F64 else QM_F32_REFINE

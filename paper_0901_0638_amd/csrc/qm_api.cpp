@@ -78,8 +78,8 @@ qm_status check_request(const qm_request& r, int* dtype_size_out, bool single_ca
         if (r.mode == QM_PAPER_T2) return fail(QM_E_DTYPE, "QM_PAPER_T2 is for the normal quantile only");
         if (r.dtype == QM_F64 && r.mode == QM_F32_REFINE)
             return fail(QM_E_DTYPE, "QM_F32_REFINE needs dtype QM_F32");
-        if (r.dtype == QM_F32 && r.mode != QM_F32_REFINE)
-            return fail(QM_E_DTYPE, "exp->normal in FP32 is only available as QM_F32_REFINE");
+        if (r.dtype == QM_F32 && r.mode == QM_PAPER)
+            return fail(QM_E_DTYPE, "exp->normal in FP32: QM_F32_REFINE or QM_PLAIN");
         break;
     case QM_STUDENT_T:
         if (!(r.dtype == QM_F64 && r.mode == QM_PLAIN) && !(r.dtype == QM_F32 && r.mode == QM_F32_REFINE))

@@ -24,7 +24,7 @@ constexpr size_t QM_BATCH_DYNAMIC_LDS_MAX = 65536 - 8192 - 256;
 
 enum BatchOp : uint32_t {
     BOP_NQ64_PLAIN = 0, BOP_NQ64_PAPER, BOP_NQ32_REFINE, BOP_NQ32_PAPER, BOP_NQ32_PLAIN,
-    BOP_E64_PLAIN, BOP_E64_PAPER, BOP_E32_REFINE, BOP_T64, BOP_T32, BOP_H64, BOP_H32,
+    BOP_E64_PLAIN, BOP_E64_PAPER, BOP_E32_REFINE, BOP_T64, BOP_T32, BOP_H64, BOP_H32, BOP_E32_PLAIN,
 };
 
 /* Device block: header, then nreq BatchReq. */

@@ -83,6 +83,7 @@ QM_CHUNK_FN(chunk_nq32_plain, float, normal_quantile_f32_plain(x))
 QM_CHUNK_FN(chunk_e64_plain, double, exp_to_normal_f64<false>(x))
 QM_CHUNK_FN(chunk_e64_paper, double, exp_to_normal_f64<true>(x))
 QM_CHUNK_FN(chunk_e32_refine, float, exp_to_normal_f32_refine(x))
+QM_CHUNK_FN(chunk_e32_plain, float, (float)exp_to_normal_f64<false>((double)x))
 QM_CHUNK_FN(chunk_copy64, double, x)
 QM_CHUNK_FN(chunk_copy32, float, x)
 #undef QM_CHUNK_FN
@@ -215,6 +216,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
         case BOP_E64_PLAIN: chunk_e64_plain(R.in, R.out, begin, end); break;
         case BOP_E64_PAPER: chunk_e64_paper(R.in, R.out, begin, end); break;
         case BOP_E32_REFINE: chunk_e32_refine(R.in, R.out, begin, end); break;
+        case BOP_E32_PLAIN: chunk_e32_plain(R.in, R.out, begin, end); break;
         case BOP_T64:
         case BOP_T32: {
             if (R.P.identity) {

@@ -27,6 +27,7 @@ struct OpNQ32Refine { __device__ float operator()(float u) const { return normal
 struct OpNQ32Paper  { __device__ float operator()(float u) const { return normal_quantile_f32_paper(u); } };
 struct OpNQ32Plain  { __device__ float operator()(float u) const { return normal_quantile_f32_plain(u); } };
 struct OpE32Refine  { __device__ float operator()(float x) const { return exp_to_normal_f32_refine(x); } };
+struct OpE32Plain   { __device__ float operator()(float x) const { return (float)exp_to_normal_f64<false>((double)x); } };
 
 /*
  * The hybrid quantiles (FP64 plain, FP32+refine) split each element into

@@ -260,6 +260,7 @@ hipError_t launch_elementwise(int kind, int dtype, int mode, const void* in, voi
         if (dtype == QM_F64 && mode == QM_PLAIN) return launch_op<double, OpE64Plain>(in, out, n, s, shape);
         if (dtype == QM_F64 && mode == QM_PAPER) return launch_op<double, OpE64Paper>(in, out, n, s, shape);
         if (dtype == QM_F32 && mode == QM_F32_REFINE) return launch_op<float, OpE32Refine>(in, out, n, s, shape);
+        if (dtype == QM_F32 && mode == QM_PLAIN) return launch_op<float, OpE32Plain>(in, out, n, s, shape);
     }
     return hipErrorInvalidValue;
 }

@@ -149,7 +149,7 @@ static uint32_t batch_op(const qm_request& r)
         return r.mode == QM_PAPER ? BOP_NQ32_PAPER : BOP_NQ32_PLAIN;
     case QM_EXP_TO_NORMAL:
         if (r.dtype == QM_F64) return r.mode == QM_PAPER ? BOP_E64_PAPER : BOP_E64_PLAIN;
-        return BOP_E32_REFINE;
+        return r.mode == QM_PLAIN ? BOP_E32_PLAIN : BOP_E32_REFINE;
     case QM_EXP_TO_HYPERBOLIC:
     case QM_EXP_TO_VG:
         return r.dtype == QM_F64 ? BOP_H64 : BOP_H32;

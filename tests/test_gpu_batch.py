@@ -160,6 +160,7 @@ ALL_COMBOS = [
     (qm.QM_NORMAL_QUANTILE, np.float32, qm.QM_F32_REFINE), (qm.QM_NORMAL_QUANTILE, np.float32, qm.QM_PAPER),
     (qm.QM_NORMAL_QUANTILE, np.float32, qm.QM_PLAIN), (qm.QM_EXP_TO_NORMAL, np.float64, qm.QM_PLAIN),
     (qm.QM_EXP_TO_NORMAL, np.float64, qm.QM_PAPER), (qm.QM_EXP_TO_NORMAL, np.float32, qm.QM_F32_REFINE),
+    (qm.QM_EXP_TO_NORMAL, np.float32, qm.QM_PLAIN),
     (qm.QM_STUDENT_T, np.float64, qm.QM_PLAIN), (qm.QM_STUDENT_T, np.float32, qm.QM_F32_REFINE),
 ]
 

@@ -319,6 +319,23 @@ def test_exp_to_normal_f64_paper(ctx):
     assert_close(run_e(ctx, x, qm.QM_PAPER), oracle.exp_to_normal(x), RTOL_F64, "exp->normal paper")
 
 
+def test_exp_to_normal_f32_plain(ctx):
+    """FP32 in/out, QM_PLAIN: the FP64 map of the widened input rounded once,
+    so the oracle value rounded to float (a midpoint within 2e-15 aside);
+    QM_PAPER is not an FP32 form of this map."""
+    x = qi.exponentials(3, 1, 1 << 18).astype(np.float32)
+    x = np.concatenate([x, -x[:100], np.array([0, -0.0, 102.9, 103.1, 500, 1e4, np.inf, -np.inf, np.nan], np.float32)])
+    ref = oracle.exp_to_normal(x.astype(np.float64))
+    got = run_e(ctx, x, qm.QM_PLAIN)
+    assert_close(got, as_f32_output(ref), RTOL_F32, "exp->normal f32 plain")
+    r32 = ref.astype(np.float32)
+    fin = np.isfinite(ref)
+    assert np.mean(got[fin] == r32[fin]) > 0.999
+    with pytest.raises(qm.QMError) as e:
+        run_e(ctx, x[:16], qm.QM_PAPER)
+    assert e.value.status == qm.QM_E_DTYPE
+
+
 def test_exp_to_normal_f32_refine(ctx):
     x = qi.exponentials(2, 1, 1 << 18).astype(np.float32)
     x = np.concatenate([x, -x[:100], np.array([0, 102.9, 103.1, 500, 1e4, np.inf, -np.inf, np.nan], np.float32)])
