@@ -228,6 +228,8 @@ def run_quantile(args, torch, qm, qi):
     d32 = [e[1].elapsed_time(e[2]) for e in events]
     avg64 = sum(d64) / len(d64)
     avg32 = sum(d32) / len(d32)
+    print("per-step ms FP64: %s" % " ".join("%.3f" % d for d in d64), file=sys.stderr)
+    print("per-step ms FP32: %s" % " ".join("%.3f" % d for d in d32), file=sys.stderr, flush=True)
     # latency percentiles over more launches than the timed steps, outside
     # the timed region (same interleaving)
     p64, p32 = per_launch(torch, stream, [f64, f32], args.pct_reps) if args.pct_reps > 0 else (d64, d32)
@@ -783,7 +785,9 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=None,
+                    help="untimed steps before the timed ones (default: 60 quantile steps, 240 hyperbolic "
+                         "steps, about 80 ms of work: the clocks settle over the first 30 ms of a run)")
     ap.add_argument("--workload", choices=["quantile", "batch", "serve", "hyperbolic"], default="quantile")
     ap.add_argument("--n", type=int, default=1 << 28, help="samples per pass (quantile workload)")
     ap.add_argument("--cpu-sample", type=int, default=1 << 28, help="oracle sample size (elements)")
@@ -803,6 +807,8 @@ def main():
     ap.add_argument("--serve-extra-count", type=int, default=500)
     ap.add_argument("--serve-extra-rates", type=float, nargs="+", default=[10000, 50000])
     args = ap.parse_args()
+    if args.warmup is None:
+        args.warmup = {"quantile": 60, "hyperbolic": 240}.get(args.workload, 1)
     if args.gpus != 1:
         print("bench.py measures one GPU only: the maps are elementwise and shard into contiguous ranges "
               "without communication, so --gpus %d is not run." % args.gpus, file=sys.stderr)
