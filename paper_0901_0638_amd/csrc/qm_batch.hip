@@ -118,7 +118,7 @@ static __device__ __noinline__ void chunk_hybrid(const void* vin_, void* vout_, 
     const uint64_t nvec = (n - head) / NV;
     const uint64_t tail_begin = head + nvec * NV;
     const uint32_t lane = __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
-    T* buf = reinterpret_cast<T*>(gather + (threadIdx.x >> 6) * GATHER_DOUBLES_PER_WAVE);
+    T* buf = reinterpret_cast<T*>(gather + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) * GATHER_DOUBLES_PER_WAVE);
     const V* vin = reinterpret_cast<const V*>(in + head);
     V* vout = reinterpret_cast<V*>(out + head);
     for (uint64_t i0 = threadIdx.x - lane; i0 < nvec; i0 += UNROLL * blockDim.x) {

@@ -352,11 +352,24 @@ __device__ __forceinline__ double halley_upper(double x0, double p_over_phi, con
     return __builtin_fma(t, 1.0 + h, x0);
 }
 
+/* One Newton correction of x0 ~ z >= 0 solving q(z) = p (notation as for
+ * halley_upper): x1 = x0 + t.  Newton leaves (x0/2) e0^2 of a seed error e0,
+ * i.e. x0^2 eps^2 / 2 relative for a relative seed error eps: 1.4e-8 at
+ * z = 14 for the 1.2e-5 seed below, so Halley's extra factor is not needed
+ * there. */
+template <int NP, int NQ>
+__device__ __forceinline__ double newton_upper(double x0, double p_over_phi, const double (&MP)[NP],
+                                               const double (&MQ)[NQ])
+{
+    double t = div_pos_fast(horner(x0, MP), horner(x0, MQ)) - p_over_phi;
+    return x0 + t;
+}
+
 /* Phi^{-1}(u) for FP32 u outside the centre: FP32 seed in the exponential
-   coordinate + one FP64 Halley step, rounded to FP32.  Here z > 1.6449, so
-   the step takes the Mills ratio of [1.6, 14.5] (8.5e-9, moving the result
-   by about 8.5e-9 / z^2 relative) and the degree-7 exponential (5.3e-9, by
-   about 5.3e-9 / z^2). */
+   coordinate (1.2e-5) + one FP64 Newton step, rounded to FP32.  Here
+   z > 1.6449, so the step takes the Mills ratio of [1.6, 14.5] (8.5e-9,
+   moving the result by about 8.5e-9 / z^2 relative) and the degree-7
+   exponential (5.3e-9, by about 5.3e-9 / z^2). */
 __device__ __forceinline__ float outer_quantile_f32_refine(float u)
 {
     const double SQRT2PI = 2.5066282746310005024;
@@ -368,13 +381,12 @@ __device__ __forceinline__ float outer_quantile_f32_refine(float u)
     double pd = (double)p;
     /* x0 has a 24-bit significand, so x0*x0/2 is exact in FP64 */
     double p_over_phi = pd * SQRT2PI * exp_refine<7>(0.5 * (x0 * x0));
-    double x1 = halley_upper(x0, p_over_phi, QM_MILLS32_P, QM_MILLS32_Q);
-    float w = __builtin_copysignf((float)x1, u - 0.5f);
-    w = (u == 0.0f) ? -__builtin_inff() : w;
-    w = (u == 1.0f) ? __builtin_inff() : w;
+    double x1 = newton_upper(x0, p_over_phi, QM_MILLS32_P, QM_MILLS32_Q);
+    /* u = 0 and u = 1 both give p = 0: +-inf by the sign of u - 1/2 */
+    float mag = (p == 0.0f) ? __builtin_inff() : (float)x1;
     /* NaN and out-of-range inputs need no select: p + p is then negative or
-       NaN, the hardware log returns NaN, and NaN propagates to w */
-    return w;
+       NaN, the hardware log returns NaN, and NaN propagates to the result */
+    return __builtin_copysignf(mag, u - 0.5f);
 }
 
 /*

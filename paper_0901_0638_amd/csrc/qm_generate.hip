@@ -76,7 +76,7 @@ __global__ __launch_bounds__(256) void k_generate(GenArgs<T> a)
     if (VECTOR) {
         const uint32_t lane = __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
         __shared__ T outer_buf[GATHER ? 4 : 1][GATHER ? 64 * K : 1];
-        T* buf = outer_buf[GATHER ? (threadIdx.x >> 6) : 0];
+        T* buf = outer_buf[GATHER ? __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) : 0];
         V* vout = reinterpret_cast<V*>(a.out + a.head);
         const uint64_t block0 = (a.first + a.head) / NV;
         /* whole waves iterate together (the bound is tested on the wave's
@@ -230,7 +230,7 @@ __global__ __launch_bounds__(256) void k_generate_t(GenArgs<T> a, const double* 
     if (VECTOR) {
         const uint32_t lane = __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
         __shared__ T outer_buf[GATHER ? 4 : 1][GATHER ? 64 * K : 1];
-        T* buf = outer_buf[GATHER ? (threadIdx.x >> 6) : 0];
+        T* buf = outer_buf[GATHER ? __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) : 0];
         V* vout = reinterpret_cast<V*>(a.out + a.head);
         const uint64_t block0 = (a.first + a.head) / NV;
         /* wave-contiguous tiles of 64 UNROLL vectors, dealt out to the waves

@@ -72,26 +72,33 @@ template <> struct HybridOf<OpNQ64Plain> { typedef HybridNQ64 type; };
 template <> struct HybridOf<OpNQ32Refine> { typedef HybridNQ32 type; };
 
 /* The gather step: u[K] per lane in, w[K] out; buf is the wave's LDS list
-   of 64 K elements.  Every lane of the wave must call it together. */
+   of 64 K elements (its address must be wave-uniform).  Every lane of the
+   wave must call it together.  Each slot's ballot is taken once, where its
+   comparison is made, and kept as a scalar mask: a lane's list position is
+   the running count (scalar) plus the set bits of that mask below the lane
+   (two mbcnt), and the list address one shift-add from those. */
 template <typename T, int K, class H>
 __device__ __forceinline__ void hybrid_eval(const T (&u)[K], T (&w)[K], T* buf, uint32_t lane)
 {
     bool outer[K];
-    uint64_t cnt = 0;
+    uint64_t m[K];
+    uint32_t cnt = 0;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         outer[k] = H::split(u[k], w[k]);
-        cnt += __popcll(__ballot(outer[k]));
+        m[k] = __ballot(outer[k]);
+        cnt += (uint32_t)__popcll(m[k]);
     }
     if (!cnt) return;
-    uint32_t pos[K];
+    T* slot[K];
     uint32_t base = 0;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-        uint64_t m = __ballot(outer[k]);
-        pos[k] = base + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-        if (outer[k]) buf[pos[k]] = u[k];
-        base += (uint32_t)__popcll(m);
+        const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(m[k] >> 32),
+                                                         __builtin_amdgcn_mbcnt_lo((uint32_t)m[k], 0u));
+        slot[k] = (buf + base) + below;
+        if (outer[k]) *slot[k] = u[k];
+        base += (uint32_t)__popcll(m[k]);
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -104,7 +111,7 @@ __device__ __forceinline__ void hybrid_eval(const T (&u)[K], T (&w)[K], T* buf, 
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 #pragma unroll
     for (int k = 0; k < K; ++k)
-        if (outer[k]) w[k] = buf[pos[k]];
+        if (outer[k]) w[k] = *slot[k];
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
 }

@@ -129,7 +129,7 @@ __global__ __launch_bounds__(256) void k_hybrid(MapArgs<T> a)
     constexpr int K = NV * UNROLL;
     constexpr uint64_t TILE = 64ull * UNROLL;
     __shared__ T outer_buf[4][64 * K];
-    T* buf = outer_buf[threadIdx.x >> 6];
+    T* buf = outer_buf[__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)];
     const uint32_t lane = __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
     const V* vin = reinterpret_cast<const V*>(a.in + a.head);
     V* vout = reinterpret_cast<V*>(a.out + a.head);

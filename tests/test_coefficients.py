@@ -160,6 +160,57 @@ def test_fp32_central_newton_step_emulated():
     assert np.max(np.abs(rounded[nz] / ref[nz] - 1)) <= 1e-7
 
 
+def exp_refine7(a):
+    """The correction step's e^a emulated in float64: a = k ln2 + r, the
+    degree-7 Taylor polynomial in r, scaled by 2^k."""
+    k = np.rint(a * 1.4426950408889634074)
+    r = (a - k * 0.69314718055994528623) - k * 2.3190468138462996154e-17
+    p = np.full_like(r, 1.0 / math.factorial(7))
+    for i in range(6, -1, -1):
+        p = p * r + 1.0 / math.factorial(i)
+    return np.ldexp(p, k.astype(np.int64))
+
+
+def test_fp32_outer_newton_step_emulated():
+    """The outer FP32+refine evaluation emulated in float32/float64 (plain
+    numpy, no FMA): v = -log(2p) and the seed v S4(v)/S5(v) in float32, then
+    one FP64 Newton step x1 = x0 + M(x0) - p sqrt(2 pi) e^{x0^2/2} with the
+    [1.6, 14.5] Mills ratio and the degree-7 exponential.  Over p from the
+    smallest FP32 denormal to 0.05 the step lands within 3e-8 of the oracle
+    before the final rounding (Newton's own error is x0^2 eps^2 / 2 for the
+    seed's eps = 1.2e-5: 1.4e-8 at z = 14), and within 1e-7 after it."""
+    c = arrays()
+    p = np.unique(np.geomspace(1.4e-45, 0.05, 40001).astype(np.float32))
+    p = p[p > 0]
+    x = (p + p).astype(np.float32)
+    sub = x < np.float32(2.0 ** -126)
+    xs = np.where(sub, x.astype(np.float64) * 2.0 ** 32, x.astype(np.float64)).astype(np.float32)
+    l2 = np.log2(xs.astype(np.float64)).astype(np.float32)
+    ln2f = np.float32(0.693147180559945309)
+    v = (-l2.astype(np.float64) * float(ln2f) + np.where(sub, 32.0 * float(ln2f), 0.0)).astype(np.float32)
+    num = np.zeros_like(v)
+    for k in c["QM_SEED_P"]:
+        num = (num * v + np.float32(k)).astype(np.float32)
+    num = (v * num).astype(np.float32)
+    den = np.zeros_like(v)
+    for k in c["QM_SEED_Q"]:
+        den = (den * v + np.float32(k)).astype(np.float32)
+    z0 = (num * (np.float32(1) / den)).astype(np.float32)
+    x0 = z0.astype(np.float64)
+    p_over_phi = p.astype(np.float64) * 2.5066282746310005024 * exp_refine7(0.5 * (x0 * x0))
+    mp_ = np.zeros_like(x0)
+    for k in c["QM_MILLS32_P"]:
+        mp_ = mp_ * x0 + k
+    mq = np.zeros_like(x0)
+    for k in c["QM_MILLS32_Q"]:
+        mq = mq * x0 + k
+    x1 = x0 + (mp_ / mq - p_over_phi)
+    ref = -oracle.norm_quantile(p.astype(np.float64))
+    assert np.max(np.abs(x1 / ref - 1)) <= 3e-8
+    rounded = x1.astype(np.float32).astype(np.float64)
+    assert np.max(np.abs(rounded / ref - 1)) <= 1e-7
+
+
 PAPER_HDR = os.path.join(os.path.dirname(__file__), "..", "paper_0901_0638_amd", "csrc", "qm_paper_coeffs.h")
 
 

@@ -261,12 +261,12 @@ def test_quantile_f32_refine_edges(ctx):
 
 def test_quantile_f32_refine_central_outer_boundary(ctx):
     """FP32+refine switches between its central piece (FP32 seed + FP64
-    Newton against erf) and the exponential-coordinate seed + Halley against
-    erfc at |u - 1/2| = 0.45; both sides and the switch points, every float
+    Newton against erf) and the exponential-coordinate seed + FP64 Newton
+    against erfc at |u - 1/2| = 0.45; both sides and the switch points, every float
     in a window around them, in mixed and single-piece waves.  Before its
     rounding to float the result is within 2.5e-8 of the oracle (central
     piece: E6 and G3 of the Newton step; outer: the Mills ratio and the
-    exponential of the Halley step), so it is the oracle value rounded to
+    exponential of that step), so it is the oracle value rounded to
     float except within 4e-8 of a midpoint, where it may be the neighbour."""
     edges = []
     for c in (0.05, 0.95, 0.25, 0.75, 0.5):
