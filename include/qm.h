@@ -373,6 +373,12 @@ qm_status qm_run_batch_noalloc(qm_ctx* ctx, const qm_request* reqs, uint64_t cou
  * previous launch as one batch; batches run on several streams, so requests
  * admitted while others are on the GPU overlap with them.  Per-request state
  * (descriptors, chunk counters) lives on the device for the batch's life.
+ * Completion is per request: the workgroup that writes a request's last
+ * chunk raises a flag in host-coherent memory once all of the request's
+ * stores have reached device memory, and the scheduler reports the request
+ * complete as soon as it sees the flag, while the rest of its batch may
+ * still run (in a batch of more than 4096 requests with n > 0, at the
+ * batch's end).
  * Ordering: the serving streams are the library's own and are not ordered
  * after any stream of the caller.  The request's input must therefore be
  * complete in device memory, and its output no longer read or written by

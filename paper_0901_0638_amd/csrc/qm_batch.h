@@ -27,18 +27,26 @@ enum BatchOp : uint32_t {
     BOP_E64_PLAIN, BOP_E64_PAPER, BOP_E32_REFINE, BOP_T64, BOP_T32, BOP_H64, BOP_H32, BOP_E32_PLAIN,
 };
 
-/* Device block: header, then nreq BatchReq. */
+/* Device block: header, then nreq BatchReq (then, with per-request
+   completion, nreq chunk counters). */
 struct BatchHeader {
     uint64_t counter;       /* next chunk to claim; 0 at launch */
     uint64_t total_chunks;
     uint32_t nreq;
     uint32_t reserved;
     uint64_t chunk;         /* elements per chunk */
+    /* per-request completion (the serving loop), or both NULL: for a
+       request marked `flagged`, left[i] holds its unfinished chunks (its
+       chunk count at launch, in device memory) and done[i] is a
+       host-visible word, 0 at launch, that the workgroup finishing its last
+       chunk sets to 1 once every store of the request has reached memory */
+    uint32_t* left;
+    uint32_t* done;
 };
 
 struct BatchReq {
     uint32_t op;            /* BatchOp */
-    uint32_t reserved;
+    uint32_t flagged;       /* per-request completion: count this request's chunks and raise its flag */
     const void* in;
     void* out;
     uint64_t n;

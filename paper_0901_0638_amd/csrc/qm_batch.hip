@@ -192,6 +192,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
     const uint64_t total = hdr->total_chunks;
     const uint64_t chunk = hdr->chunk;
     const uint32_t nreq = hdr->nreq;
+    uint32_t* const left = hdr->left;
+    uint32_t* const done = hdr->done;
     for (;;) {
         if (threadIdx.x == 0) s_chunk = atomicAdd(reinterpret_cast<unsigned long long*>(&hdr->counter), 1ull);
         __syncthreads();
@@ -252,6 +254,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
         }
         default:
             break;
+        }
+        if (done && R.flagged) {
+            /* per-request completion: each thread's stores of the chunk
+               reach device scope before the workgroup counts the chunk;
+               the workgroup that counts a request's last chunk raises its
+               host-visible flag (release at system scope).  Only requests
+               of a few chunks are flagged: the fence writes back the L2,
+               too dear for every chunk of a large batch */
+            __threadfence();
+            __syncthreads();
+            if (threadIdx.x == 0 &&
+                __hip_atomic_fetch_add(left + lo, ~0u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) == 1u)
+                __hip_atomic_store(done + lo, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
         }
     }
 }

@@ -42,6 +42,13 @@ namespace qm {
 /* Batch runner                                                             */
 /* ------------------------------------------------------------------------ */
 
+/* Per-request completion costs the workgroups of a flagged request an L2
+   write-back per chunk, so only requests of at most this many chunks are
+   flagged (measured: flagging every chunk slowed the batch kernel enough
+   that the 50k requests/s trace fell behind its arrivals); larger ones
+   dominate their batch's time anyway and complete with its event. */
+constexpr uint64_t BATCH_FLAG_CHUNKS = 8;
+
 struct Staging {
     void* host = nullptr;
     void* dev = nullptr;
@@ -264,7 +271,8 @@ static uint64_t batch_blocks(const qm_ctx* ctx, uint64_t chunks)
  * done is not NULL, an event that completes with the launch is recorded
  * into it (the caller owns the event).
  */
-qm_status enqueue_batch(qm_ctx* ctx, const qm_request* reqs, uint64_t count, hipStream_t s, hipEvent_t done)
+qm_status enqueue_batch(qm_ctx* ctx, const qm_request* reqs, uint64_t count, hipStream_t s, hipEvent_t done,
+                        uint32_t* flags)
 {
     qm_status st = validate_batch(ctx, reqs, count);
     if (st != QM_OK) return st;
@@ -281,10 +289,26 @@ qm_status enqueue_batch(qm_ctx* ctx, const qm_request* reqs, uint64_t count, hip
         if (done && hipEventRecord(done, s) != hipSuccess) return set_error(QM_E_HIP, "hipEventRecord failed");
         return QM_OK;
     }
-    size_t bytes = sizeof(BatchHeader) + d.size() * sizeof(BatchReq);
+    const size_t reqs_bytes = sizeof(BatchHeader) + d.size() * sizeof(BatchReq);
+    size_t bytes = reqs_bytes + (flags ? d.size() * sizeof(uint32_t) : 0);
     Staging* slot = nullptr;
     st = acquire_slot(runner_of(ctx), bytes, &slot);
     if (st != QM_OK) return st;
+    if (flags) {
+        /* the chunk counters follow the descriptors; requests of at most
+           BATCH_FLAG_CHUNKS chunks are flagged, the others complete with
+           the batch */
+        uint32_t* left = reinterpret_cast<uint32_t*>((char*)slot->host + reqs_bytes);
+        for (size_t i = 0; i < d.size(); ++i) {
+            const uint64_t c = (d[i].n + h.chunk - 1) / h.chunk;
+            left[i] = (uint32_t)c;
+            d[i].flagged = c <= BATCH_FLAG_CHUNKS;
+        }
+    }
+    if (flags) {
+        h.left = reinterpret_cast<uint32_t*>((char*)slot->dev + reqs_bytes);
+        h.done = flags;
+    }
     memcpy(slot->host, &h, sizeof h);
     memcpy((char*)slot->host + sizeof h, d.data(), d.size() * sizeof(BatchReq));
     hipError_t e = hipMemcpyAsync(slot->dev, slot->host, bytes, hipMemcpyHostToDevice, s);
@@ -373,11 +397,20 @@ constexpr size_t SERVE_KEEP_LATENCIES = 1 << 20;
 struct InFlight {
     hipEvent_t ev;
     std::vector<uint64_t> tickets;
-    uint64_t bytes;
+    uint64_t bytes;             /* of the tickets not yet observed complete */
     int stream;
+    /* per-request completion: flag[k] is ticket k's word in its stream's
+       flag array, or -1 (n = 0, or no flags: the batch's event completes it) */
+    std::vector<int32_t> flag;
+    uint32_t* flags;
+    size_t open;                /* tickets not yet observed complete */
 };
 
 constexpr int SERVE_STREAMS = 4;
+/* Requests per batch that get a completion flag (a batch with more relies
+   on its event alone); one host-coherent array of this many words per
+   stream. */
+constexpr size_t SERVE_FLAGS = 4096;
 
 struct Server {
     qm_ctx* ctx = nullptr;
@@ -391,6 +424,7 @@ struct Server {
     bool stop = false;
     hipStream_t streams[SERVE_STREAMS] = {};
     bool stream_busy[SERVE_STREAMS] = {};
+    uint32_t* flags[SERVE_STREAMS] = {};  /* host-coherent, device-visible; NULL: events only */
     std::vector<InFlight> inflight;
     std::vector<hipEvent_t> free_events;
     std::deque<uint64_t> finished;        /* terminal tickets, oldest first */
@@ -410,6 +444,27 @@ static void finish_ticket(Server* S, uint64_t t)
     }
 }
 
+/* Ticket k of in-flight batch f observed complete at `now`. */
+static void complete_ticket(Server* S, InFlight& f, size_t k, clk::time_point now)
+{
+    const uint64_t t = f.tickets[k];
+    auto it = S->tickets.find(t);
+    /* already complete by its flag (and perhaps forgotten since) */
+    if (it == S->tickets.end() || it->second.state == T_DONE) return;
+    Ticket& tk = it->second;
+    tk.state = T_DONE;
+    tk.t_done = now;
+    uint64_t lat = (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(now - tk.t_submit).count();
+    if (S->latencies_ns.size() < SERVE_KEEP_LATENCIES) S->latencies_ns.push_back(lat);
+    else S->latencies_ns[S->completed % SERVE_KEEP_LATENCIES] = lat;
+    ++S->completed;
+    --S->in_flight_requests;
+    S->in_flight_bytes -= tk.bytes;
+    f.bytes -= tk.bytes;
+    --f.open;
+    finish_ticket(S, t);
+}
+
 static void server_loop(Server* S)
 {
     (void)hipSetDevice(S->ctx->device);
@@ -426,29 +481,24 @@ static void server_loop(Server* S)
     std::vector<qm_request> reqs;
     for (;;) {
         std::unique_lock<std::mutex> lk(S->mu);
-        /* retire finished batches */
+        /* complete requests whose flag is up, and retire finished batches
+           (their event completes whatever the flags have not) */
         clk::time_point now = clk::now();
         for (size_t i = 0; i < S->inflight.size();) {
-            if (hipEventQuery(S->inflight[i].ev) == hipSuccess) {
-                for (uint64_t t : S->inflight[i].tickets) {
-                    Ticket& tk = S->tickets[t];
-                    tk.state = T_DONE;
-                    tk.t_done = now;
-                    uint64_t lat =
-                        (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(now - tk.t_submit).count();
-                    if (S->latencies_ns.size() < SERVE_KEEP_LATENCIES) S->latencies_ns.push_back(lat);
-                    else S->latencies_ns[S->completed % SERVE_KEEP_LATENCIES] = lat;
-                    ++S->completed;
-                    finish_ticket(S, t);
-                }
-                S->in_flight_requests -= S->inflight[i].tickets.size();
-                S->in_flight_bytes -= S->inflight[i].bytes;
-                S->stream_busy[S->inflight[i].stream] = false;
-                S->free_events.push_back(S->inflight[i].ev);
+            InFlight& f = S->inflight[i];
+            if (hipEventQuery(f.ev) == hipSuccess) {
+                for (size_t k = 0; k < f.tickets.size(); ++k) complete_ticket(S, f, k, now);
+                S->stream_busy[f.stream] = false;
+                S->free_events.push_back(f.ev);
                 S->inflight.erase(S->inflight.begin() + i);
-            } else {
-                ++i;
+                continue;
             }
+            if (f.flags && f.open) {
+                for (size_t k = 0; k < f.tickets.size(); ++k)
+                    if (f.flag[k] >= 0 && __atomic_load_n(f.flags + f.flag[k], __ATOMIC_ACQUIRE) != 0)
+                        complete_ticket(S, f, k, now);
+            }
+            ++i;
         }
         /* continuous batching: a batch is formed only when a stream is idle,
            from everything queued by then (in arrival order, within the
@@ -493,6 +543,18 @@ static void server_loop(Server* S)
         }
         reqs.clear();
         for (uint64_t t : admit) reqs.push_back(S->tickets[t].req);
+        /* completion flags: one word per request with n > 0, in order */
+        std::vector<int32_t> flag(admit.size(), -1);
+        uint32_t* flags = S->flags[idle];
+        int32_t live = 0;
+        for (size_t k = 0; k < reqs.size(); ++k)
+            if (reqs[k].n > 0) flag[k] = live++;
+        if (flags && (size_t)live <= SERVE_FLAGS) {
+            for (int32_t k = 0; k < live; ++k) __atomic_store_n(flags + k, 0u, __ATOMIC_RELAXED);
+        } else {
+            flags = nullptr;
+            std::fill(flag.begin(), flag.end(), -1);
+        }
         S->in_flight_bytes += bytes;
         S->in_flight_requests += admit.size();
         if (S->in_flight_bytes > S->in_flight_bytes_hwm) S->in_flight_bytes_hwm = S->in_flight_bytes;
@@ -502,7 +564,7 @@ static void server_loop(Server* S)
         S->stream_busy[idle] = true;
         lk.unlock();
         if (!ev) (void)hipEventCreateWithFlags(&ev, hipEventDisableTiming);
-        qm_status rc = enqueue_batch(S->ctx, reqs.data(), reqs.size(), st, ev);
+        qm_status rc = enqueue_batch(S->ctx, reqs.data(), reqs.size(), st, ev, flags);
         lk.lock();
         if (rc != QM_OK) {
             for (uint64_t t : admit) {
@@ -516,7 +578,7 @@ static void server_loop(Server* S)
             S->free_events.push_back(ev);
             continue;
         }
-        S->inflight.push_back(InFlight{ev, admit, bytes, idle});
+        S->inflight.push_back(InFlight{ev, admit, bytes, idle, std::move(flag), flags, admit.size()});
     }
 }
 
@@ -534,6 +596,12 @@ static Server* server_of(qm_ctx* ctx, qm_status* st)
             *st = set_error(QM_E_HIP, "hipStreamCreate failed");
             return nullptr;
         }
+        /* completion flags in pinned host memory that the GPU writes
+           through to while a batch runs; without them (allocation failed)
+           every request completes with its batch's event */
+        void* p = nullptr;
+        if (hipHostMalloc(&p, SERVE_FLAGS * sizeof(uint32_t), hipHostMallocCoherent) == hipSuccess)
+            S->flags[i] = static_cast<uint32_t*>(p);
     }
     S->th = std::thread(server_loop, S);
     ctx->server = S;
@@ -559,6 +627,8 @@ void server_stop(Server* S)
             (void)hipStreamSynchronize(S->streams[i]);
             (void)hipStreamDestroy(S->streams[i]);
         }
+    for (int i = 0; i < SERVE_STREAMS; ++i)
+        if (S->flags[i]) (void)hipHostFree(S->flags[i]);
     delete S;
 }
 

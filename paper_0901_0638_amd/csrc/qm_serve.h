@@ -35,8 +35,11 @@ uint64_t ctx_budget(const qm_ctx* ctx);
 qm_status set_error(qm_status s, const char* msg);
 
 /* Validate and enqueue requests as one persistent launch (done: optional
-   event recorded after it). */
-qm_status enqueue_batch(qm_ctx* ctx, const qm_request* reqs, uint64_t count, hipStream_t s, hipEvent_t done);
+   event recorded after it).  flags, if not NULL, is a host-coherent array
+   with a zero word for each request with n > 0, in request order: the
+   launch sets a request's word to 1 once its output is complete. */
+qm_status enqueue_batch(qm_ctx* ctx, const qm_request* reqs, uint64_t count, hipStream_t s, hipEvent_t done,
+                        uint32_t* flags = nullptr);
 void runner_free(qm_ctx* ctx);
 void server_stop(Server* s);
 

@@ -445,3 +445,65 @@ def test_serving_budget_high_water_under_burst():
         assert torch.equal(ref, ys[-1])
     finally:
         c.close()
+
+
+def test_serving_request_completes_before_its_batch():
+    """Per-request completion inside one batch.  A 2^28-element request
+    fills the whole 4 GiB budget, so the next group waits and is admitted
+    as one batch after it: eight 2^12-element requests (first in the batch,
+    so their chunks are claimed first) and one large request that fills the
+    budget again.  Each small request is reported complete before the large
+    one (its flag, raised by the workgroup that writes its last chunk, not
+    the batch's end), and its output is already complete when read at that
+    moment, while the large request is still running: bitwise the single
+    call."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    budget = 4 << 30
+    c = qm.Context(0, hbm_budget_bytes=budget)
+    try:
+        n_block, n_small = 1 << 28, 1 << 12
+        n_big = n_block - 8 * n_small
+        block_in = torch.from_numpy(qi.uniform53(11, 0, n_block)).cuda()
+        block_out = torch.empty_like(block_in)
+        big_in = torch.from_numpy(qi.uniform53(11, 1, n_big)).cuda()
+        big_out = torch.full_like(big_in, float("nan"))
+        smalls = [torch.from_numpy(qi.uniform53(11, 2 + i, n_small)).cuda() for i in range(8)]
+        small_out = [torch.full_like(x, float("nan")) for x in smalls]
+        refs = []
+        for x in smalls:
+            r = torch.empty_like(x)
+            qm.qm_normal_quantile(c, x, r)
+            refs.append(r)
+        torch.cuda.synchronize()
+        print("per-request completion: blocker 2^28, 8 x 2^12 + %d in one batch" % n_big, flush=True)
+        t_block = qm.qm_submit(c, qm.make_request(qm.QM_NORMAL_QUANTILE, block_in, block_out))
+        ts = [qm.qm_submit(c, qm.make_request(qm.QM_NORMAL_QUANTILE, x, y)) for x, y in zip(smalls, small_out)]
+        t_big = qm.qm_submit(c, qm.make_request(qm.QM_NORMAL_QUANTILE, big_in, big_out))
+        seen = {}
+        deadline = time.time() + 60
+        while len(seen) < len(ts) and time.time() < deadline:
+            for i, t in enumerate(ts):
+                if i not in seen and qm.qm_poll(c, t) == qm.QM_OK:
+                    # read at once, on the caller's stream, while the batch may still run
+                    seen[i] = (small_out[i].cpu(), qm.qm_poll(c, t_big))
+        assert len(seen) == len(ts), "small requests did not complete"
+        wait_all(c, [t_block, t_big])
+        _, _, big_done = qm.qm_poll_times(c, t_big)
+        for i, t in enumerate(ts):
+            got, big_state = seen[i]
+            assert torch.equal(got.view(torch.int64), refs[i].cpu().view(torch.int64)), i
+            _, _, done = qm.qm_poll_times(c, t)
+            assert done < big_done, (i, done, big_done)
+        print("large request still pending when the small ones were read: %d of 8"
+              % sum(1 for g, s in seen.values() if s == qm.QM_PENDING), flush=True)
+        st = qm.qm_serving_stats_of(c)
+        assert st["completed"] == 10 and st["in_flight_bytes"] == 0 and st["in_flight_requests"] == 0
+        assert st["in_flight_bytes_high_water"] <= budget
+        idx = np.unique(np.random.default_rng(3).integers(0, n_big, 2000))
+        got = big_out[torch.from_numpy(idx).cuda()].cpu().numpy()
+        assert_close(got, oracle.norm_quantile(big_in[torch.from_numpy(idx).cuda()].cpu().numpy()), RTOL_F64, "big")
+        del block_in, block_out, big_in, big_out
+    finally:
+        c.close()
+        torch.cuda.empty_cache()
