@@ -43,11 +43,20 @@ namespace qm {
 /* ------------------------------------------------------------------------ */
 
 /* Per-request completion costs the workgroups of a flagged request an L2
-   write-back per chunk, so only requests of at most this many chunks are
+   write-back per chunk, so only requests of at most eight chunks are
    flagged (measured: flagging every chunk slowed the batch kernel enough
    that the 50k requests/s trace fell behind its arrivals); larger ones
    dominate their batch's time anyway and complete with its event. */
-constexpr uint64_t BATCH_FLAG_CHUNKS = 8;
+static uint64_t batch_flag_chunks()
+{
+    /* tuning: QM_SERVE_FLAG_CHUNKS overrides the limit (0: completion by
+       batch only) */
+    static const uint64_t v = [] {
+        const char* e = getenv("QM_SERVE_FLAG_CHUNKS");
+        return e ? (uint64_t)strtoull(e, nullptr, 10) : (uint64_t)8;
+    }();
+    return v;
+}
 
 struct Staging {
     void* host = nullptr;
@@ -296,13 +305,13 @@ qm_status enqueue_batch(qm_ctx* ctx, const qm_request* reqs, uint64_t count, hip
     if (st != QM_OK) return st;
     if (flags) {
         /* the chunk counters follow the descriptors; requests of at most
-           BATCH_FLAG_CHUNKS chunks are flagged, the others complete with
+           batch_flag_chunks() chunks are flagged, the others complete with
            the batch */
         uint32_t* left = reinterpret_cast<uint32_t*>((char*)slot->host + reqs_bytes);
         for (size_t i = 0; i < d.size(); ++i) {
             const uint64_t c = (d[i].n + h.chunk - 1) / h.chunk;
             left[i] = (uint32_t)c;
-            d[i].flagged = c <= BATCH_FLAG_CHUNKS;
+            d[i].flagged = c <= batch_flag_chunks();
         }
     }
     if (flags) {
@@ -495,8 +504,10 @@ static void server_loop(Server* S)
             }
             if (f.flags && f.open) {
                 for (size_t k = 0; k < f.tickets.size(); ++k)
-                    if (f.flag[k] >= 0 && __atomic_load_n(f.flags + f.flag[k], __ATOMIC_ACQUIRE) != 0)
+                    if (f.flag[k] >= 0 && __atomic_load_n(f.flags + f.flag[k], __ATOMIC_ACQUIRE) != 0) {
                         complete_ticket(S, f, k, now);
+                        f.flag[k] = -1;
+                    }
             }
             ++i;
         }
