@@ -279,10 +279,10 @@ qm_status qm_generate_student_t(qm_ctx* ctx, uint64_t seed, uint64_t stream, uin
  * Fused generation of hyperbolic samples (Section 8.1): element e's open
  * uniform u (as qm_generate kind QM_UNIFORM writes it, widened to FP64 for
  * F32) becomes a sample of the two-sided exponential base,
- *   v = log(u / p-) * (1 / (alpha + beta))        for u < p-,
- *   v = -log((1 - u) / p+) * (1 / (alpha - beta))  otherwise,
+ *   v = log(u * (1 / p-)) * (1 / (alpha + beta))        for u < p-,
+ *   v = -log((1 - u) * (1 / p+)) * (1 / (alpha - beta))  otherwise,
  * with p- = exp(log p-), p+ = exp(log p+) of qm_hyperbolic_masses and the
- * reciprocals each rounded once (all in FP64; the quotients are correctly
+ * reciprocals each rounded once (all in FP64; the products are correctly
  * rounded, the logarithm is within about an ulp), and then
  * x = mu + Q(v) as qm_recycle_exp_to_hyperbolic maps it.  Only x is written.
  * dtype/mode: F64 PLAIN; F32 F32_REFINE.  Other arguments and errors as for

@@ -200,17 +200,6 @@ hipError_t launch_generate(int kind, int dtype, int mode, uint32_t seed, uint32_
 
 StudentParams make_params(const TTableHeader& h, const TCells& c, const double* d_rows);
 
-/* The base's constants as the fused hyperbolic kernel takes them: p- and p+
-   as exp of the table's log masses, the reciprocal rates 1/(alpha + beta)
-   and 1/(alpha - beta), each one rounding. */
-static void hyp_base_constants(const HypTableHeader& h, double* p_minus, double* p_plus, double* inv_minus,
-                               double* inv_plus)
-{
-    *p_minus = std::exp(h.log_p_minus);
-    *p_plus = std::exp(h.log_p_plus);
-    *inv_minus = 1.0 / (h.alpha + h.beta);
-    *inv_plus = 1.0 / (h.alpha - h.beta);
-}
 
 /* Fused uniform -> normal -> Student t.  The quantile stage is the one of
    k_generate (H, gathered per wave with GATHER); each normal then goes
@@ -292,19 +281,33 @@ __global__ __launch_bounds__(256) void k_generate_t(GenArgs<T> a, const double* 
 /* The two-sided exponential base sample of an open uniform (Section 8.1),
    in FP64: one logarithm of the side's ratio, by the reduced atanh-series
    log of the quantile path (neg_log_unit; about an ulp, a third of the
-   instructions of the library log). */
+   instructions of the library log).  The ratio is a product with the
+   side's reciprocal mass, selected before one multiply: two IEEE divisions
+   on diverged lanes had cost some 20 instructions per sample. */
 struct HypBase {
-    double p_minus, p_plus, inv_rate_minus, inv_rate_plus;
+    double p_minus, inv_p_minus, inv_p_plus, inv_rate_minus, inv_rate_plus;
     __device__ __forceinline__ double operator()(double u) const
     {
         const bool neg = u < p_minus;
-        const double ratio = neg ? u / p_minus : (1.0 - u) / p_plus;
+        const double ratio = (neg ? u : 1.0 - u) * (neg ? inv_p_minus : inv_p_plus);
         /* u = 1 (an FP64 uniform of the top 53-bit value rounds to 1) is the
            base's right end, v = +inf (mapped to +inf) */
         const double l = ratio > 0.0 ? neg_log_unit(ratio) : __builtin_inf();
         return l * (neg ? -inv_rate_minus : inv_rate_plus);
     }
 };
+
+/* The base's constants as the fused hyperbolic kernel takes them: p- and p+
+   as exp of the table's log masses, their reciprocals, and the reciprocal
+   rates 1/(alpha + beta) and 1/(alpha - beta), each one rounding. */
+static void hyp_base_constants(const HypTableHeader& h, HypBase* B)
+{
+    B->p_minus = std::exp(h.log_p_minus);
+    B->inv_p_minus = 1.0 / B->p_minus;
+    B->inv_p_plus = 1.0 / std::exp(h.log_p_plus);
+    B->inv_rate_minus = 1.0 / (h.alpha + h.beta);
+    B->inv_rate_plus = 1.0 / (h.alpha - h.beta);
+}
 
 /* Fused uniform -> base sample -> hyperbolic: all K elements of a lane
    through the LDS cells, then one wave vote for the far ones (as
@@ -502,7 +505,7 @@ hipError_t launch_generate_hyperbolic(int dtype, int mode, uint32_t seed, uint32
     size_t lds = 0;
     if (!make_hyp_params(h, f32, d_table, ncoef, mu, &P, &lds)) return hipErrorInvalidValue;
     HypBase B;
-    hyp_base_constants(h, &B.p_minus, &B.p_plus, &B.inv_rate_minus, &B.inv_rate_plus);
+    hyp_base_constants(h, &B);
     if (f32) {
         GenArgs<float> a{};
         a.out = static_cast<float*>(out);
