@@ -32,6 +32,13 @@ __device__ __forceinline__ PhiloxWords philox4x32_10(uint64_t block, uint32_t k0
 {
     const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u, W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
     uint32_t c0 = (uint32_t)block, c1 = (uint32_t)(block >> 32), c2 = 0u, c3 = 0u;
+    /* The key (uniform across the wave) is passed through an empty asm
+       statement, so that the round keys below are formed per block by
+       scalar adds instead of being hoisted out of the caller's loop: held
+       for the whole loop, the twenty of them crowd the scalar registers of
+       the fused kernels, which then spill them to vector lanes and reload
+       them with vector instructions in every block. */
+    asm volatile("" : "+s"(k0), "+s"(k1));
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
         uint64_t p0 = (uint64_t)M0 * c0;
