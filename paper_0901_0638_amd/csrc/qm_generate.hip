@@ -79,15 +79,13 @@ __global__ __launch_bounds__(256) void k_generate(GenArgs<T> a)
         T* buf = outer_buf[GATHER ? __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) : 0];
         V* vout = reinterpret_cast<V*>(a.out + a.head);
         const uint64_t block0 = (a.first + a.head) / NV;
-        /* whole waves iterate together (the bound is tested on the wave's
-           first lane), as the gather needs */
         /* wave-contiguous tiles of 64 UNROLL vectors, dealt out to the waves
-           in turn; whole waves iterate together, as the gather needs, and the
-           blocks of a partial last tile past the end are drawn but not stored */
+           in turn; whole waves iterate together, as the gather needs.  Whole
+           tiles store without bound tests; in the one partial last tile the
+           blocks past the end are drawn but not stored. */
         constexpr uint64_t TILE = 64ull * UNROLL;
         const uint64_t step = (uint64_t)gridDim.x * 4 * TILE;
-        for (uint64_t t = gen_wave_uniform(((uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * TILE); t < a.nvec;
-             t += step) {
+        auto tile = [&](uint64_t t, auto whole) {
             const uint64_t i = t + lane;
             T u[K], w[K];
 #pragma unroll
@@ -110,9 +108,12 @@ __global__ __launch_bounds__(256) void k_generate(GenArgs<T> a)
                 V y;
 #pragma unroll
                 for (int j = 0; j < NV; ++j) y[j] = w[NV * k + j];
-                if (idx < a.nvec) __builtin_nontemporal_store(y, vout + idx);
+                if (decltype(whole)::value || idx < a.nvec) __builtin_nontemporal_store(y, vout + idx);
             }
-        }
+        };
+        uint64_t t = gen_wave_uniform(((uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * TILE);
+        for (; t + TILE <= a.nvec; t += step) tile(t, std::true_type());
+        if (t < a.nvec) tile(t, std::false_type());
         if (blockIdx.x == 0) {
             uint64_t extra = a.head + (a.n - a.tail_begin);
             for (uint64_t e = threadIdx.x; e < extra; e += blockDim.x) {
@@ -222,13 +223,12 @@ __global__ __launch_bounds__(256) void k_generate_t(GenArgs<T> a, const double* 
         T* buf = outer_buf[GATHER ? __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) : 0];
         V* vout = reinterpret_cast<V*>(a.out + a.head);
         const uint64_t block0 = (a.first + a.head) / NV;
-        /* wave-contiguous tiles of 64 UNROLL vectors, dealt out to the waves
-           in turn; whole waves iterate together, as the gather needs, and the
-           blocks of a partial last tile past the end are drawn but not stored */
+        /* wave-contiguous tiles of 64 UNROLL vectors, as k_generate: whole
+           tiles store without bound tests, the one partial last tile draws
+           its blocks past the end but does not store them */
         constexpr uint64_t TILE = 64ull * UNROLL;
         const uint64_t step = (uint64_t)gridDim.x * 4 * TILE;
-        for (uint64_t t = gen_wave_uniform(((uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * TILE); t < a.nvec;
-             t += step) {
+        auto tile = [&](uint64_t t, auto whole) {
             const uint64_t i = t + lane;
             T u[K], w[K];
 #pragma unroll
@@ -253,9 +253,12 @@ __global__ __launch_bounds__(256) void k_generate_t(GenArgs<T> a, const double* 
                 V y;
 #pragma unroll
                 for (int j = 0; j < NV; ++j) y[j] = w[NV * k + j];
-                if (idx < a.nvec) __builtin_nontemporal_store(y, vout + idx);
+                if (decltype(whole)::value || idx < a.nvec) __builtin_nontemporal_store(y, vout + idx);
             }
-        }
+        };
+        uint64_t t = gen_wave_uniform(((uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * TILE);
+        for (; t + TILE <= a.nvec; t += step) tile(t, std::true_type());
+        if (t < a.nvec) tile(t, std::false_type());
         if (blockIdx.x == 0) {
             uint64_t extra = a.head + (a.n - a.tail_begin);
             for (uint64_t e = threadIdx.x; e < extra; e += blockDim.x) {
@@ -331,11 +334,11 @@ __global__ __launch_bounds__(256) void k_generate_h(GenArgs<T> a, HypParams P, H
         V* vout = reinterpret_cast<V*>(a.out + a.head);
         const uint64_t block0 = (a.first + a.head) / NV;
         const uint32_t lane = __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
-        /* wave-contiguous tiles, as k_generate */
+        /* wave-contiguous tiles, as k_generate (whole tiles unchecked, the
+           partial last one checked) */
         constexpr uint64_t TILE = 64ull * UNROLL;
         const uint64_t step = (uint64_t)gridDim.x * 4 * TILE;
-        for (uint64_t t = gen_wave_uniform(((uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * TILE); t < a.nvec;
-             t += step) {
+        auto tile = [&](uint64_t t, auto whole) {
             const uint64_t i = t + lane;
             double v[K], q[K];
             bool far[K];
@@ -368,9 +371,12 @@ __global__ __launch_bounds__(256) void k_generate_h(GenArgs<T> a, HypParams P, H
                 V y;
 #pragma unroll
                 for (int j = 0; j < NV; ++j) y[j] = (T)(P.mu + __builtin_copysign(q[NV * k + j], v[NV * k + j]));
-                if (idx < a.nvec) __builtin_nontemporal_store(y, vout + idx);
+                if (decltype(whole)::value || idx < a.nvec) __builtin_nontemporal_store(y, vout + idx);
             }
-        }
+        };
+        uint64_t t = gen_wave_uniform(((uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * TILE);
+        for (; t + TILE <= a.nvec; t += step) tile(t, std::true_type());
+        if (t < a.nvec) tile(t, std::false_type());
         if (blockIdx.x == 0) {
             uint64_t extra = a.head + (a.n - a.tail_begin);
             for (uint64_t e = threadIdx.x; e < extra; e += blockDim.x) {
