@@ -313,8 +313,6 @@ qm_status enqueue_batch(qm_ctx* ctx, const qm_request* reqs, uint64_t count, hip
             left[i] = (uint32_t)c;
             d[i].flagged = c <= batch_flag_chunks();
         }
-    }
-    if (flags) {
         h.left = reinterpret_cast<uint32_t*>((char*)slot->dev + reqs_bytes);
         h.done = flags;
     }
@@ -602,7 +600,10 @@ static Server* server_of(qm_ctx* ctx, qm_status* st)
     (void)hipSetDevice(ctx->device);
     for (int i = 0; i < SERVE_STREAMS; ++i) {
         if (hipStreamCreateWithFlags(&S->streams[i], hipStreamNonBlocking) != hipSuccess) {
-            for (int j = 0; j < i; ++j) (void)hipStreamDestroy(S->streams[j]);
+            for (int j = 0; j < i; ++j) {
+                (void)hipStreamDestroy(S->streams[j]);
+                if (S->flags[j]) (void)hipHostFree(S->flags[j]);
+            }
             delete S;
             *st = set_error(QM_E_HIP, "hipStreamCreate failed");
             return nullptr;
