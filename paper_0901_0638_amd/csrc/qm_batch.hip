@@ -27,43 +27,96 @@
 
 namespace qm {
 
-typedef float f2 __attribute__((ext_vector_type(2)));
+/* 16-byte vectors per lane, BATCH_UNROLL rows in flight per wave (two
+   doubles or four floats each), as the streaming kernels read them. */
+constexpr int BATCH_UNROLL = 2;
 
-/* 8-byte vectors per lane here (one double or two floats): with many maps in
-   one kernel, fewer elements in flight per lane keeps the register budget of
-   the widest map within reach of 4 waves per SIMD. */
-template <typename T> struct bvec;
-template <> struct bvec<double> { typedef double type; static constexpr int n = 1; };
-template <> struct bvec<float> { typedef f2 type; static constexpr int n = 2; };
+/* The first lane's value of x, as a wave-uniform (scalar) value. */
+__device__ __forceinline__ uint64_t wave_first(uint64_t x)
+{
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)x);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(x >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
 
-template <typename V, typename T> __device__ __forceinline__ T vget(const V& v, int j) { return v[j]; }
-template <> __device__ __forceinline__ double vget<double, double>(const double& v, int) { return v; }
-template <typename V, typename T> __device__ __forceinline__ void vset(V& v, int j, T x) { v[j] = x; }
-template <> __device__ __forceinline__ void vset<double, double>(double& v, int, double x) { v = x; }
+/*
+ * The co-aligned 16-byte body of elements [begin, end) of one request:
+ * *head elements precede it and *tail_begin follows its nvec vectors (the
+ * return value).  Arrays that are not co-aligned have no body (head = n).
+ */
+template <typename T>
+__device__ __forceinline__ uint64_t chunk_body(const T* in, const T* out, uint64_t n, uint64_t* head,
+                                               uint64_t* tail_begin)
+{
+    constexpr int NV = vec16<T>::n;
+    const uintptr_t pi = reinterpret_cast<uintptr_t>(in), po = reinterpret_cast<uintptr_t>(out);
+    uint64_t h = ((16 - (pi % 16)) % 16) / sizeof(T);
+    if ((pi - po) % 16 != 0 || h > n) h = n;
+    const uint64_t nvec = (n - h) / NV;
+    *head = h;
+    *tail_begin = h + nvec * NV;
+    return nvec;
+}
 
-/* Elements [begin, end) of one request by the whole workgroup. */
+/*
+ * Elements [begin, end) of one request by the whole workgroup, streamed as
+ * the single-request kernels stream an array: each wave takes whole tiles
+ * of 64 BATCH_UNROLL consecutive 16-byte vectors (lane l reads vector l of
+ * each 1 KB row), the tiles dealt out to the workgroup's waves in turn.
+ * Only the chunk's last tile can be partial, and whole waves enter it
+ * together (the maps' wave votes need every lane).  The elements before the
+ * first co-aligned 16-byte boundary and after the last whole vector, or
+ * all of them when the arrays are not co-aligned, go one by one.
+ */
 template <typename T, class F>
-__device__ __forceinline__ void chunk_map(const T* __restrict__ in, T* __restrict__ out, uint64_t begin,
+__device__ __forceinline__ void chunk_map(const T* __restrict__ in_, T* __restrict__ out_, uint64_t begin,
                                           uint64_t end, F f)
 {
-    typedef typename bvec<T>::type V;
-    constexpr int NV = bvec<T>::n;
-    uintptr_t pi = reinterpret_cast<uintptr_t>(in + begin), po = reinterpret_cast<uintptr_t>(out + begin);
-    uint64_t n = end - begin;
-    if ((pi % sizeof(V)) == 0 && (po % sizeof(V)) == 0) {
-        const V* vin = reinterpret_cast<const V*>(in + begin);
-        V* vout = reinterpret_cast<V*>(out + begin);
-        uint64_t nvec = n / NV;
-        for (uint64_t i = threadIdx.x; i < nvec; i += blockDim.x) {
-            V x = __builtin_nontemporal_load(vin + i);
+    typedef typename vec16<T>::type V;
+    constexpr int NV = vec16<T>::n;
+    constexpr uint64_t TILE = 64ull * BATCH_UNROLL;
+    const T* in = in_ + begin;
+    T* out = out_ + begin;
+    const uint64_t n = end - begin;
+    uint64_t head, tail_begin;
+    const uint64_t nvec = chunk_body(in, out, n, &head, &tail_begin);
+    const uint32_t lane = __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+    const V* vin = reinterpret_cast<const V*>(in + head);
+    V* vout = reinterpret_cast<V*>(out + head);
+    const uint64_t step = (uint64_t)(blockDim.x >> 6) * TILE;
+    uint64_t t = wave_first((uint64_t)(threadIdx.x >> 6) * TILE);
+    for (; t + TILE <= nvec; t += step) {
+        V x[BATCH_UNROLL];
+#pragma unroll
+        for (int k = 0; k < BATCH_UNROLL; ++k) x[k] = __builtin_nontemporal_load(vin + t + 64 * k + lane);
+#pragma unroll
+        for (int k = 0; k < BATCH_UNROLL; ++k) {
             V y;
 #pragma unroll
-            for (int j = 0; j < NV; ++j) vset<V, T>(y, j, f(vget<V, T>(x, j)));
-            __builtin_nontemporal_store(y, vout + i);
+            for (int j = 0; j < NV; ++j) y[j] = f(x[k][j]);
+            __builtin_nontemporal_store(y, vout + t + 64 * k + lane);
         }
-        for (uint64_t i = nvec * NV + threadIdx.x; i < n; i += blockDim.x) out[begin + i] = f(in[begin + i]);
-    } else {
-        for (uint64_t i = threadIdx.x; i < n; i += blockDim.x) out[begin + i] = f(in[begin + i]);
+    }
+    if (t < nvec) {
+        V x[BATCH_UNROLL];
+#pragma unroll
+        for (int k = 0; k < BATCH_UNROLL; ++k) {
+            const uint64_t idx = t + 64 * k + lane;
+            x[k] = idx < nvec ? __builtin_nontemporal_load(vin + idx) : (V)(T)0.5;
+        }
+#pragma unroll
+        for (int k = 0; k < BATCH_UNROLL; ++k) {
+            const uint64_t idx = t + 64 * k + lane;
+            V y;
+#pragma unroll
+            for (int j = 0; j < NV; ++j) y[j] = f(x[k][j]);
+            if (idx < nvec) __builtin_nontemporal_store(y, vout + idx);
+        }
+    }
+    const uint64_t extra = head + (n - tail_begin);
+    for (uint64_t e = threadIdx.x; e < extra; e += blockDim.x) {
+        const uint64_t idx = e < head ? e : tail_begin + (e - head);
+        out[idx] = f(in[idx]);
     }
 }
 
@@ -89,17 +142,17 @@ QM_CHUNK_FN(chunk_copy32, float, x)
 #undef QM_CHUNK_FN
 
 /* LDS list of the hybrid quantiles' gather: 64 K elements per wave (K = 4
-   FP64 or 8 FP32 per lane), 8 KB per workgroup of four waves. */
+   FP64 or 8 FP32 per lane, two 16-byte vectors), 8 KB per workgroup of four
+   waves. */
 constexpr int GATHER_DOUBLES_PER_WAVE = 64 * 4;
 
 /*
  * Hybrid quantile chunk (FP64 plain, FP32+refine): the streaming kernel's
- * gather (hybrid_eval) over two 16-byte vectors per lane, so that the outer
- * path runs once per 64 outer elements rather than on every lane of a wave
- * holding one; bitwise the per-element function.  Whole waves iterate
- * together, as the gather needs.  Elements before the first co-aligned
- * 16-byte boundary, after the last whole vector, or of arrays that are not
- * co-aligned take the per-element function.
+ * gather (hybrid_eval) over the same wave tiles as chunk_map, so that the
+ * outer path runs once per 64 outer elements rather than on every lane of a
+ * wave holding one; bitwise the per-element function.  Whole waves enter
+ * every tile together, as the gather needs.  Elements outside the
+ * co-aligned 16-byte body take the per-element function.
  */
 template <typename T, class H>
 static __device__ __noinline__ void chunk_hybrid(const void* vin_, void* vout_, uint64_t begin, uint64_t end,
@@ -107,34 +160,31 @@ static __device__ __noinline__ void chunk_hybrid(const void* vin_, void* vout_, 
 {
     typedef typename vec16<T>::type V;
     constexpr int NV = vec16<T>::n;
-    constexpr int UNROLL = 2;
-    constexpr int K = NV * UNROLL;
+    constexpr int K = NV * BATCH_UNROLL;
+    constexpr uint64_t TILE = 64ull * BATCH_UNROLL;
     const T* in = (const T*)vin_ + begin;
     T* out = (T*)vout_ + begin;
     const uint64_t n = end - begin;
-    uintptr_t pi = reinterpret_cast<uintptr_t>(in), po = reinterpret_cast<uintptr_t>(out);
-    uint64_t head = ((16 - (pi % 16)) % 16) / sizeof(T);
-    if ((pi - po) % 16 != 0 || head > n) head = n;          /* not co-aligned: all element-wise */
-    const uint64_t nvec = (n - head) / NV;
-    const uint64_t tail_begin = head + nvec * NV;
+    uint64_t head, tail_begin;
+    const uint64_t nvec = chunk_body(in, out, n, &head, &tail_begin);
     const uint32_t lane = __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
     T* buf = reinterpret_cast<T*>(gather + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) * GATHER_DOUBLES_PER_WAVE);
     const V* vin = reinterpret_cast<const V*>(in + head);
     V* vout = reinterpret_cast<V*>(out + head);
-    for (uint64_t i0 = threadIdx.x - lane; i0 < nvec; i0 += UNROLL * blockDim.x) {
-        const uint64_t i = i0 + lane;
+    const uint64_t step = (uint64_t)(blockDim.x >> 6) * TILE;
+    for (uint64_t t = wave_first((uint64_t)(threadIdx.x >> 6) * TILE); t < nvec; t += step) {
         T u[K], w[K];
 #pragma unroll
-        for (int k = 0; k < UNROLL; ++k) {
-            uint64_t idx = i + k * blockDim.x;
+        for (int k = 0; k < BATCH_UNROLL; ++k) {
+            const uint64_t idx = t + 64 * k + lane;
             V x = idx < nvec ? __builtin_nontemporal_load(vin + idx) : (V)(T)0.5;
 #pragma unroll
             for (int j = 0; j < NV; ++j) u[NV * k + j] = x[j];
         }
         hybrid_eval<T, K, H>(u, w, buf, lane);
 #pragma unroll
-        for (int k = 0; k < UNROLL; ++k) {
-            uint64_t idx = i + k * blockDim.x;
+        for (int k = 0; k < BATCH_UNROLL; ++k) {
+            const uint64_t idx = t + 64 * k + lane;
             V y;
 #pragma unroll
             for (int j = 0; j < NV; ++j) y[j] = w[NV * k + j];
@@ -143,7 +193,7 @@ static __device__ __noinline__ void chunk_hybrid(const void* vin_, void* vout_, 
     }
     const uint64_t extra = head + (n - tail_begin);
     for (uint64_t e = threadIdx.x; e < extra; e += blockDim.x) {
-        uint64_t idx = e < head ? e : tail_begin + (e - head);
+        const uint64_t idx = e < head ? e : tail_begin + (e - head);
         out[idx] = H::whole(in[idx]);
     }
 }
