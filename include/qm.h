@@ -103,14 +103,15 @@ typedef struct qm_ctx qm_ctx;
  * The context owns the per-nu Student t tables and the serving state.
  * Each kernel family has its own launch shape (workgroups of 256 per compute
  * unit x 16-byte vectors in flight per lane, from measured sweeps: light
- * maps 2 x 4, FP64 quantile 64 x 4, FP32+refine quantile 16 x 4, fused
- * generation 64 x 4 (FP64) and 32 x 2 (FP32), Student t 2 x 4 (FP64) and
- * 3 x 4 (FP32), exp -> hyperbolic or variance-gamma 16 x 4 (FP64) and 16 x 2
- * (FP32)); the environment variables QM_BLOCKS_PER_CU (1..64) and
- * QM_UNROLL (1, 2 or 4), read here, override every family, and
- * QM_SHAPE_STREAM, QM_SHAPE_NQ64, QM_SHAPE_NQ32, QM_SHAPE_GEN64,
- * QM_SHAPE_GEN32, QM_SHAPE_T64, QM_SHAPE_T32, QM_SHAPE_H64, QM_SHAPE_H32
- * ("blocks,unroll") one family each.  QM_COMPACT=0 turns off the quantiles' gathering of
+ * FP64 maps 2 x 4, the other FP32 maps 32 x 2, FP64 quantile 64 x 4,
+ * FP32+refine quantile 16 x 4, fused generation 64 x 4 (FP64) and 32 x 2
+ * (FP32), Student t 2 x 4 (FP64) and 3 x 4 (FP32), exp -> hyperbolic or
+ * variance-gamma 16 x 4 (FP64) and 16 x 2 (FP32)); the environment
+ * variables QM_BLOCKS_PER_CU (1..64) and QM_UNROLL (1, 2 or 4), read here,
+ * override every family, and QM_SHAPE_STREAM, QM_SHAPE_STREAM32,
+ * QM_SHAPE_NQ64, QM_SHAPE_NQ32, QM_SHAPE_GEN64, QM_SHAPE_GEN32,
+ * QM_SHAPE_T64, QM_SHAPE_T32, QM_SHAPE_H64, QM_SHAPE_H32 ("blocks,unroll")
+ * one family each.  QM_COMPACT=0 turns off the quantiles' gathering of
  * non-central lanes across the wave (the results are bitwise the same
  * either way).
  * Errors: QM_E_INVAL (out == NULL or no such device), QM_E_HIP, QM_E_NOMEM.

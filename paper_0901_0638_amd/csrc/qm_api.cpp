@@ -282,6 +282,11 @@ qm_status qm_init(int hip_device, uint64_t hbm_budget_bytes, qm_ctx** out)
     const uint64_t ncu = (uint64_t)(cus > 0 ? cus : 256);
     struct { qm::KernelShape* ks; const char* env; long bpc, unroll; } fam[] = {
         {&c->shape.stream, "QM_SHAPE_STREAM", 2, 4},   /* light maps: few workgroups, deep unroll */
+        /* FP32 maps: four elements per 16-byte vector carry twice the
+           arithmetic per byte; exp -> normal FP32 (2^26, scrubbed launches)
+           ran 473-478 Gs/s refined and 590-600 plain at 16..32 x 2, against
+           393-411 and 498-526 at 2 x 4 */
+        {&c->shape.stream32, "QM_SHAPE_STREAM32", 32, 2},
         /* quantiles, wave-contiguous tiles: FP32+refine 16 x 4 (8..16 x 4
            measured 0.504-0.505 ms on the 2^28 FP32 mixture, 32 x 2 0.52-0.54),
            FP64 64 x 4 */

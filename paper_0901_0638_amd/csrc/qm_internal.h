@@ -25,7 +25,8 @@ struct KernelShape {
    few workgroups with deep unrolling, the VALU-heavy hybrid quantiles from
    many. */
 struct LaunchShape {
-    KernelShape stream;      /* k_map: exp -> normal, paper modes, FP32 plain */
+    KernelShape stream;      /* k_map, FP64: exp -> normal, paper mode */
+    KernelShape stream32;    /* k_map, FP32: exp -> normal, paper and plain quantiles */
     KernelShape hybrid[2];   /* [0] FP32+refine, [1] FP64 quantile: k_hybrid */
     KernelShape generate[2]; /* [0] FP32, [1] FP64 outputs: k_generate, k_generate_t */
     KernelShape student[2];  /* [0] FP32, [1] FP64 outputs: k_student */

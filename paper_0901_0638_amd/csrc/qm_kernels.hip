@@ -209,7 +209,7 @@ static hipError_t launch_op(const void* in, void* out, uint64_t n, hipStream_t s
 {
     typedef typename HybridOf<Op>::type H;
     const bool gather = shape.compact && !std::is_void<H>::value;
-    const KernelShape ks = gather ? shape.hybrid[sizeof(T) == 8] : shape.stream;
+    const KernelShape ks = gather ? shape.hybrid[sizeof(T) == 8] : (sizeof(T) == 8 ? shape.stream : shape.stream32);
     MapArgs<T> a;
     a.in = static_cast<const T*>(in);
     a.out = static_cast<T*>(out);
