@@ -468,6 +468,12 @@ def oracle_leg(args, acc, h64):
     base = {"value": round(mm / cdt / 1e9, 6), "unit": "Gsamples/s", "cores": threads, "kind": "oracle",
             "sample": "first %d elements of the FP64 mixture workload, FP64 quantile, %.1f s wall on %d threads "
                       "(%s)" % (mm, cdt, threads, cpu_model())}
+    m1 = min(1 << 20, h64.size)                 # the same oracle on one thread, a smaller sample
+    c0 = time.perf_counter()
+    oracle.norm_quantile(h64[:m1], 1)
+    c1 = time.perf_counter() - c0
+    base["one_thread"] = {"value": round(m1 / c1 / 1e9, 6), "unit": "Gsamples/s",
+                          "sample": "first %d elements, %.1f s wall on 1 thread" % (m1, c1)}
     errors = {}
     for name, (x, got, fn, rtol) in acc.items():
         if name == "fp64":
